@@ -1,0 +1,22 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+for p in (ROOT, os.path.join(ROOT, "oracle"), os.path.join(ROOT, "tests")):
+    if p not in sys.path:
+        sys.path.insert(0, p)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    config.addinivalue_line("markers", "slow: long CPU-only check")
+
+
+@pytest.fixture(scope="session")
+def orc():
+    import oracle  # noqa: F401  (tests/ put oracle/ on the path)
+    if not os.path.exists(oracle.LIB):
+        oracle.build()
+    return oracle
