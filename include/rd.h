@@ -1,0 +1,187 @@
+/*
+ * rd.h - C ABI of librd, a GPU (AMD Instinct MI355X, gfx950) library for the
+ * multidimensional upwind residual-distribution scheme of Paardekooper (2017),
+ * "Multidimensional upwind hydrodynamics on unstructured meshes using
+ * Graphics Processing Units - I. Two-dimensional uniform meshes".
+ *
+ * The library advances the two-dimensional Euler equations of an ideal gas
+ * (Section 3, conservation form) on a static triangular mesh. Each step
+ * Roe-averages the parameter vectors of a triangle's three vertices, builds
+ * the flux Jacobians K_i along the inward edge normals and their positive
+ * and negative parts (Section 3.2 and Appendix A), forms the triangle
+ * residual, distributes it to the vertices with the N, LDA or blended B
+ * schemes (Section 3.3), sums the parts per vertex and updates the state with
+ * forward Euler or the two-stage Runge-Kutta scheme of Section 3.4, with
+ * periodic, non-reflecting (ghost) and reflecting-wall boundaries
+ * (Section 3.6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - States are float64, structure of arrays: W[k * n_vertices + i] is
+ *    component k of vertex i, k = 0..3 for (rho, rho u, rho v, e) with
+ *    e = rho (u^2 + v^2)/2 + p/(gamma - 1).
+ *  - Every call returns an rd_status; no C++ exception crosses this ABI.
+ *    On a non-OK status rd_last_error() returns a message (thread-local,
+ *    valid until the next call from the same thread).
+ *  - `on_device` = 0: the pointer is host memory; the call copies and
+ *    returns when the copy is complete. `on_device` = 1: the pointer is
+ *    device memory of the current HIP device (e.g. a torch tensor's
+ *    data_ptr); the work is ordered on the mesh's stream and the call
+ *    returns without waiting.
+ *  - The library never frees memory it did not allocate. Arrays passed to
+ *    rd_mesh_create and host states are copied; the caller keeps ownership.
+ *  - One mesh is used by one host thread at a time.
+ *  - Kernels never use floating-point atomics: the vertex sums run over a
+ *    fixed (ascending-triangle) order, so repeated runs give bitwise
+ *    identical results.
+ */
+#ifndef RD_H
+#define RD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rd_mesh rd_mesh;   /* opaque; owns its device buffers */
+typedef struct rd_batch rd_batch; /* opaque; owns its device buffers */
+
+typedef enum {
+  RD_OK = 0,
+  RD_EINVAL = 1,        /* an argument or the mesh is invalid */
+  RD_ENOMEM = 2,        /* device or host allocation failed */
+  RD_EDEVICE = 3,       /* a HIP runtime call failed */
+  RD_ENONPHYS = 4,      /* a state with rho <= 0, p <= 0 or a non-finite value */
+  RD_EUNSUPPORTED = 5   /* valid request this build does not provide */
+} rd_status;
+
+/* Distribution schemes (Section 3.3): N, LDA, and the blend B with its
+ * diagonal Theta; BMAX / BMIN set every Theta_kk to the largest / smallest. */
+typedef enum { RD_N = 0, RD_LDA = 1, RD_B = 2, RD_BMAX = 3, RD_BMIN = 4 } rd_scheme;
+
+/* Time integration: forward Euler (the update of Section 3.2) or the
+ * two-stage Runge-Kutta scheme of Section 3.4 with global lumping and the
+ * mass matrix |T|/3 beta_i. */
+typedef enum { RD_EULER1 = 1, RD_RK2 = 2 } rd_time;
+
+/* Arithmetic: FP64 throughout, or the triangle algebra in FP32 with the
+ * vertex sums and the state update in FP64 (compensated summation). */
+typedef enum { RD_FP64 = 0, RD_FP32_ACC64 = 1 } rd_precision;
+
+typedef struct {
+  int64_t n_vertices;      /* > 0 */
+  int64_t n_triangles;     /* > 0, 3 * n_triangles < 2^31 */
+  const double* x;         /* [n_vertices] host */
+  const double* y;         /* [n_vertices] host */
+  const int32_t* tri;      /* [3 * n_triangles] host, corners counter-clockwise
+                              after unwrapping to the minimum image of corner 0 */
+  double period_x;         /* 0: x bounded; > 0: x periodic with this period */
+  double period_y;         /* 0: y bounded; > 0: y periodic with this period */
+  const uint8_t* ghost;    /* [n_vertices] host or NULL; 1 marks a ghost vertex that
+                              keeps its state (non-reflecting / inflow, Section 3.6) */
+  int64_t n_wall_edges;    /* >= 0 */
+  const int32_t* wall_edges; /* [2 * n_wall_edges] host: (a, b) with the domain on the
+                                left of a -> b; reflecting wall of Section 3.6 */
+  double gamma;            /* ratio of specific heats, > 1 */
+} rd_mesh_desc;
+
+/* Checks a mesh description on the host only (no GPU needed): indices in
+ * range, positive unwrapped areas, every vertex in some triangle, valid wall
+ * edges. RD_OK or RD_EINVAL. */
+rd_status rd_mesh_validate(const rd_mesh_desc* desc);
+
+/* Validates `desc`, precomputes vertex volumes V_i = sum |T|/3 (median dual,
+ * Section 3.2 update with global lumping), the vertex -> (triangle, corner)
+ * CSR used by the deterministic gather, longest edges for the CFL limit and
+ * the wall-edge lists, and allocates the device buffers. `stream` is a
+ * hipStream_t (NULL: the null stream). The state is zero until
+ * rd_set_state. RD_EINVAL, RD_ENOMEM or RD_EDEVICE on failure (*out = NULL). */
+rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh** out);
+
+/* Waits for the mesh's stream, frees every buffer. NULL is accepted. */
+rd_status rd_mesh_destroy(rd_mesh* mesh);
+
+/* Sizes of a mesh. */
+rd_status rd_mesh_info(const rd_mesh* mesh, int64_t* n_vertices, int64_t* n_triangles);
+
+/* Replaces the stream all later work of this mesh is ordered on. */
+rd_status rd_set_stream(rd_mesh* mesh, void* stream);
+
+/* Sets the state W [4][n_vertices]. Host input is checked (rho > 0, p > 0,
+ * finite: else RD_ENONPHYS and nothing changes); device input is checked on
+ * the device and reported by rd_sync. Ghost vertices keep this value. */
+rd_status rd_set_state(rd_mesh* mesh, const double* W, int on_device);
+
+/* Copies the current state into W [4][n_vertices]. With on_device = 0 it
+ * waits and returns RD_ENONPHYS if a non-physical state was latched
+ * (the copy is still made). */
+rd_status rd_get_state(rd_mesh* mesh, double* W, int on_device);
+
+/* CFL limit of Section 3.2 at the current state, times `cfl`:
+ * cfl * min_i 2 V_i / sum_{T ni i} l_max^T lambda_max^T, with
+ * lambda_max^T = max over the corners of |v| + c. Waits for the result. */
+rd_status rd_max_dt(rd_mesh* mesh, double cfl, double* dt_out);
+
+/* One time step of size dt > 0 (Sections 3.2-3.4). Enqueues only. */
+rd_status rd_step(rd_mesh* mesh, double dt, int scheme, int time, int precision);
+
+/* `n_steps` steps, each with dt = cfl * (CFL limit at the step's start),
+ * computed on the device: no host synchronisation. Enqueues only. */
+rd_status rd_step_cfl(rd_mesh* mesh, int n_steps, double cfl, int scheme, int time, int precision);
+
+/* Kernels of one step, in launch order, as reported by rd_step_timed. */
+enum {
+  RD_K_CFL_TRI = 0,    /* l_max lambda_max per triangle */
+  RD_K_CFL_VERTEX = 1, /* 2 V_i / sum per vertex, block minima */
+  RD_K_CFL_FINAL = 2,  /* minimum over blocks -> dt */
+  RD_K_WALL1 = 3,      /* wall term at W^n (meshes with walls) */
+  RD_K_TRI1 = 4,       /* triangle pass, stage 1 */
+  RD_K_GATHER1 = 5,    /* vertex sums and update, stage 1 */
+  RD_K_WALL2 = 6,      /* wall term at W* (RK2 with walls) */
+  RD_K_TRI2 = 7,       /* triangle pass, stage 2 (RK2) */
+  RD_K_GATHER2 = 8,    /* vertex sums and update, stage 2 (RK2) */
+  RD_NKERNELS = 9
+};
+
+/* One step as rd_step_cfl(mesh, 1, ...) does, with a HIP event recorded on
+ * the mesh's stream between consecutive kernels; waits, then writes the
+ * duration of every kernel in milliseconds to ms[RD_NKERNELS] (0 for
+ * kernels the step does not launch). For profiling. */
+rd_status rd_step_timed(rd_mesh* mesh, double cfl, int scheme, int time, int precision, double* ms);
+
+/* Spatial residual at the current state (Section 3.2-3.3, FP64): R_i = sum
+ * over the triangles of i (ascending triangle order) of the scheme's part
+ * phi_i^T, plus the wall term; R is [4][n_vertices]. phiT (may be NULL)
+ * receives the triangle residuals [4][n_triangles]. */
+rd_status rd_residual(rd_mesh* mesh, int scheme, double* R, double* phiT, int on_device);
+
+/* Adjoint of one step for a fixed dt (FP64 only): given the state W_n
+ * [4][n_vertices] the step started from and lam_np1 = dL/dW^{n+1}, writes
+ * lam_n = (dW^{n+1}/dW^n)^T lam_np1. Does not change the mesh's state.
+ * Derivatives follow the branch the forward values take; d|x|/dx = 0 at 0. */
+rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int scheme, int time,
+                          const double* lam_np1, double* lam_n, int on_device);
+
+/* Many independent meshes advanced together. The batch keeps its own copy of
+ * the meshes' geometry; rd_batch_run takes each mesh's current state, runs
+ * n_steps steps in one captured HIP graph (per-mesh CFL dt each step, computed
+ * on the device) and writes the states back to the meshes. Meshes must share
+ * gamma and must not be periodic. */
+rd_status rd_batch_create(rd_mesh* const* meshes, int n_meshes, void* stream, rd_batch** out);
+rd_status rd_batch_run(rd_batch* batch, int n_steps, double cfl, int scheme, int time, int precision);
+rd_status rd_batch_destroy(rd_batch* batch);
+
+/* Waits for the mesh's stream. RD_ENONPHYS if a non-physical state was
+ * produced since the last rd_set_state (the flag stays set), RD_EDEVICE on a
+ * runtime error. */
+rd_status rd_sync(rd_mesh* mesh);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* rd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RD_H */

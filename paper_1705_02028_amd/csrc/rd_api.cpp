@@ -1,0 +1,608 @@
+// Host side of the librd C ABI: mesh validation and precompute, device
+// buffers, and the order of kernel launches for one step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rd.h"
+#include "rd_launch.h"
+
+#define RD_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rd_status fail(rd_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIPCHK(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(RD_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+double unwrap_h(double d, double period) {
+  if (period > 0.0) {
+    if (d > 0.5 * period) d -= period;
+    else if (d < -0.5 * period) d += period;
+  }
+  return d;
+}
+
+// Geometry the device does not recompute: vertex volumes (median dual) and
+// longest edges. Also the checks of rd_mesh_validate.
+struct HostGeom {
+  std::vector<double> V, lmax;
+};
+
+rd_status check_desc(const rd_mesh_desc* d, HostGeom* out) {
+  if (!d) return fail(RD_EINVAL, "null mesh description");
+  if (d->n_vertices <= 0 || d->n_triangles <= 0) return fail(RD_EINVAL, "empty mesh");
+  if (d->n_vertices >= (int64_t(1) << 31) || 3 * d->n_triangles >= (int64_t(1) << 31))
+    return fail(RD_EINVAL, "mesh too large for 32-bit indices");
+  if (!d->x || !d->y || !d->tri) return fail(RD_EINVAL, "null coordinate or triangle array");
+  if (!(d->gamma > 1.0)) return fail(RD_EINVAL, "gamma must exceed 1");
+  if (d->period_x < 0.0 || d->period_y < 0.0) return fail(RD_EINVAL, "negative period");
+  if (d->n_wall_edges < 0 || (d->n_wall_edges > 0 && !d->wall_edges))
+    return fail(RD_EINVAL, "bad wall edge list");
+  const int64_t nv = d->n_vertices, nt = d->n_triangles;
+  std::vector<double> V(nv, 0.0), lmax(nt, 0.0), area(nt, 0.0);
+  for (int64_t t = 0; t < nt; ++t) {
+    int32_t v[3] = {d->tri[3 * t], d->tri[3 * t + 1], d->tri[3 * t + 2]};
+    for (int k = 0; k < 3; ++k)
+      if (v[k] < 0 || v[k] >= nv)
+        return fail(RD_EINVAL, "triangle " + std::to_string(t) + " has a vertex index out of range");
+    double px[3] = {0.0, 0.0, 0.0}, py[3] = {0.0, 0.0, 0.0};
+    for (int k = 1; k < 3; ++k) {
+      px[k] = unwrap_h(d->x[v[k]] - d->x[v[0]], d->period_x);
+      py[k] = unwrap_h(d->y[v[k]] - d->y[v[0]], d->period_y);
+    }
+    const double a = 0.5 * (px[1] * py[2] - py[1] * px[2]);
+    if (!(a > 0.0))
+      return fail(RD_EINVAL, "triangle " + std::to_string(t) + " is not counter-clockwise with positive area");
+    area[t] = a;
+    double lm = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      const int j = (i + 1) % 3, k = (i + 2) % 3;
+      const double ex = px[k] - px[j], ey = py[k] - py[j];
+      lm = std::max(lm, std::sqrt(ex * ex + ey * ey));
+    }
+    lmax[t] = lm;
+  }
+  for (int64_t t = 0; t < nt; ++t)
+    for (int k = 0; k < 3; ++k) V[d->tri[3 * t + k]] += area[t] / 3.0;
+  for (int64_t i = 0; i < nv; ++i)
+    if (!(V[i] > 0.0)) return fail(RD_EINVAL, "vertex " + std::to_string(i) + " belongs to no triangle");
+  for (int64_t e = 0; e < d->n_wall_edges; ++e) {
+    const int32_t a = d->wall_edges[2 * e], b = d->wall_edges[2 * e + 1];
+    if (a < 0 || a >= nv || b < 0 || b >= nv || a == b)
+      return fail(RD_EINVAL, "wall edge " + std::to_string(e) + " is invalid");
+  }
+  if (out) {
+    out->V.swap(V);
+    out->lmax.swap(lmax);
+  }
+  return RD_OK;
+}
+
+}  // namespace
+
+struct rd_mesh {
+  rd::Dev d;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // host copies, kept for batches
+  std::vector<double> x, y, V, lmax;
+  std::vector<int32_t> tri, wall, row, slot, bc, wv, wptr;
+  std::vector<uint8_t> ghost;
+  std::vector<rd::WallEnt> went;
+  double px = 0.0, py = 0.0, gamma = 1.4;
+  // device buffers
+  std::vector<void*> allocs;
+  rd::CflPlan cfl;
+  void* C[2] = {nullptr, nullptr};
+  void* keepN[2] = {nullptr, nullptr};
+  void* keepT[2] = {nullptr, nullptr};
+  void* dW[2] = {nullptr, nullptr};
+  double* scratch = nullptr;  // [4 * max(nv, nt)]
+  int zprec = -1;             // precision the parameter vectors are valid for
+  hipEvent_t events[RD_NKERNELS + 1] = {};
+};
+
+namespace {
+
+template <class T>
+rd_status dalloc(rd_mesh* m, T** p, size_t n) {
+  void* q = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&q, n * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(RD_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  m->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return RD_OK;
+}
+
+template <class T>
+rd_status upload(rd_mesh* m, T** p, const std::vector<T>& h) {
+  rd_status st = dalloc(m, p, h.size());
+  if (st != RD_OK) return st;
+  if (!h.empty()) HIPCHK(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return RD_OK;
+}
+
+void free_all(rd_mesh* m) {
+  for (void* p : m->allocs) (void)hipFree(p);
+  m->allocs.clear();
+}
+
+// Buffers of one arithmetic precision, allocated on first use.
+rd_status ensure_prec(rd_mesh* m, int fp32) {
+  if (m->C[fp32]) return RD_OK;
+  const size_t q = fp32 ? sizeof(rd::F4) : sizeof(rd::D4);
+  const int64_t nt = m->d.nt, nv = m->d.nv;
+  char* p = nullptr;
+  rd_status st;
+  if ((st = dalloc(m, &p, q * 3 * nt)) != RD_OK) return st;
+  m->C[fp32] = p;
+  if ((st = dalloc(m, &p, q * 3 * nt)) != RD_OK) return st;
+  m->keepN[fp32] = p;
+  if ((st = dalloc(m, &p, q * nt)) != RD_OK) return st;
+  m->keepT[fp32] = p;
+  if ((st = dalloc(m, &p, q * nv)) != RD_OK) return st;
+  m->dW[fp32] = p;
+  if (fp32 && !m->d.Zf) {
+    rd::F4* z = nullptr;
+    if ((st = dalloc(m, &z, nv)) != RD_OK) return st;
+    m->d.Zf = z;
+  }
+  return RD_OK;
+}
+
+rd::Dev dev_for(const rd_mesh* m, int fp32) {
+  rd::Dev d = m->d;
+  d.C = m->C[fp32];
+  d.keepN = m->keepN[fp32];
+  d.keepT = m->keepT[fp32];
+  d.dW = m->dW[fp32];
+  return d;
+}
+
+// The parameter vectors must be valid for the arithmetic about to run.
+rd_status ensure_z(rd_mesh* m, int fp32) {
+  if (m->zprec == fp32) return RD_OK;
+  HIPCHK(rd::launch_refresh(dev_for(m, fp32), fp32, m->stream));
+  m->zprec = fp32;
+  return RD_OK;
+}
+
+// One step of Sections 3.2-3.4 with the time step already in d.dt. With
+// `ev` (RD_NKERNELS + 1 events) an event is recorded before every kernel
+// slot RD_K_WALL1.. and after the last.
+rd_status run_step(rd_mesh* m, int scheme, int time, int fp32, hipEvent_t* ev = nullptr) {
+  const rd::Dev d = dev_for(m, fp32);
+  hipStream_t s = m->stream;
+  auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
+  HIPCHK(mark(RD_K_WALL1));
+  HIPCHK(rd::launch_wall(d, false, s));
+  HIPCHK(mark(RD_K_TRI1));
+  HIPCHK(rd::launch_tri(d, fp32, scheme, 1, time == RD_RK2, s));
+  HIPCHK(mark(RD_K_GATHER1));
+  HIPCHK(rd::launch_gather(d, fp32, time == RD_RK2 ? rd::G_STAGE1 : rd::G_EULER, nullptr, s));
+  HIPCHK(mark(RD_K_WALL2));
+  if (time == RD_RK2) {
+    HIPCHK(rd::launch_wall(d, true, s));
+    HIPCHK(mark(RD_K_TRI2));
+    HIPCHK(rd::launch_tri(d, fp32, scheme, 2, false, s));
+    HIPCHK(mark(RD_K_GATHER2));
+    HIPCHK(rd::launch_gather(d, fp32, rd::G_STAGE2, nullptr, s));
+  } else {
+    HIPCHK(mark(RD_K_TRI2));
+    HIPCHK(mark(RD_K_GATHER2));
+  }
+  HIPCHK(mark(RD_NKERNELS));
+  m->zprec = fp32;
+  return RD_OK;
+}
+
+rd_status check_step_args(int scheme, int time, int precision) {
+  if (scheme < RD_N || scheme > RD_BMIN) return fail(RD_EINVAL, "unknown scheme");
+  if (time != RD_EULER1 && time != RD_RK2) return fail(RD_EINVAL, "unknown time integration");
+  if (precision != RD_FP64 && precision != RD_FP32_ACC64) return fail(RD_EINVAL, "unknown precision");
+  return RD_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool physical(const double* W, int64_t nv, int64_t i, double gamma) {
+  const double rho = W[i], mx = W[nv + i], my = W[2 * nv + i], e = W[3 * nv + i];
+  if (!std::isfinite(rho) || !std::isfinite(mx) || !std::isfinite(my) || !std::isfinite(e)) return false;
+  if (!(rho > 0.0)) return false;
+  const double p = (gamma - 1.0) * (e - 0.5 * (mx * mx + my * my) / rho);
+  return p > 0.0;
+}
+
+}  // namespace
+
+RD_API rd_status rd_mesh_validate(const rd_mesh_desc* desc) { return check_desc(desc, nullptr); }
+
+RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh** out) {
+  if (!out) return fail(RD_EINVAL, "null output pointer");
+  *out = nullptr;
+  HostGeom geo;
+  rd_status st = check_desc(desc, &geo);
+  if (st != RD_OK) return st;
+  rd_mesh* m = new rd_mesh();
+  m->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&m->device) != hipSuccess) {
+    delete m;
+    return fail(RD_EDEVICE, "no HIP device");
+  }
+  const int64_t nv = desc->n_vertices, nt = desc->n_triangles;
+  m->x.assign(desc->x, desc->x + nv);
+  m->y.assign(desc->y, desc->y + nv);
+  m->tri.assign(desc->tri, desc->tri + 3 * nt);
+  m->ghost.assign(nv, 0);
+  if (desc->ghost)
+    for (int64_t i = 0; i < nv; ++i) m->ghost[i] = desc->ghost[i] ? 1 : 0;
+  if (desc->n_wall_edges > 0) m->wall.assign(desc->wall_edges, desc->wall_edges + 2 * desc->n_wall_edges);
+  m->px = desc->period_x;
+  m->py = desc->period_y;
+  m->gamma = desc->gamma;
+  m->V.swap(geo.V);
+  m->lmax.swap(geo.lmax);
+
+  // vertex -> (triangle, corner) CSR, ascending triangle order in every row
+  m->row.assign(nv + 1, 0);
+  for (int64_t s = 0; s < 3 * nt; ++s) m->row[m->tri[s] + 1]++;
+  for (int64_t i = 0; i < nv; ++i) m->row[i + 1] += m->row[i];
+  m->slot.assign(3 * nt, 0);
+  {
+    std::vector<int32_t> fill(m->row.begin(), m->row.end() - 1);
+    for (int64_t s = 0; s < 3 * nt; ++s) m->slot[fill[m->tri[s]]++] = (int32_t)s;
+  }
+  // boundary kinds and wall incidences (ascending edge id per vertex)
+  bool has_bc = false;
+  for (int64_t i = 0; i < nv; ++i) has_bc |= m->ghost[i] != 0;
+  has_bc |= !m->wall.empty();
+  if (has_bc) {
+    m->bc.assign(nv, -1);
+    std::vector<std::vector<rd::WallEnt>> per(nv);
+    const int64_t nw = (int64_t)m->wall.size() / 2;
+    for (int64_t e = 0; e < nw; ++e) {
+      const int32_t a = m->wall[2 * e], b = m->wall[2 * e + 1];
+      const double dx = unwrap_h(m->x[b] - m->x[a], m->px), dy = unwrap_h(m->y[b] - m->y[a], m->py);
+      const double len = std::sqrt(dx * dx + dy * dy);
+      rd::WallEnt ea{b, 0, len / 2.0, dy / len, -dx / len};
+      rd::WallEnt eb{a, 1, len / 2.0, dy / len, -dx / len};
+      per[a].push_back(ea);
+      per[b].push_back(eb);
+    }
+    m->wptr.push_back(0);
+    for (int64_t i = 0; i < nv; ++i) {
+      if (m->ghost[i]) {
+        m->bc[i] = -2;
+      } else if (!per[i].empty()) {
+        m->bc[i] = (int32_t)m->wv.size();
+        m->wv.push_back((int32_t)i);
+        for (const auto& e : per[i]) m->went.push_back(e);
+        m->wptr.push_back((int32_t)m->went.size());
+      }
+    }
+  }
+
+  rd::Dev& d = m->d;
+  d.nv = nv;
+  d.nt = nt;
+  d.nwv = (int32_t)m->wv.size();
+  d.gamma = m->gamma;
+  d.px = m->px;
+  d.py = m->py;
+  {
+    DeviceGuard g(m->device);
+    std::vector<double2> xy(nv);
+    for (int64_t i = 0; i < nv; ++i) xy[i] = make_double2(m->x[i], m->y[i]);
+    std::vector<int32_t> tv(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+      for (int k = 0; k < 3; ++k) tv[k * nt + t] = m->tri[3 * t + k];
+    double2* pxy;
+    double *pV, *plmax;
+    int32_t *prow, *pslot, *ptv;
+    if ((st = upload(m, &pxy, xy)) || (st = upload(m, &pV, m->V)) || (st = upload(m, &plmax, m->lmax)) ||
+        (st = upload(m, &prow, m->row)) || (st = upload(m, &pslot, m->slot)) || (st = upload(m, &ptv, tv))) {
+      free_all(m);
+      delete m;
+      return st;
+    }
+    d.xy = pxy;
+    d.V = pV;
+    d.lmax = plmax;
+    d.row = prow;
+    d.slot = pslot;
+    d.tv = ptv;
+    if (has_bc) {
+      int32_t *pbc, *pwv, *pwptr;
+      rd::WallEnt* pwent;
+      if ((st = upload(m, &pbc, m->bc)) || (st = upload(m, &pwv, m->wv)) || (st = upload(m, &pwptr, m->wptr)) ||
+          (st = upload(m, &pwent, m->went))) {
+        free_all(m);
+        delete m;
+        return st;
+      }
+      d.bc = pbc;
+      d.wv = pwv;
+      d.wptr = pwptr;
+      d.went = pwent;
+      rd::D4 *wcn, *wcs;
+      if ((st = dalloc(m, &wcn, d.nwv)) || (st = dalloc(m, &wcs, d.nwv))) {
+        free_all(m);
+        delete m;
+        return st;
+      }
+      d.WCn = wcn;
+      d.WCs = wcs;
+    }
+    rd::D4 *W, *Ws, *Z;
+    double *sig, *lam, *dt, *scratch;
+    int* flag;
+    if ((st = dalloc(m, &W, nv)) || (st = dalloc(m, &Ws, nv)) || (st = dalloc(m, &Z, nv)) ||
+        (st = dalloc(m, &sig, nv)) || (st = dalloc(m, &lam, nt)) || (st = dalloc(m, &dt, 1)) ||
+        (st = dalloc(m, &flag, 1)) || (st = dalloc(m, &scratch, 4 * std::max(nv, nt)))) {
+      free_all(m);
+      delete m;
+      return st;
+    }
+    d.W = W;
+    d.Ws = Ws;
+    d.Z = Z;
+    d.sig = sig;
+    d.lam = lam;
+    d.dt = dt;
+    d.flag = flag;
+    m->scratch = scratch;
+    // CFL reduction plan: vertex blocks of kBlock, one segment
+    const int32_t nb = (int32_t)((nv + rd::kBlock - 1) / rd::kBlock);
+    std::vector<int32_t> v0(nb), v1(nb), b0 = {0, nb};
+    for (int32_t b = 0; b < nb; ++b) {
+      v0[b] = b * rd::kBlock;
+      v1[b] = (int32_t)std::min<int64_t>(nv, (int64_t)(b + 1) * rd::kBlock);
+    }
+    int32_t *pv0, *pv1, *pb0;
+    double* part;
+    if ((st = upload(m, &pv0, v0)) || (st = upload(m, &pv1, v1)) || (st = upload(m, &pb0, b0)) ||
+        (st = dalloc(m, &part, nb))) {
+      free_all(m);
+      delete m;
+      return st;
+    }
+    m->cfl.nblocks = nb;
+    m->cfl.nmesh = 1;
+    m->cfl.blk_v0 = pv0;
+    m->cfl.blk_v1 = pv1;
+    m->cfl.mesh_b0 = pb0;
+    m->cfl.part = part;
+    if ((st = ensure_prec(m, 0)) != RD_OK) {
+      free_all(m);
+      delete m;
+      return st;
+    }
+    hipError_t e = hipMemset(W, 0, sizeof(rd::D4) * nv);
+    if (e == hipSuccess) e = hipMemset(flag, 0, sizeof(int));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      free_all(m);
+      delete m;
+      return fail(RD_EDEVICE, std::string("initialising buffers: ") + hipGetErrorString(e));
+    }
+  }
+  *out = m;
+  return RD_OK;
+}
+
+RD_API rd_status rd_mesh_destroy(rd_mesh* m) {
+  if (!m) return RD_OK;
+  DeviceGuard g(m->device);
+  (void)hipStreamSynchronize(m->stream);
+  for (hipEvent_t e : m->events)
+    if (e) (void)hipEventDestroy(e);
+  free_all(m);
+  delete m;
+  return RD_OK;
+}
+
+RD_API rd_status rd_mesh_info(const rd_mesh* m, int64_t* nv, int64_t* nt) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  if (nv) *nv = m->d.nv;
+  if (nt) *nt = m->d.nt;
+  return RD_OK;
+}
+
+RD_API rd_status rd_set_stream(rd_mesh* m, void* stream) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  m->stream = static_cast<hipStream_t>(stream);
+  return RD_OK;
+}
+
+RD_API rd_status rd_set_state(rd_mesh* m, const double* W, int on_device) {
+  if (!m || !W) return fail(RD_EINVAL, "null argument");
+  DeviceGuard g(m->device);
+  const int64_t nv = m->d.nv;
+  const double* src = W;
+  if (!on_device) {
+    for (int64_t i = 0; i < nv; ++i)
+      if (!physical(W, nv, i, m->gamma))
+        return fail(RD_ENONPHYS, "vertex " + std::to_string(i) + " has rho <= 0, p <= 0 or a non-finite value");
+    HIPCHK(hipMemcpyAsync(m->scratch, W, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, m->stream));
+    src = m->scratch;
+  }
+  rd::Dev d = dev_for(m, 0);
+  HIPCHK(rd::launch_set_int(d.flag, 0, m->stream));
+  HIPCHK(rd::launch_set_state(d, src, 0, m->stream));
+  m->zprec = 0;
+  if (!on_device) HIPCHK(hipStreamSynchronize(m->stream));
+  return RD_OK;
+}
+
+RD_API rd_status rd_get_state(rd_mesh* m, double* W, int on_device) {
+  if (!m || !W) return fail(RD_EINVAL, "null argument");
+  DeviceGuard g(m->device);
+  const int64_t nv = m->d.nv;
+  if (on_device) {
+    HIPCHK(rd::launch_get_state(m->d, m->d.W, W, m->stream));
+    return RD_OK;
+  }
+  HIPCHK(rd::launch_get_state(m->d, m->d.W, m->scratch, m->stream));
+  HIPCHK(hipMemcpyAsync(W, m->scratch, sizeof(double) * 4 * nv, hipMemcpyDeviceToHost, m->stream));
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, m->d.flag, sizeof(int), hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if (flag) return fail(RD_ENONPHYS, "a non-physical state was produced");
+  return RD_OK;
+}
+
+RD_API rd_status rd_max_dt(rd_mesh* m, double cfl, double* dt_out) {
+  if (!m || !dt_out) return fail(RD_EINVAL, "null argument");
+  if (!(cfl > 0.0)) return fail(RD_EINVAL, "cfl must be positive");
+  DeviceGuard g(m->device);
+  HIPCHK(rd::launch_cfl(m->d, m->cfl, cfl, m->stream));
+  HIPCHK(hipMemcpyAsync(dt_out, m->d.dt, sizeof(double), hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return RD_OK;
+}
+
+RD_API rd_status rd_step(rd_mesh* m, double dt, int scheme, int time, int precision) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RD_EINVAL, "dt must be positive and finite");
+  rd_status st = check_step_args(scheme, time, precision);
+  if (st != RD_OK) return st;
+  DeviceGuard g(m->device);
+  const int fp32 = precision == RD_FP32_ACC64;
+  if ((st = ensure_prec(m, fp32)) != RD_OK) return st;
+  if ((st = ensure_z(m, fp32)) != RD_OK) return st;
+  HIPCHK(rd::launch_set_scalar(m->d.dt, dt, m->stream));
+  return run_step(m, scheme, time, fp32);
+}
+
+RD_API rd_status rd_step_cfl(rd_mesh* m, int n_steps, double cfl, int scheme, int time, int precision) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  if (n_steps < 0) return fail(RD_EINVAL, "negative step count");
+  if (!(cfl > 0.0)) return fail(RD_EINVAL, "cfl must be positive");
+  rd_status st = check_step_args(scheme, time, precision);
+  if (st != RD_OK) return st;
+  DeviceGuard g(m->device);
+  const int fp32 = precision == RD_FP32_ACC64;
+  if ((st = ensure_prec(m, fp32)) != RD_OK) return st;
+  if ((st = ensure_z(m, fp32)) != RD_OK) return st;
+  for (int n = 0; n < n_steps; ++n) {
+    HIPCHK(rd::launch_cfl(m->d, m->cfl, cfl, m->stream));
+    if ((st = run_step(m, scheme, time, fp32)) != RD_OK) return st;
+  }
+  return RD_OK;
+}
+
+RD_API rd_status rd_step_timed(rd_mesh* m, double cfl, int scheme, int time, int precision, double* ms) {
+  if (!m || !ms) return fail(RD_EINVAL, "null argument");
+  if (!(cfl > 0.0)) return fail(RD_EINVAL, "cfl must be positive");
+  rd_status st = check_step_args(scheme, time, precision);
+  if (st != RD_OK) return st;
+  DeviceGuard g(m->device);
+  const int fp32 = precision == RD_FP32_ACC64;
+  if ((st = ensure_prec(m, fp32)) != RD_OK) return st;
+  if ((st = ensure_z(m, fp32)) != RD_OK) return st;
+  if (!m->events[0])
+    for (int k = 0; k <= RD_NKERNELS; ++k) HIPCHK(hipEventCreate(&m->events[k]));
+  hipEvent_t* ev = m->events;
+  for (int part = 0; part < 3; ++part) {
+    HIPCHK(hipEventRecord(ev[RD_K_CFL_TRI + part], m->stream));
+    HIPCHK(rd::launch_cfl_part(m->d, m->cfl, cfl, part, m->stream));
+  }
+  if ((st = run_step(m, scheme, time, fp32, ev)) != RD_OK) return st;
+  HIPCHK(hipEventSynchronize(ev[RD_NKERNELS]));
+  for (int k = 0; k < RD_NKERNELS; ++k) {
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+    ms[k] = t;
+  }
+  return RD_OK;
+}
+
+RD_API rd_status rd_residual(rd_mesh* m, int scheme, double* R, double* phiT, int on_device) {
+  if (!m || !R) return fail(RD_EINVAL, "null argument");
+  if (scheme < RD_N || scheme > RD_BMIN) return fail(RD_EINVAL, "unknown scheme");
+  DeviceGuard g(m->device);
+  rd_status st;
+  if ((st = ensure_z(m, 0)) != RD_OK) return st;
+  const rd::Dev d = dev_for(m, 0);
+  hipStream_t s = m->stream;
+  const int64_t nv = d.nv, nt = d.nt;
+  HIPCHK(rd::launch_wall(d, false, s));
+  HIPCHK(rd::launch_tri(d, 0, scheme, 1, true, s));
+  if (on_device) {
+    HIPCHK(rd::launch_gather(d, 0, rd::G_RESIDUAL, R, s));
+    if (phiT) HIPCHK(rd::launch_aos_to_soa(static_cast<const rd::D4*>(d.keepT), phiT, nt, s));
+    return RD_OK;
+  }
+  HIPCHK(rd::launch_gather(d, 0, rd::G_RESIDUAL, m->scratch, s));
+  HIPCHK(hipMemcpyAsync(R, m->scratch, sizeof(double) * 4 * nv, hipMemcpyDeviceToHost, s));
+  if (phiT) {
+    HIPCHK(rd::launch_aos_to_soa(static_cast<const rd::D4*>(d.keepT), m->scratch, nt, s));
+    HIPCHK(hipMemcpyAsync(phiT, m->scratch, sizeof(double) * 4 * nt, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return RD_OK;
+}
+
+RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int scheme, int time,
+                                 const double* lam_np1, double* lam_n, int on_device) {
+  (void)m; (void)W_n; (void)dt; (void)scheme; (void)time; (void)lam_np1; (void)lam_n; (void)on_device;
+  return fail(RD_EUNSUPPORTED, "adjoint step not available in this build");
+}
+
+RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd_batch** out) {
+  (void)meshes; (void)n; (void)stream;
+  if (out) *out = nullptr;
+  return fail(RD_EUNSUPPORTED, "batches not available in this build");
+}
+
+RD_API rd_status rd_batch_run(rd_batch* b, int n_steps, double cfl, int scheme, int time, int precision) {
+  (void)b; (void)n_steps; (void)cfl; (void)scheme; (void)time; (void)precision;
+  return fail(RD_EUNSUPPORTED, "batches not available in this build");
+}
+
+RD_API rd_status rd_batch_destroy(rd_batch* b) {
+  (void)b;
+  return RD_OK;
+}
+
+RD_API rd_status rd_sync(rd_mesh* m) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  DeviceGuard g(m->device);
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, m->d.flag, sizeof(int), hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if (flag) return fail(RD_ENONPHYS, "a non-physical state was produced");
+  return RD_OK;
+}
+
+RD_API const char* rd_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,567 @@
+// Per-element bodies of the residual-distribution step for gfx950.
+//
+// One triangle body computes, for one triangle, everything Sections 3.2-3.4
+// ask of it: the Roe average of its three parameter vectors, the positive and
+// negative parts of the three K_i, the triangle residual, the N and LDA
+// distributions (one 4x4 pivoted solve with two right-hand sides), the B
+// blend, and for the second Runge-Kutta stage the total residuals. One vertex
+// body sums a vertex's parts over the vertex->(triangle, corner) CSR in
+// ascending triangle order (no atomics), adds the wall term and updates the
+// state, then refreshes the parameter vector and signal speed of the vertex.
+//
+// Algebra used on the GPU (equal in exact arithmetic to Appendix A's explicit
+// entries): with unit normal n, Roe state (u, v, h, c), w = u n_x + v n_y,
+//   E = (1, u, v, h), N = (0, n_x, n_y, w),
+//   g(y) = alpha/c y0 - (gamma-1)(u/c y1 + v/c y2 - y3/c),
+//   d(y) = -w y0 + n_x y1 + n_y y2,
+// the matrix with eigenvalues (l1, l2, l3, l3) on the acoustic and the two
+// linear waves acts as
+//   K(l) y = l3 y + (l1-l3)/(2c) (g+d) (E + c N) + (l2-l3)/(2c) (g-d) (E - c N),
+// i.e. K(l) = l3 I + (l1-l3) r1 l1^T + (l2-l3) r2 l2^T with r_{1,2} = E +- c N
+// the acoustic right eigenvectors and l_{1,2}^T the matching rows of R^{-1}.
+// This needs no 4x4 matrix per corner; only A = sum_i K_i^+ is built.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace rd {
+
+template <typename R>
+struct alignas(4 * sizeof(R)) Q4 {
+  R v[4];
+};
+using D4 = Q4<double>;
+using F4 = Q4<float>;
+
+// One wall-edge incidence of a wall vertex (Section 3.6).
+struct alignas(16) WallEnt {
+  int32_t other;  // the edge's other vertex
+  int32_t role;   // 0: this vertex is the edge's start a, 1: its end b
+  double hl;      // half the edge length
+  double nx, ny;  // outward unit normal
+};
+
+enum { SCH_N = 0, SCH_LDA = 1, SCH_B = 2, SCH_BMAX = 3, SCH_BMIN = 4 };
+enum { G_EULER = 0, G_STAGE1 = 1, G_STAGE2 = 2, G_RESIDUAL = 3 };
+
+// Device view of one mesh (or of a batch laid end to end).
+struct Dev {
+  int64_t nv = 0, nt = 0;
+  int32_t nwv = 0;
+  double gamma = 1.4, px = 0.0, py = 0.0;
+  // geometry and connectivity
+  const double2* xy = nullptr;   // [nv]
+  const double* V = nullptr;     // [nv] vertex volume
+  const int32_t* row = nullptr;  // [nv+1] CSR row pointers
+  const int32_t* slot = nullptr; // [3nt] slot = 3 t + corner, ascending t per row
+  const int32_t* bc = nullptr;   // [nv] or null: -1 interior, -2 ghost, >= 0 wall vertex
+  const int32_t* tv = nullptr;   // [3][nt] corner vertex ids
+  const double* lmax = nullptr;  // [nt] longest edge
+  const int32_t* wv = nullptr;   // [nwv] wall vertex ids
+  const int32_t* wptr = nullptr; // [nwv+1]
+  const WallEnt* went = nullptr; // wall incidences, ascending edge id per vertex
+  const int32_t* tmesh = nullptr; // [nt] mesh id (batch) or null
+  const int32_t* vmesh = nullptr; // [nv] mesh id (batch) or null
+  // state
+  D4* W = nullptr;    // [nv] state
+  D4* Ws = nullptr;   // [nv] first-stage state
+  D4* Z = nullptr;    // [nv] parameter vector (FP64 arithmetic)
+  F4* Zf = nullptr;   // [nv] parameter vector (FP32 arithmetic)
+  void* dW = nullptr; // [nv] W* - W^n (D4 or F4)
+  double* sig = nullptr;   // [nv] |v| + c
+  // triangle buffers
+  void* C = nullptr;      // [3nt] distributed parts (D4 or F4)
+  void* keepN = nullptr;  // [3nt] stage-1 N parts (D4 or F4)
+  void* keepT = nullptr;  // [nt] stage-1 triangle residual (D4 or F4)
+  D4* WCn = nullptr;      // [nwv] wall term at W^n
+  D4* WCs = nullptr;      // [nwv] wall term at W*
+  double* lam = nullptr;  // [nt] l_max * lambda_max
+  double* dt = nullptr;   // [n meshes] time step
+  int* flag = nullptr;    // non-physical state latch
+};
+
+__host__ __device__ inline double unwrap(double d, double period) {
+  if (period > 0.0) {
+    if (d > 0.5 * period) d -= period;
+    else if (d < -0.5 * period) d += period;
+  }
+  return d;
+}
+
+template <typename R> __host__ __device__ inline R rmax(R a, R b) { return a < b ? b : a; }
+template <typename R> __host__ __device__ inline R rmin(R a, R b) { return b < a ? b : a; }
+
+template <typename R>
+__host__ __device__ inline R sel4(int r, R a0, R a1, R a2, R a3) {
+  R t = r == 1 ? a1 : a0;
+  t = r == 2 ? a2 : t;
+  return r == 3 ? a3 : t;
+}
+
+// Per-corner coefficients of K_i^{+-} (scaled by s = |n_i|/2).
+template <typename R>
+struct Corner {
+  R nx, ny, w, s;
+  R l3p, h1p, h2p;  // s l3^+, s (l1^+ - l3^+)/(2c), s (l2^+ - l3^+)/(2c)
+  R l3m, h1m, h2m;  // same for the negative parts
+};
+
+template <typename R>
+struct Roe {
+  R u, v, h, c, ic, ac, uc, vc, g1;
+};
+
+// y -> K^{+} y or K^{-} y of one corner.
+template <typename R>
+__host__ __device__ inline void apply_split(const Roe<R>& q, const Corner<R>& k, R sl3, R h1, R h2,
+                                            const R y[4], R out[4]) {
+  R g = q.ac * y[0] - q.g1 * (q.uc * y[1] + q.vc * y[2] - q.ic * y[3]);
+  R d = -k.w * y[0] + k.nx * y[1] + k.ny * y[2];
+  R a1 = h1 * (g + d), a2 = h2 * (g - d);
+  R sp = a1 + a2, sm = (a1 - a2) * q.c;
+  out[0] = sl3 * y[0] + sp;
+  out[1] = sl3 * y[1] + sp * q.u + sm * k.nx;
+  out[2] = sl3 * y[2] + sp * q.v + sm * k.ny;
+  out[3] = sl3 * y[3] + sp * q.h + sm * k.w;
+}
+
+// y -> K y (l = lambda): s (w y + d E + c g N).
+template <typename R>
+__host__ __device__ inline void apply_full(const Roe<R>& q, const Corner<R>& k, const R y[4], R out[4]) {
+  R g = q.ac * y[0] - q.g1 * (q.uc * y[1] + q.vc * y[2] - q.ic * y[3]);
+  R d = -k.w * y[0] + k.nx * y[1] + k.ny * y[2];
+  R cg = q.c * g;
+  out[0] = k.s * (k.w * y[0] + d);
+  out[1] = k.s * (k.w * y[1] + d * q.u + cg * k.nx);
+  out[2] = k.s * (k.w * y[2] + d * q.v + cg * k.ny);
+  out[3] = k.s * (k.w * y[3] + d * q.h + cg * k.w);
+}
+
+// A = sum_i K_i^+ as a dense 4x4 matrix:
+// A = L3 I + E ev^T + c (sum Q_i N_i) G^T + c sum_i P_i N_i D_i^T with
+// P = h1 + h2, Q = h1 - h2, G = (alpha/c, -g1 u/c, -g1 v/c, g1/c), D_i = (-w, nx, ny, 0).
+template <typename R>
+__host__ __device__ inline void build_A(const Roe<R>& q, const Corner<R> k[3], R A[4][4]) {
+  R G[4] = {q.ac, -q.g1 * q.uc, -q.g1 * q.vc, q.g1 * q.ic};
+  R E[4] = {R(1), q.u, q.v, q.h};
+  R L3 = k[0].l3p + k[1].l3p + k[2].l3p;
+  R P[3], Qv[3];
+  for (int i = 0; i < 3; ++i) {
+    P[i] = k[i].h1p + k[i].h2p;
+    Qv[i] = k[i].h1p - k[i].h2p;
+  }
+  R sP = P[0] + P[1] + P[2];
+  R ev[4];
+  ev[0] = sP * G[0] - (Qv[0] * k[0].w + Qv[1] * k[1].w + Qv[2] * k[2].w);
+  ev[1] = sP * G[1] + (Qv[0] * k[0].nx + Qv[1] * k[1].nx + Qv[2] * k[2].nx);
+  ev[2] = sP * G[2] + (Qv[0] * k[0].ny + Qv[1] * k[1].ny + Qv[2] * k[2].ny);
+  ev[3] = sP * G[3];
+  R nvv[4];
+  nvv[0] = R(0);
+  nvv[1] = q.c * (Qv[0] * k[0].nx + Qv[1] * k[1].nx + Qv[2] * k[2].nx);
+  nvv[2] = q.c * (Qv[0] * k[0].ny + Qv[1] * k[1].ny + Qv[2] * k[2].ny);
+  nvv[3] = q.c * (Qv[0] * k[0].w + Qv[1] * k[1].w + Qv[2] * k[2].w);
+  // S[r][j] for r = 1..3 (N rows nx, ny, w) and j = 0..2 (D cols -w, nx, ny)
+  R S[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int j = 0; j < 4; ++j) S[r][j] = R(0);
+  for (int i = 0; i < 3; ++i) {
+    R cp = q.c * P[i];
+    R Nr[4] = {R(0), k[i].nx, k[i].ny, k[i].w};
+    R Dc[4] = {-k[i].w, k[i].nx, k[i].ny, R(0)};
+    for (int r = 1; r < 4; ++r) {
+      R t = cp * Nr[r];
+      for (int j = 0; j < 3; ++j) S[r][j] = S[r][j] + t * Dc[j];
+    }
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int j = 0; j < 4; ++j) {
+      R a = E[r] * ev[j] + nvv[r] * G[j] + S[r][j];
+      A[r][j] = r == j ? a + L3 : a;
+    }
+}
+
+// Gaussian elimination with partial pivoting for two right-hand sides
+// (A, b0 and b1 are overwritten).
+// Pivot: largest |entry| among rows not yet used, lowest row on ties; a
+// column whose best pivot is at most 2^-45 max|A| is skipped and its unknown
+// set to 0 (A is singular at stagnation; the K^+ x products stay unique).
+template <typename R>
+__host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x1[4]) {
+  R amax = R(0);
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) amax = rmax(amax, (R)fabs(A[r][c]));
+  const R tol = amax * R(2.8421709430404007e-14);  // 2^-45
+  bool used[4] = {false, false, false, false};
+  R P[4][4], PB0[4], PB1[4], PI[4];
+  bool OK[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    R best = R(-1);
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      R a = (R)fabs(A[i][k]);
+      bool take = !used[i] && a > best;
+      best = take ? a : best;
+      r = take ? i : r;
+    }
+    const bool ok = best > tol;
+    OK[k] = ok;
+#pragma unroll
+    for (int j = k; j < 4; ++j) P[k][j] = sel4(r, A[0][j], A[1][j], A[2][j], A[3][j]);
+    PB0[k] = sel4(r, b0[0], b0[1], b0[2], b0[3]);
+    PB1[k] = sel4(r, b1[0], b1[1], b1[2], b1[3]);
+    PI[k] = ok ? R(1) / P[k][k] : R(0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) used[i] = used[i] || (ok && r == i);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool elim = ok && !used[i];
+      R f = elim ? A[i][k] * PI[k] : R(0);
+#pragma unroll
+      for (int j = k + 1; j < 4; ++j) A[i][j] = elim ? A[i][j] - f * P[k][j] : A[i][j];
+      b0[i] = elim ? b0[i] - f * PB0[k] : b0[i];
+      b1[i] = elim ? b1[i] - f * PB1[k] : b1[i];
+    }
+  }
+#pragma unroll
+  for (int k = 3; k >= 0; --k) {
+    R s0 = PB0[k], s1 = PB1[k];
+#pragma unroll
+    for (int j = k + 1; j < 4; ++j) {
+      s0 = s0 - P[k][j] * x0[j];
+      s1 = s1 - P[k][j] * x1[j];
+    }
+    x0[k] = OK[k] ? s0 * PI[k] : R(0);
+    x1[k] = OK[k] ? s1 * PI[k] : R(0);
+  }
+}
+
+// Blend of Section 3.3.3: Theta_k = |res_k| / sum_i |N_{i,k}| (0 if the sum is
+// 0, at most 1); BMAX / BMIN use the largest / smallest Theta_k for all k.
+template <typename R, int SCHEME>
+__host__ __device__ inline void blend_theta(const R res[4], const R n[3][4], R th[4]) {
+  for (int k = 0; k < 4; ++k) {
+    R den = (R)fabs(n[0][k]) + (R)fabs(n[1][k]) + (R)fabs(n[2][k]);
+    R q = den == R(0) ? R(0) : (R)fabs(res[k]) / den;
+    th[k] = q > R(1) ? R(1) : q;
+  }
+  if (SCHEME == SCH_BMAX || SCHEME == SCH_BMIN) {
+    R t = th[0];
+    for (int k = 1; k < 4; ++k) {
+      bool better = SCHEME == SCH_BMAX ? th[k] > t : th[k] < t;
+      t = better ? th[k] : t;
+    }
+    for (int k = 0; k < 4; ++k) th[k] = t;
+  }
+}
+
+template <typename R>
+__host__ __device__ inline Q4<R> ld4(const void* base, int64_t i) {
+  return reinterpret_cast<const Q4<R>*>(base)[i];
+}
+template <typename R>
+__host__ __device__ inline void st4(void* base, int64_t i, const R a[4]) {
+  Q4<R> q;
+  q.v[0] = a[0];
+  q.v[1] = a[1];
+  q.v[2] = a[2];
+  q.v[3] = a[3];
+  reinterpret_cast<Q4<R>*>(base)[i] = q;
+}
+
+template <typename R> __host__ __device__ inline const Q4<R>* zbuf(const Dev& d);
+template <> __host__ __device__ inline const Q4<double>* zbuf<double>(const Dev& d) { return d.Z; }
+template <> __host__ __device__ inline const Q4<float>* zbuf<float>(const Dev& d) { return d.Zf; }
+
+// One triangle, stage 1 (STAGE = 1) or stage 2 (STAGE = 2) of Section 3.4.
+// Stage 1 writes the scheme's parts phi_i to C and, when SAVE, keeps phi^N_i
+// and phi^T for stage 2. Stage 2 forms the total residuals
+//   Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2,
+//   Phi^T   = |T|/3 sum_j (W*_j - W^n_j)/dt + (phi^T(n) + phi^T(*))/2,
+//   Phi^LDA_i = K_i^+(*) A(*)^{-1} Phi^T,
+// blends them and writes them to C.
+template <typename R, int SCHEME, int STAGE, bool SAVE>
+__host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
+  const int64_t nt = d.nt;
+  const int32_t iv[3] = {d.tv[t], d.tv[nt + t], d.tv[2 * nt + t]};
+  const double2 p0 = d.xy[iv[0]], p1 = d.xy[iv[1]], p2 = d.xy[iv[2]];
+  const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
+  const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
+  // inward normals scaled by edge length: rotate the opposite edge by +90 degrees
+  const double nxd[3] = {-(d2y - d1y), d2y, -d1y};
+  const double nyd[3] = {d2x - d1x, -d2x, d1x};
+
+  const Q4<R>* Zp = zbuf<R>(d);
+  Q4<R> Zc[3];
+  for (int i = 0; i < 3; ++i) Zc[i] = Zp[iv[i]];
+
+  const R gam = (R)d.gamma;
+  Roe<R> q;
+  q.g1 = gam - R(1);
+  const R third = R(1) / R(3);
+  R zb[4];
+  for (int k = 0; k < 4; ++k) zb[k] = (Zc[0].v[k] + Zc[1].v[k] + Zc[2].v[k]) * third;
+  const R iz = R(1) / zb[0];
+  q.u = zb[1] * iz;
+  q.v = zb[2] * iz;
+  q.h = zb[3] * iz;
+  const R q2 = q.u * q.u + q.v * q.v;
+  q.c = (R)sqrt(q.g1 * (q.h - R(0.5) * q2));
+  q.ic = R(1) / q.c;
+  q.ac = R(0.5) * q.g1 * q2 * q.ic;
+  q.uc = q.u * q.ic;
+  q.vc = q.v * q.ic;
+
+  // dW_i = M(Zbar)(Z_i - Z_0), M = dW/dZ
+  R dWh[3][4];
+  const R igam = R(1) / gam;
+  for (int k = 0; k < 4; ++k) dWh[0][k] = R(0);
+  for (int i = 1; i < 3; ++i) {
+    R dz[4];
+    for (int k = 0; k < 4; ++k) dz[k] = Zc[i].v[k] - Zc[0].v[k];
+    dWh[i][0] = R(2) * zb[0] * dz[0];
+    dWh[i][1] = zb[1] * dz[0] + zb[0] * dz[1];
+    dWh[i][2] = zb[2] * dz[0] + zb[0] * dz[2];
+    dWh[i][3] = (zb[3] * dz[0] + q.g1 * (zb[1] * dz[1] + zb[2] * dz[2]) + zb[0] * dz[3]) * igam;
+  }
+
+  Corner<R> kc[3];
+  const R hic = R(0.5) * q.ic;
+  for (int i = 0; i < 3; ++i) {
+    const double L = sqrt(nxd[i] * nxd[i] + nyd[i] * nyd[i]);
+    const double iL = 1.0 / L;
+    Corner<R>& k = kc[i];
+    k.nx = (R)(nxd[i] * iL);
+    k.ny = (R)(nyd[i] * iL);
+    k.s = (R)(0.5 * L);
+    k.w = q.u * k.nx + q.v * k.ny;
+    const R l1 = k.w + q.c, l2 = k.w - q.c, l3 = k.w;
+    const R p1 = rmax(l1, R(0)), p2 = rmax(l2, R(0)), p3 = rmax(l3, R(0));
+    const R m1 = rmin(l1, R(0)), m2 = rmin(l2, R(0)), m3 = rmin(l3, R(0));
+    const R sh = k.s * hic;
+    k.l3p = k.s * p3;
+    k.h1p = sh * (p1 - p3);
+    k.h2p = sh * (p2 - p3);
+    k.l3m = k.s * m3;
+    k.h1m = sh * (m1 - m3);
+    k.h2m = sh * (m2 - m3);
+  }
+
+  // triangle residual and the N right-hand side
+  R phiT[4], bN[4], t1[4], t2[4];
+  apply_full(q, kc[1], dWh[1], t1);
+  apply_full(q, kc[2], dWh[2], t2);
+  for (int k = 0; k < 4; ++k) phiT[k] = t1[k] + t2[k];
+  R A[4][4];
+  build_A(q, kc, A);
+
+  constexpr bool needN = SCHEME != SCH_LDA;
+  constexpr bool needL = SCHEME != SCH_N;
+  R pN[3][4];
+  R rhs1[4];
+  R keepNv[3][4];
+  R rate[3][4];
+  R mass = R(0);
+  if (needN) {
+    apply_split(q, kc[1], kc[1].l3m, kc[1].h1m, kc[1].h2m, dWh[1], t1);
+    apply_split(q, kc[2], kc[2].l3m, kc[2].h1m, kc[2].h2m, dWh[2], t2);
+    for (int k = 0; k < 4; ++k) bN[k] = t1[k] + t2[k];
+  } else {
+    for (int k = 0; k < 4; ++k) bN[k] = R(0);
+  }
+  if (STAGE == 1) {
+    for (int k = 0; k < 4; ++k) rhs1[k] = phiT[k];
+  } else {
+    const int m = d.tmesh ? d.tmesh[t] : 0;
+    const R idt = (R)(1.0 / d.dt[m]);
+    mass = (R)((0.5 * (d1x * d2y - d1y * d2x)) / 3.0);
+    for (int i = 0; i < 3; ++i) {
+      const Q4<R> dwv = ld4<R>(d.dW, iv[i]);
+      for (int k = 0; k < 4; ++k) rate[i][k] = dwv.v[k] * idt;
+    }
+    if (needL) {
+      const Q4<R> kt = ld4<R>(d.keepT, t);
+      for (int k = 0; k < 4; ++k)
+        rhs1[k] = mass * (rate[0][k] + rate[1][k] + rate[2][k]) + R(0.5) * (kt.v[k] + phiT[k]);
+    } else {
+      for (int k = 0; k < 4; ++k) rhs1[k] = R(0);
+    }
+  }
+  R xN[4], xL[4], b0[4], b1[4];
+  for (int k = 0; k < 4; ++k) {
+    b0[k] = bN[k];
+    b1[k] = rhs1[k];
+  }
+  solve2(A, b0, b1, xN, xL);
+  if (needN) {
+    for (int i = 0; i < 3; ++i) {
+      R y[4];
+      for (int k = 0; k < 4; ++k) y[k] = dWh[i][k] + xN[k];
+      apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, y, pN[i]);
+    }
+  }
+  if (STAGE == 1 && SAVE) {
+    if (needN)
+      for (int i = 0; i < 3; ++i) st4<R>(d.keepN, 3 * t + i, pN[i]);
+    st4<R>(d.keepT, t, phiT);
+  }
+  if (STAGE == 2 && needN) {
+    for (int i = 0; i < 3; ++i) {
+      const Q4<R> kn = ld4<R>(d.keepN, 3 * t + i);
+      for (int k = 0; k < 4; ++k) keepNv[i][k] = mass * rate[i][k] + R(0.5) * (kn.v[k] + pN[i][k]);
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 4; ++k) pN[i][k] = keepNv[i][k];
+  }
+  // rhs1 is the residual being split (phi^T or Phi^T); pN its N parts
+  R th[4] = {R(0), R(0), R(0), R(0)};
+  if (SCHEME >= SCH_B) blend_theta<R, SCHEME>(rhs1, pN, th);
+  for (int i = 0; i < 3; ++i) {
+    R out[4];
+    if (SCHEME == SCH_N) {
+      for (int k = 0; k < 4; ++k) out[k] = pN[i][k];
+    } else {
+      R pl[4];
+      apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, pl);
+      if (SCHEME == SCH_LDA) {
+        for (int k = 0; k < 4; ++k) out[k] = pl[k];
+      } else {
+        for (int k = 0; k < 4; ++k) out[k] = pl[k] + th[k] * (pN[i][k] - pl[k]);
+      }
+    }
+    st4<R>(d.C, 3 * t + i, out);
+  }
+}
+
+// Parameter vector, signal speed and physicality of one state.
+__host__ __device__ inline void vertex_epilogue(const Dev& d, int64_t v, const double w[4], bool fp32) {
+  const double g1 = d.gamma - 1.0;
+  const double rho = w[0], u = w[1] / rho, vv = w[2] / rho;
+  const double p = g1 * (w[3] - 0.5 * rho * (u * u + vv * vv));
+  const double h = (w[3] + p) / rho;
+  const double s = sqrt(rho);
+  const double z[4] = {s, s * u, s * vv, s * h};
+  if (fp32) {
+    const float zf[4] = {(float)z[0], (float)z[1], (float)z[2], (float)z[3]};
+    st4<float>(d.Zf, v, zf);
+  } else {
+    st4<double>(d.Z, v, z);
+  }
+  const double sg = sqrt(u * u + vv * vv) + sqrt(d.gamma * p / rho);
+  d.sig[v] = sg;
+  const bool finite = fabs(sg) < INFINITY && fabs(w[1]) < INFINITY && fabs(w[2]) < INFINITY &&
+                      fabs(w[3]) < INFINITY;
+  if (!(rho > 0.0) || !(p > 0.0) || !finite) d.flag[0] = 1;
+}
+
+// One vertex of the gather (MODE: G_EULER, G_STAGE1, G_STAGE2, G_RESIDUAL).
+// R is the arithmetic type of the parts; sums are FP64 (Neumaier-compensated
+// when the parts are FP32).
+template <typename R, int MODE>
+__host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out_soa) {
+  const int32_t b = d.bc ? d.bc[v] : -1;
+  if (b == -2 && MODE != G_RESIDUAL) {
+    if (MODE == G_STAGE1) {
+      d.Ws[v] = d.W[v];
+      const R z[4] = {R(0), R(0), R(0), R(0)};
+      st4<R>(d.dW, v, z);
+    }
+    return;
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double cmp[4] = {0.0, 0.0, 0.0, 0.0};
+  const int32_t r0 = d.row[v], r1 = d.row[v + 1];
+  for (int32_t s = r0; s < r1; ++s) {
+    const Q4<R> c = ld4<R>(d.C, d.slot[s]);
+    for (int k = 0; k < 4; ++k) {
+      if (sizeof(R) == sizeof(double)) {
+        acc[k] += (double)c.v[k];
+      } else {
+        const double x = (double)c.v[k];
+        const double tsum = acc[k] + x;
+        cmp[k] += fabs(acc[k]) >= fabs(x) ? (acc[k] - tsum) + x : (x - tsum) + acc[k];
+        acc[k] = tsum;
+      }
+    }
+  }
+  if (sizeof(R) != sizeof(double))
+    for (int k = 0; k < 4; ++k) acc[k] = acc[k] + cmp[k];
+  if (b >= 0) {
+    const D4 wn = d.WCn[b];
+    if (MODE == G_STAGE2) {
+      const D4 ws = d.WCs[b];
+      for (int k = 0; k < 4; ++k) acc[k] = acc[k] + 0.5 * (wn.v[k] + ws.v[k]);
+    } else {
+      for (int k = 0; k < 4; ++k) acc[k] = acc[k] + wn.v[k];
+    }
+  }
+  if (MODE == G_RESIDUAL) {
+    for (int k = 0; k < 4; ++k) out_soa[k * d.nv + v] = acc[k];
+    return;
+  }
+  const int m = d.vmesh ? d.vmesh[v] : 0;
+  const double f = d.dt[m] / d.V[v];
+  const D4 win = MODE == G_STAGE2 ? d.Ws[v] : d.W[v];
+  double wo[4];
+  for (int k = 0; k < 4; ++k) wo[k] = win.v[k] - f * acc[k];
+  if (MODE == G_STAGE1) {
+    st4<double>(d.Ws, v, wo);
+    R dw[4];
+    for (int k = 0; k < 4; ++k) dw[k] = (R)(wo[k] - win.v[k]);
+    st4<R>(d.dW, v, dw);
+  } else {
+    st4<double>(d.W, v, wo);
+  }
+  vertex_epilogue(d, v, wo, sizeof(R) != sizeof(double));
+}
+
+// Wall correction of one wall vertex (Section 3.6), at W (STAGE2 = false) or W*.
+template <bool STAGE2>
+__host__ __device__ inline void wall_body(int64_t b, const Dev& d) {
+  const double alpha = 0.75, g1 = d.gamma - 1.0;
+  const D4* src = STAGE2 ? d.Ws : d.W;
+  const int32_t v = d.wv[b];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t e = d.wptr[b]; e < d.wptr[b + 1]; ++e) {
+    const WallEnt we = d.went[e];
+    double F[2][4];
+    const int32_t ids[2] = {v, we.other};
+    for (int s = 0; s < 2; ++s) {
+      const D4 w = src[ids[s]];
+      const double u = w.v[1] / w.v[0], vv = w.v[2] / w.v[0];
+      const double p = g1 * (w.v[3] - 0.5 * w.v[0] * (u * u + vv * vv));
+      const double vn = u * we.nx + vv * we.ny;
+      F[s][0] = -vn * w.v[0];
+      F[s][1] = -vn * w.v[1];
+      F[s][2] = -vn * w.v[2];
+      F[s][3] = -vn * (w.v[3] + p);
+    }
+    for (int k = 0; k < 4; ++k) {
+      const double part = we.role == 0 ? alpha * F[0][k] + (1.0 - alpha) * F[1][k]
+                                       : (1.0 - alpha) * F[1][k] + alpha * F[0][k];
+      acc[k] += we.hl * part;
+    }
+  }
+  st4<double>(STAGE2 ? d.WCs : d.WCn, b, acc);
+}
+
+// l_max^T lambda_max^T of one triangle.
+__host__ __device__ inline void cfl_tri_body(int64_t t, const Dev& d) {
+  double lam = 0.0;
+  for (int i = 0; i < 3; ++i) lam = rmax(lam, d.sig[d.tv[i * d.nt + t]]);
+  d.lam[t] = d.lmax[t] * lam;
+}
+
+// 2 V_i / sum_{T ni i} l_max lambda_max of one vertex.
+__host__ __device__ inline double cfl_vertex_bound(int64_t v, const Dev& d) {
+  double acc = 0.0;
+  for (int32_t s = d.row[v]; s < d.row[v + 1]; ++s) acc += d.lam[d.slot[s] / 3];
+  return 2.0 * d.V[v] / acc;
+}
+
+}  // namespace rd

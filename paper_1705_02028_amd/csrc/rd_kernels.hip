@@ -1,0 +1,204 @@
+// gfx950 kernels of the residual-distribution step and their launchers.
+//
+// Launch shapes: one thread per triangle (triangle passes) or per vertex
+// (gather, CFL), 256-thread workgroups. Consecutive workgroup ids are
+// dispatched round-robin over the 8 XCDs of an MI355X, each with its own L2;
+// `xcd_block` renumbers them so that each XCD walks one contiguous range of
+// triangles or vertices, which keeps the vertex data a range touches in that
+// XCD's L2.
+#include "rd_launch.h"
+
+namespace rd {
+
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  const int64_t x = b % 8, q = nb / 8, r = nb % 8;
+  return x * q + (x < r ? x : r) + b / 8;
+}
+
+template <typename R, int SCHEME, int STAGE, bool SAVE>
+__global__ __launch_bounds__(kBlock) void k_tri(Dev d) {
+  const int64_t t = xcd_block() * kBlock + threadIdx.x;
+  if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE>(t, d);
+}
+
+template <typename R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gather(Dev d, double* out_soa) {
+  const int64_t v = xcd_block() * kBlock + threadIdx.x;
+  if (v < d.nv) gather_body<R, MODE>(v, d, out_soa);
+}
+
+template <bool STAGE2>
+__global__ __launch_bounds__(kBlock) void k_wall(Dev d) {
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (b < d.nwv) wall_body<STAGE2>(b, d);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cfl_tri(Dev d) {
+  const int64_t t = xcd_block() * kBlock + threadIdx.x;
+  if (t < d.nt) cfl_tri_body(t, d);
+}
+
+__device__ __forceinline__ double block_min(double x) {
+  __shared__ double red[kBlock];
+  red[threadIdx.x] = x;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = rmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cfl_vertex(Dev d, CflPlan p) {
+  const int b = blockIdx.x;
+  const int64_t v = (int64_t)p.blk_v0[b] + threadIdx.x;
+  const double x = v < p.blk_v1[b] ? cfl_vertex_bound(v, d) : INFINITY;
+  const double m = block_min(x);
+  if (threadIdx.x == 0) p.part[b] = m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cfl_final(Dev d, CflPlan p, double cfl) {
+  const int m = blockIdx.x;
+  double x = INFINITY;
+  for (int b = p.mesh_b0[m] + threadIdx.x; b < p.mesh_b0[m + 1]; b += kBlock) x = rmin(x, p.part[b]);
+  x = block_min(x);
+  if (threadIdx.x == 0) d.dt[m] = cfl * x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_state(Dev d, const double* soa, int fp32) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (v >= d.nv) return;
+  const double w[4] = {soa[v], soa[d.nv + v], soa[2 * d.nv + v], soa[3 * d.nv + v]};
+  st4<double>(d.W, v, w);
+  vertex_epilogue(d, v, w, fp32 != 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_refresh(Dev d, int fp32) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (v >= d.nv) return;
+  const D4 w = d.W[v];
+  vertex_epilogue(d, v, w.v, fp32 != 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_aos_to_soa(const D4* src, double* soa, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const D4 w = src[i];
+  for (int k = 0; k < 4; ++k) soa[k * n + i] = w.v[k];
+}
+
+__global__ void k_set_scalar(double* p, double v) { p[0] = v; }
+__global__ void k_set_int(int* p, int v) { p[0] = v; }
+
+__global__ __launch_bounds__(kBlock) void k_copy4(D4* dst, const D4* src, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename R, int SCHEME>
+static hipError_t tri_dispatch(const Dev& d, int stage, bool save, hipStream_t s) {
+  const dim3 g(nblk(d.nt)), b(kBlock);
+  if (stage == 1 && save) hipLaunchKernelGGL((k_tri<R, SCHEME, 1, true>), g, b, 0, s, d);
+  else if (stage == 1) hipLaunchKernelGGL((k_tri<R, SCHEME, 1, false>), g, b, 0, s, d);
+  else hipLaunchKernelGGL((k_tri<R, SCHEME, 2, false>), g, b, 0, s, d);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t tri_scheme(const Dev& d, int scheme, int stage, bool save, hipStream_t s) {
+  switch (scheme) {
+    case SCH_N: return tri_dispatch<R, SCH_N>(d, stage, save, s);
+    case SCH_LDA: return tri_dispatch<R, SCH_LDA>(d, stage, save, s);
+    case SCH_B: return tri_dispatch<R, SCH_B>(d, stage, save, s);
+    case SCH_BMAX: return tri_dispatch<R, SCH_BMAX>(d, stage, save, s);
+    case SCH_BMIN: return tri_dispatch<R, SCH_BMIN>(d, stage, save, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_tri(const Dev& d, int fp32, int scheme, int stage, bool save, hipStream_t s) {
+  if (d.nt == 0) return hipSuccess;
+  return fp32 ? tri_scheme<float>(d, scheme, stage, save, s) : tri_scheme<double>(d, scheme, stage, save, s);
+}
+
+template <typename R>
+static hipError_t gather_mode(const Dev& d, int mode, double* out, hipStream_t s) {
+  const dim3 g(nblk(d.nv)), b(kBlock);
+  switch (mode) {
+    case G_EULER: hipLaunchKernelGGL((k_gather<R, G_EULER>), g, b, 0, s, d, out); break;
+    case G_STAGE1: hipLaunchKernelGGL((k_gather<R, G_STAGE1>), g, b, 0, s, d, out); break;
+    case G_STAGE2: hipLaunchKernelGGL((k_gather<R, G_STAGE2>), g, b, 0, s, d, out); break;
+    case G_RESIDUAL: hipLaunchKernelGGL((k_gather<R, G_RESIDUAL>), g, b, 0, s, d, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const Dev& d, int fp32, int mode, double* out_soa, hipStream_t s) {
+  if (d.nv == 0) return hipSuccess;
+  return fp32 ? gather_mode<float>(d, mode, out_soa, s) : gather_mode<double>(d, mode, out_soa, s);
+}
+
+hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s) {
+  if (d.nwv == 0) return hipSuccess;
+  if (stage2) hipLaunchKernelGGL((k_wall<true>), dim3(nblk(d.nwv)), dim3(kBlock), 0, s, d);
+  else hipLaunchKernelGGL((k_wall<false>), dim3(nblk(d.nwv)), dim3(kBlock), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s) {
+  if (part == 0) hipLaunchKernelGGL(k_cfl_tri, dim3(nblk(d.nt)), dim3(kBlock), 0, s, d);
+  else if (part == 1) hipLaunchKernelGGL(k_cfl_vertex, dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else hipLaunchKernelGGL(k_cfl_final, dim3(p.nmesh), dim3(kBlock), 0, s, d, p, cfl);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl(const Dev& d, const CflPlan& p, double cfl, hipStream_t s) {
+  for (int part = 0; part < 3; ++part) {
+    hipError_t e = launch_cfl_part(d, p, cfl, part, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_set_state(const Dev& d, const double* soa, int fp32, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(nblk(d.nv)), dim3(kBlock), 0, s, d, soa, fp32);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh(const Dev& d, int fp32, hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh, dim3(nblk(d.nv)), dim3(kBlock), 0, s, d, fp32);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(const Dev& d, const D4* src, double* soa, hipStream_t s) {
+  hipLaunchKernelGGL(k_aos_to_soa, dim3(nblk(d.nv)), dim3(kBlock), 0, s, src, soa, d.nv);
+  return hipGetLastError();
+}
+
+hipError_t launch_aos_to_soa(const D4* src, double* soa, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_aos_to_soa, dim3(nblk(n)), dim3(kBlock), 0, s, src, soa, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_scalar(double* p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy4(D4* dst, const D4* src, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy4, dim3(nblk(n)), dim3(kBlock), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+}  // namespace rd

@@ -1,0 +1,37 @@
+// Host-side launchers of the gfx950 kernels (defined in rd_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "rd_device.h"
+
+namespace rd {
+
+constexpr int kBlock = 256;
+
+// Segmented min-reduction layout for the CFL limit: vertex block b covers
+// vertices [blk_v0[b], blk_v1[b]) of one mesh; mesh m owns blocks
+// [mesh_b0[m], mesh_b0[m+1]).
+struct CflPlan {
+  int32_t nblocks = 0, nmesh = 0;
+  const int32_t* blk_v0 = nullptr;
+  const int32_t* blk_v1 = nullptr;
+  const int32_t* mesh_b0 = nullptr;
+  double* part = nullptr;
+};
+
+hipError_t launch_tri(const Dev& d, int fp32, int scheme, int stage, bool save, hipStream_t s);
+hipError_t launch_gather(const Dev& d, int fp32, int mode, double* out_soa, hipStream_t s);
+hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s);
+hipError_t launch_cfl(const Dev& d, const CflPlan& p, double cfl, hipStream_t s);
+// part 0: per triangle, 1: per vertex, 2: final minimum
+hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s);
+hipError_t launch_set_state(const Dev& d, const double* soa, int fp32, hipStream_t s);
+hipError_t launch_refresh(const Dev& d, int fp32, hipStream_t s);
+hipError_t launch_get_state(const Dev& d, const D4* src, double* soa, hipStream_t s);
+hipError_t launch_aos_to_soa(const D4* src, double* soa, int64_t n, hipStream_t s);
+hipError_t launch_set_scalar(double* p, double v, hipStream_t s);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
+hipError_t launch_copy4(D4* dst, const D4* src, int64_t n, hipStream_t s);
+
+}  // namespace rd

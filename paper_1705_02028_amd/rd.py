@@ -1,0 +1,277 @@
+"""Python binding of librd (``include/rd.h``): argument marshalling only.
+
+Every function named like the C entry points takes and returns plain
+values, numpy arrays (host) or torch tensors (device, float64, contiguous,
+on the current HIP device). All arithmetic runs in the library's HIP
+kernels; if ``librd.so`` is missing this module raises instead of falling
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librd.so")
+
+RD_OK, RD_EINVAL, RD_ENOMEM, RD_EDEVICE, RD_ENONPHYS, RD_EUNSUPPORTED = range(6)
+N, LDA, B, BMAX, BMIN = range(5)
+EULER1, RK2 = 1, 2
+FP64, FP32_ACC64 = 0, 1
+
+_STATUS = {0: "RD_OK", 1: "RD_EINVAL", 2: "RD_ENOMEM", 3: "RD_EDEVICE", 4: "RD_ENONPHYS",
+           5: "RD_EUNSUPPORTED"}
+
+
+class RDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class rd_mesh_desc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("n_triangles", C.c_int64),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("tri", C.c_void_p),
+                ("period_x", C.c_double), ("period_y", C.c_double),
+                ("ghost", C.c_void_p), ("n_wall_edges", C.c_int64), ("wall_edges", C.c_void_p),
+                ("gamma", C.c_double)]
+
+
+EXPORTS = ["rd_mesh_validate", "rd_mesh_create", "rd_mesh_destroy", "rd_mesh_info", "rd_set_stream",
+           "rd_set_state", "rd_get_state", "rd_max_dt", "rd_step", "rd_step_cfl", "rd_step_timed", "rd_residual",
+           "rd_adjoint_step", "rd_batch_create", "rd_batch_run", "rd_batch_destroy", "rd_sync",
+           "rd_last_error"]
+
+_lib = None
+
+
+def lib():
+    """The loaded librd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P, I, D, I64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
+        sig = {
+            "rd_mesh_validate": [P],
+            "rd_mesh_create": [P, P, P],
+            "rd_mesh_destroy": [P],
+            "rd_mesh_info": [P, P, P],
+            "rd_set_stream": [P, P],
+            "rd_set_state": [P, P, I],
+            "rd_get_state": [P, P, I],
+            "rd_max_dt": [P, D, P],
+            "rd_step": [P, D, I, I, I],
+            "rd_step_cfl": [P, I, D, I, I, I],
+            "rd_step_timed": [P, D, I, I, I, P],
+            "rd_residual": [P, I, P, P, I],
+            "rd_adjoint_step": [P, P, D, I, I, P, P, I],
+            "rd_batch_create": [P, I, P, P],
+            "rd_batch_run": [P, I, D, I, I, I],
+            "rd_batch_destroy": [P],
+            "rd_sync": [P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = I
+        L.rd_last_error.restype = C.c_char_p
+        L.rd_last_error.argtypes = []
+        _ = I64
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != RD_OK:
+        raise RDError(st, lib().rd_last_error().decode())
+
+
+def _ptr(a, dev: bool):
+    """(pointer, on_device) for a numpy array or a torch tensor."""
+    if dev:
+        if a.dtype.__str__() != "torch.float64" or not a.is_contiguous() or not a.is_cuda:
+            raise ValueError("device arrays must be contiguous float64 tensors on the GPU")
+        return a.data_ptr()
+    if a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise ValueError("host arrays must be C-contiguous float64")
+    return a.ctypes.data
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def current_stream():
+    """hipStream_t of torch's current stream (None when torch has no GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+def _desc(mesh: dict):
+    keep = dict(x=np.ascontiguousarray(mesh["x"], np.float64),
+                y=np.ascontiguousarray(mesh["y"], np.float64),
+                tri=np.ascontiguousarray(mesh["tri"], np.int32),
+                ghost=np.ascontiguousarray(mesh.get("ghost", np.zeros(mesh["nv"])), np.uint8),
+                wall=np.ascontiguousarray(mesh.get("wall", np.zeros((0, 2))), np.int32))
+    d = rd_mesh_desc(int(mesh["nv"]), int(mesh["nt"]), keep["x"].ctypes.data, keep["y"].ctypes.data,
+                     keep["tri"].ctypes.data, float(mesh.get("px", 0.0)), float(mesh.get("py", 0.0)),
+                     keep["ghost"].ctypes.data if keep["ghost"].any() else None,
+                     int(keep["wall"].shape[0]), keep["wall"].ctypes.data if keep["wall"].size else None,
+                     float(mesh.get("gamma", 1.4)))
+    return d, keep
+
+
+# ------------------------------------------------ C-named thin wrappers ----
+
+def rd_mesh_validate(mesh: dict) -> None:
+    d, keep = _desc(mesh)
+    _check(lib().rd_mesh_validate(C.byref(d)))
+
+
+def rd_mesh_create(mesh: dict, stream=None):
+    d, keep = _desc(mesh)
+    h = C.c_void_p()
+    _check(lib().rd_mesh_create(C.byref(d), stream, C.byref(h)))
+    return h
+
+
+def rd_mesh_destroy(h) -> None:
+    _check(lib().rd_mesh_destroy(h))
+
+
+def rd_mesh_info(h):
+    nv, nt = C.c_int64(), C.c_int64()
+    _check(lib().rd_mesh_info(h, C.byref(nv), C.byref(nt)))
+    return nv.value, nt.value
+
+
+def rd_set_stream(h, stream) -> None:
+    _check(lib().rd_set_stream(h, stream))
+
+
+def rd_set_state(h, W) -> None:
+    dev = _is_torch(W)
+    _check(lib().rd_set_state(h, _ptr(W, dev), int(dev)))
+
+
+def rd_get_state(h, out) -> None:
+    dev = _is_torch(out)
+    _check(lib().rd_get_state(h, _ptr(out, dev), int(dev)))
+
+
+def rd_max_dt(h, cfl: float) -> float:
+    dt = C.c_double()
+    _check(lib().rd_max_dt(h, float(cfl), C.byref(dt)))
+    return dt.value
+
+
+def rd_step(h, dt: float, scheme: int = B, time: int = RK2, precision: int = FP64) -> None:
+    _check(lib().rd_step(h, float(dt), int(scheme), int(time), int(precision)))
+
+
+def rd_step_cfl(h, n_steps: int, cfl: float, scheme: int = B, time: int = RK2, precision: int = FP64) -> None:
+    _check(lib().rd_step_cfl(h, int(n_steps), float(cfl), int(scheme), int(time), int(precision)))
+
+
+KERNELS = ["cfl_tri", "cfl_vertex", "cfl_final", "wall1", "tri1", "gather1", "wall2", "tri2", "gather2"]
+
+
+def rd_step_timed(h, cfl: float, scheme: int = B, time: int = RK2, precision: int = FP64) -> dict:
+    ms = np.zeros(len(KERNELS))
+    _check(lib().rd_step_timed(h, float(cfl), int(scheme), int(time), int(precision), ms.ctypes.data))
+    return dict(zip(KERNELS, ms.tolist()))
+
+
+def rd_residual(h, scheme: int, R, phiT=None) -> None:
+    dev = _is_torch(R)
+    _check(lib().rd_residual(h, int(scheme), _ptr(R, dev), _ptr(phiT, dev) if phiT is not None else None,
+                             int(dev)))
+
+
+def rd_adjoint_step(h, W_n, dt: float, scheme: int, time: int, lam_np1, lam_n) -> None:
+    dev = _is_torch(lam_n)
+    _check(lib().rd_adjoint_step(h, _ptr(W_n, dev), float(dt), int(scheme), int(time),
+                                 _ptr(lam_np1, dev), _ptr(lam_n, dev), int(dev)))
+
+
+def rd_batch_create(handles, stream=None):
+    arr = (C.c_void_p * len(handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    b = C.c_void_p()
+    _check(lib().rd_batch_create(arr, len(handles), stream, C.byref(b)))
+    return b
+
+
+def rd_batch_run(b, n_steps: int, cfl: float, scheme: int = B, time: int = RK2, precision: int = FP64) -> None:
+    _check(lib().rd_batch_run(b, int(n_steps), float(cfl), int(scheme), int(time), int(precision)))
+
+
+def rd_batch_destroy(b) -> None:
+    _check(lib().rd_batch_destroy(b))
+
+
+def rd_sync(h) -> None:
+    _check(lib().rd_sync(h))
+
+
+def rd_last_error() -> str:
+    return lib().rd_last_error().decode()
+
+
+# ----------------------------------------------------- convenience class ---
+
+class Mesh:
+    """Owns an rd_mesh; host states are numpy [4, nv] float64 arrays."""
+
+    def __init__(self, mesh: dict, stream=None):
+        self.nv = int(mesh["nv"])
+        self.nt = int(mesh["nt"])
+        self.h = rd_mesh_create(mesh, stream if stream is not None else current_stream())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            rd_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, W):
+        if not _is_torch(W):
+            W = np.ascontiguousarray(W, dtype=np.float64)
+        rd_set_state(self.h, W)
+
+    def get_state(self, out=None):
+        if out is None:
+            out = np.zeros((4, self.nv))
+        rd_get_state(self.h, out)
+        return out
+
+    def max_dt(self, cfl: float) -> float:
+        return rd_max_dt(self.h, cfl)
+
+    def step(self, dt, scheme=B, time=RK2, precision=FP64):
+        rd_step(self.h, dt, scheme, time, precision)
+
+    def step_cfl(self, n_steps, cfl, scheme=B, time=RK2, precision=FP64):
+        rd_step_cfl(self.h, n_steps, cfl, scheme, time, precision)
+
+    def residual(self, scheme=B, with_phiT=False):
+        R = np.zeros((4, self.nv))
+        phiT = np.zeros((4, self.nt)) if with_phiT else None
+        rd_residual(self.h, scheme, R, phiT)
+        return (R, phiT) if with_phiT else R
+
+    def sync(self):
+        rd_sync(self.h)

@@ -1,0 +1,281 @@
+"""GPU (gfx950) parity of librd against the CPU oracle, through the C ABI.
+
+Tolerances: FP64 results agree with the oracle to 1e-12 in the max
+field-normwise relative error max_i |a_i - b_i| / max_i |b_i| per field,
+per step from identical input states. The FP32-distribute / FP64-accumulate
+variant carries the triangle algebra in single precision: its per-step error
+is bounded by 2e-5 (about 2^-24 amplified by the 4x4 solve and by the
+contrast between the field and its update; measured values are printed).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1705_02028_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+@pytest.fixture(scope="module")
+def rd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1705_02028_amd import rd as rdmod
+    rdmod.lib()
+    return rdmod
+
+
+def err(a, b):
+    return max(np.abs(a[k] - b[k]).max() / max(np.abs(b[k]).max(), 1e-300) for k in range(4))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gpu_step(rd, m, W, dt, scheme, time, prec, n=1):
+    g = rd.Mesh(m)
+    g.set_state(W)
+    for _ in range(n):
+        g.step(dt, scheme, time, prec)
+    out = g.get_state()
+    g.close()
+    return out
+
+
+CASES = {
+    "periodic_random": lambda: (I.split_square(40, diagonal="random", jitter=0.15, seed=1),
+                                lambda m: I.random_smooth_state(m, seed=3, amp=0.2)),
+    "sod_walls": lambda: (I.split_square(41, periodic=(False, False), bc=("ghost", "wall")), I.ic_sod),
+    "kh": lambda: (I.split_square(48), lambda m: I.ic_kelvin_helmholtz(m, seed=1)),
+    "quadrants": lambda: (I.split_square(45, periodic=(False, False), diagonal="random", seed=2),
+                          lambda m: I.ic_quadrants(m, I.quadrant_states(4))),
+    "closed_box": lambda: (I.split_square(23, periodic=(False, False), bc=("wall", "wall")),
+                           lambda m: I.random_smooth_state(m, seed=5, amp=0.2)),
+    "morton_channel": lambda: (I.split_square(37, periodic=(True, False), bc=("ghost", "wall"),
+                                              renumber="morton", rotate_corners=True, seed=7),
+                               lambda m: I.random_smooth_state(m, seed=6, amp=0.15)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("time", [1, 2])
+def test_one_step_all_schemes(orc, rd, case, time):
+    m, icf = CASES[case]()
+    W = icf(m)
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W, 0.4)
+    for scheme in range(5):
+        ref = om.step(W, dt, scheme, time)
+        say(f"case={case} nt={m['nt']} scheme={scheme} time={time} fp64")
+        e64 = err(gpu_step(rd, m, W, dt, scheme, time, rd.FP64), ref)
+        say(f"case={case} nt={m['nt']} scheme={scheme} time={time} fp32")
+        e32 = err(gpu_step(rd, m, W, dt, scheme, time, rd.FP32_ACC64), ref)
+        say(f"  err fp64 {e64:.2e} fp32 {e32:.2e}")
+        assert e64 <= TOL64
+        assert e32 <= TOL32
+
+
+def test_advected_sine_trajectory_n_euler(orc, rd):
+    """64x64 periodic advected density wave, N scheme, forward Euler,
+    CFL 0.5, 100 steps: per-step parity at states along the oracle's own
+    trajectory, and the end state of the full GPU run."""
+    m = I.split_square(64)
+    W = I.ic_advected_sine(m)
+    om = orc.OracleMesh(m)
+    states, dts = [W], []
+    for n in range(100):
+        dts.append(om.max_dt(states[-1], 0.5))
+        states.append(om.step(states[-1], dts[-1], orc.N, orc.EULER1))
+    g = rd.Mesh(m)
+    for n in (0, 33, 66, 99):
+        g.set_state(states[n])
+        say(f"advected sine step {n}")
+        assert abs(g.max_dt(0.5) - dts[n]) <= 1e-14 * dts[n]
+        g.step(dts[n], rd.N, rd.EULER1, rd.FP64)
+        assert err(g.get_state(), states[n + 1]) <= TOL64
+    g.set_state(W)
+    for n in range(100):
+        g.step(dts[n], rd.N, rd.EULER1, rd.FP64)
+    e = err(g.get_state(), states[-1])
+    say(f"advected sine 100-step end-state error {e:.2e}")
+    assert e <= 1e-11
+    g.close()
+
+
+def test_step_cfl_matches_oracle_trajectory(orc, rd):
+    m = I.split_square(33, periodic=(False, False), bc=("ghost", "wall"), diagonal="random", seed=3)
+    W = I.ic_quadrants(m, I.quadrant_states(9))
+    om = orc.OracleMesh(m)
+    ref = W
+    for _ in range(10):
+        ref = om.step(ref, om.max_dt(ref, 0.4), orc.B, orc.RK2)
+    g = rd.Mesh(m)
+    g.set_state(W)
+    g.step_cfl(10, 0.4, rd.B, rd.RK2, rd.FP64)
+    e = err(g.get_state(), ref)
+    say(f"step_cfl 10 steps error {e:.2e}")
+    assert e <= 1e-11
+    g.close()
+
+
+def test_residual_and_triangle_residual(orc, rd):
+    for name in ("periodic_random", "sod_walls", "closed_box"):
+        m, icf = CASES[name]()
+        W = icf(m)
+        om = orc.OracleMesh(m)
+        g = rd.Mesh(m)
+        g.set_state(W)
+        for scheme in range(5):
+            say(f"residual case={name} scheme={scheme}")
+            R, phiT = g.residual(scheme, with_phiT=True)
+            Ro, phiTo = om.residual(W, scheme, with_phiT=True)
+            scale = np.abs(Ro).max()
+            assert np.abs(R - Ro).max() <= 1e-12 * scale
+            assert np.abs(phiT - phiTo).max() <= 1e-12 * np.abs(phiTo).max()
+        g.close()
+
+
+def test_bitwise_determinism(rd):
+    m = I.split_square(129, diagonal="random", seed=4)
+    W = I.ic_kelvin_helmholtz(m, seed=4)
+    outs = []
+    for rep in range(3):
+        say(f"determinism rep {rep}")
+        g = rd.Mesh(m)
+        g.set_state(W)
+        g.step_cfl(5, 0.4, rd.B, rd.RK2, rd.FP64)
+        g.step_cfl(2, 0.4, rd.B, rd.RK2, rd.FP32_ACC64)
+        outs.append(g.get_state())
+        g.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_uniform_states_preserved_bitwise(rd, prec):
+    cases = [(I.split_square(50, diagonal="random", seed=5, jitter=0.2), (1.3, 0.4, -0.7, 0.8)),
+             (I.split_square(31, periodic=(False, False), bc=("ghost", "wall")), (0.9, 0.5, 0.0, 1.7)),
+             (I.split_square(31, periodic=(False, False), bc=("wall", "wall")), (1.0, 0.0, 0.0, 1.0))]
+    for m, prim in cases:
+        W = I.ic_uniform(m, *prim)
+        for scheme in range(5):
+            for time in (1, 2):
+                say(f"uniform nt={m['nt']} scheme={scheme} time={time} prec={prec}")
+                out = gpu_step(rd, m, W, 1e-3, scheme, time, prec, n=2)
+                assert np.array_equal(out, W)
+
+
+def test_all_ghost_and_tiny_meshes(orc, rd):
+    m = I.split_square(3, periodic=(False, False), bc=("ghost", "ghost"))
+    W = I.ic_quadrants(m, I.quadrant_states(1))
+    out = gpu_step(rd, m, W, 1e-3, rd.B, rd.RK2, rd.FP64)
+    assert np.array_equal(out, W)
+    m = I.split_square(4, diagonal="random", seed=1)  # 9 vertices, 18 triangles
+    W = I.random_smooth_state(m, seed=1)
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W, 0.4)
+    for scheme in range(5):
+        assert err(gpu_step(rd, m, W, dt, scheme, 2, rd.FP64), om.step(W, dt, scheme, 2)) <= TOL64
+
+
+def test_device_pointers_and_nonphysical_flag(orc, rd):
+    import torch
+    m = I.split_square(20)
+    W = I.ic_kelvin_helmholtz(m, seed=3)
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W, 0.4)
+    g = rd.Mesh(m)
+    Wt = torch.from_numpy(W).cuda()
+    rd.rd_set_state(g.h, Wt)
+    g.step(dt, rd.B, rd.RK2, rd.FP64)
+    out = torch.zeros_like(Wt)
+    rd.rd_get_state(g.h, out)
+    torch.cuda.synchronize()
+    assert err(out.cpu().numpy(), om.step(W, dt, orc.B, orc.RK2)) <= TOL64
+    R = torch.zeros_like(Wt)
+    rd.rd_residual(g.h, rd.B, R)
+    torch.cuda.synchronize()
+    g.sync()
+    # host input with negative pressure is refused
+    bad = W.copy()
+    bad[3, 7] = 0.1 * 0.5 * (bad[1, 7] ** 2 + bad[2, 7] ** 2) / bad[0, 7]
+    with pytest.raises(rd.RDError) as e:
+        g.set_state(bad)
+    assert e.value.status == rd.RD_ENONPHYS
+    # device input is checked on the device and reported by rd_sync
+    rd.rd_set_state(g.h, torch.from_numpy(bad).cuda())
+    with pytest.raises(rd.RDError) as e:
+        g.sync()
+    assert e.value.status == rd.RD_ENONPHYS
+    g.set_state(W)
+    g.sync()
+    for args in [(0.0, rd.B, rd.RK2, rd.FP64), (dt, 9, rd.RK2, rd.FP64), (dt, rd.B, 3, rd.FP64),
+                 (dt, rd.B, rd.RK2, 5)]:
+        with pytest.raises(rd.RDError) as e:
+            g.step(*args)
+        assert e.value.status == rd.RD_EINVAL
+    g.close()
+
+
+def test_precision_switch(orc, rd):
+    m = I.split_square(30, diagonal="random", seed=8)
+    W = I.random_smooth_state(m, seed=8, amp=0.2)
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W, 0.4)
+    g = rd.Mesh(m)
+    g.set_state(W)
+    g.step(dt, rd.B, rd.RK2, rd.FP32_ACC64)
+    mid = g.get_state()
+    g.step(dt, rd.B, rd.RK2, rd.FP64)
+    assert err(g.get_state(), om.step(mid, dt, orc.B, orc.RK2)) <= TOL64
+    g.close()
+
+
+# ------------------------------------------------ full-size configurations --
+
+def test_sod_1024_one_step_full_size(orc, rd):
+    """1024x1024 Sod tube (2,093,058 triangles), B / RK2 / CFL 0.4: one step
+    from the initial state and one from the exact solution at t = 0.1."""
+    import exact_riemann as E
+    m = I.split_square(1024, periodic=(False, False), bc=("ghost", "wall"))
+    om = orc.OracleMesh(m)
+    W0 = I.ic_sod(m)
+    r, u, p = E.sample(np.unique(m["x"]), 0.1, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    ix = np.searchsorted(np.unique(m["x"]), m["x"])
+    W1 = I.prim_to_cons(r[ix], u[ix], 0.0, p[ix])
+    for name, W in (("initial", W0), ("exact t=0.1", W1)):
+        dt = om.max_dt(W, 0.4)
+        ref = om.step(W, dt, orc.B, orc.RK2)
+        say(f"sod 1024 {name} fp64")
+        e64 = err(gpu_step(rd, m, W, dt, rd.B, rd.RK2, rd.FP64), ref)
+        say(f"sod 1024 {name} fp32")
+        e32 = err(gpu_step(rd, m, W, dt, rd.B, rd.RK2, rd.FP32_ACC64), ref)
+        say(f"  sod 1024 {name}: fp64 {e64:.2e} fp32 {e32:.2e}")
+        assert e64 <= TOL64 and e32 <= TOL32
+
+
+def test_kh_2048_one_step_full_size(orc, rd):
+    """2048x2048 periodic Kelvin-Helmholtz (8,380,418 triangles), B / RK2,
+    the launch configuration the benchmark times."""
+    m = I.split_square(2048)
+    om = orc.OracleMesh(m)
+    W = I.ic_kelvin_helmholtz(m, seed=0)
+    dt = om.max_dt(W, 0.4)
+    ref = om.step(W, dt, orc.B, orc.RK2)
+    say("kh 2048 fp64")
+    g = rd.Mesh(m)
+    g.set_state(W)
+    assert abs(g.max_dt(0.4) - dt) <= 1e-14 * dt
+    g.step_cfl(1, 0.4, rd.B, rd.RK2, rd.FP64)
+    e64 = err(g.get_state(), ref)
+    say("kh 2048 fp32")
+    g.set_state(W)
+    g.step_cfl(1, 0.4, rd.B, rd.RK2, rd.FP32_ACC64)
+    e32 = err(g.get_state(), ref)
+    g.close()
+    say(f"  kh 2048: fp64 {e64:.2e} fp32 {e32:.2e}")
+    assert e64 <= TOL64 and e32 <= TOL32
