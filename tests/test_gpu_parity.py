@@ -1,11 +1,17 @@
 """GPU (gfx950) parity of librd against the CPU oracle, through the C ABI.
 
-Tolerances: FP64 results agree with the oracle to 1e-12 in the max
-field-normwise relative error max_i |a_i - b_i| / max_i |b_i| per field,
-per step from identical input states. The FP32-distribute / FP64-accumulate
-variant carries the triangle algebra in single precision: its per-step error
-is bounded by 2e-5 (about 2^-24 amplified by the 4x4 solve and by the
-contrast between the field and its update; measured values are printed).
+Tolerances, in the max field-normwise relative error
+max_i |a_i - b_i| / max_i |b_i| per field, per step from identical inputs,
+use the oracle's own sensitivity s(u): how far one oracle step moves when
+its input is perturbed by random relative amounts of size u.
+  * FP64: 1e-12, or 10 s(2^-52) when larger. s(2^-52) is ~1e-14 for N, LDA
+    and B; the Bmax/Bmin blends take one Theta for all four equations from a
+    ratio that can be dominated by rounding in one equation, and there it
+    reaches ~1e-12.
+  * FP32 distribution / FP64 accumulation: 10 s(2^-24) (at least 1e-6): the
+    parameter vectors enter the triangle algebra rounded to FP32 (relative
+    2^-24), and the algebra's own rounding is of the same order.
+Measured errors and bars are printed.
 """
 import os
 
@@ -17,7 +23,6 @@ from paper_1705_02028_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
-TOL32 = 2e-5
 
 
 @pytest.fixture(scope="module")
@@ -31,6 +36,25 @@ def rd():
 
 def err(a, b):
     return max(np.abs(a[k] - b[k]).max() / max(np.abs(b[k]).max(), 1e-300) for k in range(4))
+
+
+def sensitivity(om, W, dt, scheme, time, rel=2.0 ** -52, reps=3, seed=0, ref=None):
+    """How far one oracle step moves under random relative input noise."""
+    rng = np.random.default_rng(seed)
+    if ref is None:
+        ref = om.step(W, dt, scheme, time)
+    s = 0.0
+    for _ in range(reps):
+        Wp = W * (1.0 + rel * rng.choice([-1.0, 0.0, 1.0], size=W.shape))
+        s = max(s, err(om.step(Wp, dt, scheme, time), ref))
+    return s
+
+
+def tols(om, W, dt, scheme, time, ref=None):
+    """(FP64 bar, FP32 bar) for one step of this case."""
+    s64 = sensitivity(om, W, dt, scheme, time, 2.0 ** -52, ref=ref)
+    s32 = sensitivity(om, W, dt, scheme, time, 2.0 ** -24, ref=ref)
+    return max(TOL64, 10.0 * s64), max(1e-6, 10.0 * s32)
 
 
 def say(*a):
@@ -71,13 +95,14 @@ def test_one_step_all_schemes(orc, rd, case, time):
     dt = om.max_dt(W, 0.4)
     for scheme in range(5):
         ref = om.step(W, dt, scheme, time)
+        t64, t32 = tols(om, W, dt, scheme, time, ref=ref)
         say(f"case={case} nt={m['nt']} scheme={scheme} time={time} fp64")
         e64 = err(gpu_step(rd, m, W, dt, scheme, time, rd.FP64), ref)
         say(f"case={case} nt={m['nt']} scheme={scheme} time={time} fp32")
         e32 = err(gpu_step(rd, m, W, dt, scheme, time, rd.FP32_ACC64), ref)
-        say(f"  err fp64 {e64:.2e} fp32 {e32:.2e}")
-        assert e64 <= TOL64
-        assert e32 <= TOL32
+        say(f"  err fp64 {e64:.2e} (tol {t64:.1e}) fp32 {e32:.2e} (tol {t32:.1e})")
+        assert e64 <= t64
+        assert e32 <= t32
 
 
 def test_advected_sine_trajectory_n_euler(orc, rd):
@@ -130,12 +155,19 @@ def test_residual_and_triangle_residual(orc, rd):
         om = orc.OracleMesh(m)
         g = rd.Mesh(m)
         g.set_state(W)
+        rng = np.random.default_rng(1)
         for scheme in range(5):
             say(f"residual case={name} scheme={scheme}")
             R, phiT = g.residual(scheme, with_phiT=True)
             Ro, phiTo = om.residual(W, scheme, with_phiT=True)
             scale = np.abs(Ro).max()
-            assert np.abs(R - Ro).max() <= 1e-12 * scale
+            noise = 0.0
+            for _ in range(3):
+                Wp = W * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 0.0, 1.0], size=W.shape))
+                noise = max(noise, np.abs(om.residual(Wp, scheme) - Ro).max())
+            e = np.abs(R - Ro).max()
+            say(f"  residual error {e / scale:.2e}, oracle 1-ulp sensitivity {noise / scale:.2e}")
+            assert e <= max(1e-12 * scale, 10 * noise)
             assert np.abs(phiT - phiTo).max() <= 1e-12 * np.abs(phiTo).max()
         g.close()
 
@@ -170,16 +202,24 @@ def test_uniform_states_preserved_bitwise(rd, prec):
 
 
 def test_all_ghost_and_tiny_meshes(orc, rd):
-    m = I.split_square(3, periodic=(False, False), bc=("ghost", "ghost"))
+    m = I.split_square(2, periodic=(False, False), bc=("ghost", "ghost"))  # every vertex a ghost
+    assert m["ghost"].all()
     W = I.ic_quadrants(m, I.quadrant_states(1))
     out = gpu_step(rd, m, W, 1e-3, rd.B, rd.RK2, rd.FP64)
     assert np.array_equal(out, W)
+    m = I.split_square(3, periodic=(False, False), bc=("ghost", "ghost"))  # one interior vertex
+    W = I.ic_quadrants(m, I.quadrant_states(1))
+    om = orc.OracleMesh(m)
+    out = gpu_step(rd, m, W, 1e-3, rd.B, rd.RK2, rd.FP64)
+    assert err(out, om.step(W, 1e-3, orc.B, orc.RK2)) <= TOL64
+    assert np.array_equal(np.delete(out, 4, axis=1), np.delete(W, 4, axis=1))
     m = I.split_square(4, diagonal="random", seed=1)  # 9 vertices, 18 triangles
     W = I.random_smooth_state(m, seed=1)
     om = orc.OracleMesh(m)
     dt = om.max_dt(W, 0.4)
     for scheme in range(5):
-        assert err(gpu_step(rd, m, W, dt, scheme, 2, rd.FP64), om.step(W, dt, scheme, 2)) <= TOL64
+        t64, _ = tols(om, W, dt, scheme, 2)
+        assert err(gpu_step(rd, m, W, dt, scheme, 2, rd.FP64), om.step(W, dt, scheme, 2)) <= t64
 
 
 def test_device_pointers_and_nonphysical_flag(orc, rd):
@@ -250,12 +290,13 @@ def test_sod_1024_one_step_full_size(orc, rd):
     for name, W in (("initial", W0), ("exact t=0.1", W1)):
         dt = om.max_dt(W, 0.4)
         ref = om.step(W, dt, orc.B, orc.RK2)
+        t64, t32 = tols(om, W, dt, orc.B, orc.RK2, ref=ref)
         say(f"sod 1024 {name} fp64")
         e64 = err(gpu_step(rd, m, W, dt, rd.B, rd.RK2, rd.FP64), ref)
         say(f"sod 1024 {name} fp32")
         e32 = err(gpu_step(rd, m, W, dt, rd.B, rd.RK2, rd.FP32_ACC64), ref)
-        say(f"  sod 1024 {name}: fp64 {e64:.2e} fp32 {e32:.2e}")
-        assert e64 <= TOL64 and e32 <= TOL32
+        say(f"  sod 1024 {name}: fp64 {e64:.2e} (tol {t64:.1e}) fp32 {e32:.2e} (tol {t32:.1e})")
+        assert e64 <= t64 and e32 <= t32
 
 
 def test_kh_2048_one_step_full_size(orc, rd):
@@ -266,6 +307,7 @@ def test_kh_2048_one_step_full_size(orc, rd):
     W = I.ic_kelvin_helmholtz(m, seed=0)
     dt = om.max_dt(W, 0.4)
     ref = om.step(W, dt, orc.B, orc.RK2)
+    t64, t32 = tols(om, W, dt, orc.B, orc.RK2, ref=ref)
     say("kh 2048 fp64")
     g = rd.Mesh(m)
     g.set_state(W)
@@ -277,5 +319,5 @@ def test_kh_2048_one_step_full_size(orc, rd):
     g.step_cfl(1, 0.4, rd.B, rd.RK2, rd.FP32_ACC64)
     e32 = err(g.get_state(), ref)
     g.close()
-    say(f"  kh 2048: fp64 {e64:.2e} fp32 {e32:.2e}")
-    assert e64 <= TOL64 and e32 <= TOL32
+    say(f"  kh 2048: fp64 {e64:.2e} (tol {t64:.1e}) fp32 {e32:.2e} (tol {t32:.1e})")
+    assert e64 <= t64 and e32 <= t32
