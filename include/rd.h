@@ -132,16 +132,15 @@ rd_status rd_step_cfl(rd_mesh* mesh, int n_steps, double cfl, int scheme, int ti
 
 /* Kernels of one step, in launch order, as reported by rd_step_timed. */
 enum {
-  RD_K_CFL_TRI = 0,    /* l_max lambda_max per triangle */
-  RD_K_CFL_VERTEX = 1, /* 2 V_i / sum per vertex, block minima */
-  RD_K_CFL_FINAL = 2,  /* minimum over blocks -> dt */
-  RD_K_WALL1 = 3,      /* wall term at W^n (meshes with walls) */
-  RD_K_TRI1 = 4,       /* triangle pass, stage 1 */
-  RD_K_GATHER1 = 5,    /* vertex sums and update, stage 1 */
-  RD_K_WALL2 = 6,      /* wall term at W* (RK2 with walls) */
-  RD_K_TRI2 = 7,       /* triangle pass, stage 2 (RK2) */
-  RD_K_GATHER2 = 8,    /* vertex sums and update, stage 2 (RK2) */
-  RD_NKERNELS = 9
+  RD_K_WALL1 = 0,      /* wall term at W^n (meshes with walls) */
+  RD_K_TRI1 = 1,       /* triangle pass, stage 1 (also l_max lambda_max per corner) */
+  RD_K_CFL_VERTEX = 2, /* 2 V_i / sum per vertex, block minima */
+  RD_K_CFL_FINAL = 3,  /* minimum over blocks -> dt */
+  RD_K_GATHER1 = 4,    /* vertex sums and update, stage 1 */
+  RD_K_WALL2 = 5,      /* wall term at W* (RK2 with walls) */
+  RD_K_TRI2 = 6,       /* triangle pass, stage 2 (RK2) */
+  RD_K_GATHER2 = 7,    /* vertex sums and update, stage 2 (RK2) */
+  RD_NKERNELS = 8
 };
 
 /* One step as rd_step_cfl(mesh, 1, ...) does, with a HIP event recorded on

@@ -38,10 +38,10 @@ double unwrap_h(double d, double period) {
   return d;
 }
 
-// Geometry the device does not recompute: vertex volumes (median dual) and
-// longest edges. Also the checks of rd_mesh_validate.
+// Geometry the device does not recompute: vertex volumes (median dual).
+// Also the checks of rd_mesh_validate.
 struct HostGeom {
-  std::vector<double> V, lmax;
+  std::vector<double> V;
 };
 
 rd_status check_desc(const rd_mesh_desc* d, HostGeom* out) {
@@ -55,7 +55,7 @@ rd_status check_desc(const rd_mesh_desc* d, HostGeom* out) {
   if (d->n_wall_edges < 0 || (d->n_wall_edges > 0 && !d->wall_edges))
     return fail(RD_EINVAL, "bad wall edge list");
   const int64_t nv = d->n_vertices, nt = d->n_triangles;
-  std::vector<double> V(nv, 0.0), lmax(nt, 0.0), area(nt, 0.0);
+  std::vector<double> V(nv, 0.0), area(nt, 0.0);
   for (int64_t t = 0; t < nt; ++t) {
     int32_t v[3] = {d->tri[3 * t], d->tri[3 * t + 1], d->tri[3 * t + 2]};
     for (int k = 0; k < 3; ++k)
@@ -70,13 +70,6 @@ rd_status check_desc(const rd_mesh_desc* d, HostGeom* out) {
     if (!(a > 0.0))
       return fail(RD_EINVAL, "triangle " + std::to_string(t) + " is not counter-clockwise with positive area");
     area[t] = a;
-    double lm = 0.0;
-    for (int i = 0; i < 3; ++i) {
-      const int j = (i + 1) % 3, k = (i + 2) % 3;
-      const double ex = px[k] - px[j], ey = py[k] - py[j];
-      lm = std::max(lm, std::sqrt(ex * ex + ey * ey));
-    }
-    lmax[t] = lm;
   }
   for (int64_t t = 0; t < nt; ++t)
     for (int k = 0; k < 3; ++k) V[d->tri[3 * t + k]] += area[t] / 3.0;
@@ -87,10 +80,7 @@ rd_status check_desc(const rd_mesh_desc* d, HostGeom* out) {
     if (a < 0 || a >= nv || b < 0 || b >= nv || a == b)
       return fail(RD_EINVAL, "wall edge " + std::to_string(e) + " is invalid");
   }
-  if (out) {
-    out->V.swap(V);
-    out->lmax.swap(lmax);
-  }
+  if (out) out->V.swap(V);
   return RD_OK;
 }
 
@@ -101,7 +91,7 @@ struct rd_mesh {
   hipStream_t stream = nullptr;
   int device = 0;
   // host copies, kept for batches
-  std::vector<double> x, y, V, lmax;
+  std::vector<double> x, y, V;
   std::vector<int32_t> tri, wall, row, slot, bc, wv, wptr;
   std::vector<uint8_t> ghost;
   std::vector<rd::WallEnt> went;
@@ -187,24 +177,31 @@ rd_status ensure_z(rd_mesh* m, int fp32) {
   return RD_OK;
 }
 
-// One step of Sections 3.2-3.4 with the time step already in d.dt. With
-// `ev` (RD_NKERNELS + 1 events) an event is recorded before every kernel
-// slot RD_K_WALL1.. and after the last.
-rd_status run_step(rd_mesh* m, int scheme, int time, int fp32, hipEvent_t* ev = nullptr) {
+// One step of Sections 3.2-3.4. With cfl > 0 the time step is computed on
+// the device from the state at the start of the step (the stage-1 triangle
+// pass writes l_max lambda_max per corner, two small passes reduce it);
+// otherwise it is already in d.dt. With `ev` (RD_NKERNELS + 1 events) an
+// event is recorded before every kernel slot and after the last.
+rd_status run_step(rd_mesh* m, int scheme, int time, int fp32, double cfl, hipEvent_t* ev = nullptr) {
   const rd::Dev d = dev_for(m, fp32);
   hipStream_t s = m->stream;
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
+  const bool with_cfl = cfl > 0.0;
   HIPCHK(mark(RD_K_WALL1));
   HIPCHK(rd::launch_wall(d, false, s));
   HIPCHK(mark(RD_K_TRI1));
-  HIPCHK(rd::launch_tri(d, fp32, scheme, 1, time == RD_RK2, s));
+  HIPCHK(rd::launch_tri(d, fp32, scheme, 1, time == RD_RK2, with_cfl, s));
+  HIPCHK(mark(RD_K_CFL_VERTEX));
+  if (with_cfl) HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 1, s));
+  HIPCHK(mark(RD_K_CFL_FINAL));
+  if (with_cfl) HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 2, s));
   HIPCHK(mark(RD_K_GATHER1));
   HIPCHK(rd::launch_gather(d, fp32, time == RD_RK2 ? rd::G_STAGE1 : rd::G_EULER, nullptr, s));
   HIPCHK(mark(RD_K_WALL2));
   if (time == RD_RK2) {
     HIPCHK(rd::launch_wall(d, true, s));
     HIPCHK(mark(RD_K_TRI2));
-    HIPCHK(rd::launch_tri(d, fp32, scheme, 2, false, s));
+    HIPCHK(rd::launch_tri(d, fp32, scheme, 2, false, false, s));
     HIPCHK(mark(RD_K_GATHER2));
     HIPCHK(rd::launch_gather(d, fp32, rd::G_STAGE2, nullptr, s));
   } else {
@@ -271,7 +268,6 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
   m->py = desc->period_y;
   m->gamma = desc->gamma;
   m->V.swap(geo.V);
-  m->lmax.swap(geo.lmax);
 
   // vertex -> (triangle, corner) CSR, ascending triangle order in every row
   m->row.assign(nv + 1, 0);
@@ -323,24 +319,27 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
     DeviceGuard g(m->device);
     std::vector<double2> xy(nv);
     for (int64_t i = 0; i < nv; ++i) xy[i] = make_double2(m->x[i], m->y[i]);
-    std::vector<int32_t> tv(3 * nt);
+    std::vector<int32_t> tv(3 * nt), pos(3 * nt);
     for (int64_t t = 0; t < nt; ++t)
       for (int k = 0; k < 3; ++k) tv[k * nt + t] = m->tri[3 * t + k];
+    for (int64_t s = 0; s < 3 * nt; ++s) {
+      const int32_t cs = m->slot[s];  // corner 3 t + k sits at CSR position s
+      pos[(cs % 3) * nt + cs / 3] = (int32_t)s;
+    }
     double2* pxy;
-    double *pV, *plmax;
-    int32_t *prow, *pslot, *ptv;
-    if ((st = upload(m, &pxy, xy)) || (st = upload(m, &pV, m->V)) || (st = upload(m, &plmax, m->lmax)) ||
-        (st = upload(m, &prow, m->row)) || (st = upload(m, &pslot, m->slot)) || (st = upload(m, &ptv, tv))) {
+    double* pV;
+    int32_t *prow, *ptv, *ppos;
+    if ((st = upload(m, &pxy, xy)) || (st = upload(m, &pV, m->V)) || (st = upload(m, &prow, m->row)) ||
+        (st = upload(m, &ptv, tv)) || (st = upload(m, &ppos, pos))) {
       free_all(m);
       delete m;
       return st;
     }
     d.xy = pxy;
     d.V = pV;
-    d.lmax = plmax;
     d.row = prow;
-    d.slot = pslot;
     d.tv = ptv;
+    d.pos = ppos;
     if (has_bc) {
       int32_t *pbc, *pwv, *pwptr;
       rd::WallEnt* pwent;
@@ -367,7 +366,7 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
     double *sig, *lam, *dt, *scratch;
     int* flag;
     if ((st = dalloc(m, &W, nv)) || (st = dalloc(m, &Ws, nv)) || (st = dalloc(m, &Z, nv)) ||
-        (st = dalloc(m, &sig, nv)) || (st = dalloc(m, &lam, nt)) || (st = dalloc(m, &dt, 1)) ||
+        (st = dalloc(m, &sig, nv)) || (st = dalloc(m, &lam, 3 * nt)) || (st = dalloc(m, &dt, 1)) ||
         (st = dalloc(m, &flag, 1)) || (st = dalloc(m, &scratch, 4 * std::max(nv, nt)))) {
       free_all(m);
       delete m;
@@ -501,7 +500,7 @@ RD_API rd_status rd_step(rd_mesh* m, double dt, int scheme, int time, int precis
   if ((st = ensure_prec(m, fp32)) != RD_OK) return st;
   if ((st = ensure_z(m, fp32)) != RD_OK) return st;
   HIPCHK(rd::launch_set_scalar(m->d.dt, dt, m->stream));
-  return run_step(m, scheme, time, fp32);
+  return run_step(m, scheme, time, fp32, 0.0);
 }
 
 RD_API rd_status rd_step_cfl(rd_mesh* m, int n_steps, double cfl, int scheme, int time, int precision) {
@@ -514,10 +513,8 @@ RD_API rd_status rd_step_cfl(rd_mesh* m, int n_steps, double cfl, int scheme, in
   const int fp32 = precision == RD_FP32_ACC64;
   if ((st = ensure_prec(m, fp32)) != RD_OK) return st;
   if ((st = ensure_z(m, fp32)) != RD_OK) return st;
-  for (int n = 0; n < n_steps; ++n) {
-    HIPCHK(rd::launch_cfl(m->d, m->cfl, cfl, m->stream));
-    if ((st = run_step(m, scheme, time, fp32)) != RD_OK) return st;
-  }
+  for (int n = 0; n < n_steps; ++n)
+    if ((st = run_step(m, scheme, time, fp32, cfl)) != RD_OK) return st;
   return RD_OK;
 }
 
@@ -533,11 +530,7 @@ RD_API rd_status rd_step_timed(rd_mesh* m, double cfl, int scheme, int time, int
   if (!m->events[0])
     for (int k = 0; k <= RD_NKERNELS; ++k) HIPCHK(hipEventCreate(&m->events[k]));
   hipEvent_t* ev = m->events;
-  for (int part = 0; part < 3; ++part) {
-    HIPCHK(hipEventRecord(ev[RD_K_CFL_TRI + part], m->stream));
-    HIPCHK(rd::launch_cfl_part(m->d, m->cfl, cfl, part, m->stream));
-  }
-  if ((st = run_step(m, scheme, time, fp32, ev)) != RD_OK) return st;
+  if ((st = run_step(m, scheme, time, fp32, cfl, ev)) != RD_OK) return st;
   HIPCHK(hipEventSynchronize(ev[RD_NKERNELS]));
   for (int k = 0; k < RD_NKERNELS; ++k) {
     float t = 0.0f;
@@ -557,7 +550,7 @@ RD_API rd_status rd_residual(rd_mesh* m, int scheme, double* R, double* phiT, in
   hipStream_t s = m->stream;
   const int64_t nv = d.nv, nt = d.nt;
   HIPCHK(rd::launch_wall(d, false, s));
-  HIPCHK(rd::launch_tri(d, 0, scheme, 1, true, s));
+  HIPCHK(rd::launch_tri(d, 0, scheme, 1, true, false, s));
   if (on_device) {
     HIPCHK(rd::launch_gather(d, 0, rd::G_RESIDUAL, R, s));
     if (phiT) HIPCHK(rd::launch_aos_to_soa(static_cast<const rd::D4*>(d.keepT), phiT, nt, s));

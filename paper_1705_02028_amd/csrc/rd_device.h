@@ -9,6 +9,10 @@
 // ascending triangle order (no atomics), adds the wall term and updates the
 // state, then refreshes the parameter vector and signal speed of the vertex.
 //
+// The triangle passes write each corner's part straight to that corner's
+// position in the vertex CSR (the inverse of the CSR's slot list), so a
+// vertex's parts are contiguous and the gather streams them.
+//
 // Algebra used on the GPU (equal in exact arithmetic to Appendix A's explicit
 // entries): with unit normal n, Roe state (u, v, h, c), w = u n_x + v n_y,
 //   E = (1, u, v, h), N = (0, n_x, n_y, w),
@@ -56,10 +60,9 @@ struct Dev {
   const double2* xy = nullptr;   // [nv]
   const double* V = nullptr;     // [nv] vertex volume
   const int32_t* row = nullptr;  // [nv+1] CSR row pointers
-  const int32_t* slot = nullptr; // [3nt] slot = 3 t + corner, ascending t per row
   const int32_t* bc = nullptr;   // [nv] or null: -1 interior, -2 ghost, >= 0 wall vertex
   const int32_t* tv = nullptr;   // [3][nt] corner vertex ids
-  const double* lmax = nullptr;  // [nt] longest edge
+  const int32_t* pos = nullptr;  // [3][nt] CSR position of corner (t, i): slot[pos] = 3 t + i
   const int32_t* wv = nullptr;   // [nwv] wall vertex ids
   const int32_t* wptr = nullptr; // [nwv+1]
   const WallEnt* went = nullptr; // wall incidences, ascending edge id per vertex
@@ -73,12 +76,12 @@ struct Dev {
   void* dW = nullptr; // [nv] W* - W^n (D4 or F4)
   double* sig = nullptr;   // [nv] |v| + c
   // triangle buffers
-  void* C = nullptr;      // [3nt] distributed parts (D4 or F4)
+  void* C = nullptr;      // [3nt] distributed parts in CSR order (D4 or F4)
   void* keepN = nullptr;  // [3nt] stage-1 N parts (D4 or F4)
   void* keepT = nullptr;  // [nt] stage-1 triangle residual (D4 or F4)
   D4* WCn = nullptr;      // [nwv] wall term at W^n
   D4* WCs = nullptr;      // [nwv] wall term at W*
-  double* lam = nullptr;  // [nt] l_max * lambda_max
+  double* lam = nullptr;  // [3nt] l_max^T lambda_max^T in CSR order
   double* dt = nullptr;   // [n meshes] time step
   int* flag = nullptr;    // non-physical state latch
 };
@@ -285,10 +288,11 @@ template <> __host__ __device__ inline const Q4<float>* zbuf<float>(const Dev& d
 //   Phi^T   = |T|/3 sum_j (W*_j - W^n_j)/dt + (phi^T(n) + phi^T(*))/2,
 //   Phi^LDA_i = K_i^+(*) A(*)^{-1} Phi^T,
 // blends them and writes them to C.
-template <typename R, int SCHEME, int STAGE, bool SAVE>
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
 __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
   const int64_t nt = d.nt;
   const int32_t iv[3] = {d.tv[t], d.tv[nt + t], d.tv[2 * nt + t]};
+  const int32_t ip[3] = {d.pos[t], d.pos[nt + t], d.pos[2 * nt + t]};
   const double2 p0 = d.xy[iv[0]], p1 = d.xy[iv[1]], p2 = d.xy[iv[2]];
   const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
   const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
@@ -332,8 +336,10 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
 
   Corner<R> kc[3];
   const R hic = R(0.5) * q.ic;
+  double lmax = 0.0;
   for (int i = 0; i < 3; ++i) {
     const double L = sqrt(nxd[i] * nxd[i] + nyd[i] * nyd[i]);
+    lmax = rmax(lmax, L);
     const double iL = 1.0 / L;
     Corner<R>& k = kc[i];
     k.nx = (R)(nxd[i] * iL);
@@ -350,6 +356,14 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
     k.l3m = k.s * m3;
     k.h1m = sh * (m1 - m3);
     k.h2m = sh * (m2 - m3);
+  }
+
+  if (CFL) {
+    // CFL limit of Section 3.2: l_max^T max_j(|v_j| + c_j), one copy per corner
+    double lam = 0.0;
+    for (int i = 0; i < 3; ++i) lam = rmax(lam, d.sig[iv[i]]);
+    const double lt = lmax * lam;
+    for (int i = 0; i < 3; ++i) d.lam[ip[i]] = lt;
   }
 
   // triangle residual and the N right-hand side
@@ -434,7 +448,7 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
         for (int k = 0; k < 4; ++k) out[k] = pl[k] + th[k] * (pN[i][k] - pl[k]);
       }
     }
-    st4<R>(d.C, 3 * t + i, out);
+    st4<R>(d.C, ip[i], out);
   }
 }
 
@@ -477,7 +491,7 @@ __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out
   double cmp[4] = {0.0, 0.0, 0.0, 0.0};
   const int32_t r0 = d.row[v], r1 = d.row[v + 1];
   for (int32_t s = r0; s < r1; ++s) {
-    const Q4<R> c = ld4<R>(d.C, d.slot[s]);
+    const Q4<R> c = ld4<R>(d.C, s);
     for (int k = 0; k < 4; ++k) {
       if (sizeof(R) == sizeof(double)) {
         acc[k] += (double)c.v[k];
@@ -550,17 +564,29 @@ __host__ __device__ inline void wall_body(int64_t b, const Dev& d) {
   st4<double>(STAGE2 ? d.WCs : d.WCn, b, acc);
 }
 
-// l_max^T lambda_max^T of one triangle.
+// l_max^T lambda_max^T of one triangle, written to its three CSR positions
+// (the same arithmetic as the fused form in tri_body).
 __host__ __device__ inline void cfl_tri_body(int64_t t, const Dev& d) {
-  double lam = 0.0;
-  for (int i = 0; i < 3; ++i) lam = rmax(lam, d.sig[d.tv[i * d.nt + t]]);
-  d.lam[t] = d.lmax[t] * lam;
+  const int64_t nt = d.nt;
+  const int32_t iv[3] = {d.tv[t], d.tv[nt + t], d.tv[2 * nt + t]};
+  const double2 p0 = d.xy[iv[0]], p1 = d.xy[iv[1]], p2 = d.xy[iv[2]];
+  const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
+  const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
+  const double nxd[3] = {-(d2y - d1y), d2y, -d1y};
+  const double nyd[3] = {d2x - d1x, -d2x, d1x};
+  double lmax = 0.0, lam = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    lmax = rmax(lmax, (double)sqrt(nxd[i] * nxd[i] + nyd[i] * nyd[i]));
+    lam = rmax(lam, d.sig[iv[i]]);
+  }
+  const double lt = lmax * lam;
+  for (int i = 0; i < 3; ++i) d.lam[d.pos[i * nt + t]] = lt;
 }
 
 // 2 V_i / sum_{T ni i} l_max lambda_max of one vertex.
 __host__ __device__ inline double cfl_vertex_bound(int64_t v, const Dev& d) {
   double acc = 0.0;
-  for (int32_t s = d.row[v]; s < d.row[v + 1]; ++s) acc += d.lam[d.slot[s] / 3];
+  for (int32_t s = d.row[v]; s < d.row[v + 1]; ++s) acc += d.lam[s];
   return 2.0 * d.V[v] / acc;
 }
 

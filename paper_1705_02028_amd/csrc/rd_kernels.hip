@@ -16,10 +16,10 @@ __device__ __forceinline__ int64_t xcd_block() {
   return x * q + (x < r ? x : r) + b / 8;
 }
 
-template <typename R, int SCHEME, int STAGE, bool SAVE>
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
 __global__ __launch_bounds__(kBlock) void k_tri(Dev d) {
   const int64_t t = xcd_block() * kBlock + threadIdx.x;
-  if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE>(t, d);
+  if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE, CFL>(t, d);
 }
 
 template <typename R, int MODE>
@@ -99,29 +99,32 @@ __global__ __launch_bounds__(kBlock) void k_copy4(D4* dst, const D4* src, int64_
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <typename R, int SCHEME>
-static hipError_t tri_dispatch(const Dev& d, int stage, bool save, hipStream_t s) {
+static hipError_t tri_dispatch(const Dev& d, int stage, bool save, bool cfl, hipStream_t s) {
   const dim3 g(nblk(d.nt)), b(kBlock);
-  if (stage == 1 && save) hipLaunchKernelGGL((k_tri<R, SCHEME, 1, true>), g, b, 0, s, d);
-  else if (stage == 1) hipLaunchKernelGGL((k_tri<R, SCHEME, 1, false>), g, b, 0, s, d);
-  else hipLaunchKernelGGL((k_tri<R, SCHEME, 2, false>), g, b, 0, s, d);
+  if (stage == 1 && save && cfl) hipLaunchKernelGGL((k_tri<R, SCHEME, 1, true, true>), g, b, 0, s, d);
+  else if (stage == 1 && save) hipLaunchKernelGGL((k_tri<R, SCHEME, 1, true, false>), g, b, 0, s, d);
+  else if (stage == 1 && cfl) hipLaunchKernelGGL((k_tri<R, SCHEME, 1, false, true>), g, b, 0, s, d);
+  else if (stage == 1) hipLaunchKernelGGL((k_tri<R, SCHEME, 1, false, false>), g, b, 0, s, d);
+  else hipLaunchKernelGGL((k_tri<R, SCHEME, 2, false, false>), g, b, 0, s, d);
   return hipGetLastError();
 }
 
 template <typename R>
-static hipError_t tri_scheme(const Dev& d, int scheme, int stage, bool save, hipStream_t s) {
+static hipError_t tri_scheme(const Dev& d, int scheme, int stage, bool save, bool cfl, hipStream_t s) {
   switch (scheme) {
-    case SCH_N: return tri_dispatch<R, SCH_N>(d, stage, save, s);
-    case SCH_LDA: return tri_dispatch<R, SCH_LDA>(d, stage, save, s);
-    case SCH_B: return tri_dispatch<R, SCH_B>(d, stage, save, s);
-    case SCH_BMAX: return tri_dispatch<R, SCH_BMAX>(d, stage, save, s);
-    case SCH_BMIN: return tri_dispatch<R, SCH_BMIN>(d, stage, save, s);
+    case SCH_N: return tri_dispatch<R, SCH_N>(d, stage, save, cfl, s);
+    case SCH_LDA: return tri_dispatch<R, SCH_LDA>(d, stage, save, cfl, s);
+    case SCH_B: return tri_dispatch<R, SCH_B>(d, stage, save, cfl, s);
+    case SCH_BMAX: return tri_dispatch<R, SCH_BMAX>(d, stage, save, cfl, s);
+    case SCH_BMIN: return tri_dispatch<R, SCH_BMIN>(d, stage, save, cfl, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_tri(const Dev& d, int fp32, int scheme, int stage, bool save, hipStream_t s) {
+hipError_t launch_tri(const Dev& d, int fp32, int scheme, int stage, bool save, bool cfl, hipStream_t s) {
   if (d.nt == 0) return hipSuccess;
-  return fp32 ? tri_scheme<float>(d, scheme, stage, save, s) : tri_scheme<double>(d, scheme, stage, save, s);
+  return fp32 ? tri_scheme<float>(d, scheme, stage, save, cfl, s)
+              : tri_scheme<double>(d, scheme, stage, save, cfl, s);
 }
 
 template <typename R>

@@ -20,7 +20,8 @@ struct CflPlan {
   double* part = nullptr;
 };
 
-hipError_t launch_tri(const Dev& d, int fp32, int scheme, int stage, bool save, hipStream_t s);
+// cfl: also write l_max lambda_max per corner (stage 1 only)
+hipError_t launch_tri(const Dev& d, int fp32, int scheme, int stage, bool save, bool cfl, hipStream_t s);
 hipError_t launch_gather(const Dev& d, int fp32, int mode, double* out_soa, hipStream_t s);
 hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s);
 hipError_t launch_cfl(const Dev& d, const CflPlan& p, double cfl, hipStream_t s);

@@ -182,7 +182,7 @@ def rd_step_cfl(h, n_steps: int, cfl: float, scheme: int = B, time: int = RK2, p
     _check(lib().rd_step_cfl(h, int(n_steps), float(cfl), int(scheme), int(time), int(precision)))
 
 
-KERNELS = ["cfl_tri", "cfl_vertex", "cfl_final", "wall1", "tri1", "gather1", "wall2", "tri2", "gather2"]
+KERNELS = ["wall1", "tri1", "cfl_vertex", "cfl_final", "gather1", "wall2", "tri2", "gather2"]
 
 
 def rd_step_timed(h, cfl: float, scheme: int = B, time: int = RK2, precision: int = FP64) -> dict:
