@@ -25,24 +25,26 @@ PEAK_FP64 = 78.6e12      # flop/s, vector FP64
 PEAK_FP32 = 157.3e12     # flop/s, vector FP32
 
 
-def algorithmic_bytes(nt, nv, fp32, scheme_b=True):
-    """Bytes each kernel of an RK2/B step must move at least once, assuming
-    every vertex record is read once per pass (ideal reuse). q = bytes per
-    real of the triangle algebra."""
+def algorithmic_bytes(nt, nv, fp32):
+    """Bytes each kernel of an RK2/B step with the CFL limit must move at
+    least once, with every vertex record read once per pass (ideal reuse).
+    q = bytes per real of the triangle algebra; a part or parameter vector is
+    4 reals; parts live in vertex-CSR order (one record per corner)."""
     q = 4 if fp32 else 8
     r4 = 4 * q
     k = {}
-    k["cfl_tri"] = nt * (12 + 8 + 8) + nv * 8
-    k["cfl_vertex"] = nv * (4 + 8) + nt * (12 + 8)
+    # stage 1: corner ids and CSR positions, coordinates, Z and |v|+c in;
+    # parts, kept N parts, phi^T and l_max lambda_max per corner out
+    k["tri1"] = nt * (12 + 12 + 3 * r4 + 3 * r4 + r4 + 24) + nv * (16 + r4 + 8)
+    # CFL: CSR rows, V and the per-corner l_max lambda_max in, block minima out
+    k["cfl_vertex"] = nv * (4 + 8) + nt * 24
     k["cfl_final"] = 0
-    # stage 1: indices, coordinates, parameter vectors in; parts, kept N parts and phi^T out
-    k["tri1"] = nt * (12 + 3 * r4 + 3 * r4 + r4) + nv * (16 + r4)
-    # gather 1: CSR, parts in; W in, W* and dW and Z and |v|+c out, V in
-    k["gather1"] = nt * (12 + 3 * r4) + nv * (4 + 32 + 32 + r4 + r4 + 8 + 8)
-    # stage 2: indices, coordinates, Z*, dW, kept N parts and phi^T in; parts out
-    k["tri2"] = nt * (12 + 3 * r4 + r4 + 3 * r4) + nv * (16 + r4 + r4)
-    # gather 2: CSR, parts in; W* in, W and Z and |v|+c out, V in
-    k["gather2"] = nt * (12 + 3 * r4) + nv * (4 + 32 + 32 + r4 + 8 + 8)
+    # gather 1: rows, parts in; W, V in; W*, W*-W, Z*, |v|+c out
+    k["gather1"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + r4 + 8)
+    # stage 2: ids, positions, coordinates, Z*, W*-W, kept N parts, phi^T in; parts out
+    k["tri2"] = nt * (12 + 12 + 3 * r4 + r4 + 3 * r4) + nv * (16 + r4 + r4)
+    # gather 2: rows, parts in; W*, V in; W, Z, |v|+c out
+    k["gather2"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + 8)
     k["wall1"] = k["wall2"] = 0
     return k
 
@@ -69,10 +71,10 @@ def time_variant(rd, torch, mesh, W0, prec, steps, warmup, cfl, timed_reps):
     ms = e0.elapsed_time(e1)
     g.sync()
     per = {}
-    for _ in range(timed_reps):
+    for _ in range(max(timed_reps, 1)):
         t = rd.rd_step_timed(g.h, cfl, rd.B, rd.RK2, prec)
         for k, v in t.items():
-            per[k] = per.get(k, 0.0) + v / timed_reps
+            per[k] = per.get(k, 0.0) + v / max(timed_reps, 1)
     g.sync()
     g.close()
     return ms, per
@@ -101,6 +103,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--timed-reps", type=int, default=5)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 512 MiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path", file=sys.stderr)
@@ -111,6 +115,13 @@ def main():
 
     torch.cuda.set_device(0)
     rd.lib()
+    if args.calibrate_copy:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     mesh = inputs.split_square(args.N)
     W0 = inputs.ic_kelvin_helmholtz(mesh, seed=0)
     nt, nv = mesh["nt"], mesh["nv"]

@@ -13,7 +13,7 @@
  * schemes (Section 3.3), sums the parts per vertex and updates the state with
  * forward Euler or the two-stage Runge-Kutta scheme of Section 3.4, with
  * periodic, non-reflecting (ghost) and reflecting-wall boundaries
- * (Section 3.6).
+ * (Section 3.5).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -79,10 +79,10 @@ typedef struct {
   double period_x;         /* 0: x bounded; > 0: x periodic with this period */
   double period_y;         /* 0: y bounded; > 0: y periodic with this period */
   const uint8_t* ghost;    /* [n_vertices] host or NULL; 1 marks a ghost vertex that
-                              keeps its state (non-reflecting / inflow, Section 3.6) */
+                              keeps its state (non-reflecting / inflow, Section 3.5) */
   int64_t n_wall_edges;    /* >= 0 */
   const int32_t* wall_edges; /* [2 * n_wall_edges] host: (a, b) with the domain on the
-                                left of a -> b; reflecting wall of Section 3.6 */
+                                left of a -> b; reflecting wall of Section 3.5 */
   double gamma;            /* ratio of specific heats, > 1 */
 } rd_mesh_desc;
 

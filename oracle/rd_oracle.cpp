@@ -406,7 +406,7 @@ template <class T> void corner_normals(const Mesh& m, int64_t t, double n[3][2])
   }
 }
 
-// Wall correction residual (Section 3.6), per vertex, AoS [nv][4].
+// Wall correction residual (Section 3.5), per vertex, AoS [nv][4].
 template <class T> void wall_term(const Mesh& m, const std::vector<T>& W, std::vector<T>& out) {
   const double alpha = 0.75, g1 = m.gamma - 1.0;
   out.assign(4 * m.nv, T(0.0));

@@ -40,7 +40,7 @@ struct alignas(4 * sizeof(R)) Q4 {
 using D4 = Q4<double>;
 using F4 = Q4<float>;
 
-// One wall-edge incidence of a wall vertex (Section 3.6).
+// One wall-edge incidence of a wall vertex (Section 3.5).
 struct alignas(16) WallEnt {
   int32_t other;  // the edge's other vertex
   int32_t role;   // 0: this vertex is the edge's start a, 1: its end b
@@ -96,6 +96,17 @@ __host__ __device__ inline double unwrap(double d, double period) {
 
 template <typename R> __host__ __device__ inline R rmax(R a, R b) { return a < b ? b : a; }
 template <typename R> __host__ __device__ inline R rmin(R a, R b) { return b < a ? b : a; }
+
+// Reciprocal: IEEE for FP64; the hardware reciprocal (about 1 ulp) for the
+// FP32 algebra, whose error budget is set by FP32 rounding anyway.
+__host__ __device__ inline double rcp(double x) { return 1.0 / x; }
+__host__ __device__ inline float rcp(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
 
 template <typename R>
 __host__ __device__ inline R sel4(int r, R a0, R a1, R a2, R a3) {
@@ -218,17 +229,17 @@ __host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x
     for (int j = k; j < 4; ++j) P[k][j] = sel4(r, A[0][j], A[1][j], A[2][j], A[3][j]);
     PB0[k] = sel4(r, b0[0], b0[1], b0[2], b0[3]);
     PB1[k] = sel4(r, b1[0], b1[1], b1[2], b1[3]);
-    PI[k] = ok ? R(1) / P[k][k] : R(0);
+    PI[k] = ok ? rcp(P[k][k]) : R(0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) used[i] = used[i] || (ok && r == i);
+    // rows not eliminated get factor 0, which leaves them exactly unchanged
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const bool elim = ok && !used[i];
-      R f = elim ? A[i][k] * PI[k] : R(0);
+      const R f = (ok && !used[i]) ? A[i][k] * PI[k] : R(0);
 #pragma unroll
-      for (int j = k + 1; j < 4; ++j) A[i][j] = elim ? A[i][j] - f * P[k][j] : A[i][j];
-      b0[i] = elim ? b0[i] - f * PB0[k] : b0[i];
-      b1[i] = elim ? b1[i] - f * PB1[k] : b1[i];
+      for (int j = k + 1; j < 4; ++j) A[i][j] = A[i][j] - f * P[k][j];
+      b0[i] = b0[i] - f * PB0[k];
+      b1[i] = b1[i] - f * PB1[k];
     }
   }
 #pragma unroll
@@ -250,7 +261,7 @@ template <typename R, int SCHEME>
 __host__ __device__ inline void blend_theta(const R res[4], const R n[3][4], R th[4]) {
   for (int k = 0; k < 4; ++k) {
     R den = (R)fabs(n[0][k]) + (R)fabs(n[1][k]) + (R)fabs(n[2][k]);
-    R q = den == R(0) ? R(0) : (R)fabs(res[k]) / den;
+    R q = den == R(0) ? R(0) : (R)fabs(res[k]) * rcp(den);
     th[k] = q > R(1) ? R(1) : q;
   }
   if (SCHEME == SCH_BMAX || SCHEME == SCH_BMIN) {
@@ -288,21 +299,48 @@ template <> __host__ __device__ inline const Q4<float>* zbuf<float>(const Dev& d
 //   Phi^T   = |T|/3 sum_j (W*_j - W^n_j)/dt + (phi^T(n) + phi^T(*))/2,
 //   Phi^LDA_i = K_i^+(*) A(*)^{-1} Phi^T,
 // blends them and writes them to C.
-template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
-__host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
+// The loads of one triangle, split in two so a kernel can issue them for the
+// next triangle while it computes the current one: corner ids and CSR
+// positions first, then the vertex records they point to.
+template <typename R>
+struct TriIn {
+  int32_t iv[3], ip[3];
+  double2 p[3];
+  Q4<R> Z[3];
+  double sig[3];
+};
+
+template <typename R>
+__host__ __device__ inline void tri_load_ids(int64_t t, const Dev& d, TriIn<R>& in) {
   const int64_t nt = d.nt;
-  const int32_t iv[3] = {d.tv[t], d.tv[nt + t], d.tv[2 * nt + t]};
-  const int32_t ip[3] = {d.pos[t], d.pos[nt + t], d.pos[2 * nt + t]};
-  const double2 p0 = d.xy[iv[0]], p1 = d.xy[iv[1]], p2 = d.xy[iv[2]];
+  for (int i = 0; i < 3; ++i) {
+    in.iv[i] = d.tv[i * nt + t];
+    in.ip[i] = d.pos[i * nt + t];
+  }
+}
+
+template <typename R, bool CFL>
+__host__ __device__ inline void tri_load_verts(const Dev& d, TriIn<R>& in) {
+  const Q4<R>* Zp = zbuf<R>(d);
+  for (int i = 0; i < 3; ++i) {
+    in.p[i] = d.xy[in.iv[i]];
+    in.Z[i] = Zp[in.iv[i]];
+    if (CFL) in.sig[i] = d.sig[in.iv[i]];
+  }
+}
+
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
+__host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const Dev& d) {
+  const int32_t* iv = in.iv;
+  const int32_t* ip = in.ip;
+  const double2 p0 = in.p[0], p1 = in.p[1], p2 = in.p[2];
   const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
   const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
   // inward normals scaled by edge length: rotate the opposite edge by +90 degrees
   const double nxd[3] = {-(d2y - d1y), d2y, -d1y};
   const double nyd[3] = {d2x - d1x, -d2x, d1x};
 
-  const Q4<R>* Zp = zbuf<R>(d);
-  Q4<R> Zc[3];
-  for (int i = 0; i < 3; ++i) Zc[i] = Zp[iv[i]];
+  const Q4<R>* Zc = in.Z;
 
   const R gam = (R)d.gamma;
   Roe<R> q;
@@ -310,20 +348,20 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
   const R third = R(1) / R(3);
   R zb[4];
   for (int k = 0; k < 4; ++k) zb[k] = (Zc[0].v[k] + Zc[1].v[k] + Zc[2].v[k]) * third;
-  const R iz = R(1) / zb[0];
+  const R iz = rcp(zb[0]);
   q.u = zb[1] * iz;
   q.v = zb[2] * iz;
   q.h = zb[3] * iz;
   const R q2 = q.u * q.u + q.v * q.v;
   q.c = (R)sqrt(q.g1 * (q.h - R(0.5) * q2));
-  q.ic = R(1) / q.c;
+  q.ic = rcp(q.c);
   q.ac = R(0.5) * q.g1 * q2 * q.ic;
   q.uc = q.u * q.ic;
   q.vc = q.v * q.ic;
 
   // dW_i = M(Zbar)(Z_i - Z_0), M = dW/dZ
   R dWh[3][4];
-  const R igam = R(1) / gam;
+  const R igam = (R)(1.0 / d.gamma);
   for (int k = 0; k < 4; ++k) dWh[0][k] = R(0);
   for (int i = 1; i < 3; ++i) {
     R dz[4];
@@ -336,15 +374,17 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
 
   Corner<R> kc[3];
   const R hic = R(0.5) * q.ic;
-  double lmax = 0.0;
+  R lmax = R(0);
   for (int i = 0; i < 3; ++i) {
-    const double L = sqrt(nxd[i] * nxd[i] + nyd[i] * nyd[i]);
+    // edge geometry in the algebra's precision, from FP64 coordinate differences
+    const R ex = (R)nxd[i], ey = (R)nyd[i];
+    const R L = (R)sqrt(ex * ex + ey * ey);
     lmax = rmax(lmax, L);
-    const double iL = 1.0 / L;
+    const R iL = rcp(L);
     Corner<R>& k = kc[i];
-    k.nx = (R)(nxd[i] * iL);
-    k.ny = (R)(nyd[i] * iL);
-    k.s = (R)(0.5 * L);
+    k.nx = ex * iL;
+    k.ny = ey * iL;
+    k.s = R(0.5) * L;
     k.w = q.u * k.nx + q.v * k.ny;
     const R l1 = k.w + q.c, l2 = k.w - q.c, l3 = k.w;
     const R p1 = rmax(l1, R(0)), p2 = rmax(l2, R(0)), p3 = rmax(l3, R(0));
@@ -361,8 +401,8 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
   if (CFL) {
     // CFL limit of Section 3.2: l_max^T max_j(|v_j| + c_j), one copy per corner
     double lam = 0.0;
-    for (int i = 0; i < 3; ++i) lam = rmax(lam, d.sig[iv[i]]);
-    const double lt = lmax * lam;
+    for (int i = 0; i < 3; ++i) lam = rmax(lam, in.sig[i]);
+    const double lt = (double)lmax * lam;
     for (int i = 0; i < 3; ++i) d.lam[ip[i]] = lt;
   }
 
@@ -378,9 +418,7 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
   constexpr bool needL = SCHEME != SCH_N;
   R pN[3][4];
   R rhs1[4];
-  R keepNv[3][4];
-  R rate[3][4];
-  R mass = R(0);
+  R mass = R(0), idt = R(0);
   if (needN) {
     apply_split(q, kc[1], kc[1].l3m, kc[1].h1m, kc[1].h2m, dWh[1], t1);
     apply_split(q, kc[2], kc[2].l3m, kc[2].h1m, kc[2].h2m, dWh[2], t2);
@@ -392,16 +430,16 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
     for (int k = 0; k < 4; ++k) rhs1[k] = phiT[k];
   } else {
     const int m = d.tmesh ? d.tmesh[t] : 0;
-    const R idt = (R)(1.0 / d.dt[m]);
+    idt = (R)(1.0 / d.dt[m]);
     mass = (R)((0.5 * (d1x * d2y - d1y * d2x)) / 3.0);
-    for (int i = 0; i < 3; ++i) {
-      const Q4<R> dwv = ld4<R>(d.dW, iv[i]);
-      for (int k = 0; k < 4; ++k) rate[i][k] = dwv.v[k] * idt;
-    }
     if (needL) {
+      R srate[4] = {R(0), R(0), R(0), R(0)};
+      for (int i = 0; i < 3; ++i) {
+        const Q4<R> dwv = ld4<R>(d.dW, iv[i]);
+        for (int k = 0; k < 4; ++k) srate[k] = srate[k] + dwv.v[k] * idt;
+      }
       const Q4<R> kt = ld4<R>(d.keepT, t);
-      for (int k = 0; k < 4; ++k)
-        rhs1[k] = mass * (rate[0][k] + rate[1][k] + rate[2][k]) + R(0.5) * (kt.v[k] + phiT[k]);
+      for (int k = 0; k < 4; ++k) rhs1[k] = mass * srate[k] + R(0.5) * (kt.v[k] + phiT[k]);
     } else {
       for (int k = 0; k < 4; ++k) rhs1[k] = R(0);
     }
@@ -425,12 +463,14 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
     st4<R>(d.keepT, t, phiT);
   }
   if (STAGE == 2 && needN) {
+    // Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2; the
+    // per-vertex differences are reloaded here (cached) to keep them out of
+    // registers across the solve
     for (int i = 0; i < 3; ++i) {
       const Q4<R> kn = ld4<R>(d.keepN, 3 * t + i);
-      for (int k = 0; k < 4; ++k) keepNv[i][k] = mass * rate[i][k] + R(0.5) * (kn.v[k] + pN[i][k]);
+      const Q4<R> dwv = ld4<R>(d.dW, iv[i]);
+      for (int k = 0; k < 4; ++k) pN[i][k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn.v[k] + pN[i][k]);
     }
-    for (int i = 0; i < 3; ++i)
-      for (int k = 0; k < 4; ++k) pN[i][k] = keepNv[i][k];
   }
   // rhs1 is the residual being split (phi^T or Phi^T); pN its N parts
   R th[4] = {R(0), R(0), R(0), R(0)};
@@ -450,6 +490,14 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
     }
     st4<R>(d.C, ip[i], out);
   }
+}
+
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
+__host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
+  TriIn<R> in;
+  tri_load_ids<R>(t, d, in);
+  tri_load_verts<R, CFL>(d, in);
+  tri_compute<R, SCHEME, STAGE, SAVE, CFL>(t, in, d);
 }
 
 // Parameter vector, signal speed and physicality of one state.
@@ -534,7 +582,7 @@ __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out
   vertex_epilogue(d, v, wo, sizeof(R) != sizeof(double));
 }
 
-// Wall correction of one wall vertex (Section 3.6), at W (STAGE2 = false) or W*.
+// Wall correction of one wall vertex (Section 3.5), at W (STAGE2 = false) or W*.
 template <bool STAGE2>
 __host__ __device__ inline void wall_body(int64_t b, const Dev& d) {
   const double alpha = 0.75, g1 = d.gamma - 1.0;

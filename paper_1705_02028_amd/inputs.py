@@ -22,7 +22,7 @@ its first corner. With ``N = 64`` and both axes periodic this gives 3,969
 vertices and 7,938 triangles.
 
 Boundary kinds for a bounded axis: ``"ghost"`` (vertices on those sides keep
-their initial state: the non-reflecting/inflow boundary of Section 3.6) and
+their initial state: the non-reflecting/inflow boundary of Section 3.5) and
 ``"wall"`` (reflecting wall edges, listed with the domain on their left).
 Corner vertices become ghosts when either adjacent side is a ghost side.
 """

@@ -327,7 +327,7 @@ def test_rk2_with_n_is_heun(orc):
 
 def test_wall_term_closed_form(orc):
     """Uniform flow in a closed box: triangle residuals vanish, so the
-    residual is the wall correction of Section 3.6 alone. Along a side with
+    residual is the wall correction of Section 3.5 alone. Along a side with
     outward unit normal n each non-corner vertex gets h * F_c with
     F_c = -(v.n) (rho, rho u, rho v, rho h); a corner gets half of each side."""
     N = 7
