@@ -1,0 +1,674 @@
+// Reverse mode of one residual-distribution step (FP64, time step fixed).
+//
+// The step of Sections 3.2-3.4 is, per triangle, a function of the three
+// corner parameter vectors (stage 1), or of the stage-1 state W*, of
+// W* - W^n and of the kept stage-1 N parts and residual (stage 2), followed
+// by per-vertex sums and updates. Its adjoint runs the same structure
+// backwards: per triangle, the forward arithmetic is recomputed in registers
+// and then differentiated line by line in reverse order (each block below
+// is the transpose of the matching block of the forward pass in
+// rd_device.h); per vertex, the corner cotangents are summed over the vertex
+// CSR in fixed order and mapped through dZ/dW. Branches follow the forward
+// values: max/min of eigenvalues, pivot order, |.| (derivative 0 at 0), the
+// 0/0 and clamped cases of the blend, the component Bmax/Bmin selects.
+// The pivoted solve is differentiated as x = A^{-1} b, so the adjoint
+// assumes no column of A was skipped (no exactly stagnant triangle).
+#pragma once
+
+#include "rd_device.h"
+
+namespace rd {
+
+struct AdjDev {
+  const D4* lam = nullptr;   // [nv] dL/dW^{n+1}
+  D4* lamS = nullptr;        // [nv] dL/dW*
+  D4* lamN = nullptr;        // [nv] running dL/dW^n (output)
+  D4* Zn = nullptr;          // [nv] parameter vectors at W^n
+  D4* cZ = nullptr;          // [3nt] corner cotangent of Z (CSR order)
+  D4* cW = nullptr;          // [3nt] corner cotangent of W* - W^n (CSR order)
+  D4* kN = nullptr;          // [3nt] cotangent of kept stage-1 N parts (triangle order)
+  D4* kT = nullptr;          // [nt] cotangent of kept stage-1 residual
+  D4* wcbar = nullptr;       // [nwv] cotangent of the wall term at W^n (stage 1 + half of stage 2)
+};
+
+// Cotangents of the quantities shared by all corners of a triangle.
+struct RoeBar {
+  double u = 0, v = 0, h = 0, c = 0, ic = 0, ac = 0, uc = 0, vc = 0;
+};
+struct CornerBar {
+  double w = 0, l3p = 0, h1p = 0, h2p = 0, l3m = 0, h1m = 0, h2m = 0;
+};
+
+__host__ __device__ inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+// Transpose of the tail shared by both K applications:
+// g = ac y0 - g1 (uc y1 + vc y2 - ic y3), d = -w y0 + nx y1 + ny y2.
+__host__ __device__ inline void gd_bar(const Roe<double>& q, const Corner<double>& k, const double y[4], double gb,
+                                       double db, double yb[4], RoeBar& qb, CornerBar& kb) {
+  yb[0] += q.ac * gb - k.w * db;
+  yb[1] += -q.g1 * q.uc * gb + k.nx * db;
+  yb[2] += -q.g1 * q.vc * gb + k.ny * db;
+  yb[3] += q.g1 * q.ic * gb;
+  qb.ac += y[0] * gb;
+  qb.uc += -q.g1 * y[1] * gb;
+  qb.vc += -q.g1 * y[2] * gb;
+  qb.ic += q.g1 * y[3] * gb;
+  kb.w += -y[0] * db;
+}
+
+// Transpose of apply_split (out = sl3 y + sp E + sm N).
+__host__ __device__ inline void apply_split_bar(const Roe<double>& q, const Corner<double>& k, double sl3, double h1,
+                                                double h2, const double y[4], const double ob[4], double yb[4],
+                                                RoeBar& qb, CornerBar& kb, double& sl3b, double& h1b, double& h2b) {
+  const double g = q.ac * y[0] - q.g1 * (q.uc * y[1] + q.vc * y[2] - q.ic * y[3]);
+  const double d = -k.w * y[0] + k.nx * y[1] + k.ny * y[2];
+  const double a1 = h1 * (g + d), a2 = h2 * (g - d);
+  const double sp = a1 + a2, sm = (a1 - a2) * q.c;
+  sl3b += ob[0] * y[0] + ob[1] * y[1] + ob[2] * y[2] + ob[3] * y[3];
+  for (int r = 0; r < 4; ++r) yb[r] += sl3 * ob[r];
+  const double spb = ob[0] + ob[1] * q.u + ob[2] * q.v + ob[3] * q.h;
+  qb.u += ob[1] * sp;
+  qb.v += ob[2] * sp;
+  qb.h += ob[3] * sp;
+  const double smb = ob[1] * k.nx + ob[2] * k.ny + ob[3] * k.w;
+  kb.w += ob[3] * sm;
+  const double a1b = spb + smb * q.c, a2b = spb - smb * q.c;
+  qb.c += smb * (a1 - a2);
+  h1b += a1b * (g + d);
+  h2b += a2b * (g - d);
+  const double gb = a1b * h1 + a2b * h2, db = a1b * h1 - a2b * h2;
+  gd_bar(q, k, y, gb, db, yb, qb, kb);
+}
+
+// Transpose of apply_full (out = s (w y + d E + c g N)).
+__host__ __device__ inline void apply_full_bar(const Roe<double>& q, const Corner<double>& k, const double y[4],
+                                               const double ob[4], double yb[4], RoeBar& qb, CornerBar& kb) {
+  const double g = q.ac * y[0] - q.g1 * (q.uc * y[1] + q.vc * y[2] - q.ic * y[3]);
+  const double d = -k.w * y[0] + k.nx * y[1] + k.ny * y[2];
+  double o[4];
+  for (int r = 0; r < 4; ++r) o[r] = k.s * ob[r];
+  kb.w += o[0] * y[0] + o[1] * y[1] + o[2] * y[2] + o[3] * y[3] + o[3] * q.c * g;
+  for (int r = 0; r < 4; ++r) yb[r] += k.w * o[r];
+  const double db = o[0] + o[1] * q.u + o[2] * q.v + o[3] * q.h;
+  qb.u += o[1] * d;
+  qb.v += o[2] * d;
+  qb.h += o[3] * d;
+  const double cgb = o[1] * k.nx + o[2] * k.ny + o[3] * k.w;
+  qb.c += g * cgb;
+  gd_bar(q, k, y, q.c * cgb, db, yb, qb, kb);
+}
+
+// Transpose of build_A.
+__host__ __device__ inline void build_A_bar(const Roe<double>& q, const Corner<double> k[3], const double Ab[4][4],
+                                            RoeBar& qb, CornerBar kb[3]) {
+  const double G[4] = {q.ac, -q.g1 * q.uc, -q.g1 * q.vc, q.g1 * q.ic};
+  const double E[4] = {1.0, q.u, q.v, q.h};
+  double P[3], Qv[3];
+  for (int i = 0; i < 3; ++i) {
+    P[i] = k[i].h1p + k[i].h2p;
+    Qv[i] = k[i].h1p - k[i].h2p;
+  }
+  const double sP = P[0] + P[1] + P[2];
+  double ev[4];
+  ev[0] = sP * G[0] - (Qv[0] * k[0].w + Qv[1] * k[1].w + Qv[2] * k[2].w);
+  ev[1] = sP * G[1] + (Qv[0] * k[0].nx + Qv[1] * k[1].nx + Qv[2] * k[2].nx);
+  ev[2] = sP * G[2] + (Qv[0] * k[0].ny + Qv[1] * k[1].ny + Qv[2] * k[2].ny);
+  ev[3] = sP * G[3];
+  double sQN[4];
+  sQN[0] = 0.0;
+  sQN[1] = Qv[0] * k[0].nx + Qv[1] * k[1].nx + Qv[2] * k[2].nx;
+  sQN[2] = Qv[0] * k[0].ny + Qv[1] * k[1].ny + Qv[2] * k[2].ny;
+  sQN[3] = Qv[0] * k[0].w + Qv[1] * k[1].w + Qv[2] * k[2].w;
+  double nvv[4];
+  for (int r = 0; r < 4; ++r) nvv[r] = q.c * sQN[r];
+  // A = L3 I + E ev^T + nvv G^T + S
+  double L3b = Ab[0][0] + Ab[1][1] + Ab[2][2] + Ab[3][3];
+  double Eb[4] = {0, 0, 0, 0}, evb[4] = {0, 0, 0, 0}, nvvb[4] = {0, 0, 0, 0}, Gb[4] = {0, 0, 0, 0};
+  for (int r = 0; r < 4; ++r)
+    for (int j = 0; j < 4; ++j) {
+      Eb[r] += Ab[r][j] * ev[j];
+      evb[j] += Ab[r][j] * E[r];
+      nvvb[r] += Ab[r][j] * G[j];
+      Gb[j] += Ab[r][j] * nvv[r];
+    }
+  // S[r][j] = c sum_i P_i N_ir D_ij  (r = 1..3, j = 0..2)
+  double Pb[3] = {0, 0, 0}, Qb[3] = {0, 0, 0};
+  for (int i = 0; i < 3; ++i) {
+    const double Nr[4] = {0.0, k[i].nx, k[i].ny, k[i].w};
+    const double Dc[4] = {-k[i].w, k[i].nx, k[i].ny, 0.0};
+    double acc = 0.0, wb = 0.0;
+    for (int r = 1; r < 4; ++r)
+      for (int j = 0; j < 3; ++j) acc += Ab[r][j] * Nr[r] * Dc[j];
+    Pb[i] += q.c * acc;
+    qb.c += P[i] * acc;
+    // w appears as N_i3 (row 3) and as -D_i0 (column 0)
+    for (int j = 0; j < 3; ++j) wb += Ab[3][j] * Dc[j];
+    for (int r = 1; r < 4; ++r) wb -= Ab[r][0] * Nr[r];
+    kb[i].w += q.c * P[i] * wb;
+  }
+  // nvv = c sQN
+  for (int r = 0; r < 4; ++r) qb.c += nvvb[r] * sQN[r];
+  for (int i = 0; i < 3; ++i) {
+    Qb[i] += q.c * (nvvb[1] * k[i].nx + nvvb[2] * k[i].ny + nvvb[3] * k[i].w);
+    kb[i].w += q.c * Qv[i] * nvvb[3];
+  }
+  // ev = sP G + sum_i Q_i D_i
+  double sPb = 0.0;
+  for (int j = 0; j < 4; ++j) {
+    sPb += evb[j] * G[j];
+    Gb[j] += sP * evb[j];
+  }
+  for (int i = 0; i < 3; ++i) {
+    Qb[i] += -evb[0] * k[i].w + evb[1] * k[i].nx + evb[2] * k[i].ny;
+    kb[i].w += -Qv[i] * evb[0];
+  }
+  for (int i = 0; i < 3; ++i) {
+    Pb[i] += sPb;
+    kb[i].h1p += Pb[i] + Qb[i];
+    kb[i].h2p += Pb[i] - Qb[i];
+    kb[i].l3p += L3b;
+  }
+  qb.u += Eb[1];
+  qb.v += Eb[2];
+  qb.h += Eb[3];
+  qb.ac += Gb[0];
+  qb.uc += -q.g1 * Gb[1];
+  qb.vc += -q.g1 * Gb[2];
+  qb.ic += q.g1 * Gb[3];
+}
+
+// Inputs of the stage-2 function of one triangle besides its parameter vectors.
+struct Stage2In {
+  double mass = 0.0, idt = 0.0;
+  double dw[3][4];     // W*_i - W^n_i
+  double keepN[3][4];  // stage-1 N parts
+  double keepT[4];     // stage-1 residual
+};
+struct Stage2Bar {
+  double dw[3][4];
+  double keepN[3][4];
+  double keepT[4];
+};
+
+// Reverse of one triangle. Zc: corner parameter vectors; geometry from the
+// unwrapped normals (nxd, nyd). ob[i]: cotangent of the scheme's part of
+// corner i. Stage 1 also takes the cotangents of the kept N parts (kNb) and
+// residual (kTb); stage 2 takes its extra inputs in s2 and returns theirs in
+// s2b. Returns the corner cotangents of Z in Zb.
+template <int SCHEME, int STAGE>
+__host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3], const double nyd[3], double gamma,
+                                            const double ob[3][4], const double kNb[3][4], const double kTb[4],
+                                            const Stage2In* s2, Stage2Bar* s2b, double Zb[3][4]) {
+  // ---------------- forward (recomputed, as in tri_compute) ----------------
+  Roe<double> q;
+  q.g1 = gamma - 1.0;
+  const double third = 1.0 / 3.0, igam = 1.0 / gamma;
+  double zb[4];
+  for (int k = 0; k < 4; ++k) zb[k] = (Zc[0].v[k] + Zc[1].v[k] + Zc[2].v[k]) * third;
+  const double iz = 1.0 / zb[0];
+  q.u = zb[1] * iz;
+  q.v = zb[2] * iz;
+  q.h = zb[3] * iz;
+  const double q2 = q.u * q.u + q.v * q.v;
+  q.c = sqrt(q.g1 * (q.h - 0.5 * q2));
+  q.ic = 1.0 / q.c;
+  q.ac = 0.5 * q.g1 * q2 * q.ic;
+  q.uc = q.u * q.ic;
+  q.vc = q.v * q.ic;
+  double dz[3][4], dWh[3][4];
+  for (int k = 0; k < 4; ++k) dz[0][k] = dWh[0][k] = 0.0;
+  for (int i = 1; i < 3; ++i) {
+    for (int k = 0; k < 4; ++k) dz[i][k] = Zc[i].v[k] - Zc[0].v[k];
+    dWh[i][0] = 2.0 * zb[0] * dz[i][0];
+    dWh[i][1] = zb[1] * dz[i][0] + zb[0] * dz[i][1];
+    dWh[i][2] = zb[2] * dz[i][0] + zb[0] * dz[i][2];
+    dWh[i][3] = (zb[3] * dz[i][0] + q.g1 * (zb[1] * dz[i][1] + zb[2] * dz[i][2]) + zb[0] * dz[i][3]) * igam;
+  }
+  Corner<double> kc[3];
+  double lam[3][3];  // l1, l2, l3 per corner
+  const double hic = 0.5 * q.ic;
+  for (int i = 0; i < 3; ++i) {
+    const double L = sqrt(nxd[i] * nxd[i] + nyd[i] * nyd[i]);
+    const double iL = 1.0 / L;
+    Corner<double>& k = kc[i];
+    k.nx = nxd[i] * iL;
+    k.ny = nyd[i] * iL;
+    k.s = 0.5 * L;
+    k.w = q.u * k.nx + q.v * k.ny;
+    lam[i][0] = k.w + q.c;
+    lam[i][1] = k.w - q.c;
+    lam[i][2] = k.w;
+    const double p1 = rmax(lam[i][0], 0.0), p2 = rmax(lam[i][1], 0.0), p3 = rmax(lam[i][2], 0.0);
+    const double m1 = rmin(lam[i][0], 0.0), m2 = rmin(lam[i][1], 0.0), m3 = rmin(lam[i][2], 0.0);
+    const double sh = k.s * hic;
+    k.l3p = k.s * p3;
+    k.h1p = sh * (p1 - p3);
+    k.h2p = sh * (p2 - p3);
+    k.l3m = k.s * m3;
+    k.h1m = sh * (m1 - m3);
+    k.h2m = sh * (m2 - m3);
+  }
+  double phiT[4], bN[4], t1[4], t2[4];
+  apply_full(q, kc[1], dWh[1], t1);
+  apply_full(q, kc[2], dWh[2], t2);
+  for (int k = 0; k < 4; ++k) phiT[k] = t1[k] + t2[k];
+  double A[4][4];
+  build_A(q, kc, A);
+  apply_split(q, kc[1], kc[1].l3m, kc[1].h1m, kc[1].h2m, dWh[1], t1);
+  apply_split(q, kc[2], kc[2].l3m, kc[2].h1m, kc[2].h2m, dWh[2], t2);
+  for (int k = 0; k < 4; ++k) bN[k] = t1[k] + t2[k];
+  double rhs1[4], srate[4] = {0, 0, 0, 0};
+  if (STAGE == 1) {
+    for (int k = 0; k < 4; ++k) rhs1[k] = phiT[k];
+  } else {
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 4; ++k) srate[k] += s2->dw[i][k] * s2->idt;
+    for (int k = 0; k < 4; ++k) rhs1[k] = s2->mass * srate[k] + 0.5 * (s2->keepT[k] + phiT[k]);
+  }
+  // A^{-1} (columns from unit right-hand sides) and the two solutions
+  double Ai[4][4];
+  {
+    double e0[4], e1[4], x0[4], x1[4], Aw[4][4];
+    for (int c2 = 0; c2 < 4; c2 += 2) {
+      for (int r = 0; r < 4; ++r) {
+        e0[r] = r == c2 ? 1.0 : 0.0;
+        e1[r] = r == c2 + 1 ? 1.0 : 0.0;
+        for (int c = 0; c < 4; ++c) Aw[r][c] = A[r][c];
+      }
+      solve2(Aw, e0, e1, x0, x1);
+      for (int r = 0; r < 4; ++r) {
+        Ai[r][c2] = x0[r];
+        Ai[r][c2 + 1] = x1[r];
+      }
+    }
+  }
+  double xN[4], xL[4];
+  for (int r = 0; r < 4; ++r) {
+    xN[r] = Ai[r][0] * bN[0] + Ai[r][1] * bN[1] + Ai[r][2] * bN[2] + Ai[r][3] * bN[3];
+    xL[r] = Ai[r][0] * rhs1[0] + Ai[r][1] * rhs1[1] + Ai[r][2] * rhs1[2] + Ai[r][3] * rhs1[3];
+  }
+  double yN[3][4], pN[3][4], PN[3][4], pl[3][4];
+  for (int i = 0; i < 3; ++i) {
+    for (int k = 0; k < 4; ++k) yN[i][k] = dWh[i][k] + xN[k];
+    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN[i], pN[i]);
+    for (int k = 0; k < 4; ++k)
+      PN[i][k] = STAGE == 1 ? pN[i][k]
+                            : s2->mass * (s2->dw[i][k] * s2->idt) + 0.5 * (s2->keepN[i][k] + pN[i][k]);
+    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, pl[i]);
+  }
+  double th[4] = {0, 0, 0, 0}, den[4] = {0, 0, 0, 0};
+  bool active[4] = {false, false, false, false};  // Theta_k = |r_k| / den_k, not 0/0, not clamped
+  int pick = 0;
+  if (SCHEME >= SCH_B) {
+    for (int k = 0; k < 4; ++k) {
+      den[k] = fabs(PN[0][k]) + fabs(PN[1][k]) + fabs(PN[2][k]);
+      const double qq = den[k] == 0.0 ? 0.0 : fabs(rhs1[k]) / den[k];
+      active[k] = den[k] != 0.0 && !(qq > 1.0);
+      th[k] = qq > 1.0 ? 1.0 : qq;
+    }
+    if (SCHEME == SCH_BMAX || SCHEME == SCH_BMIN) {
+      double t = th[0];
+      for (int k = 1; k < 4; ++k) {
+        const bool better = SCHEME == SCH_BMAX ? th[k] > t : th[k] < t;
+        t = better ? th[k] : t;
+        pick = better ? k : pick;
+      }
+      for (int k = 0; k < 4; ++k) th[k] = t;
+    }
+  }
+
+  // ---------------- reverse ----------------
+  RoeBar qb;
+  CornerBar kb[3];
+  double PNb[3][4], plb[3][4], rhs1b[4] = {0, 0, 0, 0};
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 4; ++k) {
+      if (SCHEME == SCH_N) {
+        PNb[i][k] = ob[i][k];
+        plb[i][k] = 0.0;
+      } else if (SCHEME == SCH_LDA) {
+        PNb[i][k] = 0.0;
+        plb[i][k] = ob[i][k];
+      } else {
+        PNb[i][k] = ob[i][k] * th[k];
+        plb[i][k] = ob[i][k] * (1.0 - th[k]);
+      }
+    }
+  if (SCHEME >= SCH_B) {
+    double thb[4];
+    for (int k = 0; k < 4; ++k)
+      thb[k] = ob[0][k] * (PN[0][k] - pl[0][k]) + ob[1][k] * (PN[1][k] - pl[1][k]) + ob[2][k] * (PN[2][k] - pl[2][k]);
+    if (SCHEME == SCH_BMAX || SCHEME == SCH_BMIN) {
+      const double s = thb[0] + thb[1] + thb[2] + thb[3];
+      for (int k = 0; k < 4; ++k) thb[k] = k == pick ? s : 0.0;
+    }
+    for (int k = 0; k < 4; ++k) {
+      if (!active[k]) continue;
+      const double qq = fabs(rhs1[k]) / den[k];
+      rhs1b[k] += thb[k] * sgn(rhs1[k]) / den[k];
+      const double denb = -thb[k] * qq / den[k];
+      for (int i = 0; i < 3; ++i) PNb[i][k] += denb * sgn(PN[i][k]);
+    }
+  }
+  double xLb[4] = {0, 0, 0, 0}, xNb[4] = {0, 0, 0, 0}, dWhb[3][4];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 4; ++k) dWhb[i][k] = 0.0;
+  double pNb[3][4];
+  for (int i = 0; i < 3; ++i) {
+    for (int k = 0; k < 4; ++k) {
+      if (STAGE == 1) {
+        pNb[i][k] = PNb[i][k] + kNb[i][k];
+      } else {
+        pNb[i][k] = 0.5 * PNb[i][k];
+        s2b->keepN[i][k] = 0.5 * PNb[i][k];
+        s2b->dw[i][k] = s2->mass * s2->idt * PNb[i][k];
+      }
+    }
+    double yb[4] = {0, 0, 0, 0};
+    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, plb[i], xLb, qb, kb[i], kb[i].l3p, kb[i].h1p,
+                    kb[i].h2p);
+    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN[i], pNb[i], yb, qb, kb[i], kb[i].l3p, kb[i].h1p,
+                    kb[i].h2p);
+    for (int k = 0; k < 4; ++k) {
+      dWhb[i][k] += yb[k];
+      xNb[k] += yb[k];
+    }
+  }
+  // x = A^{-1} b: b_bar = A^{-T} x_bar, A_bar = -(bN_bar xN^T + rhs_bar xL^T)
+  double bNb[4], rb[4];
+  for (int c = 0; c < 4; ++c) {
+    bNb[c] = Ai[0][c] * xNb[0] + Ai[1][c] * xNb[1] + Ai[2][c] * xNb[2] + Ai[3][c] * xNb[3];
+    rb[c] = Ai[0][c] * xLb[0] + Ai[1][c] * xLb[1] + Ai[2][c] * xLb[2] + Ai[3][c] * xLb[3];
+  }
+  double Ab[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) Ab[r][c] = -(bNb[r] * xN[c] + rb[r] * xL[c]);
+  for (int k = 0; k < 4; ++k) rhs1b[k] += rb[k];
+  double phiTb[4];
+  if (STAGE == 1) {
+    for (int k = 0; k < 4; ++k) phiTb[k] = rhs1b[k] + kTb[k];
+  } else {
+    for (int k = 0; k < 4; ++k) {
+      phiTb[k] = 0.5 * rhs1b[k];
+      s2b->keepT[k] = 0.5 * rhs1b[k];
+      const double rateb = s2->mass * rhs1b[k] * s2->idt;
+      for (int i = 0; i < 3; ++i) s2b->dw[i][k] += rateb;
+    }
+  }
+  build_A_bar(q, kc, Ab, qb, kb);
+  for (int i = 1; i < 3; ++i) {
+    apply_split_bar(q, kc[i], kc[i].l3m, kc[i].h1m, kc[i].h2m, dWh[i], bNb, dWhb[i], qb, kb[i], kb[i].l3m, kb[i].h1m,
+                    kb[i].h2m);
+    apply_full_bar(q, kc[i], dWh[i], phiTb, dWhb[i], qb, kb[i]);
+  }
+  // corners: (l3, h1, h2)^{+-} from the eigenvalues, w = u nx + v ny
+  for (int i = 0; i < 3; ++i) {
+    const Corner<double>& k = kc[i];
+    const double p[3] = {rmax(lam[i][0], 0.0), rmax(lam[i][1], 0.0), rmax(lam[i][2], 0.0)};
+    const double m[3] = {rmin(lam[i][0], 0.0), rmin(lam[i][1], 0.0), rmin(lam[i][2], 0.0)};
+    const double sh = k.s * hic;
+    double pb[3] = {0, 0, 0}, mb[3] = {0, 0, 0};
+    pb[2] += k.s * kb[i].l3p;
+    mb[2] += k.s * kb[i].l3m;
+    pb[0] += sh * kb[i].h1p;
+    pb[2] -= sh * kb[i].h1p;
+    pb[1] += sh * kb[i].h2p;
+    pb[2] -= sh * kb[i].h2p;
+    mb[0] += sh * kb[i].h1m;
+    mb[2] -= sh * kb[i].h1m;
+    mb[1] += sh * kb[i].h2m;
+    mb[2] -= sh * kb[i].h2m;
+    const double shb = kb[i].h1p * (p[0] - p[2]) + kb[i].h2p * (p[1] - p[2]) + kb[i].h1m * (m[0] - m[2]) +
+                       kb[i].h2m * (m[1] - m[2]);
+    qb.ic += 0.5 * k.s * shb;
+    double lb[3];
+    for (int j = 0; j < 3; ++j) lb[j] = (lam[i][j] > 0.0 ? pb[j] : 0.0) + (lam[i][j] < 0.0 ? mb[j] : 0.0);
+    const double wb = kb[i].w + lb[0] + lb[1] + lb[2];
+    qb.c += lb[0] - lb[1];
+    qb.u += wb * k.nx;
+    qb.v += wb * k.ny;
+  }
+  // Roe average and dW = M(zbar)(Z_i - Z_0)
+  double zbb[4] = {0, 0, 0, 0}, dzb[3][4];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 4; ++k) dzb[i][k] = 0.0;
+  for (int i = 1; i < 3; ++i) {
+    const double* g = dWhb[i];
+    const double* z = dz[i];
+    zbb[0] += 2.0 * z[0] * g[0];
+    dzb[i][0] += 2.0 * zb[0] * g[0];
+    zbb[1] += z[0] * g[1];
+    dzb[i][0] += zb[1] * g[1];
+    zbb[0] += z[1] * g[1];
+    dzb[i][1] += zb[0] * g[1];
+    zbb[2] += z[0] * g[2];
+    dzb[i][0] += zb[2] * g[2];
+    zbb[0] += z[2] * g[2];
+    dzb[i][2] += zb[0] * g[2];
+    const double t3 = g[3] * igam;
+    zbb[3] += z[0] * t3;
+    dzb[i][0] += zb[3] * t3;
+    zbb[1] += q.g1 * z[1] * t3;
+    dzb[i][1] += q.g1 * zb[1] * t3;
+    zbb[2] += q.g1 * z[2] * t3;
+    dzb[i][2] += q.g1 * zb[2] * t3;
+    zbb[0] += z[3] * t3;
+    dzb[i][3] += zb[0] * t3;
+  }
+  // ac = g1 q2 ic / 2, uc = u ic, vc = v ic, ic = 1/c, c = sqrt(g1 (h - q2/2)), q2 = u^2 + v^2
+  double q2b = 0.5 * q.g1 * q.ic * qb.ac;
+  qb.ic += 0.5 * q.g1 * q2 * qb.ac;
+  qb.u += q.ic * qb.uc;
+  qb.ic += q.u * qb.uc;
+  qb.v += q.ic * qb.vc;
+  qb.ic += q.v * qb.vc;
+  qb.c += -q.ic * q.ic * qb.ic;
+  const double c2b = qb.c / (2.0 * q.c);
+  qb.h += q.g1 * c2b;
+  q2b += -0.5 * q.g1 * c2b;
+  qb.u += 2.0 * q.u * q2b;
+  qb.v += 2.0 * q.v * q2b;
+  // u = zb1/zb0, v = zb2/zb0, h = zb3/zb0
+  zbb[1] += iz * qb.u;
+  zbb[2] += iz * qb.v;
+  zbb[3] += iz * qb.h;
+  const double izb = zb[1] * qb.u + zb[2] * qb.v + zb[3] * qb.h;
+  zbb[0] += -iz * iz * izb;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 4; ++k) Zb[i][k] = zbb[k] * third;
+  for (int i = 1; i < 3; ++i)
+    for (int k = 0; k < 4; ++k) {
+      Zb[i][k] += dzb[i][k];
+      Zb[0][k] -= dzb[i][k];
+    }
+}
+
+// Transpose of W -> Z at one state: Wb += (dZ/dW)^T Zb.
+__host__ __device__ inline void z_of_w_bar(const double w[4], double gamma, const double Zb[4], double Wb[4]) {
+  const double g1 = gamma - 1.0;
+  const double rho = w[0], u = w[1] / rho, v = w[2] / rho;
+  const double s = sqrt(rho);
+  const double p = g1 * (w[3] - 0.5 * rho * (u * u + v * v));
+  const double Z3 = (w[3] + p) / s;
+  const double is = 1.0 / s;
+  // Z0 = s, Z1 = m/s, Z2 = n/s, Z3 = (gamma e - g1 (m^2+n^2)/(2 rho)) / s
+  Wb[0] += Zb[0] * 0.5 * is - Zb[1] * 0.5 * u * is - Zb[2] * 0.5 * v * is +
+           Zb[3] * (0.5 * g1 * (u * u + v * v) * is - 0.5 * Z3 / rho);
+  Wb[1] += Zb[1] * is - Zb[3] * g1 * u * is;
+  Wb[2] += Zb[2] * is - Zb[3] * g1 * v * is;
+  Wb[3] += Zb[3] * gamma * is;
+}
+
+// Transpose of one wall flux F = -v_n (rho, rho u, rho v, rho h) at state w:
+// Wb += (dF/dW)^T Fb.
+__host__ __device__ inline void wall_flux_bar(const double w[4], double gamma, double nx, double ny, const double Fb[4],
+                                              double Wb[4]) {
+  const double g1 = gamma - 1.0;
+  const double rho = w[0], u = w[1] / rho, v = w[2] / rho;
+  const double p = g1 * (w[3] - 0.5 * rho * (u * u + v * v));
+  const double vn = u * nx + v * ny;
+  const double G[4] = {w[0], w[1], w[2], w[3] + p};
+  const double GtF = G[0] * Fb[0] + G[1] * Fb[1] + G[2] * Fb[2] + G[3] * Fb[3];
+  // dvn/dW = (-vn/rho, nx/rho, ny/rho, 0); dG/dW = I + e3 (g1 q^2/2, -g1 u, -g1 v, g1)
+  Wb[0] += -GtF * (-vn / rho) - vn * (Fb[0] + Fb[3] * 0.5 * g1 * (u * u + v * v));
+  Wb[1] += -GtF * (nx / rho) - vn * (Fb[1] - Fb[3] * g1 * u);
+  Wb[2] += -GtF * (ny / rho) - vn * (Fb[2] - Fb[3] * g1 * v);
+  Wb[3] += -vn * (Fb[3] * (1.0 + g1));
+}
+
+}  // namespace rd
+
+namespace rd {
+
+// mu = -(dt / V) lam at a vertex whose update uses its residual (0 at ghosts).
+__host__ __device__ inline void mu_of(const Dev& d, const D4* lam, int64_t v, double mu[4]) {
+  const bool ghost = d.bc && is_ghost(d.bc[v]);
+  const double f = ghost ? 0.0 : -d.dt[0] / d.V[v];
+  const D4 l = lam[v];
+  for (int k = 0; k < 4; ++k) mu[k] = f * l.v[k];
+}
+
+__host__ __device__ inline void tri_normals(const Dev& d, const int32_t iv[3], double nxd[3], double nyd[3],
+                                            double* area) {
+  const double2 p0 = d.xy[iv[0]], p1 = d.xy[iv[1]], p2 = d.xy[iv[2]];
+  const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
+  const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
+  nxd[0] = -(d2y - d1y);
+  nxd[1] = d2y;
+  nxd[2] = -d1y;
+  nyd[0] = d2x - d1x;
+  nyd[1] = -d2x;
+  nyd[2] = d1x;
+  if (area) *area = 0.5 * (d1x * d2y - d1y * d2x);
+}
+
+// Stage-2 reverse of one triangle: cotangents of Z*, W* - W^n (CSR order) and
+// of the kept stage-1 parts (triangle order), from lam = dL/dW^{n+1}.
+template <int SCHEME>
+__host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const AdjDev& a) {
+  const int64_t nt = d.nt;
+  int32_t iv[3], ip[3];
+  for (int i = 0; i < 3; ++i) {
+    iv[i] = d.tv[i * nt + t];
+    ip[i] = d.pos[i * nt + t];
+  }
+  double nxd[3], nyd[3], area;
+  tri_normals(d, iv, nxd, nyd, &area);
+  D4 Zc[3];
+  Stage2In s2;
+  s2.mass = area / 3.0;
+  s2.idt = 1.0 / d.dt[0];
+  double ob[3][4];
+  for (int i = 0; i < 3; ++i) {
+    Zc[i] = d.Z[iv[i]];
+    const D4 dw = ld4<double>(d.dW, iv[i]);
+    const D4 kn = ld4<double>(d.keepN, 3 * t + i);
+    for (int k = 0; k < 4; ++k) {
+      s2.dw[i][k] = dw.v[k];
+      s2.keepN[i][k] = SCHEME == SCH_LDA ? 0.0 : kn.v[k];
+    }
+    mu_of(d, a.lam, iv[i], ob[i]);
+  }
+  const D4 kt = ld4<double>(d.keepT, t);
+  for (int k = 0; k < 4; ++k) s2.keepT[k] = SCHEME == SCH_N ? 0.0 : kt.v[k];
+  Stage2Bar s2b;
+  double Zb[3][4];
+  tri_adjoint<SCHEME, 2>(Zc, nxd, nyd, d.gamma, ob, nullptr, nullptr, &s2, &s2b, Zb);
+  for (int i = 0; i < 3; ++i) {
+    st4<double>(a.cZ, ip[i], Zb[i]);
+    st4<double>(a.cW, ip[i], s2b.dw[i]);
+    st4<double>(a.kN, 3 * t + i, s2b.keepN[i]);
+  }
+  st4<double>(a.kT, t, s2b.keepT);
+}
+
+// Stage-1 reverse of one triangle: cotangents of Z^n (CSR order), from
+// mu1 = -(dt/V) dL/dW* and the cotangents of the kept parts.
+template <int SCHEME>
+__host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const AdjDev& a, bool rk2) {
+  const int64_t nt = d.nt;
+  int32_t iv[3], ip[3];
+  for (int i = 0; i < 3; ++i) {
+    iv[i] = d.tv[i * nt + t];
+    ip[i] = d.pos[i * nt + t];
+  }
+  double nxd[3], nyd[3];
+  tri_normals(d, iv, nxd, nyd, nullptr);
+  D4 Zc[3];
+  double ob[3][4], kNb[3][4], kTb[4];
+  for (int i = 0; i < 3; ++i) {
+    Zc[i] = a.Zn[iv[i]];
+    mu_of(d, a.lamS, iv[i], ob[i]);
+    const D4 kn = rk2 ? a.kN[3 * t + i] : D4{{0.0, 0.0, 0.0, 0.0}};
+    for (int k = 0; k < 4; ++k) kNb[i][k] = kn.v[k];
+  }
+  const D4 kt = rk2 ? a.kT[t] : D4{{0.0, 0.0, 0.0, 0.0}};
+  for (int k = 0; k < 4; ++k) kTb[k] = kt.v[k];
+  double Zb[3][4];
+  tri_adjoint<SCHEME, 1>(Zc, nxd, nyd, d.gamma, ob, kNb, kTb, nullptr, nullptr, Zb);
+  for (int i = 0; i < 3; ++i) st4<double>(a.cZ, ip[i], Zb[i]);
+}
+
+// Wall-term transpose at one wall vertex b: sum over its wall edges of
+// (dF_v/dW_v)^T (|e|/2)(alpha mu_v + (1 - alpha) mu_other), mu = cotangent of
+// the wall term (mu_of(lamA) * sa + mu_of(lamB) * sb).
+__host__ __device__ inline void wall_bar(const Dev& d, int64_t v, const D4* src, const D4* lamA, double sa,
+                                         const D4* lamB, double sb, double Wb[4]) {
+  const int32_t b = d.bc ? wall_index(d.bc[v]) : -1;
+  if (b < 0) return;
+  const double alpha = 0.75;
+  const D4 wv = src[v];
+  double ms[4], mo[4], t1[4], t2[4];
+  mu_of(d, lamA, v, t1);
+  if (lamB) mu_of(d, lamB, v, t2);
+  for (int k = 0; k < 4; ++k) ms[k] = sa * t1[k] + (lamB ? sb * t2[k] : 0.0);
+  for (int32_t e = d.wptr[b]; e < d.wptr[b + 1]; ++e) {
+    const WallEnt we = d.went[e];
+    mu_of(d, lamA, we.other, t1);
+    if (lamB) mu_of(d, lamB, we.other, t2);
+    for (int k = 0; k < 4; ++k) mo[k] = sa * t1[k] + (lamB ? sb * t2[k] : 0.0);
+    double Fb[4];
+    for (int k = 0; k < 4; ++k) Fb[k] = we.hl * (alpha * ms[k] + (1.0 - alpha) * mo[k]);
+    wall_flux_bar(wv.v, d.gamma, we.nx, we.ny, Fb, Wb);
+  }
+}
+
+// Reverse of the stage-2 vertex sums: dL/dW* and the W^n part of W* - W^n.
+__host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const AdjDev& a) {
+  double zb[4] = {0, 0, 0, 0}, wb[4] = {0, 0, 0, 0};
+  for (int32_t s = d.row[v]; s < d.row[v + 1]; ++s) {
+    const D4 cz = a.cZ[s], cw = a.cW[s];
+    for (int k = 0; k < 4; ++k) {
+      zb[k] += cz.v[k];
+      wb[k] += cw.v[k];
+    }
+  }
+  const D4 ws = d.Ws[v], l = a.lam[v];
+  double ls[4];
+  for (int k = 0; k < 4; ++k) ls[k] = l.v[k] + wb[k];
+  z_of_w_bar(ws.v, d.gamma, zb, ls);
+  wall_bar(d, v, d.Ws, a.lam, 0.5, nullptr, 0.0, ls);
+  st4<double>(a.lamS, v, ls);
+  double ln[4];
+  for (int k = 0; k < 4; ++k) ln[k] = -wb[k];
+  st4<double>(a.lamN, v, ln);
+}
+
+// Reverse of the stage-1 vertex sums and of W -> Z at W^n: dL/dW^n, written
+// structure-of-arrays to out.
+__host__ __device__ inline void adj_gather1_body(int64_t v, const Dev& d, const AdjDev& a, bool rk2, double* out) {
+  double zb[4] = {0, 0, 0, 0};
+  for (int32_t s = d.row[v]; s < d.row[v + 1]; ++s) {
+    const D4 cz = a.cZ[s];
+    for (int k = 0; k < 4; ++k) zb[k] += cz.v[k];
+  }
+  const D4 w = d.W[v], ls = a.lamS[v], ln = a.lamN[v];
+  double r[4];
+  for (int k = 0; k < 4; ++k) r[k] = ln.v[k] + ls.v[k];
+  z_of_w_bar(w.v, d.gamma, zb, r);
+  // wall term at W^n: cotangent mu1 (stage 1) + mu2 / 2 (stage 2)
+  wall_bar(d, v, d.W, a.lamS, 1.0, rk2 ? a.lam : nullptr, 0.5, r);
+  for (int k = 0; k < 4; ++k) out[k * d.nv + v] = r[k];
+}
+
+}  // namespace rd

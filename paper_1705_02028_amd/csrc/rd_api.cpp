@@ -105,6 +105,11 @@ struct rd_mesh {
   void* dW[2] = {nullptr, nullptr};
   double* scratch = nullptr;  // [4 * max(nv, nt)]
   int zprec = -1;             // precision the parameter vectors are valid for
+  // adjoint buffers, allocated on first use
+  rd::AdjDev adj;
+  rd::D4* adjW = nullptr;     // W^n of the step being reversed
+  double* adjIn = nullptr;    // [4 nv] host staging (W^n, then dL/dW^{n+1})
+  double* adjOut = nullptr;   // [4 nv] dL/dW^n
   hipEvent_t events[RD_NKERNELS + 1] = {};
 };
 
@@ -297,14 +302,15 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
     }
     m->wptr.push_back(0);
     for (int64_t i = 0; i < nv; ++i) {
-      if (m->ghost[i]) {
-        m->bc[i] = -2;
-      } else if (!per[i].empty()) {
-        m->bc[i] = (int32_t)m->wv.size();
+      int32_t b = -1;
+      if (!per[i].empty()) {
+        b = (int32_t)m->wv.size();
         m->wv.push_back((int32_t)i);
         for (const auto& e : per[i]) m->went.push_back(e);
         m->wptr.push_back((int32_t)m->went.size());
       }
+      if (m->ghost[i]) m->bc[i] = b >= 0 ? -3 - b : -2;
+      else m->bc[i] = b;
     }
   }
 
@@ -568,23 +574,240 @@ RD_API rd_status rd_residual(rd_mesh* m, int scheme, double* R, double* phiT, in
 
 RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int scheme, int time,
                                  const double* lam_np1, double* lam_n, int on_device) {
-  (void)m; (void)W_n; (void)dt; (void)scheme; (void)time; (void)lam_np1; (void)lam_n; (void)on_device;
-  return fail(RD_EUNSUPPORTED, "adjoint step not available in this build");
+  if (!m || !W_n || !lam_np1 || !lam_n) return fail(RD_EINVAL, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RD_EINVAL, "dt must be positive and finite");
+  rd_status st = check_step_args(scheme, time, RD_FP64);
+  if (st != RD_OK) return st;
+  DeviceGuard g(m->device);
+  const int64_t nv = m->d.nv, nt = m->d.nt;
+  if (!m->adjW) {
+    rd::AdjDev& a = m->adj;
+    rd::D4 *lamIn, *lamS, *lamN, *Zn, *cZ, *cW, *kN, *kT, *Wa;
+    double *in, *out;
+    if ((st = dalloc(m, &lamIn, nv)) || (st = dalloc(m, &lamS, nv)) || (st = dalloc(m, &lamN, nv)) ||
+        (st = dalloc(m, &Zn, nv)) || (st = dalloc(m, &cZ, 3 * nt)) || (st = dalloc(m, &cW, 3 * nt)) ||
+        (st = dalloc(m, &kN, 3 * nt)) || (st = dalloc(m, &kT, nt)) || (st = dalloc(m, &Wa, nv)) ||
+        (st = dalloc(m, &in, 4 * nv)) || (st = dalloc(m, &out, 4 * nv)))
+      return st;
+    a.lam = lamIn;
+    a.lamS = lamS;
+    a.lamN = lamN;
+    a.Zn = Zn;
+    a.cZ = cZ;
+    a.cW = cW;
+    a.kN = kN;
+    a.kT = kT;
+    m->adjW = Wa;
+    m->adjIn = in;
+    m->adjOut = out;
+  }
+  hipStream_t s = m->stream;
+  // the step is recomputed on private state; the mesh's own W is untouched
+  rd::Dev d = dev_for(m, 0);
+  d.W = m->adjW;
+  const double* src = W_n;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(m->adjIn, W_n, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, s));
+    src = m->adjIn;
+  }
+  HIPCHK(rd::launch_set_state(d, src, 0, s));
+  HIPCHK(rd::launch_copy4(m->adj.Zn, d.Z, nv, s));
+  HIPCHK(rd::launch_set_scalar(d.dt, dt, s));
+  const bool rk2 = time == RD_RK2;
+  if (rk2) {
+    HIPCHK(rd::launch_wall(d, false, s));
+    HIPCHK(rd::launch_tri(d, 0, scheme, 1, true, false, s));
+    HIPCHK(rd::launch_gather(d, 0, rd::G_STAGE1, nullptr, s));
+  }
+  const double* lsrc = lam_np1;
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(m->adjIn, lam_np1, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, s));
+    lsrc = m->adjIn;
+  }
+  HIPCHK(rd::launch_soa_to_aos(lsrc, const_cast<rd::D4*>(m->adj.lam), nv, s));
+  double* out = on_device ? lam_n : m->adjOut;
+  HIPCHK(rd::launch_adjoint(d, m->adj, scheme, rk2 ? 1 : 0, out, s));
+  m->zprec = -1;  // the parameter-vector buffer now holds the recomputation's values
+  if (!on_device) {
+    HIPCHK(hipMemcpyAsync(lam_n, m->adjOut, sizeof(double) * 4 * nv, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return RD_OK;
 }
 
+// ------------------------------------------------------------- batches --
+//
+// A batch lays its meshes end to end as one disjoint mesh (vertex and
+// triangle ids offset in order), adds a mesh id per vertex and per triangle so
+// every kernel reads its own mesh's time step, and reduces the CFL limit per
+// mesh over vertex blocks that never straddle two meshes. n steps are
+// captured once into a HIP graph and replayed; the members' states are
+// copied in before and out after.
+
+struct rd_batch {
+  rd_mesh* flat = nullptr;
+  std::vector<rd_mesh*> members;
+  std::vector<int64_t> voff, toff;
+  hipStream_t stream = nullptr;
+  struct Graph {
+    int n_steps, scheme, time, fp32;
+    double cfl;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+};
+
+namespace {
+
+void destroy_graphs(rd_batch* b) {
+  for (auto& g : b->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  b->graphs.clear();
+}
+
+}  // namespace
+
 RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd_batch** out) {
-  (void)meshes; (void)n; (void)stream;
-  if (out) *out = nullptr;
-  return fail(RD_EUNSUPPORTED, "batches not available in this build");
+  if (!out) return fail(RD_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!meshes || n <= 0) return fail(RD_EINVAL, "empty batch");
+  const double gamma = meshes[0] ? meshes[0]->gamma : 0.0;
+  std::vector<double> x, y;
+  std::vector<int32_t> tri, wall;
+  std::vector<uint8_t> ghost;
+  std::vector<int64_t> voff{0}, toff{0};
+  for (int k = 0; k < n; ++k) {
+    const rd_mesh* m = meshes[k];
+    if (!m) return fail(RD_EINVAL, "null mesh in batch");
+    if (m->px != 0.0 || m->py != 0.0) return fail(RD_EINVAL, "batched meshes must not be periodic");
+    if (m->gamma != gamma) return fail(RD_EINVAL, "batched meshes must share gamma");
+    if (m->device != meshes[0]->device) return fail(RD_EINVAL, "batched meshes must live on one device");
+    const int32_t vo = (int32_t)voff.back();
+    x.insert(x.end(), m->x.begin(), m->x.end());
+    y.insert(y.end(), m->y.begin(), m->y.end());
+    for (int32_t v : m->tri) tri.push_back(v + vo);
+    for (int32_t v : m->wall) wall.push_back(v + vo);
+    ghost.insert(ghost.end(), m->ghost.begin(), m->ghost.end());
+    voff.push_back(voff.back() + m->d.nv);
+    toff.push_back(toff.back() + m->d.nt);
+  }
+  if (voff.back() >= (int64_t(1) << 31) || 3 * toff.back() >= (int64_t(1) << 31))
+    return fail(RD_EINVAL, "batch too large for 32-bit indices");
+  rd_mesh_desc desc{};
+  desc.n_vertices = voff.back();
+  desc.n_triangles = toff.back();
+  desc.x = x.data();
+  desc.y = y.data();
+  desc.tri = tri.data();
+  desc.period_x = 0.0;
+  desc.period_y = 0.0;
+  desc.ghost = ghost.data();
+  desc.n_wall_edges = (int64_t)wall.size() / 2;
+  desc.wall_edges = wall.empty() ? nullptr : wall.data();
+  desc.gamma = gamma;
+  DeviceGuard g(meshes[0]->device);
+  rd_mesh* flat = nullptr;
+  rd_status st = rd_mesh_create(&desc, stream, &flat);
+  if (st != RD_OK) return st;
+  // mesh ids, per-mesh time steps, per-mesh CFL segments
+  std::vector<int32_t> vm(voff.back()), tm(toff.back()), v0, v1, b0{0};
+  for (int k = 0; k < n; ++k) {
+    for (int64_t i = voff[k]; i < voff[k + 1]; ++i) vm[i] = k;
+    for (int64_t t = toff[k]; t < toff[k + 1]; ++t) tm[t] = k;
+    for (int64_t v = voff[k]; v < voff[k + 1]; v += rd::kBlock) {
+      v0.push_back((int32_t)v);
+      v1.push_back((int32_t)std::min<int64_t>(v + rd::kBlock, voff[k + 1]));
+    }
+    b0.push_back((int32_t)v0.size());
+  }
+  int32_t *pvm, *ptm, *pv0, *pv1, *pb0;
+  double *dt, *part;
+  if ((st = upload(flat, &pvm, vm)) || (st = upload(flat, &ptm, tm)) || (st = upload(flat, &pv0, v0)) ||
+      (st = upload(flat, &pv1, v1)) || (st = upload(flat, &pb0, b0)) || (st = dalloc(flat, &dt, n)) ||
+      (st = dalloc(flat, &part, v0.size()))) {
+    rd_mesh_destroy(flat);
+    return st;
+  }
+  flat->d.vmesh = pvm;
+  flat->d.tmesh = ptm;
+  flat->d.dt = dt;
+  flat->cfl.nblocks = (int32_t)v0.size();
+  flat->cfl.nmesh = n;
+  flat->cfl.blk_v0 = pv0;
+  flat->cfl.blk_v1 = pv1;
+  flat->cfl.mesh_b0 = pb0;
+  flat->cfl.part = part;
+  rd_batch* b = new rd_batch();
+  b->flat = flat;
+  b->members.assign(meshes, meshes + n);
+  b->voff = voff;
+  b->toff = toff;
+  b->stream = static_cast<hipStream_t>(stream);
+  *out = b;
+  return RD_OK;
 }
 
 RD_API rd_status rd_batch_run(rd_batch* b, int n_steps, double cfl, int scheme, int time, int precision) {
-  (void)b; (void)n_steps; (void)cfl; (void)scheme; (void)time; (void)precision;
-  return fail(RD_EUNSUPPORTED, "batches not available in this build");
+  if (!b) return fail(RD_EINVAL, "null batch");
+  if (n_steps < 0) return fail(RD_EINVAL, "negative step count");
+  if (!(cfl > 0.0)) return fail(RD_EINVAL, "cfl must be positive");
+  rd_status st = check_step_args(scheme, time, precision);
+  if (st != RD_OK) return st;
+  rd_mesh* f = b->flat;
+  DeviceGuard g(f->device);
+  const int fp32 = precision == RD_FP32_ACC64;
+  if ((st = ensure_prec(f, fp32)) != RD_OK) return st;
+  hipStream_t s = f->stream;
+  // members' states in (ordered after each member's pending work)
+  for (size_t k = 0; k < b->members.size(); ++k) {
+    rd_mesh* m = b->members[k];
+    if (m->stream != s) HIPCHK(hipStreamSynchronize(m->stream));
+    HIPCHK(rd::launch_copy4(f->d.W + b->voff[k], m->d.W, m->d.nv, s));
+  }
+  HIPCHK(rd::launch_set_int(f->d.flag, 0, s));
+  f->zprec = -1;
+  if ((st = ensure_z(f, fp32)) != RD_OK) return st;
+  if (n_steps > 0) {
+    rd_batch::Graph* gr = nullptr;
+    for (auto& c : b->graphs)
+      if (c.n_steps == n_steps && c.scheme == scheme && c.time == time && c.fp32 == fp32 && c.cfl == cfl) gr = &c;
+    if (!gr) {
+      rd_batch::Graph c{n_steps, scheme, time, fp32, cfl, nullptr, nullptr};
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      rd_status rs = RD_OK;
+      for (int k = 0; k < n_steps && rs == RD_OK; ++k) rs = run_step(f, scheme, time, fp32, cfl);
+      hipError_t ce = hipStreamEndCapture(s, &c.graph);
+      if (rs != RD_OK) return rs;
+      if (ce != hipSuccess) return fail(RD_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+      HIPCHK(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
+      b->graphs.push_back(c);
+      gr = &b->graphs.back();
+    }
+    HIPCHK(hipGraphLaunch(gr->exec, s));
+  }
+  // states out; each member refreshes its parameter vectors before its next step
+  for (size_t k = 0; k < b->members.size(); ++k) {
+    rd_mesh* m = b->members[k];
+    HIPCHK(rd::launch_copy4(m->d.W, f->d.W + b->voff[k], m->d.nv, s));
+    HIPCHK(rd::launch_or_int(m->d.flag, f->d.flag, s));
+    m->zprec = -1;
+    if (m->stream != s) HIPCHK(hipStreamSynchronize(s));
+  }
+  return RD_OK;
 }
 
 RD_API rd_status rd_batch_destroy(rd_batch* b) {
-  (void)b;
+  if (!b) return RD_OK;
+  {
+    DeviceGuard g(b->flat->device);
+    (void)hipStreamSynchronize(b->flat->stream);
+    destroy_graphs(b);
+  }
+  rd_mesh_destroy(b->flat);
+  delete b;
   return RD_OK;
 }
 

@@ -60,7 +60,7 @@ struct Dev {
   const double2* xy = nullptr;   // [nv]
   const double* V = nullptr;     // [nv] vertex volume
   const int32_t* row = nullptr;  // [nv+1] CSR row pointers
-  const int32_t* bc = nullptr;   // [nv] or null: -1 interior, -2 ghost, >= 0 wall vertex
+  const int32_t* bc = nullptr;   // [nv] or null: boundary code, see is_ghost / wall_index
   const int32_t* tv = nullptr;   // [3][nt] corner vertex ids
   const int32_t* pos = nullptr;  // [3][nt] CSR position of corner (t, i): slot[pos] = 3 t + i
   const int32_t* wv = nullptr;   // [nwv] wall vertex ids
@@ -85,6 +85,12 @@ struct Dev {
   double* dt = nullptr;   // [n meshes] time step
   int* flag = nullptr;    // non-physical state latch
 };
+
+// Boundary code of a vertex: -1 interior, -2 ghost, b >= 0 wall vertex b,
+// -3 - b ghost that is also wall vertex b (its wall term is never applied,
+// but its state enters its neighbours' wall terms).
+__host__ __device__ inline bool is_ghost(int32_t bc) { return bc == -2 || bc <= -3; }
+__host__ __device__ inline int32_t wall_index(int32_t bc) { return bc >= 0 ? bc : (bc <= -3 ? -3 - bc : -1); }
 
 __host__ __device__ inline double unwrap(double d, double period) {
   if (period > 0.0) {
@@ -526,8 +532,9 @@ __host__ __device__ inline void vertex_epilogue(const Dev& d, int64_t v, const d
 // when the parts are FP32).
 template <typename R, int MODE>
 __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out_soa) {
-  const int32_t b = d.bc ? d.bc[v] : -1;
-  if (b == -2 && MODE != G_RESIDUAL) {
+  const int32_t code = d.bc ? d.bc[v] : -1;
+  const int32_t b = is_ghost(code) ? -1 : wall_index(code);
+  if (is_ghost(code) && MODE != G_RESIDUAL) {
     if (MODE == G_STAGE1) {
       d.Ws[v] = d.W[v];
       const R z[4] = {R(0), R(0), R(0), R(0)};

@@ -6,6 +6,7 @@
 // `xcd_block` renumbers them so that each XCD walks one contiguous range of
 // triangles or vertices, which keeps the vertex data a range touches in that
 // XCD's L2.
+#include "rd_adjoint.h"
 #include "rd_launch.h"
 
 namespace rd {
@@ -127,13 +128,87 @@ __global__ __launch_bounds__(kBlock) void k_aos_to_soa(const D4* src, double* so
 
 __global__ void k_set_scalar(double* p, double v) { p[0] = v; }
 __global__ void k_set_int(int* p, int v) { p[0] = v; }
+__global__ void k_or_int(int* dst, const int* src) { dst[0] = dst[0] | src[0]; }
+
 
 __global__ __launch_bounds__(kBlock) void k_copy4(D4* dst, const D4* src, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) dst[i] = src[i];
 }
 
+// ------------------------------------------------------------- adjoint --
+
+template <int SCHEME>
+__global__ __launch_bounds__(kBlock) void k_adj_tri2(Dev d, AdjDev a) {
+  const int64_t t = xcd_block() * kBlock + threadIdx.x;
+  if (t < d.nt) adj_tri2_body<SCHEME>(t, d, a);
+}
+
+template <int SCHEME>
+__global__ __launch_bounds__(kBlock) void k_adj_tri1(Dev d, AdjDev a, int rk2) {
+  const int64_t t = xcd_block() * kBlock + threadIdx.x;
+  if (t < d.nt) adj_tri1_body<SCHEME>(t, d, a, rk2 != 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_gather2(Dev d, AdjDev a) {
+  const int64_t v = xcd_block() * kBlock + threadIdx.x;
+  if (v < d.nv) adj_gather2_body(v, d, a);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_gather1(Dev d, AdjDev a, int rk2, double* out) {
+  const int64_t v = xcd_block() * kBlock + threadIdx.x;
+  if (v < d.nv) adj_gather1_body(v, d, a, rk2 != 0, out);
+}
+
+__global__ __launch_bounds__(kBlock) void k_soa_to_aos(const double* soa, D4* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double w[4] = {soa[i], soa[n + i], soa[2 * n + i], soa[3 * n + i]};
+  st4<double>(dst, i, w);
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero4(D4* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double z[4] = {0.0, 0.0, 0.0, 0.0};
+  st4<double>(dst, i, z);
+}
+
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <int SCHEME>
+static void adj_tris(const Dev& d, const AdjDev& a, int stage, int rk2, hipStream_t s) {
+  if (stage == 2) hipLaunchKernelGGL((k_adj_tri2<SCHEME>), dim3(nblk(d.nt)), dim3(kBlock), 0, s, d, a);
+  else hipLaunchKernelGGL((k_adj_tri1<SCHEME>), dim3(nblk(d.nt)), dim3(kBlock), 0, s, d, a, rk2);
+}
+
+hipError_t launch_adjoint(const Dev& d, const AdjDev& a, int scheme, int rk2, double* out, hipStream_t s) {
+  auto tris = [&](int stage) {
+    switch (scheme) {
+      case SCH_N: adj_tris<SCH_N>(d, a, stage, rk2, s); break;
+      case SCH_LDA: adj_tris<SCH_LDA>(d, a, stage, rk2, s); break;
+      case SCH_B: adj_tris<SCH_B>(d, a, stage, rk2, s); break;
+      case SCH_BMAX: adj_tris<SCH_BMAX>(d, a, stage, rk2, s); break;
+      default: adj_tris<SCH_BMIN>(d, a, stage, rk2, s); break;
+    }
+  };
+  if (rk2) {
+    tris(2);
+    hipLaunchKernelGGL(k_adj_gather2, dim3(nblk(d.nv)), dim3(kBlock), 0, s, d, a);
+  } else {
+    hipLaunchKernelGGL(k_copy4, dim3(nblk(d.nv)), dim3(kBlock), 0, s, a.lamS, a.lam, d.nv);
+    hipLaunchKernelGGL(k_zero4, dim3(nblk(d.nv)), dim3(kBlock), 0, s, a.lamN, d.nv);
+  }
+  tris(1);
+  hipLaunchKernelGGL(k_adj_gather1, dim3(nblk(d.nv)), dim3(kBlock), 0, s, d, a, rk2, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_soa_to_aos(const double* soa, D4* dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_soa_to_aos, dim3(nblk(n)), dim3(kBlock), 0, s, soa, dst, n);
+  return hipGetLastError();
+}
 
 // Grid of the persistent triangle pass: as many workgroups as the device
 // holds at once for this kernel (queried once per kernel).
@@ -257,6 +332,11 @@ hipError_t launch_set_scalar(double* p, double v, hipStream_t s) {
 
 hipError_t launch_set_int(int* p, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_or_int(int* dst, const int* src, hipStream_t s) {
+  hipLaunchKernelGGL(k_or_int, dim3(1), dim3(1), 0, s, dst, src);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "rd_adjoint.h"
 #include "rd_device.h"
 
 namespace rd {
@@ -33,6 +34,12 @@ hipError_t launch_get_state(const Dev& d, const D4* src, double* soa, hipStream_
 hipError_t launch_aos_to_soa(const D4* src, double* soa, int64_t n, hipStream_t s);
 hipError_t launch_set_scalar(double* p, double v, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
+// *dst |= *src
+hipError_t launch_or_int(int* dst, const int* src, hipStream_t s);
 hipError_t launch_copy4(D4* dst, const D4* src, int64_t n, hipStream_t s);
+hipError_t launch_soa_to_aos(const double* soa, D4* dst, int64_t n, hipStream_t s);
+// Reverse of one step (FP64): stage-2 triangles and gather (rk2), then
+// stage-1 triangles and gather; dL/dW^n goes to out [4][nv].
+hipError_t launch_adjoint(const Dev& d, const AdjDev& a, int scheme, int rk2, double* out, hipStream_t s);
 
 }  // namespace rd

@@ -275,3 +275,26 @@ class Mesh:
 
     def sync(self):
         rd_sync(self.h)
+
+
+class Batch:
+    """Owns an rd_batch over a list of ``Mesh`` objects (kept alive here)."""
+
+    def __init__(self, meshes, stream=None):
+        self.meshes = list(meshes)
+        self.h = rd_batch_create([m.h for m in self.meshes],
+                                 stream if stream is not None else current_stream())
+
+    def run(self, n_steps, cfl, scheme=B, time=RK2, precision=FP64):
+        rd_batch_run(self.h, n_steps, cfl, scheme, time, precision)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            rd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

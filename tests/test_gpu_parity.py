@@ -321,3 +321,147 @@ def test_kh_2048_one_step_full_size(orc, rd):
     g.close()
     say(f"  kh 2048: fp64 {e64:.2e} (tol {t64:.1e}) fp32 {e32:.2e} (tol {t32:.1e})")
     assert e64 <= t64 and e32 <= t32
+
+
+# ------------------------------------------------------------ batches ---
+
+def test_batch_bitwise_equals_single_runs(orc, rd):
+    """Independent four-quadrant meshes of uneven size advanced together in
+    one captured graph give, mesh by mesh, bitwise the result of each mesh's
+    own run, and match the oracle."""
+    sides = [17, 33, 9, 40, 24, 3, 50]
+    meshes, states = I.batch_problem(seed=3, sides=sides)
+    for prec in (rd.FP64, rd.FP32_ACC64):
+        singles = []
+        for m, W in zip(meshes, states):
+            say(f"batch single N={m['N']} prec={prec}")
+            g = rd.Mesh(m)
+            g.set_state(W)
+            g.step_cfl(6, 0.4, rd.B, rd.RK2, prec)
+            singles.append(g.get_state())
+            g.close()
+        gm = [rd.Mesh(m) for m in meshes]
+        for g, W in zip(gm, states):
+            g.set_state(W)
+        b = rd.Batch(gm)
+        say(f"batch run prec={prec}")
+        b.run(3, 0.4, rd.B, rd.RK2, prec)
+        b.run(3, 0.4, rd.B, rd.RK2, prec)   # replays the cached graph
+        for g, ref in zip(gm, singles):
+            assert np.array_equal(g.get_state(), ref)
+        # a member continues on its own after the batch
+        gm[3].step_cfl(1, 0.4, rd.B, rd.RK2, prec)
+        gm[3].sync()
+        b.close()
+        for g in gm:
+            g.close()
+    m, W = meshes[3], states[3]
+    om = orc.OracleMesh(m)
+    ref = W
+    for _ in range(6):
+        ref = om.step(ref, om.max_dt(ref, 0.4), orc.B, orc.RK2)
+    g = rd.Mesh(m)
+    g.set_state(W)
+    b = rd.Batch([g])
+    b.run(6, 0.4, rd.B, rd.RK2, rd.FP64)
+    assert err(g.get_state(), ref) <= 1e-11
+    b.close()
+    g.close()
+
+
+def test_batch_rejects_periodic_and_empty(rd):
+    g = rd.Mesh(I.split_square(8))
+    with pytest.raises(rd.RDError) as e:
+        rd.Batch([g])
+    assert e.value.status == rd.RD_EINVAL
+    with pytest.raises(rd.RDError):
+        rd.rd_batch_create([])
+    g.close()
+
+
+# ------------------------------------------------------------- adjoint ---
+
+ADJ_CASES = {
+    "periodic_random": lambda: (I.split_square(30, diagonal="random", jitter=0.15, seed=1),
+                                lambda m: I.random_smooth_state(m, seed=3, amp=0.2)),
+    "kh": lambda: (I.split_square(32), lambda m: I.ic_kelvin_helmholtz(m, seed=1)),
+    "ghost_walls": lambda: (I.split_square(21, periodic=(False, False), bc=("ghost", "wall"), diagonal="random",
+                                           seed=2), lambda m: I.random_smooth_state(m, seed=5, amp=0.2)),
+    "fourier_density": lambda: (I.split_square(33), lambda m: I.ic_fourier_density(m, seed=4)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(ADJ_CASES))
+def test_adjoint_dot_product_against_oracle_jvp(orc, rd, case):
+    """<lam, J v> from the oracle's exact forward-mode derivative equals
+    <J^T lam, v> from rd_adjoint_step, for every scheme and time order."""
+    m, icf = ADJ_CASES[case]()
+    W = icf(m)
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W, 0.4)
+    g = rd.Mesh(m)
+    g.set_state(W)
+    rng = np.random.default_rng(11)
+    for time in (1, 2):
+        for scheme in range(5):
+            v = rng.normal(size=W.shape) * np.abs(W).mean(axis=1, keepdims=True)
+            lam = rng.normal(size=W.shape)
+            _, Jv = om.step_jvp(W, v, dt, scheme, time)
+            JTl = np.zeros_like(W)
+            say(f"adjoint case={case} scheme={scheme} time={time}")
+            rd.rd_adjoint_step(g.h, W, dt, scheme, time, lam, JTl)
+            a, b = float(np.sum(lam * Jv)), float(np.sum(JTl * v))
+            scale = float(np.sum(np.abs(lam * Jv)))
+            say(f"  <lam,Jv> {a:.15e}  <J^T lam,v> {b:.15e}  rel {abs(a - b) / scale:.2e}")
+            assert abs(a - b) <= 1e-12 * scale
+    # the mesh's own state is untouched by the adjoint
+    assert np.array_equal(g.get_state(), W)
+    g.close()
+
+
+def test_rollout_gradient_checkpointed(orc, rd):
+    """Gradient of sum (rho_T - rho_target)^2 with respect to the initial
+    density (u, v, p fixed), B / RK2, fixed dt, 40 steps with checkpoints
+    every 20: directional derivatives against the oracle's exact forward-mode
+    rollout and against central differences of the GPU forward."""
+    import torch
+    from paper_1705_02028_amd.autograd import RDRollout, conserved_from_density
+    m = I.split_square(33)
+    W0 = I.ic_fourier_density(m, seed=0)
+    target = I.ic_fourier_density(m, seed=1)[0]
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W0, 0.4)
+    nsteps = 40
+    g = rd.Mesh(m)
+    dev = torch.device("cuda")
+    rho = torch.tensor(W0[0], dtype=torch.float64, device=dev, requires_grad=True)
+    u, v, p = 0.5, 0.3, 1.0
+    tgt = torch.tensor(target, dtype=torch.float64, device=dev)
+
+    def loss_of(r):
+        W = conserved_from_density(r, u, v, p, m["gamma"])
+        WT = RDRollout.apply(W, g, dt, nsteps, rd.B, rd.RK2, 20)
+        return ((WT[0] - tgt) ** 2).sum()
+
+    L = loss_of(rho)
+    L.backward()
+    grad = rho.grad.detach().cpu().numpy()
+    rng = np.random.default_rng(5)
+    for trial in range(2):
+        d = rng.normal(size=m["nv"])
+        # exact directional derivative through the oracle's rollout
+        Wd = np.stack([d, d * u, d * v, 0.5 * d * (u * u + v * v)])
+        Wc = W0.copy()
+        for _ in range(nsteps):
+            Wc, Wd = om.step_jvp(Wc, Wd, dt, orc.B, orc.RK2)
+        exact = float(np.sum(2.0 * (Wc[0] - target) * Wd[0]))
+        got = float(np.dot(grad, d))
+        say(f"rollout gradient: <grad,d> {got:.15e} exact {exact:.15e}")
+        assert abs(got - exact) <= 1e-10 * abs(exact)
+        eps = 1e-6
+        with torch.no_grad():
+            dd = torch.tensor(d, dtype=torch.float64, device=dev)
+            fd = (loss_of(rho + eps * dd) - loss_of(rho - eps * dd)).item() / (2 * eps)
+        say(f"  central difference {fd:.10e}")
+        assert abs(fd - got) <= 1e-6 * abs(got)
+    g.close()
