@@ -80,6 +80,137 @@ def time_variant(rd, torch, mesh, W0, prec, steps, warmup, cfl, timed_reps):
     return ms, per
 
 
+def adjoint_ratio(rd, torch, mesh, W0, cfl, reps):
+    """time(rd_adjoint_step) / time(rd_step) on the same mesh, FP64, B / RK2,
+    fixed dt, device-resident states; each timed over `reps` calls."""
+    g = rd.Mesh(mesh)
+    g.set_state(W0)
+    dt = g.max_dt(cfl)
+    W = torch.from_numpy(W0).cuda()
+    lam = torch.randn_like(W)
+    out = torch.empty_like(W)
+    for _ in range(2):
+        g.step(dt, rd.B, rd.RK2, rd.FP64)
+        rd.rd_adjoint_step(g.h, W, dt, rd.B, rd.RK2, lam, out)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    for _ in range(reps):
+        g.step(dt, rd.B, rd.RK2, rd.FP64)
+    e[1].record()
+    for _ in range(reps):
+        rd.rd_adjoint_step(g.h, W, dt, rd.B, rd.RK2, lam, out)
+    e[2].record()
+    torch.cuda.synchronize()
+    fwd = e[0].elapsed_time(e[1]) / reps
+    adj = e[1].elapsed_time(e[2]) / reps
+    g.close()
+    return {"ratio": round(adj / fwd, 3), "forward_ms": round(fwd, 4), "adjoint_ms": round(adj, 4),
+            "triangles": mesh["nt"]}
+
+
+def batch_vs_single(rd, torch, inputs, n_meshes, steps, cfl, seed=0):
+    """Four-quadrant problems of uneven size: per-mesh rd_step_cfl launches vs
+    one rd_batch_run graph, FP64, B / RK2; results are bitwise equal."""
+    import numpy as np
+    meshes, states = inputs.batch_problem(seed=seed, n=n_meshes)
+    nt = sum(m["nt"] for m in meshes)
+    gm = [rd.Mesh(m) for m in meshes]
+    for g, W in zip(gm, states):
+        g.set_state(W)
+        g.step_cfl(1, cfl, rd.B, rd.RK2, rd.FP64)   # warm-up
+    torch.cuda.synchronize()
+    for g, W in zip(gm, states):
+        g.set_state(W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in gm:
+        g.step_cfl(steps, cfl, rd.B, rd.RK2, rd.FP64)
+    torch.cuda.synchronize()
+    single = time.perf_counter() - t0
+    ref = [g.get_state() for g in gm]
+    b = rd.Batch(gm)
+    for g, W in zip(gm, states):
+        g.set_state(W)
+    b.run(steps, cfl, rd.B, rd.RK2, rd.FP64)       # captures the graph
+    for g, W in zip(gm, states):
+        g.set_state(W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps, cfl, rd.B, rd.RK2, rd.FP64)
+    torch.cuda.synchronize()
+    batched = time.perf_counter() - t0
+    equal = all(np.array_equal(g.get_state(), r) for g, r in zip(gm, ref))
+    b.close()
+    for g in gm:
+        g.close()
+    return {"meshes": n_meshes, "triangles": nt, "steps": steps,
+            "per_instance_s": round(single, 4), "batched_graph_s": round(batched, 4),
+            "speedup": round(single / batched, 3), "bitwise_equal": bool(equal),
+            "batched_value": round(nt * steps / batched, 1)}
+
+
+def _err(a, b):
+    import numpy as np
+    return float(max(np.abs(a[k] - b[k]).max() / max(np.abs(b[k]).max(), 1e-300) for k in range(4)))
+
+
+def fp32_table(rd, inputs):
+    """Error of the FP32-distribution / FP64-accumulation variant per
+    workload: one step from the initial state against the FP64 oracle, and the
+    end state of a run against the same run in FP64 on the GPU (which matches
+    the oracle step by step)."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle
+
+    def run(mesh, W0, n, cfl, scheme, time_, prec, t_end=None):
+        g = rd.Mesh(mesh)
+        g.set_state(W0)
+        if t_end is None:
+            g.step_cfl(n, cfl, scheme, time_, prec)
+        else:
+            t = 0.0
+            while t < t_end * (1 - 1e-14):
+                dt = min(g.max_dt(cfl), t_end - t)
+                g.step(dt, scheme, time_, prec)
+                t += dt
+        out = g.get_state()
+        g.close()
+        return out
+
+    rows = []
+    cases = [
+        ("advected sine 64^2, N / Euler, 100 steps", inputs.split_square(64), inputs.ic_advected_sine,
+         rd.N, rd.EULER1, 0.5, 100, None),
+        ("Sod 1024^2, B / RK2, to t = 0.2", inputs.split_square(1024, periodic=(False, False), bc=("ghost", "wall")),
+         inputs.ic_sod, rd.B, rd.RK2, 0.4, None, 0.2),
+        ("Kelvin-Helmholtz 2048^2, B / RK2, 500 steps", inputs.split_square(2048),
+         lambda m: inputs.ic_kelvin_helmholtz(m, seed=0), rd.B, rd.RK2, 0.4, 500, None),
+        ("four-quadrant 512^2, B / RK2, 200 steps", inputs.split_square(512, periodic=(False, False)),
+         lambda m: inputs.ic_quadrants(m, inputs.quadrant_states(0)), rd.B, rd.RK2, 0.4, 200, None),
+        ("Fourier density 256^2, B / RK2, 200 steps", inputs.split_square(256),
+         lambda m: inputs.ic_fourier_density(m, seed=0), rd.B, rd.RK2, 0.4, 200, None),
+    ]
+    for name, mesh, icf, scheme, time_, cfl, n, t_end in cases:
+        print(f"bench: fp32 table: {name}", file=sys.stderr, flush=True)
+        W0 = icf(mesh)
+        om = oracle.OracleMesh(mesh)
+        dt = om.max_dt(W0, cfl)
+        ref1 = om.step(W0, dt, scheme, time_)
+        one = {}
+        for prec in (rd.FP64, rd.FP32_ACC64):
+            g = rd.Mesh(mesh)
+            g.set_state(W0)
+            g.step(dt, scheme, time_, prec)
+            one[prec] = _err(g.get_state(), ref1)
+            g.close()
+        e64 = run(mesh, W0, n, cfl, scheme, time_, rd.FP64, t_end)
+        e32 = run(mesh, W0, n, cfl, scheme, time_, rd.FP32_ACC64, t_end)
+        rows.append({"workload": name, "one_step_fp64_vs_oracle": one[rd.FP64],
+                     "one_step_fp32_vs_oracle": one[rd.FP32_ACC64], "end_fp32_vs_fp64": _err(e32, e64)})
+    return rows
+
+
 def cpu_baseline(mesh, W0, cfl):
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle
@@ -103,6 +234,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--timed-reps", type=int, default=5)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--batch", type=int, default=0, metavar="NMESH",
+                    help="also time NMESH four-quadrant meshes (32^2..512^2) per instance vs one batched graph")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--fp32-table", action="store_true",
+                    help="only print the FP32-variant error table per workload (JSON)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 512 MiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -122,6 +259,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.fp32_table:
+        print(json.dumps({"fp32_errors": fp32_table(rd, inputs)}), flush=True)
+        return
     mesh = inputs.split_square(args.N)
     W0 = inputs.ic_kelvin_helmholtz(mesh, seed=0)
     nt, nv = mesh["nt"], mesh["nv"]
@@ -165,6 +305,15 @@ def main():
                           "kernels_ms": {k: round(v, 5) for k, v in per64.items()},
                           "kernels_GBps": {k: round(b64[k] / (v * 1e-3) / 1e9, 1)
                                            for k, v in per64.items() if v > 0 and b64[k]}}
+    if not args.no_adjoint:
+        print("bench: adjoint / forward", file=sys.stderr, flush=True)
+        result["adjoint_forward_ratio"] = adjoint_ratio(rd, torch, mesh, W0, args.cfl, 10)
+        m256 = inputs.split_square(256)
+        result["adjoint_forward_ratio_256"] = adjoint_ratio(rd, torch, m256, inputs.ic_fourier_density(m256, seed=0),
+                                                            args.cfl, 20)
+    if args.batch:
+        print(f"bench: batch of {args.batch} meshes", file=sys.stderr, flush=True)
+        result["batch"] = batch_vs_single(rd, torch, inputs, args.batch, args.batch_steps, args.cfl)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(mesh, W0, args.cfl)

@@ -424,6 +424,47 @@ def test_rotation_and_mirror_equivariance(orc, scheme):
     assert np.max(np.abs(Rm - expect)) <= 1e-12 * np.abs(R).max()
 
 
+def test_ghost_vertices_keep_their_state(orc):
+    """Section 3.5: ghost vertices never change from their initial state,
+    also when the flow next to them does."""
+    m = I.split_square(15, periodic=(False, True), bc=("ghost", "ghost"), diagonal="random", seed=12)
+    om = orc.OracleMesh(m)
+    W = I.random_smooth_state(m, seed=21, amp=0.2)
+    g = m["ghost"].astype(bool)
+    assert g.any() and (~g).any()
+    for scheme, order in ((0, 1), (2, 2), (1, 2)):
+        W1 = W
+        for _ in range(3):
+            W1 = om.step(W1, om.max_dt(W1, 0.4), scheme, order)
+        assert np.array_equal(W1[:, g], W[:, g])
+        assert np.abs(W1[:, ~g] - W[:, ~g]).max() > 1e-6
+
+
+def _advect_error(orc, N, scheme, order, t_end=0.5):
+    m = I.split_square(N)
+    om = orc.OracleMesh(m)
+    W = I.ic_advected_sine(m)
+    t = 0.0
+    while t < t_end * (1 - 1e-14):
+        dt = min(om.max_dt(W, 0.4), t_end - t)
+        W = om.step(W, dt, scheme, order)
+        t += dt
+    exact = 1.0 + 0.1 * np.sin(2.0 * np.pi * (m["x"] - 1.0 * t_end))  # density carried at u = 1
+    return np.mean(np.abs(W[0] - exact))
+
+
+def test_convergence_orders_on_smooth_advection(orc):
+    """A density wave carried by a uniform flow (an exact Euler solution):
+    LDA with the RK2 scheme of Section 3.4 converges at second order; the N
+    scheme with forward Euler at first order."""
+    e = [_advect_error(orc, N, orc.LDA, orc.RK2) for N in (17, 33, 65)]
+    p = np.log2(e[1] / e[2])
+    assert 1.7 < p < 2.4, (e, p)
+    e1 = [_advect_error(orc, N, orc.N, orc.EULER1) for N in (17, 33, 65)]
+    p1 = np.log2(e1[1] / e1[2])
+    assert 0.6 < p1 < 1.3, (e1, p1)
+
+
 # ------------------------------------------------------------ Sod tube ----
 
 def sod_strip(nx):
