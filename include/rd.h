@@ -163,10 +163,13 @@ rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int schem
                           const double* lam_np1, double* lam_n, int on_device);
 
 /* Many independent meshes advanced together. The batch keeps its own copy of
- * the meshes' geometry; rd_batch_run takes each mesh's current state, runs
- * n_steps steps in one captured HIP graph (per-mesh CFL dt each step, computed
- * on the device) and writes the states back to the meshes. Meshes must share
- * gamma and must not be periodic. */
+ * the meshes' geometry and its own HIP stream (a null stream cannot be
+ * captured); rd_batch_run is ordered after pending work on `stream` and on the
+ * members' streams, takes each mesh's current state, runs n_steps steps in one
+ * captured HIP graph (per-mesh CFL dt each step, computed on the device),
+ * writes the states back to the meshes, and makes those streams wait for it.
+ * Enqueues only. Meshes must share gamma and device and must not be periodic;
+ * each mesh's result is bitwise what its own rd_step_cfl would give. */
 rd_status rd_batch_create(rd_mesh* const* meshes, int n_meshes, void* stream, rd_batch** out);
 rd_status rd_batch_run(rd_batch* batch, int n_steps, double cfl, int scheme, int time, int precision);
 rd_status rd_batch_destroy(rd_batch* batch);

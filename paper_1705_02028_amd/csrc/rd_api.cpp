@@ -648,7 +648,9 @@ struct rd_batch {
   rd_mesh* flat = nullptr;
   std::vector<rd_mesh*> members;
   std::vector<int64_t> voff, toff;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // the caller's stream
+  hipStream_t own = nullptr;     // the batch's own stream (a null stream cannot be captured)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   struct Graph {
     int n_steps, scheme, time, fp32;
     double cfl;
@@ -709,9 +711,22 @@ RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd
   desc.wall_edges = wall.empty() ? nullptr : wall.data();
   desc.gamma = gamma;
   DeviceGuard g(meshes[0]->device);
+  hipStream_t own = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+  if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev_out, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(own);
+    return fail(RD_EDEVICE, "hipEventCreate failed");
+  }
   rd_mesh* flat = nullptr;
-  rd_status st = rd_mesh_create(&desc, stream, &flat);
-  if (st != RD_OK) return st;
+  rd_status st = rd_mesh_create(&desc, own, &flat);
+  if (st != RD_OK) {
+    (void)hipEventDestroy(ev_in);
+    (void)hipEventDestroy(ev_out);
+    (void)hipStreamDestroy(own);
+    return st;
+  }
   // mesh ids, per-mesh time steps, per-mesh CFL segments
   std::vector<int32_t> vm(voff.back()), tm(toff.back()), v0, v1, b0{0};
   for (int k = 0; k < n; ++k) {
@@ -746,6 +761,9 @@ RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd
   b->voff = voff;
   b->toff = toff;
   b->stream = static_cast<hipStream_t>(stream);
+  b->own = own;
+  b->ev_in = ev_in;
+  b->ev_out = ev_out;
   *out = b;
   return RD_OK;
 }
@@ -760,11 +778,17 @@ RD_API rd_status rd_batch_run(rd_batch* b, int n_steps, double cfl, int scheme, 
   DeviceGuard g(f->device);
   const int fp32 = precision == RD_FP32_ACC64;
   if ((st = ensure_prec(f, fp32)) != RD_OK) return st;
-  hipStream_t s = f->stream;
-  // members' states in (ordered after each member's pending work)
+  hipStream_t s = f->stream;  // the batch's own stream
+  // order after the caller's and the members' pending work
+  std::vector<hipStream_t> outer{b->stream};
+  for (rd_mesh* m : b->members)
+    if (std::find(outer.begin(), outer.end(), m->stream) == outer.end()) outer.push_back(m->stream);
+  for (hipStream_t o : outer) {
+    HIPCHK(hipEventRecord(b->ev_in, o));
+    HIPCHK(hipStreamWaitEvent(s, b->ev_in, 0));
+  }
   for (size_t k = 0; k < b->members.size(); ++k) {
     rd_mesh* m = b->members[k];
-    if (m->stream != s) HIPCHK(hipStreamSynchronize(m->stream));
     HIPCHK(rd::launch_copy4(f->d.W + b->voff[k], m->d.W, m->d.nv, s));
   }
   HIPCHK(rd::launch_set_int(f->d.flag, 0, s));
@@ -794,19 +818,21 @@ RD_API rd_status rd_batch_run(rd_batch* b, int n_steps, double cfl, int scheme, 
     HIPCHK(rd::launch_copy4(m->d.W, f->d.W + b->voff[k], m->d.nv, s));
     HIPCHK(rd::launch_or_int(m->d.flag, f->d.flag, s));
     m->zprec = -1;
-    if (m->stream != s) HIPCHK(hipStreamSynchronize(s));
   }
+  HIPCHK(hipEventRecord(b->ev_out, s));
+  for (hipStream_t o : outer) HIPCHK(hipStreamWaitEvent(o, b->ev_out, 0));
   return RD_OK;
 }
 
 RD_API rd_status rd_batch_destroy(rd_batch* b) {
   if (!b) return RD_OK;
-  {
-    DeviceGuard g(b->flat->device);
-    (void)hipStreamSynchronize(b->flat->stream);
-    destroy_graphs(b);
-  }
+  DeviceGuard g(b->flat->device);
+  (void)hipStreamSynchronize(b->own);
+  destroy_graphs(b);
   rd_mesh_destroy(b->flat);
+  (void)hipEventDestroy(b->ev_in);
+  (void)hipEventDestroy(b->ev_out);
+  (void)hipStreamDestroy(b->own);
   delete b;
   return RD_OK;
 }

@@ -17,47 +17,17 @@ __device__ __forceinline__ int64_t xcd_block() {
   return x * q + (x < r ? x : r) + b / 8;
 }
 
-// Minimum waves per SIMD the triangle kernels are compiled for, and how far
-// ahead each thread loads: 2 = vertex records of the next triangle and ids
-// of the one after; 1 = ids of the next triangle only (FP64 stage 2, whose
-// registers leave no room for more without spilling).
+// Minimum waves per SIMD the triangle kernels are compiled for.
 template <typename R> struct TriWaves { static constexpr int value = 2; };
-template <> struct TriWaves<float> { static constexpr int value = 3; };
-template <typename R, int STAGE> struct TriPipe { static constexpr int value = 2; };
-template <> struct TriPipe<double, 2> { static constexpr int value = 1; };
+template <> struct TriWaves<float> { static constexpr int value = 4; };
 
-// Persistent triangle pass: the grid holds as many workgroups as are
-// resident at once; at sweep i, workgroup w handles the kBlock triangles of
-// row i * gridDim + w (w numbered XCD by XCD), so the whole GPU walks one
-// contiguous window of triangles and the vertex records and CSR lines it
-// touches stay in L2. Each thread keeps a pipeline: while it computes one
-// triangle it has the vertex records of its next triangle (PIPE 2) and the
-// corner ids of the one after in flight.
+// One thread per triangle. (A persistent grid with the next triangle's loads
+// software-pipelined was measured slower: fewer waves in flight and, with
+// per-workgroup chunks, scattered working sets.)
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
-__global__ __launch_bounds__(kBlock, TriWaves<R>::value) void k_tri(Dev d, int64_t stride) {
-  constexpr int PIPE = TriPipe<R, STAGE>::value;
-  const int64_t nt = d.nt;
-  int64_t t = xcd_block() * kBlock + threadIdx.x;
-  TriIn<R> cur, nxt;
-  if (t < nt) {
-    tri_load_ids<R>(t, d, cur);
-    tri_load_verts<R, CFL>(d, cur);
-  }
-  if (t + stride < nt) tri_load_ids<R>(t + stride, d, nxt);
-  for (; t < nt; t += stride) {
-    TriIn<R> after;
-    if (PIPE == 2) {
-      if (t + stride < nt) tri_load_verts<R, CFL>(d, nxt);
-      if (t + 2 * stride < nt) tri_load_ids<R>(t + 2 * stride, d, after);
-    }
-    tri_compute<R, SCHEME, STAGE, SAVE, CFL>(t, cur, d);
-    if (PIPE == 1) {
-      if (t + stride < nt) tri_load_verts<R, CFL>(d, nxt);
-      if (t + 2 * stride < nt) tri_load_ids<R>(t + 2 * stride, d, after);
-    }
-    cur = nxt;
-    nxt = after;
-  }
+__global__ __launch_bounds__(kBlock, TriWaves<R>::value) void k_tri(Dev d) {
+  const int64_t t = xcd_block() * kBlock + threadIdx.x;
+  if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE, CFL>(t, d);
 }
 
 template <typename R, int MODE>
@@ -210,30 +180,9 @@ hipError_t launch_soa_to_aos(const double* soa, D4* dst, int64_t n, hipStream_t 
   return hipGetLastError();
 }
 
-// Grid of the persistent triangle pass: as many workgroups as the device
-// holds at once for this kernel (queried once per kernel).
-template <typename K>
-static unsigned resident_groups(K kernel) {
-  static int n = 0;
-  if (n == 0) {
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1)
-      per_cu = 1;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-      cus = 256;
-    n = per_cu * cus;
-  }
-  return (unsigned)n;
-}
-
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
 static hipError_t tri_launch(const Dev& d, hipStream_t s) {
-  auto kern = k_tri<R, SCHEME, STAGE, SAVE, CFL>;
-  const int64_t rows = (d.nt + kBlock - 1) / kBlock;
-  int64_t groups = resident_groups(kern);
-  if (groups > rows) groups = rows;
-  hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(kBlock), 0, s, d, groups * kBlock);
+  hipLaunchKernelGGL((k_tri<R, SCHEME, STAGE, SAVE, CFL>), dim3(nblk(d.nt)), dim3(kBlock), 0, s, d);
   return hipGetLastError();
 }
 
