@@ -24,8 +24,8 @@ struct AdjDev {
   D4* lamS = nullptr;        // [nv] dL/dW*
   D4* lamN = nullptr;        // [nv] running dL/dW^n (output)
   D4* Zn = nullptr;          // [nv] parameter vectors at W^n
-  D4* cZ = nullptr;          // [3nt] corner cotangent of Z (CSR order)
-  D4* cW = nullptr;          // [3nt] corner cotangent of W* - W^n (CSR order)
+  D4* cZ = nullptr;          // [ns] corner cotangent of Z (sliced part layout)
+  D4* cW = nullptr;          // [ns] corner cotangent of W* - W^n (sliced part layout)
   D4* kN = nullptr;          // [3nt] cotangent of kept stage-1 N parts (triangle order)
   D4* kT = nullptr;          // [nt] cotangent of kept stage-1 residual
   D4* wcbar = nullptr;       // [nwv] cotangent of the wall term at W^n (stage 1 + half of stage 2)
@@ -636,7 +636,9 @@ __host__ __device__ inline void wall_bar(const Dev& d, int64_t v, const D4* src,
 // Reverse of the stage-2 vertex sums: dL/dW* and the W^n part of W* - W^n.
 __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const AdjDev& a) {
   double zb[4] = {0, 0, 0, 0}, wb[4] = {0, 0, 0, 0};
-  for (int32_t s = d.row[v]; s < d.row[v + 1]; ++s) {
+  const int32_t deg = d.row[v + 1] - d.row[v];
+  for (int32_t j = 0; j < deg; ++j) {
+    const int64_t s = d.sbeg[v] + 64 * (int64_t)j;
     const D4 cz = a.cZ[s], cw = a.cW[s];
     for (int k = 0; k < 4; ++k) {
       zb[k] += cz.v[k];
@@ -658,8 +660,9 @@ __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const 
 // structure-of-arrays to out.
 __host__ __device__ inline void adj_gather1_body(int64_t v, const Dev& d, const AdjDev& a, bool rk2, double* out) {
   double zb[4] = {0, 0, 0, 0};
-  for (int32_t s = d.row[v]; s < d.row[v + 1]; ++s) {
-    const D4 cz = a.cZ[s];
+  const int32_t deg = d.row[v + 1] - d.row[v];
+  for (int32_t j = 0; j < deg; ++j) {
+    const D4 cz = a.cZ[d.sbeg[v] + 64 * (int64_t)j];
     for (int k = 0; k < 4; ++k) zb[k] += cz.v[k];
   }
   const D4 w = d.W[v], ls = a.lamS[v], ln = a.lamN[v];

@@ -149,7 +149,7 @@ rd_status ensure_prec(rd_mesh* m, int fp32) {
   const int64_t nt = m->d.nt, nv = m->d.nv;
   char* p = nullptr;
   rd_status st;
-  if ((st = dalloc(m, &p, q * 3 * nt)) != RD_OK) return st;
+  if ((st = dalloc(m, &p, q * m->d.ns)) != RD_OK) return st;
   m->C[fp32] = p;
   if ((st = dalloc(m, &p, q * 3 * nt)) != RD_OK) return st;
   m->keepN[fp32] = p;
@@ -325,18 +325,34 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
     DeviceGuard g(m->device);
     std::vector<double2> xy(nv);
     for (int64_t i = 0; i < nv; ++i) xy[i] = make_double2(m->x[i], m->y[i]);
-    std::vector<int32_t> tv(3 * nt), pos(3 * nt);
+    std::vector<int32_t> tv(3 * nt), pos(3 * nt), sbeg(nv);
     for (int64_t t = 0; t < nt; ++t)
       for (int k = 0; k < 3; ++k) tv[k * nt + t] = m->tri[3 * t + k];
-    for (int64_t s = 0; s < 3 * nt; ++s) {
-      const int32_t cs = m->slot[s];  // corner 3 t + k sits at CSR position s
-      pos[(cs % 3) * nt + cs / 3] = (int32_t)s;
+    // sliced part layout: 64-vertex slices, each as wide as its largest degree
+    int64_t base = 0;
+    for (int64_t g0 = 0; g0 < nv; g0 += 64) {
+      const int64_t g1 = std::min<int64_t>(g0 + 64, nv);
+      int32_t width = 0;
+      for (int64_t v = g0; v < g1; ++v) width = std::max(width, m->row[v + 1] - m->row[v]);
+      for (int64_t v = g0; v < g1; ++v) sbeg[v] = (int32_t)(base + (v - g0));
+      base += 64 * (int64_t)width;
     }
+    if (base >= (int64_t(1) << 31)) {
+      free_all(m);
+      delete m;
+      return fail(RD_EINVAL, "mesh too large for 32-bit part slots");
+    }
+    d.ns = base;
+    for (int64_t v = 0; v < nv; ++v)
+      for (int32_t j = 0; j < m->row[v + 1] - m->row[v]; ++j) {
+        const int32_t cs = m->slot[m->row[v] + j];  // corner 3 t + k is the j-th part of v
+        pos[(cs % 3) * nt + cs / 3] = sbeg[v] + 64 * j;
+      }
     double2* pxy;
     double* pV;
-    int32_t *prow, *ptv, *ppos;
+    int32_t *prow, *ptv, *ppos, *psbeg;
     if ((st = upload(m, &pxy, xy)) || (st = upload(m, &pV, m->V)) || (st = upload(m, &prow, m->row)) ||
-        (st = upload(m, &ptv, tv)) || (st = upload(m, &ppos, pos))) {
+        (st = upload(m, &ptv, tv)) || (st = upload(m, &ppos, pos)) || (st = upload(m, &psbeg, sbeg))) {
       free_all(m);
       delete m;
       return st;
@@ -346,6 +362,7 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
     d.row = prow;
     d.tv = ptv;
     d.pos = ppos;
+    d.sbeg = psbeg;
     if (has_bc) {
       int32_t *pbc, *pwv, *pwptr;
       rd::WallEnt* pwent;
@@ -372,7 +389,7 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
     double *sig, *lam, *dt, *scratch;
     int* flag;
     if ((st = dalloc(m, &W, nv)) || (st = dalloc(m, &Ws, nv)) || (st = dalloc(m, &Z, nv)) ||
-        (st = dalloc(m, &sig, nv)) || (st = dalloc(m, &lam, 3 * nt)) || (st = dalloc(m, &dt, 1)) ||
+        (st = dalloc(m, &sig, nv)) || (st = dalloc(m, &lam, d.ns)) || (st = dalloc(m, &dt, 1)) ||
         (st = dalloc(m, &flag, 1)) || (st = dalloc(m, &scratch, 4 * std::max(nv, nt)))) {
       free_all(m);
       delete m;
@@ -585,7 +602,7 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     rd::D4 *lamIn, *lamS, *lamN, *Zn, *cZ, *cW, *kN, *kT, *Wa;
     double *in, *out;
     if ((st = dalloc(m, &lamIn, nv)) || (st = dalloc(m, &lamS, nv)) || (st = dalloc(m, &lamN, nv)) ||
-        (st = dalloc(m, &Zn, nv)) || (st = dalloc(m, &cZ, 3 * nt)) || (st = dalloc(m, &cW, 3 * nt)) ||
+        (st = dalloc(m, &Zn, nv)) || (st = dalloc(m, &cZ, m->d.ns)) || (st = dalloc(m, &cW, m->d.ns)) ||
         (st = dalloc(m, &kN, 3 * nt)) || (st = dalloc(m, &kT, nt)) || (st = dalloc(m, &Wa, nv)) ||
         (st = dalloc(m, &in, 4 * nv)) || (st = dalloc(m, &out, 4 * nv)))
       return st;

@@ -9,9 +9,12 @@
 // ascending triangle order (no atomics), adds the wall term and updates the
 // state, then refreshes the parameter vector and signal speed of the vertex.
 //
-// The triangle passes write each corner's part straight to that corner's
-// position in the vertex CSR (the inverse of the CSR's slot list), so a
-// vertex's parts are contiguous and the gather streams them.
+// Parts are stored sliced: vertices are taken 64 at a time (one wavefront of
+// the gather), a slice is as wide as its largest vertex degree, and the j-th
+// part (ascending triangle order) of the slice's l-th vertex sits at
+// slice_base + 64 j + l. The triangle passes write each corner's part
+// straight to its slot; the gather's j-th load is then one contiguous,
+// fully coalesced read across the wavefront.
 //
 // Algebra used on the GPU (equal in exact arithmetic to Appendix A's explicit
 // entries): with unit normal n, Roe state (u, v, h, c), w = u n_x + v n_y,
@@ -59,10 +62,12 @@ struct Dev {
   // geometry and connectivity
   const double2* xy = nullptr;   // [nv]
   const double* V = nullptr;     // [nv] vertex volume
-  const int32_t* row = nullptr;  // [nv+1] CSR row pointers
+  const int32_t* row = nullptr;  // [nv+1] CSR row pointers (row[v+1] - row[v] = degree of v)
+  const int32_t* sbeg = nullptr; // [nv] first part slot of v; its j-th part is at sbeg[v] + 64 j
+  int64_t ns = 0;                // part slots, including the padding of the 64-vertex slices
   const int32_t* bc = nullptr;   // [nv] or null: boundary code, see is_ghost / wall_index
   const int32_t* tv = nullptr;   // [3][nt] corner vertex ids
-  const int32_t* pos = nullptr;  // [3][nt] CSR position of corner (t, i): slot[pos] = 3 t + i
+  const int32_t* pos = nullptr;  // [3][nt] part slot of corner (t, i)
   const int32_t* wv = nullptr;   // [nwv] wall vertex ids
   const int32_t* wptr = nullptr; // [nwv+1]
   const WallEnt* went = nullptr; // wall incidences, ascending edge id per vertex
@@ -76,12 +81,12 @@ struct Dev {
   void* dW = nullptr; // [nv] W* - W^n (D4 or F4)
   double* sig = nullptr;   // [nv] |v| + c
   // triangle buffers
-  void* C = nullptr;      // [3nt] distributed parts in CSR order (D4 or F4)
+  void* C = nullptr;      // [ns] distributed parts, sliced layout (D4 or F4)
   void* keepN = nullptr;  // [3nt] stage-1 N parts (D4 or F4)
   void* keepT = nullptr;  // [nt] stage-1 triangle residual (D4 or F4)
   D4* WCn = nullptr;      // [nwv] wall term at W^n
   D4* WCs = nullptr;      // [nwv] wall term at W*
-  double* lam = nullptr;  // [3nt] l_max^T lambda_max^T in CSR order
+  double* lam = nullptr;  // [ns] l_max^T lambda_max^T, sliced layout
   double* dt = nullptr;   // [n meshes] time step
   int* flag = nullptr;    // non-physical state latch
 };
@@ -544,9 +549,10 @@ __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out
   }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double cmp[4] = {0.0, 0.0, 0.0, 0.0};
-  const int32_t r0 = d.row[v], r1 = d.row[v + 1];
-  for (int32_t s = r0; s < r1; ++s) {
-    const Q4<R> c = ld4<R>(d.C, s);
+  const int32_t deg = d.row[v + 1] - d.row[v];
+  const int64_t s0 = d.sbeg[v];
+  for (int32_t j = 0; j < deg; ++j) {
+    const Q4<R> c = ld4<R>(d.C, s0 + 64 * (int64_t)j);
     for (int k = 0; k < 4; ++k) {
       if (sizeof(R) == sizeof(double)) {
         acc[k] += (double)c.v[k];
@@ -641,7 +647,9 @@ __host__ __device__ inline void cfl_tri_body(int64_t t, const Dev& d) {
 // 2 V_i / sum_{T ni i} l_max lambda_max of one vertex.
 __host__ __device__ inline double cfl_vertex_bound(int64_t v, const Dev& d) {
   double acc = 0.0;
-  for (int32_t s = d.row[v]; s < d.row[v + 1]; ++s) acc += d.lam[s];
+  const int32_t deg = d.row[v + 1] - d.row[v];
+  const int64_t s0 = d.sbeg[v];
+  for (int32_t j = 0; j < deg; ++j) acc += d.lam[s0 + 64 * (int64_t)j];
   return 2.0 * d.V[v] / acc;
 }
 
