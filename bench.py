@@ -37,14 +37,40 @@ def algorithmic_bytes(nt, nv, fp32):
     # parts, kept N parts, phi^T and l_max lambda_max per corner out
     k["tri1"] = nt * (12 + 12 + 3 * r4 + 3 * r4 + r4 + 24) + nv * (16 + r4 + 8)
     # CFL: CSR rows, V and the per-corner l_max lambda_max in, block minima out
-    k["cfl_vertex"] = nv * (4 + 8) + nt * 24
-    k["cfl_final"] = 0
+    k["shared1"] = 0
+    k["cfl"] = nv * (4 + 8) + nt * 24
     # gather 1: rows, parts in; W, V in; W*, W*-W, Z*, |v|+c out
     k["gather1"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + r4 + 8)
     # stage 2: ids, positions, coordinates, Z*, W*-W, kept N parts, phi^T in; parts out
     k["tri2"] = nt * (12 + 12 + 3 * r4 + r4 + 3 * r4) + nv * (16 + r4 + r4)
     # gather 2: rows, parts in; W*, V in; W, Z, |v|+c out
     k["gather2"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + 8)
+    k["wall1"] = k["wall2"] = 0
+    return k
+
+
+def algorithmic_bytes_tiled(nt, nv, fp32, info):
+    """The same for the tiled form. info = rd_mesh_tile_info: L local vertex
+    records over all tiles (a vertex on a tile border is loaded by each of its
+    tiles), S shared vertices, P their parts; I = nv - S vertices are finished
+    inside their tile. Parts of interior vertices never leave LDS."""
+    q = 4 if fp32 else 8
+    r4 = 4 * q
+    L, S, P = info["local_vertices"], info["shared_vertices"], info["shared_parts"]
+    I = nv - S
+    k = {}
+    # tile pass 1: corner tables, vertex records (id, xy, Z, |v|+c) in; kept N parts and phi^T,
+    # interior R1 and CFL bound, shared parts and l_max lambda_max out
+    k["tri1"] = nt * (18 + 3 * r4 + r4) + L * (4 + 16 + r4 + 8) + I * (4 + 8 + 32 + 8) + P * (r4 + 8)
+    # shared pass 1: ids, slots, rows, V in; parts and CFL terms in; R1 and CFL bound out
+    k["shared1"] = S * (4 + 4 + 8 + 8 + 32 + 8) + P * (r4 + 8)
+    k["cfl"] = nv * 8
+    k["gather1"] = 0
+    # tile pass 2: corner tables, kept N parts and phi^T, vertex records (id, xy, W, R1, V) in;
+    # interior W, Z, |v|+c and shared parts out
+    k["tri2"] = nt * (18 + 3 * r4 + r4) + L * (4 + 16 + 32 + 32 + 8) + I * (4 + 32 + r4 + 8) + P * r4
+    # shared pass 2: ids, slots, rows, V, W, R1, parts in; W, Z, |v|+c out
+    k["gather2"] = S * (4 + 4 + 8 + 8 + 32 + 32 + 32 + r4 + 8) + P * r4
     k["wall1"] = k["wall2"] = 0
     return k
 
@@ -56,9 +82,16 @@ def roofline_entry(name, bytes_, ms):
             "algorithmic_bytes": int(bytes_), "avg_ms": round(ms, 5)}
 
 
-def time_variant(rd, torch, mesh, W0, prec, steps, warmup, cfl, timed_reps):
+def time_variant(rd, torch, mesh, W0, prec, steps, warmup, cfl, timed_reps, tile):
     g = rd.Mesh(mesh)
     g.set_state(W0)
+    tuned = None
+    if tile < 0:
+        best, table = g.tune(cfl, rd.B, rd.RK2, prec, n_steps=3)
+        tuned = {"chosen": best, "ms_per_step": {str(k): round(v, 5) for k, v in table.items()}}
+    else:
+        g.tile = tile
+    info = rd.rd_mesh_tile_info(g.h)
     if warmup:
         g.step_cfl(warmup, cfl, rd.B, rd.RK2, prec)
     torch.cuda.synchronize()
@@ -76,15 +109,21 @@ def time_variant(rd, torch, mesh, W0, prec, steps, warmup, cfl, timed_reps):
         for k, v in t.items():
             per[k] = per.get(k, 0.0) + v / max(timed_reps, 1)
     g.sync()
+    tile_used = g.tile
     g.close()
-    return ms, per
+    return ms, per, {"tile": tile_used, "tuner": tuned, "tile_info": info}
 
 
-def adjoint_ratio(rd, torch, mesh, W0, cfl, reps):
+def adjoint_ratio(rd, torch, mesh, W0, cfl, reps, tile):
     """time(rd_adjoint_step) / time(rd_step) on the same mesh, FP64, B / RK2,
-    fixed dt, device-resident states; each timed over `reps` calls."""
+    fixed dt, device-resident states; each timed over `reps` calls. The
+    forward step runs in the form the tuner picks (tile < 0) or `tile`."""
     g = rd.Mesh(mesh)
     g.set_state(W0)
+    if tile < 0:
+        g.tune(cfl, rd.B, rd.RK2, rd.FP64, n_steps=3)
+    else:
+        g.tile = tile
     dt = g.max_dt(cfl)
     W = torch.from_numpy(W0).cuda()
     lam = torch.randn_like(W)
@@ -104,18 +143,31 @@ def adjoint_ratio(rd, torch, mesh, W0, cfl, reps):
     torch.cuda.synchronize()
     fwd = e[0].elapsed_time(e[1]) / reps
     adj = e[1].elapsed_time(e[2]) / reps
+    out = {"ratio": round(adj / fwd, 3), "forward_ms": round(fwd, 4), "adjoint_ms": round(adj, 4),
+           "triangles": mesh["nt"], "forward_tile": g.tile}
     g.close()
-    return {"ratio": round(adj / fwd, 3), "forward_ms": round(fwd, 4), "adjoint_ms": round(adj, 4),
-            "triangles": mesh["nt"]}
+    return out
 
 
-def batch_vs_single(rd, torch, inputs, n_meshes, steps, cfl, seed=0):
+def batch_vs_single(rd, torch, inputs, n_meshes, steps, cfl, tile, seed=0):
     """Four-quadrant problems of uneven size: per-mesh rd_step_cfl launches vs
-    one rd_batch_run graph, FP64, B / RK2; results are bitwise equal."""
+    one rd_batch_run graph, FP64, B / RK2, the same tile size for both (the
+    batch autotuner's choice when tile < 0); results are bitwise equal."""
     import numpy as np
     meshes, states = inputs.batch_problem(seed=seed, n=n_meshes)
     nt = sum(m["nt"] for m in meshes)
     gm = [rd.Mesh(m) for m in meshes]
+    b = rd.Batch(gm)
+    tuned = None
+    if tile < 0:
+        for g, W in zip(gm, states):
+            g.set_state(W)
+        tile, table = b.tune(cfl, rd.B, rd.RK2, rd.FP64, n_steps=steps)
+        tuned = {str(k): round(v, 5) for k, v in table.items()}
+    else:
+        b.set_tile(tile)
+    for g in gm:
+        g.tile = tile
     for g, W in zip(gm, states):
         g.set_state(W)
         g.step_cfl(1, cfl, rd.B, rd.RK2, rd.FP64)   # warm-up
@@ -129,7 +181,6 @@ def batch_vs_single(rd, torch, inputs, n_meshes, steps, cfl, seed=0):
     torch.cuda.synchronize()
     single = time.perf_counter() - t0
     ref = [g.get_state() for g in gm]
-    b = rd.Batch(gm)
     for g, W in zip(gm, states):
         g.set_state(W)
     b.run(steps, cfl, rd.B, rd.RK2, rd.FP64)       # captures the graph
@@ -147,7 +198,7 @@ def batch_vs_single(rd, torch, inputs, n_meshes, steps, cfl, seed=0):
     return {"meshes": n_meshes, "triangles": nt, "steps": steps,
             "per_instance_s": round(single, 4), "batched_graph_s": round(batched, 4),
             "speedup": round(single / batched, 3), "bitwise_equal": bool(equal),
-            "batched_value": round(nt * steps / batched, 1)}
+            "batched_value": round(nt * steps / batched, 1), "tile": tile, "tuner_ms_per_step": tuned}
 
 
 def _err(a, b):
@@ -187,7 +238,7 @@ def fp32_table(rd, inputs):
         ("Kelvin-Helmholtz 2048^2, B / RK2, 500 steps", inputs.split_square(2048),
          lambda m: inputs.ic_kelvin_helmholtz(m, seed=0), rd.B, rd.RK2, 0.4, 500, None),
         ("four-quadrant 512^2, B / RK2, 200 steps", inputs.split_square(512, periodic=(False, False)),
-         lambda m: inputs.ic_quadrants(m, inputs.quadrant_states(0)), rd.B, rd.RK2, 0.4, 200, None),
+         lambda m: inputs.ic_quadrants(m, inputs.quadrant_states(0, **inputs.BATCH_QUADRANTS)), rd.B, rd.RK2, 0.4, 200, None),
         ("Fourier density 256^2, B / RK2, 200 steps", inputs.split_square(256),
          lambda m: inputs.ic_fourier_density(m, seed=0), rd.B, rd.RK2, 0.4, 200, None),
     ]
@@ -234,6 +285,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--timed-reps", type=int, default=5)
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="triangles per tile of the fused step (0: two-pass form; -1: run the autotuner)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batch", type=int, default=0, metavar="NMESH",
                     help="also time NMESH four-quadrant meshes (32^2..512^2) per instance vs one batched graph")
@@ -267,10 +320,11 @@ def main():
     nt, nv = mesh["nt"], mesh["nv"]
 
     print(f"bench: mesh {args.N}^2, {nt} triangles; fp32-acc64 {args.steps} steps", file=sys.stderr, flush=True)
-    ms32, per32 = time_variant(rd, torch, mesh, W0, rd.FP32_ACC64, args.steps, args.warmup, args.cfl,
-                               args.timed_reps)
+    ms32, per32, form32 = time_variant(rd, torch, mesh, W0, rd.FP32_ACC64, args.steps, args.warmup, args.cfl,
+                                       args.timed_reps, args.tile)
     value = nt * args.steps / (ms32 * 1e-3)
-    b32 = algorithmic_bytes(nt, nv, True)
+    b32 = (algorithmic_bytes_tiled(nt, nv, True, form32["tile_info"]) if form32["tile"]
+           else algorithmic_bytes(nt, nv, True))
     dom32 = max(per32, key=per32.get)
     result = {
         "metric": "triangle-updates/sec (FP64 & FP32) at 2048^2 mesh; adjoint/forward time ratio",
@@ -291,29 +345,33 @@ def main():
                    "triangles": nt, "vertices": nv, "seed": 0},
         "roofline": roofline_entry(dom32, b32[dom32], per32[dom32]),
         "kernels_ms": {k: round(v, 5) for k, v in per32.items()},
-        "kernels_GBps": {k: round(b32[k] / (v * 1e-3) / 1e9, 1) for k, v in per32.items() if v > 0 and b32[k]},
+        "kernels_GBps": {k: round(b32[k] / (v * 1e-3) / 1e9, 1) for k, v in per32.items()
+                         if v > 0 and b32.get(k)},
+        "form": form32,
     }
     if not args.no_fp64:
         print(f"bench: fp64 {args.steps} steps", file=sys.stderr, flush=True)
-        ms64, per64 = time_variant(rd, torch, mesh, W0, rd.FP64, args.steps, args.warmup, args.cfl,
-                                   args.timed_reps)
-        b64 = algorithmic_bytes(nt, nv, False)
+        ms64, per64, form64 = time_variant(rd, torch, mesh, W0, rd.FP64, args.steps, args.warmup, args.cfl,
+                                           args.timed_reps, args.tile)
+        b64 = (algorithmic_bytes_tiled(nt, nv, False, form64["tile_info"]) if form64["tile"]
+               else algorithmic_bytes(nt, nv, False))
         dom64 = max(per64, key=per64.get)
         result["fp64"] = {"value": round(nt * args.steps / (ms64 * 1e-3), 1), "unit": "triangle-updates/s",
                           "ms_per_step": round(ms64 / args.steps, 5),
                           "roofline": roofline_entry(dom64, b64[dom64], per64[dom64]),
                           "kernels_ms": {k: round(v, 5) for k, v in per64.items()},
                           "kernels_GBps": {k: round(b64[k] / (v * 1e-3) / 1e9, 1)
-                                           for k, v in per64.items() if v > 0 and b64[k]}}
+                                           for k, v in per64.items() if v > 0 and b64.get(k)},
+                          "form": form64}
     if not args.no_adjoint:
         print("bench: adjoint / forward", file=sys.stderr, flush=True)
-        result["adjoint_forward_ratio"] = adjoint_ratio(rd, torch, mesh, W0, args.cfl, 10)
+        result["adjoint_forward_ratio"] = adjoint_ratio(rd, torch, mesh, W0, args.cfl, 10, args.tile)
         m256 = inputs.split_square(256)
         result["adjoint_forward_ratio_256"] = adjoint_ratio(rd, torch, m256, inputs.ic_fourier_density(m256, seed=0),
-                                                            args.cfl, 20)
+                                                            args.cfl, 20, args.tile)
     if args.batch:
         print(f"bench: batch of {args.batch} meshes", file=sys.stderr, flush=True)
-        result["batch"] = batch_vs_single(rd, torch, inputs, args.batch, args.batch_steps, args.cfl)
+        result["batch"] = batch_vs_single(rd, torch, inputs, args.batch, args.batch_steps, args.cfl, args.tile)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(mesh, W0, args.cfl)

@@ -130,16 +130,20 @@ rd_status rd_step(rd_mesh* mesh, double dt, int scheme, int time, int precision)
  * computed on the device: no host synchronisation. Enqueues only. */
 rd_status rd_step_cfl(rd_mesh* mesh, int n_steps, double cfl, int scheme, int time, int precision);
 
-/* Kernels of one step, in launch order, as reported by rd_step_timed. */
+/* Kernel slots of one step, in launch order, as reported by rd_step_timed.
+ * Two-pass form: every part goes to HBM, a vertex gather sums it. Tiled
+ * form: a tile pass sums the parts of tile-interior vertices in LDS and a
+ * shared pass sums those of vertices on tile borders. */
 enum {
-  RD_K_WALL1 = 0,      /* wall term at W^n (meshes with walls) */
-  RD_K_TRI1 = 1,       /* triangle pass, stage 1 (also l_max lambda_max per corner) */
-  RD_K_CFL_VERTEX = 2, /* 2 V_i / sum per vertex, block minima */
-  RD_K_CFL_FINAL = 3,  /* minimum over blocks -> dt */
-  RD_K_GATHER1 = 4,    /* vertex sums and update, stage 1 */
-  RD_K_WALL2 = 5,      /* wall term at W* (RK2 with walls) */
-  RD_K_TRI2 = 6,       /* triangle pass, stage 2 (RK2) */
-  RD_K_GATHER2 = 7,    /* vertex sums and update, stage 2 (RK2) */
+  RD_K_WALL1 = 0,   /* wall term at W^n (meshes with walls) */
+  RD_K_TRI1 = 1,    /* stage-1 (or Euler) triangle pass; two-pass form: also l_max lambda_max per
+                       corner; tiled form: tile pass, also interior vertex residuals and CFL bounds */
+  RD_K_SHARED1 = 2, /* tiled form: shared-vertex residuals and CFL bounds */
+  RD_K_CFL = 3,     /* CFL reduction: per-vertex bounds, block and per-mesh minima -> dt */
+  RD_K_GATHER1 = 4, /* two-pass form: stage-1 vertex sums and update; tiled form: Euler update */
+  RD_K_WALL2 = 5,   /* wall term at W* (RK2 with walls) */
+  RD_K_TRI2 = 6,    /* stage-2 triangle pass (RK2); tiled form: also the interior vertex update */
+  RD_K_GATHER2 = 7, /* stage-2 vertex sums and update (RK2); tiled form: shared vertices only */
   RD_NKERNELS = 8
 };
 
@@ -148,6 +152,32 @@ enum {
  * duration of every kernel in milliseconds to ms[RD_NKERNELS] (0 for
  * kernels the step does not launch). For profiling. */
 rd_status rd_step_timed(rd_mesh* mesh, double cfl, int scheme, int time, int precision, double* ms);
+
+/* Form of the step (Sections 3.2-3.4 computed either way). tile_triangles
+ * = 0 selects the two-pass form. A value in [32, 1024] selects the tiled
+ * form: triangles are ordered along a Morton curve of their centroids and cut
+ * into tiles of that many triangles; one workgroup per tile stages the
+ * tile's vertex data in LDS and finishes the vertices all of whose
+ * triangles are in the tile. Every vertex sums its parts in ascending
+ * triangle order in both forms, so results are bitwise identical for every
+ * choice. RD_EUNSUPPORTED if a tile would need more LDS than a workgroup
+ * may use (64 KiB). Waits for the mesh's stream. The default is 0. */
+rd_status rd_mesh_set_tile(rd_mesh* mesh, int tile_triangles);
+rd_status rd_mesh_get_tile(const rd_mesh* mesh, int* tile_triangles);
+/* Shape of the current tiling (all zero in the two-pass form): info[0] tiles,
+ * info[1] local vertex records over all tiles (vertices on tile borders
+ * count once per tile), info[2] shared vertices, info[3] their parts
+ * (shared corners). */
+rd_status rd_mesh_tile_info(const rd_mesh* mesh, int64_t info[4]);
+
+/* Autotuner: for each of the n_candidates tile sizes (NULL: 0, 64, 128,
+ * 256, 512; unsupported sizes are skipped and report a negative time) runs
+ * one warm-up step and n_steps >= 1 timed steps (dt from `cfl`, as
+ * rd_step_cfl), writes milliseconds per step to ms_per_step (may be NULL,
+ * else n_candidates entries), selects the fastest size for the mesh and
+ * returns it in *best. The mesh's state is restored afterwards. Waits. */
+rd_status rd_tune(rd_mesh* mesh, double cfl, int scheme, int time, int precision, int n_steps,
+                  const int* candidates, int n_candidates, double* ms_per_step, int* best);
 
 /* Spatial residual at the current state (Section 3.2-3.3, FP64): R_i = sum
  * over the triangles of i (ascending triangle order) of the scheme's part
@@ -173,6 +203,13 @@ rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int schem
 rd_status rd_batch_create(rd_mesh* const* meshes, int n_meshes, void* stream, rd_batch** out);
 rd_status rd_batch_run(rd_batch* batch, int n_steps, double cfl, int scheme, int time, int precision);
 rd_status rd_batch_destroy(rd_batch* batch);
+/* Tile size of the batch's step (as rd_mesh_set_tile; tiles never straddle
+ * two meshes, so each member is tiled exactly as it would be alone). */
+rd_status rd_batch_set_tile(rd_batch* batch, int tile_triangles);
+/* Autotuner of a batch: as rd_tune, timing one replay of the captured
+ * n_steps-step graph per candidate; members' states are not changed. */
+rd_status rd_batch_tune(rd_batch* batch, double cfl, int scheme, int time, int precision, int n_steps,
+                        const int* candidates, int n_candidates, double* ms_per_step, int* best);
 
 /* Waits for the mesh's stream. RD_ENONPHYS if a non-physical state was
  * produced since the last rd_set_state (the flag stays set), RD_EDEVICE on a

@@ -11,6 +11,7 @@
 
 #include "rd.h"
 #include "rd_launch.h"
+#include "rd_tiling.h"
 
 #define RD_API extern "C" __attribute__((visibility("default")))
 
@@ -111,12 +112,18 @@ struct rd_mesh {
   double* adjIn = nullptr;    // [4 nv] host staging (W^n, then dL/dW^{n+1})
   double* adjOut = nullptr;   // [4 nv] dL/dW^n
   hipEvent_t events[RD_NKERNELS + 1] = {};
+  // tiled form
+  int tile = 0;                     // triangles per tile, 0: two-pass form
+  rd::Tiles tiles;
+  int64_t tile_info[4] = {0, 0, 0, 0};
+  std::vector<void*> tile_allocs;
+  std::vector<int64_t> voff, toff;  // vertex / triangle ranges of the meshes laid end to end
 };
 
 namespace {
 
 template <class T>
-rd_status dalloc(rd_mesh* m, T** p, size_t n) {
+rd_status dalloc_in(std::vector<void*>& list, T** p, size_t n) {
   void* q = nullptr;
   if (n == 0) n = 1;
   hipError_t e = hipMalloc(&q, n * sizeof(T));
@@ -124,22 +131,37 @@ rd_status dalloc(rd_mesh* m, T** p, size_t n) {
     *p = nullptr;
     return fail(RD_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
   }
-  m->allocs.push_back(q);
+  list.push_back(q);
   *p = static_cast<T*>(q);
   return RD_OK;
 }
 
 template <class T>
-rd_status upload(rd_mesh* m, T** p, const std::vector<T>& h) {
-  rd_status st = dalloc(m, p, h.size());
+rd_status dalloc(rd_mesh* m, T** p, size_t n) {
+  return dalloc_in(m->allocs, p, n);
+}
+
+template <class T>
+rd_status upload_in(std::vector<void*>& list, T** p, const std::vector<T>& h) {
+  rd_status st = dalloc_in(list, p, h.size());
   if (st != RD_OK) return st;
   if (!h.empty()) HIPCHK(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   return RD_OK;
 }
 
+template <class T>
+rd_status upload(rd_mesh* m, T** p, const std::vector<T>& h) {
+  return upload_in(m->allocs, p, h);
+}
+
+void free_list(std::vector<void*>& list) {
+  for (void* p : list) (void)hipFree(p);
+  list.clear();
+}
+
 void free_all(rd_mesh* m) {
-  for (void* p : m->allocs) (void)hipFree(p);
-  m->allocs.clear();
+  free_list(m->tile_allocs);
+  free_list(m->allocs);
 }
 
 // Buffers of one arithmetic precision, allocated on first use.
@@ -187,7 +209,22 @@ rd_status ensure_z(rd_mesh* m, int fp32) {
 // pass writes l_max lambda_max per corner, two small passes reduce it);
 // otherwise it is already in d.dt. With `ev` (RD_NKERNELS + 1 events) an
 // event is recorded before every kernel slot and after the last.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+rd_status run_step_tiled(rd_mesh* m, int scheme, int time, int fp32, double cfl, hipEvent_t* ev);
+
 rd_status run_step(rd_mesh* m, int scheme, int time, int fp32, double cfl, hipEvent_t* ev = nullptr) {
+  if (m->tile > 0) return run_step_tiled(m, scheme, time, fp32, cfl, ev);
   const rd::Dev d = dev_for(m, fp32);
   hipStream_t s = m->stream;
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
@@ -196,10 +233,12 @@ rd_status run_step(rd_mesh* m, int scheme, int time, int fp32, double cfl, hipEv
   HIPCHK(rd::launch_wall(d, false, s));
   HIPCHK(mark(RD_K_TRI1));
   HIPCHK(rd::launch_tri(d, fp32, scheme, 1, time == RD_RK2, with_cfl, s));
-  HIPCHK(mark(RD_K_CFL_VERTEX));
-  if (with_cfl) HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 1, s));
-  HIPCHK(mark(RD_K_CFL_FINAL));
-  if (with_cfl) HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 2, s));
+  HIPCHK(mark(RD_K_SHARED1));
+  HIPCHK(mark(RD_K_CFL));
+  if (with_cfl) {
+    HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 1, s));
+    HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 2, s));
+  }
   HIPCHK(mark(RD_K_GATHER1));
   HIPCHK(rd::launch_gather(d, fp32, time == RD_RK2 ? rd::G_STAGE1 : rd::G_EULER, nullptr, s));
   HIPCHK(mark(RD_K_WALL2));
@@ -218,24 +257,131 @@ rd_status run_step(rd_mesh* m, int scheme, int time, int fp32, double cfl, hipEv
   return RD_OK;
 }
 
+// The tiled form of the same step: the tile pass finishes interior vertices
+// (stage 1: their residual R1 and CFL bound; stage 2: their new state), the
+// shared pass the rest. Stage 1 stores R1 only; W* is rebuilt from it where
+// needed, after dt is known.
+rd_status run_step_tiled(rd_mesh* m, int scheme, int time, int fp32, double cfl, hipEvent_t* ev) {
+  const rd::Dev d = dev_for(m, fp32);
+  const rd::Tiles& tl = m->tiles;
+  hipStream_t s = m->stream;
+  auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
+  const bool with_cfl = cfl > 0.0, rk2 = time == RD_RK2;
+  HIPCHK(mark(RD_K_WALL1));
+  HIPCHK(rd::launch_wall(d, false, s));
+  HIPCHK(mark(RD_K_TRI1));
+  HIPCHK(rd::launch_tile(d, tl, fp32, scheme, 1, rk2, with_cfl, s));
+  HIPCHK(mark(RD_K_SHARED1));
+  HIPCHK(rd::launch_shared(d, tl, fp32, 1, with_cfl, s));
+  HIPCHK(mark(RD_K_CFL));
+  if (with_cfl) {
+    HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 3, s));
+    HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 2, s));
+  }
+  HIPCHK(mark(RD_K_GATHER1));
+  if (!rk2) HIPCHK(rd::launch_euler_apply(d, fp32, s));
+  HIPCHK(mark(RD_K_WALL2));
+  if (rk2) HIPCHK(rd::launch_wall(d, true, s, true));
+  HIPCHK(mark(RD_K_TRI2));
+  if (rk2) HIPCHK(rd::launch_tile(d, tl, fp32, scheme, 2, false, false, s));
+  HIPCHK(mark(RD_K_GATHER2));
+  if (rk2) HIPCHK(rd::launch_shared(d, tl, fp32, 2, false, s));
+  HIPCHK(mark(RD_NKERNELS));
+  m->zprec = fp32;
+  return RD_OK;
+}
+
+// Largest dynamic LDS a tile workgroup may use.
+constexpr size_t kTileLdsLimit = 64 * 1024;
+
+// Builds (or drops, tt = 0) the tiles of a mesh.
+rd_status set_tile(rd_mesh* m, int tt) {
+  if (tt == m->tile) return RD_OK;
+  if (tt != 0 && (tt < 32 || tt > 1024)) return fail(RD_EINVAL, "tile size must be 0 or in [32, 1024]");
+  DeviceGuard g(m->device);
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if (tt == 0) {
+    free_list(m->tile_allocs);
+    m->tiles = rd::Tiles();
+    m->tile = 0;
+    for (int64_t& x : m->tile_info) x = 0;
+    return RD_OK;
+  }
+  const rd::Dev& d = m->d;
+  rd::TilePlan P;
+  const std::string why = rd::build_tile_plan(d.nv, d.nt, m->tri.data(), m->x.data(), m->y.data(), m->px, m->py,
+                                              m->row.data(), m->slot.data(), m->voff, m->toff, tt, P);
+  if (!why.empty()) return fail(RD_EINVAL, why);
+  rd::Tiles tl;
+  tl.ntiles = P.ntiles;
+  tl.tt = P.tt;
+  tl.max_lv = P.max_lv;
+  tl.max_lvi = P.max_lvi;
+  tl.max_slots = P.max_slots;
+  tl.nsv = (int64_t)P.sv.size();
+  tl.nss = P.nss;
+  const size_t need = std::max(rd::tile_lds_bytes(tl, 0, 1, true), rd::tile_lds_bytes(tl, 0, 2, false));
+  if (need > kTileLdsLimit)
+    return fail(RD_EUNSUPPORTED, "tiles of " + std::to_string(tt) + " triangles need " + std::to_string(need) +
+                                     " bytes of LDS");
+  std::vector<void*> list;
+  int32_t *tbeg, *vbeg, *nvi, *lpb, *lp, *tvl, *dst, *tm, *sv, *ssbeg;
+  uint16_t* lv;
+  rd::D4* cs;
+  double* lams;
+  rd_status st;
+  if ((st = upload_in(list, &tbeg, P.tbeg)) || (st = upload_in(list, &vbeg, P.vbeg)) ||
+      (st = upload_in(list, &nvi, P.nvi)) || (st = upload_in(list, &lpb, P.lpb)) ||
+      (st = upload_in(list, &lp, P.lp)) || (st = upload_in(list, &tvl, P.tvl)) ||
+      (st = upload_in(list, &lv, P.lv)) || (st = upload_in(list, &dst, P.dst)) ||
+      (st = upload_in(list, &tm, P.tmesh)) || (st = upload_in(list, &sv, P.sv)) ||
+      (st = upload_in(list, &ssbeg, P.ssbeg)) || (st = dalloc_in(list, &cs, (size_t)P.nss)) ||
+      (st = dalloc_in(list, &lams, (size_t)P.nss))) {
+    free_list(list);
+    return st;
+  }
+  if (!m->d.R1) {
+    rd::D4* r1;
+    double* cv;
+    if ((st = dalloc(m, &r1, d.nv)) || (st = dalloc(m, &cv, d.nv))) {
+      free_list(list);
+      return st;
+    }
+    m->d.R1 = r1;
+    m->d.cflv = cv;
+  }
+  tl.tbeg = tbeg;
+  tl.vbeg = vbeg;
+  tl.nvi = nvi;
+  tl.lpb = lpb;
+  tl.lp = lp;
+  tl.tvl = tvl;
+  tl.lv = lv;
+  tl.dst = dst;
+  tl.tmesh = m->voff.size() > 2 ? tm : nullptr;
+  tl.sv = sv;
+  tl.ssbeg = ssbeg;
+  tl.Cs = cs;
+  tl.lams = lams;
+  free_list(m->tile_allocs);
+  m->tile_allocs.swap(list);
+  m->tiles = tl;
+  m->tile = tt;
+  int64_t nsc = 0;
+  for (int32_t v : P.sv) nsc += m->row[v + 1] - m->row[v];
+  m->tile_info[0] = P.ntiles;
+  m->tile_info[1] = (int64_t)P.tvl.size();
+  m->tile_info[2] = (int64_t)P.sv.size();
+  m->tile_info[3] = nsc;
+  return RD_OK;
+}
+
 rd_status check_step_args(int scheme, int time, int precision) {
   if (scheme < RD_N || scheme > RD_BMIN) return fail(RD_EINVAL, "unknown scheme");
   if (time != RD_EULER1 && time != RD_RK2) return fail(RD_EINVAL, "unknown time integration");
   if (precision != RD_FP64 && precision != RD_FP32_ACC64) return fail(RD_EINVAL, "unknown precision");
   return RD_OK;
 }
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
 
 bool physical(const double* W, int64_t nv, int64_t i, double gamma) {
   const double rho = W[i], mx = W[nv + i], my = W[2 * nv + i], e = W[3 * nv + i];
@@ -273,6 +419,8 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
   m->py = desc->period_y;
   m->gamma = desc->gamma;
   m->V.swap(geo.V);
+  m->voff = {0, nv};
+  m->toff = {0, nt};
 
   // vertex -> (triangle, corner) CSR, ascending triangle order in every row
   m->row.assign(nv + 1, 0);
@@ -563,6 +711,122 @@ RD_API rd_status rd_step_timed(rd_mesh* m, double cfl, int scheme, int time, int
   return RD_OK;
 }
 
+RD_API rd_status rd_mesh_set_tile(rd_mesh* m, int tile_triangles) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  return set_tile(m, tile_triangles);
+}
+
+RD_API rd_status rd_mesh_get_tile(const rd_mesh* m, int* tile_triangles) {
+  if (!m || !tile_triangles) return fail(RD_EINVAL, "null argument");
+  *tile_triangles = m->tile;
+  return RD_OK;
+}
+
+RD_API rd_status rd_mesh_tile_info(const rd_mesh* m, int64_t* info) {
+  if (!m || !info) return fail(RD_EINVAL, "null argument");
+  for (int k = 0; k < 4; ++k) info[k] = m->tile_info[k];
+  return RD_OK;
+}
+
+namespace {
+
+const int kTuneDefault[] = {0, 64, 128, 256, 512};
+
+rd_status tune_args(double cfl, int scheme, int time, int precision, int n_steps, const int*& cand, int& nc,
+                    int* best) {
+  if (!best) return fail(RD_EINVAL, "null argument");
+  if (!(cfl > 0.0)) return fail(RD_EINVAL, "cfl must be positive");
+  if (n_steps < 1) return fail(RD_EINVAL, "n_steps must be at least 1");
+  if (!cand) {
+    cand = kTuneDefault;
+    nc = (int)(sizeof(kTuneDefault) / sizeof(kTuneDefault[0]));
+  }
+  if (nc < 1) return fail(RD_EINVAL, "no candidates");
+  return check_step_args(scheme, time, precision);
+}
+
+// Times `body` (enqueued on s) with two events; returns milliseconds.
+template <class F>
+rd_status time_on(hipStream_t s, F body, float* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(RD_EDEVICE, "hipEventCreate failed");
+  }
+  rd_status st = RD_OK;
+  hipError_t e = hipEventRecord(e0, s);
+  if (e == hipSuccess) st = body();
+  if (e == hipSuccess && st == RD_OK) e = hipEventRecord(e1, s);
+  if (e == hipSuccess && st == RD_OK) e = hipEventSynchronize(e1);
+  if (e == hipSuccess && st == RD_OK) e = hipEventElapsedTime(ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != RD_OK) return st;
+  if (e != hipSuccess) return fail(RD_EDEVICE, std::string("timing: ") + hipGetErrorString(e));
+  return RD_OK;
+}
+
+}  // namespace
+
+RD_API rd_status rd_tune(rd_mesh* m, double cfl, int scheme, int time, int precision, int n_steps,
+                         const int* candidates, int n_candidates, double* ms_per_step, int* best) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  rd_status st = tune_args(cfl, scheme, time, precision, n_steps, candidates, n_candidates, best);
+  if (st != RD_OK) return st;
+  DeviceGuard g(m->device);
+  const int fp32 = precision == RD_FP32_ACC64;
+  if ((st = ensure_prec(m, fp32)) != RD_OK) return st;
+  hipStream_t s = m->stream;
+  // the state and the flag are saved in the scratch buffer (4 max(nv, nt) doubles)
+  rd::D4* saveW = reinterpret_cast<rd::D4*>(m->scratch);
+  HIPCHK(rd::launch_copy4(saveW, m->d.W, m->d.nv, s));
+  int flag0 = 0;
+  HIPCHK(hipMemcpyAsync(&flag0, m->d.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  auto restore = [&]() -> rd_status {
+    HIPCHK(rd::launch_copy4(m->d.W, saveW, m->d.nv, s));
+    HIPCHK(rd::launch_set_int(m->d.flag, flag0, s));
+    m->zprec = -1;
+    return RD_OK;
+  };
+  const int prev = m->tile;
+  int pick = -1;
+  float pick_ms = 0.0f;
+  for (int i = 0; i < n_candidates; ++i) {
+    if (ms_per_step) ms_per_step[i] = -1.0;
+    st = set_tile(m, candidates[i]);
+    if (st == RD_EUNSUPPORTED || st == RD_EINVAL) continue;
+    if (st != RD_OK) break;
+    if ((st = ensure_z(m, fp32)) != RD_OK || (st = run_step(m, scheme, time, fp32, cfl)) != RD_OK) break;
+    float t = 0.0f;
+    st = time_on(s, [&]() -> rd_status {
+      for (int k = 0; k < n_steps; ++k) {
+        rd_status r = run_step(m, scheme, time, fp32, cfl);
+        if (r != RD_OK) return r;
+      }
+      return RD_OK;
+    }, &t);
+    if (st != RD_OK) break;
+    if ((st = restore()) != RD_OK) break;
+    if (ms_per_step) ms_per_step[i] = t / n_steps;
+    if (pick < 0 || t < pick_ms) {
+      pick = candidates[i];
+      pick_ms = t;
+    }
+  }
+  if (st == RD_EUNSUPPORTED || st == RD_EINVAL) st = RD_OK;
+  rd_status st2 = set_tile(m, pick >= 0 ? pick : prev);
+  rd_status st3 = restore();
+  HIPCHK(hipStreamSynchronize(s));
+  if (st != RD_OK) return st;
+  if (st2 != RD_OK) return st2;
+  if (st3 != RD_OK) return st3;
+  if (pick < 0) return fail(RD_EUNSUPPORTED, "no candidate tile size is usable");
+  *best = pick;
+  return RD_OK;
+}
+
 RD_API rd_status rd_residual(rd_mesh* m, int scheme, double* R, double* phiT, int on_device) {
   if (!m || !R) return fail(RD_EINVAL, "null argument");
   if (scheme < RD_N || scheme > RD_BMIN) return fail(RD_EINVAL, "unknown scheme");
@@ -763,6 +1027,8 @@ RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd
     rd_mesh_destroy(flat);
     return st;
   }
+  flat->voff = voff;
+  flat->toff = toff;
   flat->d.vmesh = pvm;
   flat->d.tmesh = ptm;
   flat->d.dt = dt;
@@ -785,19 +1051,14 @@ RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd
   return RD_OK;
 }
 
-RD_API rd_status rd_batch_run(rd_batch* b, int n_steps, double cfl, int scheme, int time, int precision) {
-  if (!b) return fail(RD_EINVAL, "null batch");
-  if (n_steps < 0) return fail(RD_EINVAL, "negative step count");
-  if (!(cfl > 0.0)) return fail(RD_EINVAL, "cfl must be positive");
-  rd_status st = check_step_args(scheme, time, precision);
-  if (st != RD_OK) return st;
+namespace {
+
+// Orders the batch's stream after the caller's and the members' pending work
+// and copies the members' states in.
+rd_status batch_begin(rd_batch* b, int fp32, std::vector<hipStream_t>& outer) {
   rd_mesh* f = b->flat;
-  DeviceGuard g(f->device);
-  const int fp32 = precision == RD_FP32_ACC64;
-  if ((st = ensure_prec(f, fp32)) != RD_OK) return st;
   hipStream_t s = f->stream;  // the batch's own stream
-  // order after the caller's and the members' pending work
-  std::vector<hipStream_t> outer{b->stream};
+  outer.assign(1, b->stream);
   for (rd_mesh* m : b->members)
     if (std::find(outer.begin(), outer.end(), m->stream) == outer.end()) outer.push_back(m->stream);
   for (hipStream_t o : outer) {
@@ -810,24 +1071,67 @@ RD_API rd_status rd_batch_run(rd_batch* b, int n_steps, double cfl, int scheme, 
   }
   HIPCHK(rd::launch_set_int(f->d.flag, 0, s));
   f->zprec = -1;
-  if ((st = ensure_z(f, fp32)) != RD_OK) return st;
-  if (n_steps > 0) {
-    rd_batch::Graph* gr = nullptr;
-    for (auto& c : b->graphs)
-      if (c.n_steps == n_steps && c.scheme == scheme && c.time == time && c.fp32 == fp32 && c.cfl == cfl) gr = &c;
-    if (!gr) {
-      rd_batch::Graph c{n_steps, scheme, time, fp32, cfl, nullptr, nullptr};
-      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      rd_status rs = RD_OK;
-      for (int k = 0; k < n_steps && rs == RD_OK; ++k) rs = run_step(f, scheme, time, fp32, cfl);
-      hipError_t ce = hipStreamEndCapture(s, &c.graph);
-      if (rs != RD_OK) return rs;
-      if (ce != hipSuccess) return fail(RD_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
-      HIPCHK(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
-      b->graphs.push_back(c);
-      gr = &b->graphs.back();
+  return ensure_z(f, fp32);
+}
+
+// The captured graph of n_steps steps (cached per configuration; the cache
+// is dropped whenever the tile size changes).
+rd_status batch_graph(rd_batch* b, int n_steps, double cfl, int scheme, int time, int fp32,
+                      hipGraphExec_t* exec) {
+  rd_mesh* f = b->flat;
+  hipStream_t s = f->stream;
+  for (auto& c : b->graphs)
+    if (c.n_steps == n_steps && c.scheme == scheme && c.time == time && c.fp32 == fp32 && c.cfl == cfl) {
+      *exec = c.exec;
+      return RD_OK;
     }
-    HIPCHK(hipGraphLaunch(gr->exec, s));
+  rd_batch::Graph c{n_steps, scheme, time, fp32, cfl, nullptr, nullptr};
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  rd_status rs = RD_OK;
+  for (int k = 0; k < n_steps && rs == RD_OK; ++k) rs = run_step(f, scheme, time, fp32, cfl);
+  hipError_t ce = hipStreamEndCapture(s, &c.graph);
+  if (rs != RD_OK) {
+    if (ce == hipSuccess) (void)hipGraphDestroy(c.graph);
+    return rs;
+  }
+  if (ce != hipSuccess) return fail(RD_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+  hipError_t ie = hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(c.graph);
+    return fail(RD_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+  }
+  b->graphs.push_back(c);
+  *exec = c.exec;
+  return RD_OK;
+}
+
+rd_status batch_set_tile(rd_batch* b, int tt) {
+  if (tt == b->flat->tile) return RD_OK;
+  DeviceGuard g(b->flat->device);
+  (void)hipStreamSynchronize(b->own);
+  destroy_graphs(b);
+  return set_tile(b->flat, tt);
+}
+
+}  // namespace
+
+RD_API rd_status rd_batch_run(rd_batch* b, int n_steps, double cfl, int scheme, int time, int precision) {
+  if (!b) return fail(RD_EINVAL, "null batch");
+  if (n_steps < 0) return fail(RD_EINVAL, "negative step count");
+  if (!(cfl > 0.0)) return fail(RD_EINVAL, "cfl must be positive");
+  rd_status st = check_step_args(scheme, time, precision);
+  if (st != RD_OK) return st;
+  rd_mesh* f = b->flat;
+  DeviceGuard g(f->device);
+  const int fp32 = precision == RD_FP32_ACC64;
+  if ((st = ensure_prec(f, fp32)) != RD_OK) return st;
+  hipStream_t s = f->stream;
+  std::vector<hipStream_t> outer;
+  if ((st = batch_begin(b, fp32, outer)) != RD_OK) return st;
+  if (n_steps > 0) {
+    hipGraphExec_t exec = nullptr;
+    if ((st = batch_graph(b, n_steps, cfl, scheme, time, fp32, &exec)) != RD_OK) return st;
+    HIPCHK(hipGraphLaunch(exec, s));
   }
   // states out; each member refreshes its parameter vectors before its next step
   for (size_t k = 0; k < b->members.size(); ++k) {
@@ -838,6 +1142,57 @@ RD_API rd_status rd_batch_run(rd_batch* b, int n_steps, double cfl, int scheme, 
   }
   HIPCHK(hipEventRecord(b->ev_out, s));
   for (hipStream_t o : outer) HIPCHK(hipStreamWaitEvent(o, b->ev_out, 0));
+  return RD_OK;
+}
+
+RD_API rd_status rd_batch_set_tile(rd_batch* b, int tile_triangles) {
+  if (!b) return fail(RD_EINVAL, "null batch");
+  return batch_set_tile(b, tile_triangles);
+}
+
+RD_API rd_status rd_batch_tune(rd_batch* b, double cfl, int scheme, int time, int precision, int n_steps,
+                               const int* candidates, int n_candidates, double* ms_per_step, int* best) {
+  if (!b) return fail(RD_EINVAL, "null batch");
+  rd_status st = tune_args(cfl, scheme, time, precision, n_steps, candidates, n_candidates, best);
+  if (st != RD_OK) return st;
+  rd_mesh* f = b->flat;
+  DeviceGuard g(f->device);
+  const int fp32 = precision == RD_FP32_ACC64;
+  if ((st = ensure_prec(f, fp32)) != RD_OK) return st;
+  hipStream_t s = f->stream;
+  const int prev = f->tile;
+  int pick = -1;
+  float pick_ms = 0.0f;
+  std::vector<hipStream_t> outer;
+  for (int i = 0; i < n_candidates; ++i) {
+    if (ms_per_step) ms_per_step[i] = -1.0;
+    st = batch_set_tile(b, candidates[i]);
+    if (st == RD_EUNSUPPORTED || st == RD_EINVAL) continue;
+    if (st != RD_OK) break;
+    hipGraphExec_t exec = nullptr;
+    if ((st = batch_begin(b, fp32, outer)) != RD_OK) break;
+    if ((st = batch_graph(b, n_steps, cfl, scheme, time, fp32, &exec)) != RD_OK) break;
+    HIPCHK(hipGraphLaunch(exec, s));  // warm-up replay
+    if ((st = batch_begin(b, fp32, outer)) != RD_OK) break;
+    float t = 0.0f;
+    st = time_on(s, [&]() -> rd_status {
+      HIPCHK(hipGraphLaunch(exec, s));
+      return RD_OK;
+    }, &t);
+    if (st != RD_OK) break;
+    if (ms_per_step) ms_per_step[i] = t / n_steps;
+    if (pick < 0 || t < pick_ms) {
+      pick = candidates[i];
+      pick_ms = t;
+    }
+  }
+  if (st == RD_EUNSUPPORTED || st == RD_EINVAL) st = RD_OK;
+  rd_status st2 = batch_set_tile(b, pick >= 0 ? pick : prev);
+  HIPCHK(hipStreamSynchronize(s));
+  if (st != RD_OK) return st;
+  if (st2 != RD_OK) return st2;
+  if (pick < 0) return fail(RD_EUNSUPPORTED, "no candidate tile size is usable");
+  *best = pick;
   return RD_OK;
 }
 

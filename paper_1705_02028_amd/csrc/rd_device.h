@@ -89,6 +89,9 @@ struct Dev {
   double* lam = nullptr;  // [ns] l_max^T lambda_max^T, sliced layout
   double* dt = nullptr;   // [n meshes] time step
   int* flag = nullptr;    // non-physical state latch
+  // tiled form
+  D4* R1 = nullptr;       // [nv] stage-1 (or Euler) vertex residual, wall term included
+  double* cflv = nullptr; // [nv] 2 V_i / sum_T l_max^T lambda_max^T
 };
 
 // Boundary code of a vertex: -1 interior, -2 ghost, b >= 0 wall vertex b,
@@ -340,10 +343,27 @@ __host__ __device__ inline void tri_load_verts(const Dev& d, TriIn<R>& in) {
   }
 }
 
-template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
-__host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const Dev& d) {
-  const int32_t* iv = in.iv;
-  const int32_t* ip = in.ip;
+// Where a triangle body reads the stage-1 differences W* - W^n of its corners
+// and sends its parts: GlobalIO is the two-pass form (vertex arrays and the
+// sliced part buffer in HBM); the tiled form has its own (LDS-staged) IO.
+// `t` indexes the triangle's saved stage-1 values (keepN, keepT).
+template <typename R>
+struct GlobalIO {
+  const Dev& d;
+  const int32_t* iv;
+  const int32_t* ip;
+  __host__ __device__ R idt(int64_t t) const { return (R)(1.0 / d.dt[d.tmesh ? d.tmesh[t] : 0]); }
+  __host__ __device__ Q4<R> dw(int i) const { return reinterpret_cast<const Q4<R>*>(d.dW)[iv[i]]; }
+  __host__ __device__ void part(int i, const R out[4]) const {
+    Q4<R> q;
+    for (int k = 0; k < 4; ++k) q.v[k] = out[k];
+    reinterpret_cast<Q4<R>*>(d.C)[ip[i]] = q;
+  }
+  __host__ __device__ void lam(int i, double x) const { d.lam[ip[i]] = x; }
+};
+
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, class IO>
+__host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const Dev& d, const IO& io) {
   const double2 p0 = in.p[0], p1 = in.p[1], p2 = in.p[2];
   const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
   const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
@@ -414,7 +434,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     double lam = 0.0;
     for (int i = 0; i < 3; ++i) lam = rmax(lam, in.sig[i]);
     const double lt = (double)lmax * lam;
-    for (int i = 0; i < 3; ++i) d.lam[ip[i]] = lt;
+    for (int i = 0; i < 3; ++i) io.lam(i, lt);
   }
 
   // triangle residual and the N right-hand side
@@ -440,13 +460,12 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   if (STAGE == 1) {
     for (int k = 0; k < 4; ++k) rhs1[k] = phiT[k];
   } else {
-    const int m = d.tmesh ? d.tmesh[t] : 0;
-    idt = (R)(1.0 / d.dt[m]);
+    idt = io.idt(t);
     mass = (R)((0.5 * (d1x * d2y - d1y * d2x)) / 3.0);
     if (needL) {
       R srate[4] = {R(0), R(0), R(0), R(0)};
       for (int i = 0; i < 3; ++i) {
-        const Q4<R> dwv = ld4<R>(d.dW, iv[i]);
+        const Q4<R> dwv = io.dw(i);
         for (int k = 0; k < 4; ++k) srate[k] = srate[k] + dwv.v[k] * idt;
       }
       const Q4<R> kt = ld4<R>(d.keepT, t);
@@ -479,7 +498,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     // registers across the solve
     for (int i = 0; i < 3; ++i) {
       const Q4<R> kn = ld4<R>(d.keepN, 3 * t + i);
-      const Q4<R> dwv = ld4<R>(d.dW, iv[i]);
+      const Q4<R> dwv = io.dw(i);
       for (int k = 0; k < 4; ++k) pN[i][k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn.v[k] + pN[i][k]);
     }
   }
@@ -499,7 +518,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
         for (int k = 0; k < 4; ++k) out[k] = pl[k] + th[k] * (pN[i][k] - pl[k]);
       }
     }
-    st4<R>(d.C, ip[i], out);
+    io.part(i, out);
   }
 }
 
@@ -508,28 +527,76 @@ __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
   TriIn<R> in;
   tri_load_ids<R>(t, d, in);
   tri_load_verts<R, CFL>(d, in);
-  tri_compute<R, SCHEME, STAGE, SAVE, CFL>(t, in, d);
+  const GlobalIO<R> io{d, in.iv, in.ip};
+  tri_compute<R, SCHEME, STAGE, SAVE, CFL>(t, in, d, io);
 }
 
 // Parameter vector, signal speed and physicality of one state.
-__host__ __device__ inline void vertex_epilogue(const Dev& d, int64_t v, const double w[4], bool fp32) {
-  const double g1 = d.gamma - 1.0;
+struct VertexDerived {
+  double z[4];
+  double sig;
+  bool ok;
+};
+
+__host__ __device__ inline VertexDerived derive(double gamma, const double w[4]) {
+  VertexDerived o;
+  const double g1 = gamma - 1.0;
   const double rho = w[0], u = w[1] / rho, vv = w[2] / rho;
   const double p = g1 * (w[3] - 0.5 * rho * (u * u + vv * vv));
   const double h = (w[3] + p) / rho;
   const double s = sqrt(rho);
-  const double z[4] = {s, s * u, s * vv, s * h};
-  if (fp32) {
-    const float zf[4] = {(float)z[0], (float)z[1], (float)z[2], (float)z[3]};
-    st4<float>(d.Zf, v, zf);
-  } else {
-    st4<double>(d.Z, v, z);
-  }
-  const double sg = sqrt(u * u + vv * vv) + sqrt(d.gamma * p / rho);
-  d.sig[v] = sg;
-  const bool finite = fabs(sg) < INFINITY && fabs(w[1]) < INFINITY && fabs(w[2]) < INFINITY &&
+  o.z[0] = s;
+  o.z[1] = s * u;
+  o.z[2] = s * vv;
+  o.z[3] = s * h;
+  o.sig = sqrt(u * u + vv * vv) + sqrt(gamma * p / rho);
+  const bool finite = fabs(o.sig) < INFINITY && fabs(w[1]) < INFINITY && fabs(w[2]) < INFINITY &&
                       fabs(w[3]) < INFINITY;
-  if (!(rho > 0.0) || !(p > 0.0) || !finite) d.flag[0] = 1;
+  o.ok = rho > 0.0 && p > 0.0 && finite;
+  return o;
+}
+
+template <typename R>
+__host__ __device__ inline Q4<R> zq(const VertexDerived& o) {
+  Q4<R> q;
+  for (int k = 0; k < 4; ++k) q.v[k] = (R)o.z[k];
+  return q;
+}
+
+__host__ __device__ inline void vertex_epilogue(const Dev& d, int64_t v, const double w[4], bool fp32) {
+  const VertexDerived o = derive(d.gamma, w);
+  if (fp32) d.Zf[v] = zq<float>(o);
+  else d.Z[v] = zq<double>(o);
+  d.sig[v] = o.sig;
+  if (!o.ok) d.flag[0] = 1;
+}
+
+// Sum of a vertex's n parts get(0), ..., get(n-1) in that order, in FP64
+// (Neumaier-compensated when the parts are FP32).
+template <typename R, class Get>
+__host__ __device__ inline void sum_parts(int32_t n, const Get& get, double acc[4]) {
+  double cmp[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < 4; ++k) acc[k] = 0.0;
+  for (int32_t j = 0; j < n; ++j) {
+    const Q4<R> c = get(j);
+    for (int k = 0; k < 4; ++k) {
+      if (sizeof(R) == sizeof(double)) {
+        acc[k] += (double)c.v[k];
+      } else {
+        const double x = (double)c.v[k];
+        const double tsum = acc[k] + x;
+        cmp[k] += fabs(acc[k]) >= fabs(x) ? (acc[k] - tsum) + x : (x - tsum) + acc[k];
+        acc[k] = tsum;
+      }
+    }
+  }
+  if (sizeof(R) != sizeof(double))
+    for (int k = 0; k < 4; ++k) acc[k] = acc[k] + cmp[k];
+}
+
+// The update of Sections 3.3-3.4: out = in - (dt / V) acc.
+__host__ __device__ inline void vertex_update(const double in[4], double f, const double acc[4], double out[4]) {
+  for (int k = 0; k < 4; ++k) out[k] = in[k] - f * acc[k];
 }
 
 // One vertex of the gather (MODE: G_EULER, G_STAGE1, G_STAGE2, G_RESIDUAL).
@@ -547,25 +614,10 @@ __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out
     }
     return;
   }
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  double cmp[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[4];
   const int32_t deg = d.row[v + 1] - d.row[v];
   const int64_t s0 = d.sbeg[v];
-  for (int32_t j = 0; j < deg; ++j) {
-    const Q4<R> c = ld4<R>(d.C, s0 + 64 * (int64_t)j);
-    for (int k = 0; k < 4; ++k) {
-      if (sizeof(R) == sizeof(double)) {
-        acc[k] += (double)c.v[k];
-      } else {
-        const double x = (double)c.v[k];
-        const double tsum = acc[k] + x;
-        cmp[k] += fabs(acc[k]) >= fabs(x) ? (acc[k] - tsum) + x : (x - tsum) + acc[k];
-        acc[k] = tsum;
-      }
-    }
-  }
-  if (sizeof(R) != sizeof(double))
-    for (int k = 0; k < 4; ++k) acc[k] = acc[k] + cmp[k];
+  sum_parts<R>(deg, [&](int32_t j) { return ld4<R>(d.C, s0 + 64 * (int64_t)j); }, acc);
   if (b >= 0) {
     const D4 wn = d.WCn[b];
     if (MODE == G_STAGE2) {
@@ -583,7 +635,7 @@ __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out
   const double f = d.dt[m] / d.V[v];
   const D4 win = MODE == G_STAGE2 ? d.Ws[v] : d.W[v];
   double wo[4];
-  for (int k = 0; k < 4; ++k) wo[k] = win.v[k] - f * acc[k];
+  vertex_update(win.v, f, acc, wo);
   if (MODE == G_STAGE1) {
     st4<double>(d.Ws, v, wo);
     R dw[4];
@@ -595,19 +647,36 @@ __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out
   vertex_epilogue(d, v, wo, sizeof(R) != sizeof(double));
 }
 
-// Wall correction of one wall vertex (Section 3.5), at W (STAGE2 = false) or W*.
-template <bool STAGE2>
+// The first-stage state W* = W^n - (dt / V) R1 of vertex v in the tiled form
+// (ghosts keep W^n), by the same arithmetic as the two-pass gather.
+__host__ __device__ inline D4 star_state(const Dev& d, int64_t v, int32_t code, int m) {
+  const D4 win = d.W[v];
+  if (is_ghost(code)) return win;
+  const double f = d.dt[m] / d.V[v];
+  const D4 r = d.R1[v];
+  D4 o;
+  vertex_update(win.v, f, r.v, o.v);
+  return o;
+}
+
+// Wall correction of one wall vertex (Section 3.5), at W (STAGE2 = false) or
+// W* (held in Ws, or formed from R1 when TILED).
+template <bool STAGE2, bool TILED = false>
 __host__ __device__ inline void wall_body(int64_t b, const Dev& d) {
   const double alpha = 0.75, g1 = d.gamma - 1.0;
   const D4* src = STAGE2 ? d.Ws : d.W;
   const int32_t v = d.wv[b];
+  auto state = [&](int32_t i) -> D4 {
+    if (STAGE2 && TILED) return star_state(d, i, d.bc[i], d.vmesh ? d.vmesh[i] : 0);
+    return src[i];
+  };
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int32_t e = d.wptr[b]; e < d.wptr[b + 1]; ++e) {
     const WallEnt we = d.went[e];
     double F[2][4];
     const int32_t ids[2] = {v, we.other};
     for (int s = 0; s < 2; ++s) {
-      const D4 w = src[ids[s]];
+      const D4 w = state(ids[s]);
       const double u = w.v[1] / w.v[0], vv = w.v[2] / w.v[0];
       const double p = g1 * (w.v[3] - 0.5 * w.v[0] * (u * u + vv * vv));
       const double vn = u * we.nx + vv * we.ny;

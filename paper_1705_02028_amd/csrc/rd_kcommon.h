@@ -1,0 +1,38 @@
+// Device helpers shared by the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "rd_launch.h"
+
+namespace rd {
+
+// Consecutive workgroup ids are dispatched round-robin over the 8 XCDs of an
+// MI355X, each with its own L2. This renumbering gives each XCD one
+// contiguous range of workgroups (triangles, tiles or vertices), which keeps
+// the vertex data a range touches in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  const int64_t x = b % 8, q = nb / 8, r = nb % 8;
+  return x * q + (x < r ? x : r) + b / 8;
+}
+
+// Minimum waves per SIMD the triangle kernels are compiled for.
+template <typename R> struct TriWaves { static constexpr int value = 2; };
+template <> struct TriWaves<float> { static constexpr int value = 4; };
+
+// Minimum over a kBlock-thread workgroup (result valid in every thread).
+__device__ __forceinline__ double block_min(double x) {
+  __shared__ double red[kBlock];
+  red[threadIdx.x] = x;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = rmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  return red[0];
+}
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace rd

@@ -1,25 +1,13 @@
-// gfx950 kernels of the residual-distribution step and their launchers.
+// gfx950 kernels of the two-pass residual-distribution step, the CFL
+// reduction, state conversion and the adjoint, with their launchers.
 //
 // Launch shapes: one thread per triangle (triangle passes) or per vertex
-// (gather, CFL), 256-thread workgroups. Consecutive workgroup ids are
-// dispatched round-robin over the 8 XCDs of an MI355X, each with its own L2;
-// `xcd_block` renumbers them so that each XCD walks one contiguous range of
-// triangles or vertices, which keeps the vertex data a range touches in that
-// XCD's L2.
+// (gather, CFL), 256-thread workgroups, block ids renumbered per XCD.
 #include "rd_adjoint.h"
+#include "rd_kcommon.h"
 #include "rd_launch.h"
 
 namespace rd {
-
-__device__ __forceinline__ int64_t xcd_block() {
-  const int64_t b = blockIdx.x, nb = gridDim.x;
-  const int64_t x = b % 8, q = nb / 8, r = nb % 8;
-  return x * q + (x < r ? x : r) + b / 8;
-}
-
-// Minimum waves per SIMD the triangle kernels are compiled for.
-template <typename R> struct TriWaves { static constexpr int value = 2; };
-template <> struct TriWaves<float> { static constexpr int value = 4; };
 
 // One thread per triangle. (A persistent grid with the next triangle's loads
 // software-pipelined was measured slower: fewer waves in flight and, with
@@ -36,10 +24,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(Dev d, double* out_soa) {
   if (v < d.nv) gather_body<R, MODE>(v, d, out_soa);
 }
 
-template <bool STAGE2>
+template <bool STAGE2, bool TILED>
 __global__ __launch_bounds__(kBlock) void k_wall(Dev d) {
   const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (b < d.nwv) wall_body<STAGE2>(b, d);
+  if (b < d.nwv) wall_body<STAGE2, TILED>(b, d);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cfl_tri(Dev d) {
@@ -47,21 +35,18 @@ __global__ __launch_bounds__(kBlock) void k_cfl_tri(Dev d) {
   if (t < d.nt) cfl_tri_body(t, d);
 }
 
-__device__ __forceinline__ double block_min(double x) {
-  __shared__ double red[kBlock];
-  red[threadIdx.x] = x;
-  __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = rmin(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  return red[0];
-}
-
 __global__ __launch_bounds__(kBlock) void k_cfl_vertex(Dev d, CflPlan p) {
   const int b = blockIdx.x;
   const int64_t v = (int64_t)p.blk_v0[b] + threadIdx.x;
   const double x = v < p.blk_v1[b] ? cfl_vertex_bound(v, d) : INFINITY;
+  const double m = block_min(x);
+  if (threadIdx.x == 0) p.part[b] = m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cfl_vmin(Dev d, CflPlan p) {
+  const int b = blockIdx.x;
+  const int64_t v = (int64_t)p.blk_v0[b] + threadIdx.x;
+  const double x = v < p.blk_v1[b] ? d.cflv[v] : INFINITY;
   const double m = block_min(x);
   if (threadIdx.x == 0) p.part[b] = m;
 }
@@ -143,8 +128,6 @@ __global__ __launch_bounds__(kBlock) void k_zero4(D4* dst, int64_t n) {
   const double z[4] = {0.0, 0.0, 0.0, 0.0};
   st4<double>(dst, i, z);
 }
-
-static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <int SCHEME>
 static void adj_tris(const Dev& d, const AdjDev& a, int stage, int rk2, hipStream_t s) {
@@ -231,16 +214,18 @@ hipError_t launch_gather(const Dev& d, int fp32, int mode, double* out_soa, hipS
   return fp32 ? gather_mode<float>(d, mode, out_soa, s) : gather_mode<double>(d, mode, out_soa, s);
 }
 
-hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s) {
+hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s, bool tiled) {
   if (d.nwv == 0) return hipSuccess;
-  if (stage2) hipLaunchKernelGGL((k_wall<true>), dim3(nblk(d.nwv)), dim3(kBlock), 0, s, d);
-  else hipLaunchKernelGGL((k_wall<false>), dim3(nblk(d.nwv)), dim3(kBlock), 0, s, d);
+  if (stage2 && tiled) hipLaunchKernelGGL((k_wall<true, true>), dim3(nblk(d.nwv)), dim3(kBlock), 0, s, d);
+  else if (stage2) hipLaunchKernelGGL((k_wall<true, false>), dim3(nblk(d.nwv)), dim3(kBlock), 0, s, d);
+  else hipLaunchKernelGGL((k_wall<false, false>), dim3(nblk(d.nwv)), dim3(kBlock), 0, s, d);
   return hipGetLastError();
 }
 
 hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s) {
   if (part == 0) hipLaunchKernelGGL(k_cfl_tri, dim3(nblk(d.nt)), dim3(kBlock), 0, s, d);
   else if (part == 1) hipLaunchKernelGGL(k_cfl_vertex, dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else if (part == 3) hipLaunchKernelGGL(k_cfl_vmin, dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
   else hipLaunchKernelGGL(k_cfl_final, dim3(p.nmesh), dim3(kBlock), 0, s, d, p, cfl);
   return hipGetLastError();
 }

@@ -5,6 +5,7 @@
 
 #include "rd_adjoint.h"
 #include "rd_device.h"
+#include "rd_tiles.h"
 
 namespace rd {
 
@@ -24,9 +25,11 @@ struct CflPlan {
 // cfl: also write l_max lambda_max per corner (stage 1 only)
 hipError_t launch_tri(const Dev& d, int fp32, int scheme, int stage, bool save, bool cfl, hipStream_t s);
 hipError_t launch_gather(const Dev& d, int fp32, int mode, double* out_soa, hipStream_t s);
-hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s);
+// tiled: the stage-2 wall term reads W* rebuilt from R1
+hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s, bool tiled = false);
 hipError_t launch_cfl(const Dev& d, const CflPlan& p, double cfl, hipStream_t s);
-// part 0: per triangle, 1: per vertex, 2: final minimum
+// part 0: per triangle, 1: per vertex (sums the sliced terms), 2: final
+// minimum, 3: per vertex from the bounds the tiled passes store in d.cflv
 hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s);
 hipError_t launch_set_state(const Dev& d, const double* soa, int fp32, hipStream_t s);
 hipError_t launch_refresh(const Dev& d, int fp32, hipStream_t s);
@@ -38,6 +41,20 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s);
 hipError_t launch_or_int(int* dst, const int* src, hipStream_t s);
 hipError_t launch_copy4(D4* dst, const D4* src, int64_t n, hipStream_t s);
 hipError_t launch_soa_to_aos(const double* soa, D4* dst, int64_t n, hipStream_t s);
+// Tiled form (rd_tiles.hip): one workgroup of min(tl.tt, kBlock) threads per
+// tile (a thread takes several triangles of a larger tile).
+inline int tile_threads(const Tiles& tl) { return tl.tt < kBlock ? tl.tt : kBlock; }
+// stage 1 (also Euler): R1 and, with cfl, the CFL bounds of interior
+// vertices; stage 2: the new state of interior vertices.
+hipError_t launch_tile(const Dev& d, const Tiles& tl, int fp32, int scheme, int stage, bool save, bool cfl,
+                       hipStream_t s);
+// The same for the shared vertices.
+hipError_t launch_shared(const Dev& d, const Tiles& tl, int fp32, int stage, bool cfl, hipStream_t s);
+// Forward-Euler update from R1.
+hipError_t launch_euler_apply(const Dev& d, int fp32, hipStream_t s);
+// Dynamic LDS bytes of a tile workgroup.
+size_t tile_lds_bytes(const Tiles& tl, int fp32, int stage, bool cfl);
+
 // Reverse of one step (FP64): stage-2 triangles and gather (rk2), then
 // stage-1 triangles and gather; dL/dW^n goes to out [4][nv].
 hipError_t launch_adjoint(const Dev& d, const AdjDev& a, int scheme, int rk2, double* out, hipStream_t s);

@@ -42,7 +42,8 @@ class rd_mesh_desc(C.Structure):
 EXPORTS = ["rd_mesh_validate", "rd_mesh_create", "rd_mesh_destroy", "rd_mesh_info", "rd_set_stream",
            "rd_set_state", "rd_get_state", "rd_max_dt", "rd_step", "rd_step_cfl", "rd_step_timed", "rd_residual",
            "rd_adjoint_step", "rd_batch_create", "rd_batch_run", "rd_batch_destroy", "rd_sync",
-           "rd_last_error"]
+           "rd_last_error", "rd_mesh_set_tile", "rd_mesh_get_tile", "rd_mesh_tile_info", "rd_tune",
+           "rd_batch_set_tile", "rd_batch_tune"]
 
 _lib = None
 
@@ -73,6 +74,12 @@ def lib():
             "rd_batch_run": [P, I, D, I, I, I],
             "rd_batch_destroy": [P],
             "rd_sync": [P],
+            "rd_mesh_set_tile": [P, I],
+            "rd_mesh_get_tile": [P, P],
+            "rd_mesh_tile_info": [P, P],
+            "rd_tune": [P, D, I, I, I, I, P, I, P, P],
+            "rd_batch_set_tile": [P, I],
+            "rd_batch_tune": [P, D, I, I, I, I, P, I, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -182,13 +189,55 @@ def rd_step_cfl(h, n_steps: int, cfl: float, scheme: int = B, time: int = RK2, p
     _check(lib().rd_step_cfl(h, int(n_steps), float(cfl), int(scheme), int(time), int(precision)))
 
 
-KERNELS = ["wall1", "tri1", "cfl_vertex", "cfl_final", "gather1", "wall2", "tri2", "gather2"]
+KERNELS = ["wall1", "tri1", "shared1", "cfl", "gather1", "wall2", "tri2", "gather2"]
+TUNE_DEFAULT = [0, 64, 128, 256, 512]
 
 
 def rd_step_timed(h, cfl: float, scheme: int = B, time: int = RK2, precision: int = FP64) -> dict:
     ms = np.zeros(len(KERNELS))
     _check(lib().rd_step_timed(h, float(cfl), int(scheme), int(time), int(precision), ms.ctypes.data))
     return dict(zip(KERNELS, ms.tolist()))
+
+
+def rd_mesh_set_tile(h, tile_triangles: int) -> None:
+    _check(lib().rd_mesh_set_tile(h, int(tile_triangles)))
+
+
+def rd_mesh_get_tile(h) -> int:
+    t = C.c_int()
+    _check(lib().rd_mesh_get_tile(h, C.byref(t)))
+    return t.value
+
+
+def rd_mesh_tile_info(h) -> dict:
+    a = (C.c_int64 * 4)()
+    _check(lib().rd_mesh_tile_info(h, a))
+    return dict(tiles=a[0], local_vertices=a[1], shared_vertices=a[2], shared_parts=a[3])
+
+
+def _tune(fn, h, cfl, scheme, time, precision, n_steps, candidates):
+    cand = list(TUNE_DEFAULT if candidates is None else candidates)
+    arr = (C.c_int * len(cand))(*cand)
+    ms = np.zeros(len(cand))
+    best = C.c_int()
+    _check(fn(h, float(cfl), int(scheme), int(time), int(precision), int(n_steps), arr, len(cand),
+              ms.ctypes.data, C.byref(best)))
+    return best.value, dict(zip(cand, ms.tolist()))
+
+
+def rd_tune(h, cfl: float, scheme: int = B, time: int = RK2, precision: int = FP64, n_steps: int = 5,
+            candidates=None):
+    """Returns (chosen tile size, {candidate: ms per step, negative if unusable})."""
+    return _tune(lib().rd_tune, h, cfl, scheme, time, precision, n_steps, candidates)
+
+
+def rd_batch_set_tile(b, tile_triangles: int) -> None:
+    _check(lib().rd_batch_set_tile(b, int(tile_triangles)))
+
+
+def rd_batch_tune(b, cfl: float, scheme: int = B, time: int = RK2, precision: int = FP64, n_steps: int = 20,
+                  candidates=None):
+    return _tune(lib().rd_batch_tune, b, cfl, scheme, time, precision, n_steps, candidates)
 
 
 def rd_residual(h, scheme: int, R, phiT=None) -> None:
@@ -267,6 +316,17 @@ class Mesh:
     def step_cfl(self, n_steps, cfl, scheme=B, time=RK2, precision=FP64):
         rd_step_cfl(self.h, n_steps, cfl, scheme, time, precision)
 
+    @property
+    def tile(self) -> int:
+        return rd_mesh_get_tile(self.h)
+
+    @tile.setter
+    def tile(self, tile_triangles: int):
+        rd_mesh_set_tile(self.h, tile_triangles)
+
+    def tune(self, cfl, scheme=B, time=RK2, precision=FP64, n_steps=5, candidates=None):
+        return rd_tune(self.h, cfl, scheme, time, precision, n_steps, candidates)
+
     def residual(self, scheme=B, with_phiT=False):
         R = np.zeros((4, self.nv))
         phiT = np.zeros((4, self.nt)) if with_phiT else None
@@ -287,6 +347,12 @@ class Batch:
 
     def run(self, n_steps, cfl, scheme=B, time=RK2, precision=FP64):
         rd_batch_run(self.h, n_steps, cfl, scheme, time, precision)
+
+    def set_tile(self, tile_triangles: int):
+        rd_batch_set_tile(self.h, tile_triangles)
+
+    def tune(self, cfl, scheme=B, time=RK2, precision=FP64, n_steps=20, candidates=None):
+        return rd_batch_tune(self.h, cfl, scheme, time, precision, n_steps, candidates)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

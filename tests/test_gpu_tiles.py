@@ -1,0 +1,216 @@
+"""GPU parity of the tiled form of the step (rd_mesh_set_tile > 0).
+
+The tiled form sums every vertex's parts in ascending triangle order, as the
+two-pass form does, so its results do not depend on the tile size: different
+tile sizes are compared bitwise. Against the oracle it is held to the same
+per-case bars as the two-pass form (see test_gpu_parity).
+"""
+import numpy as np
+import pytest
+
+from paper_1705_02028_amd import inputs as I
+from test_gpu_parity import CASES, TOL64, err, say, tols
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1705_02028_amd import rd as rdmod
+    rdmod.lib()
+    return rdmod
+
+
+def run(rd, m, W, dt, scheme, time, prec, tile, n=1, cfl=None):
+    g = rd.Mesh(m)
+    g.tile = tile
+    assert g.tile == tile
+    g.set_state(W)
+    if cfl is None:
+        for _ in range(n):
+            g.step(dt, scheme, time, prec)
+    else:
+        g.step_cfl(n, cfl, scheme, time, prec)
+    out = g.get_state()
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("time", [1, 2])
+def test_tiled_one_step_all_schemes(orc, rd, case, time):
+    m, icf = CASES[case]()
+    W = icf(m)
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W, 0.4)
+    for scheme in range(5):
+        ref = om.step(W, dt, scheme, time)
+        t64, t32 = tols(om, W, dt, scheme, time, ref=ref)
+        for prec, bar in ((rd.FP64, t64), (rd.FP32_ACC64, t32)):
+            say(f"tiled case={case} nt={m['nt']} scheme={scheme} time={time} prec={prec} tile=64")
+            a = run(rd, m, W, dt, scheme, time, prec, 64)
+            e = err(a, ref)
+            say(f"  err {e:.2e} (tol {bar:.1e})")
+            assert e <= bar
+            for tile in (32, 256):
+                say(f"tiled case={case} scheme={scheme} time={time} prec={prec} tile={tile}")
+                assert np.array_equal(run(rd, m, W, dt, scheme, time, prec, tile), a)
+
+
+def test_tiled_cfl_steps_match_oracle_and_two_pass(orc, rd):
+    m = I.split_square(33, periodic=(False, False), bc=("ghost", "wall"), diagonal="random", seed=3)
+    W = I.ic_quadrants(m, I.quadrant_states(9))
+    om = orc.OracleMesh(m)
+    ref = W
+    for _ in range(10):
+        ref = om.step(ref, om.max_dt(ref, 0.4), orc.B, orc.RK2)
+    for prec, bar in ((0, 1e-11), (1, 1e-5)):
+        say(f"tiled step_cfl prec={prec}")
+        a = run(rd, m, W, 0.0, rd.B, rd.RK2, prec, 64, n=10, cfl=0.4)
+        b = run(rd, m, W, 0.0, rd.B, rd.RK2, prec, 0, n=10, cfl=0.4)
+        e, e2 = err(a, ref), err(a, b)
+        say(f"  tiled vs oracle {e:.2e}, tiled vs two-pass {e2:.2e}")
+        assert e <= bar and e2 <= bar
+        assert np.array_equal(run(rd, m, W, 0.0, rd.B, rd.RK2, prec, 128, n=10, cfl=0.4), a)
+    # forward Euler with the CFL step
+    ref = W
+    for _ in range(5):
+        ref = om.step(ref, om.max_dt(ref, 0.4), orc.N, orc.EULER1)
+    a = run(rd, m, W, 0.0, rd.N, rd.EULER1, rd.FP64, 32, n=5, cfl=0.4)
+    assert err(a, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tiled_uniform_states_preserved_bitwise(rd, prec):
+    cases = [(I.split_square(50, diagonal="random", seed=5, jitter=0.2), (1.3, 0.4, -0.7, 0.8)),
+             (I.split_square(31, periodic=(False, False), bc=("ghost", "wall")), (0.9, 0.5, 0.0, 1.7)),
+             (I.split_square(31, periodic=(False, False), bc=("wall", "wall")), (1.0, 0.0, 0.0, 1.0))]
+    for m, prim in cases:
+        W = I.ic_uniform(m, *prim)
+        for scheme in range(5):
+            for time in (1, 2):
+                say(f"tiled uniform nt={m['nt']} scheme={scheme} time={time} prec={prec}")
+                assert np.array_equal(run(rd, m, W, 1e-3, scheme, time, prec, 64, n=2), W)
+
+
+def test_tiled_tiny_meshes_and_ragged_tiles(orc, rd):
+    m = I.split_square(2, periodic=(False, False), bc=("ghost", "ghost"))  # every vertex a ghost
+    W = I.ic_quadrants(m, I.quadrant_states(1))
+    assert np.array_equal(run(rd, m, W, 1e-3, rd.B, rd.RK2, rd.FP64, 32), W)
+    m = I.split_square(3, periodic=(False, False), bc=("ghost", "ghost"))  # one interior vertex
+    W = I.ic_quadrants(m, I.quadrant_states(1))
+    om = orc.OracleMesh(m)
+    assert err(run(rd, m, W, 1e-3, rd.B, rd.RK2, rd.FP64, 32), om.step(W, 1e-3, orc.B, orc.RK2)) <= TOL64
+    # 21x21 periodic: 882 triangles, not a multiple of any tile size
+    m = I.split_square(21, diagonal="random", seed=2)
+    W = I.random_smooth_state(m, seed=2, amp=0.2)
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W, 0.4)
+    ref = om.step(W, dt, orc.B, orc.RK2)
+    outs = [run(rd, m, W, dt, rd.B, rd.RK2, rd.FP64, t) for t in (32, 100, 200)]
+    assert err(outs[0], ref) <= TOL64
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_tile_info_and_invalid_sizes(rd):
+    m = I.split_square(64)
+    g = rd.Mesh(m)
+    assert g.tile == 0
+    assert rd.rd_mesh_tile_info(g.h)["tiles"] == 0
+    g.tile = 128
+    info = rd.rd_mesh_tile_info(g.h)
+    say(f"tile info 64^2 / 128: {info}")
+    assert info["tiles"] == -(-m["nt"] // 128)
+    assert 0 < info["shared_vertices"] < m["nv"]
+    assert info["local_vertices"] >= m["nv"]
+    for bad in (-1, 1, 31, 1025):
+        with pytest.raises(rd.RDError) as e:
+            g.tile = bad
+        assert e.value.status == rd.RD_EINVAL
+    assert g.tile == 128
+    g.tile = 0
+    assert rd.rd_mesh_tile_info(g.h)["tiles"] == 0
+    g.close()
+
+
+def test_tune_restores_state(orc, rd):
+    m = I.split_square(129, diagonal="random", seed=6)
+    W = I.ic_kelvin_helmholtz(m, seed=6)
+    g = rd.Mesh(m)
+    g.set_state(W)
+    say("tune 129^2")
+    best, table = g.tune(0.4, rd.B, rd.RK2, rd.FP64, n_steps=3)
+    say(f"  tuner table {table} -> {best}")
+    assert best in table and table[best] > 0
+    assert g.tile == best
+    assert np.array_equal(g.get_state(), W)
+    g.step_cfl(2, 0.4, rd.B, rd.RK2, rd.FP64)
+    a = g.get_state()
+    g.close()
+    b = run(rd, m, W, 0.0, rd.B, rd.RK2, rd.FP64, 0, n=2, cfl=0.4)
+    assert err(a, b) <= 1e-13
+
+
+def test_tiled_batch_bitwise_equals_single_runs(orc, rd):
+    sides = [17, 33, 9, 40, 24, 3, 50]
+    meshes, states = I.batch_problem(seed=3, sides=sides)
+    for prec in (rd.FP64, rd.FP32_ACC64):
+        singles = [run(rd, m, W, 0.0, rd.B, rd.RK2, prec, 64, n=6, cfl=0.4) for m, W in zip(meshes, states)]
+        gm = [rd.Mesh(m) for m in meshes]
+        for g, W in zip(gm, states):
+            g.set_state(W)
+        b = rd.Batch(gm)
+        b.set_tile(64)
+        say(f"tiled batch run prec={prec}")
+        b.run(3, 0.4, rd.B, rd.RK2, prec)
+        b.run(3, 0.4, rd.B, rd.RK2, prec)
+        for g, ref in zip(gm, singles):
+            assert np.array_equal(g.get_state(), ref)
+        # the tuner leaves the members alone and keeps results bitwise
+        for g, W in zip(gm, states):
+            g.set_state(W)
+        best, table = b.tune(0.4, rd.B, rd.RK2, prec, n_steps=4, candidates=[0, 32, 64, 128])
+        say(f"  batch tuner {table} -> {best}")
+        for g, W in zip(gm, states):
+            assert np.array_equal(g.get_state(), W)
+        if best != 0:
+            b.run(6, 0.4, rd.B, rd.RK2, prec)
+            for g, ref in zip(gm, singles):
+                assert np.array_equal(g.get_state(), ref)
+        b.close()
+        for g in gm:
+            g.close()
+    m, W = meshes[3], states[3]
+    om = orc.OracleMesh(m)
+    ref = W
+    for _ in range(6):
+        ref = om.step(ref, om.max_dt(ref, 0.4), orc.B, orc.RK2)
+    assert err(run(rd, m, W, 0.0, rd.B, rd.RK2, rd.FP64, 64, n=6, cfl=0.4), ref) <= 1e-11
+
+
+def test_tiled_kh_2048_full_size(orc, rd):
+    """2048x2048 periodic Kelvin-Helmholtz, B / RK2, one CFL step in the tiled
+    form at the tile sizes the benchmark's tuner chooses between."""
+    m = I.split_square(2048)
+    om = orc.OracleMesh(m)
+    W = I.ic_kelvin_helmholtz(m, seed=0)
+    dt = om.max_dt(W, 0.4)
+    ref = om.step(W, dt, orc.B, orc.RK2)
+    t64, t32 = tols(om, W, dt, orc.B, orc.RK2, ref=ref)
+    g = rd.Mesh(m)
+    out = {}
+    for tile in (256, 128):
+        g.tile = tile
+        for prec in (rd.FP64, rd.FP32_ACC64):
+            say(f"tiled kh 2048 tile={tile} prec={prec}")
+            g.set_state(W)
+            g.step_cfl(1, 0.4, rd.B, rd.RK2, prec)
+            out[tile, prec] = g.get_state()
+    g.close()
+    e64, e32 = err(out[256, 0], ref), err(out[256, 1], ref)
+    say(f"  tiled kh 2048: fp64 {e64:.2e} (tol {t64:.1e}) fp32 {e32:.2e} (tol {t32:.1e})")
+    assert e64 <= t64 and e32 <= t32
+    assert np.array_equal(out[128, 0], out[256, 0]) and np.array_equal(out[128, 1], out[256, 1])
