@@ -98,9 +98,13 @@ __host__ __device__ inline void apply_full_bar(const Roe<double>& q, const Corne
   gd_bar(q, k, y, q.c * cgb, db, yb, qb, kb);
 }
 
-// Transpose of build_A.
-__host__ __device__ inline void build_A_bar(const Roe<double>& q, const Corner<double> k[3], const double Ab[4][4],
-                                            RoeBar& qb, CornerBar kb[3]) {
+// Transpose of build_A for the rank-2 cotangent A_bar = -(a b^T + c d^T)
+// (the cotangent of A in x = A^{-1} rhs for two right-hand sides): every
+// contraction of A_bar is formed from dot products with a, b, c, d.
+__host__ __device__ inline void build_A_bar(const Roe<double>& q, const Corner<double> k[3], const double a[4],
+                                            const double b[4], const double c[4], const double dd[4], RoeBar& qb,
+                                            CornerBar kb[3]) {
+  auto dot = [](const double* x, const double* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2] + x[3] * y[3]; };
   const double G[4] = {q.ac, -q.g1 * q.uc, -q.g1 * q.vc, q.g1 * q.ic};
   const double E[4] = {1.0, q.u, q.v, q.h};
   double P[3], Qv[3];
@@ -122,28 +126,27 @@ __host__ __device__ inline void build_A_bar(const Roe<double>& q, const Corner<d
   double nvv[4];
   for (int r = 0; r < 4; ++r) nvv[r] = q.c * sQN[r];
   // A = L3 I + E ev^T + nvv G^T + S
-  double L3b = Ab[0][0] + Ab[1][1] + Ab[2][2] + Ab[3][3];
-  double Eb[4] = {0, 0, 0, 0}, evb[4] = {0, 0, 0, 0}, nvvb[4] = {0, 0, 0, 0}, Gb[4] = {0, 0, 0, 0};
-  for (int r = 0; r < 4; ++r)
-    for (int j = 0; j < 4; ++j) {
-      Eb[r] += Ab[r][j] * ev[j];
-      evb[j] += Ab[r][j] * E[r];
-      nvvb[r] += Ab[r][j] * G[j];
-      Gb[j] += Ab[r][j] * nvv[r];
-    }
+  const double L3b = -(dot(a, b) + dot(c, dd));
+  const double bev = dot(b, ev), dev = dot(dd, ev), bG = dot(b, G), dG = dot(dd, G);
+  const double aE = dot(a, E), cE = dot(c, E), an = dot(a, nvv), cn = dot(c, nvv);
+  double Eb[4], evb[4], nvvb[4], Gb[4];
+  for (int r = 0; r < 4; ++r) {
+    Eb[r] = -(a[r] * bev + c[r] * dev);
+    evb[r] = -(b[r] * aE + dd[r] * cE);
+    nvvb[r] = -(a[r] * bG + c[r] * dG);
+    Gb[r] = -(b[r] * an + dd[r] * cn);
+  }
   // S[r][j] = c sum_i P_i N_ir D_ij  (r = 1..3, j = 0..2)
   double Pb[3] = {0, 0, 0}, Qb[3] = {0, 0, 0};
   for (int i = 0; i < 3; ++i) {
     const double Nr[4] = {0.0, k[i].nx, k[i].ny, k[i].w};
     const double Dc[4] = {-k[i].w, k[i].nx, k[i].ny, 0.0};
-    double acc = 0.0, wb = 0.0;
-    for (int r = 1; r < 4; ++r)
-      for (int j = 0; j < 3; ++j) acc += Ab[r][j] * Nr[r] * Dc[j];
+    const double aN = dot(a, Nr), cN = dot(c, Nr), bD = dot(b, Dc), dD = dot(dd, Dc);
+    const double acc = -(aN * bD + cN * dD);
     Pb[i] += q.c * acc;
     qb.c += P[i] * acc;
     // w appears as N_i3 (row 3) and as -D_i0 (column 0)
-    for (int j = 0; j < 3; ++j) wb += Ab[3][j] * Dc[j];
-    for (int r = 1; r < 4; ++r) wb -= Ab[r][0] * Nr[r];
+    const double wb = -(a[3] * bD + c[3] * dD) + (b[0] * aN + dd[0] * cN);
     kb[i].w += q.c * P[i] * wb;
   }
   // nvv = c sQN
@@ -287,21 +290,28 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
     xN[r] = Ai[r][0] * bN[0] + Ai[r][1] * bN[1] + Ai[r][2] * bN[2] + Ai[r][3] * bN[3];
     xL[r] = Ai[r][0] * rhs1[0] + Ai[r][1] * rhs1[1] + Ai[r][2] * rhs1[2] + Ai[r][3] * rhs1[3];
   }
-  double yN[3][4], pN[3][4], PN[3][4], pl[3][4];
+  // per corner: N part pN (stage 2: total PN), LDA part pl; kept are only
+  // the blend's sums and the signs of PN (the reverse recomputes the rest)
+  double th[4] = {0, 0, 0, 0}, den[4] = {0, 0, 0, 0}, thb[4] = {0, 0, 0, 0};
+  unsigned spos = 0, sneg = 0;  // bit 4 i + k: PN_ik > 0, PN_ik < 0
   for (int i = 0; i < 3; ++i) {
-    for (int k = 0; k < 4; ++k) yN[i][k] = dWh[i][k] + xN[k];
-    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN[i], pN[i]);
+    double yN[4], pN[4], PN[4], pl[4];
+    for (int k = 0; k < 4; ++k) yN[k] = dWh[i][k] + xN[k];
+    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN, pN);
     for (int k = 0; k < 4; ++k)
-      PN[i][k] = STAGE == 1 ? pN[i][k]
-                            : s2->mass * (s2->dw[i][k] * s2->idt) + 0.5 * (s2->keepN[i][k] + pN[i][k]);
-    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, pl[i]);
+      PN[k] = STAGE == 1 ? pN[k] : s2->mass * (s2->dw[i][k] * s2->idt) + 0.5 * (s2->keepN[i][k] + pN[k]);
+    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, pl);
+    for (int k = 0; k < 4; ++k) {
+      den[k] = den[k] + fabs(PN[k]);
+      thb[k] = thb[k] + ob[i][k] * (PN[k] - pl[k]);
+      spos |= (PN[k] > 0.0 ? 1u : 0u) << (4 * i + k);
+      sneg |= (PN[k] < 0.0 ? 1u : 0u) << (4 * i + k);
+    }
   }
-  double th[4] = {0, 0, 0, 0}, den[4] = {0, 0, 0, 0};
   bool active[4] = {false, false, false, false};  // Theta_k = |r_k| / den_k, not 0/0, not clamped
   int pick = 0;
   if (SCHEME >= SCH_B) {
     for (int k = 0; k < 4; ++k) {
-      den[k] = fabs(PN[0][k]) + fabs(PN[1][k]) + fabs(PN[2][k]);
       const double qq = den[k] == 0.0 ? 0.0 : fabs(rhs1[k]) / den[k];
       active[k] = den[k] != 0.0 && !(qq > 1.0);
       th[k] = qq > 1.0 ? 1.0 : qq;
@@ -320,24 +330,8 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
   // ---------------- reverse ----------------
   RoeBar qb;
   CornerBar kb[3];
-  double PNb[3][4], plb[3][4], rhs1b[4] = {0, 0, 0, 0};
-  for (int i = 0; i < 3; ++i)
-    for (int k = 0; k < 4; ++k) {
-      if (SCHEME == SCH_N) {
-        PNb[i][k] = ob[i][k];
-        plb[i][k] = 0.0;
-      } else if (SCHEME == SCH_LDA) {
-        PNb[i][k] = 0.0;
-        plb[i][k] = ob[i][k];
-      } else {
-        PNb[i][k] = ob[i][k] * th[k];
-        plb[i][k] = ob[i][k] * (1.0 - th[k]);
-      }
-    }
+  double rhs1b[4] = {0, 0, 0, 0}, denb[4] = {0, 0, 0, 0};
   if (SCHEME >= SCH_B) {
-    double thb[4];
-    for (int k = 0; k < 4; ++k)
-      thb[k] = ob[0][k] * (PN[0][k] - pl[0][k]) + ob[1][k] * (PN[1][k] - pl[1][k]) + ob[2][k] * (PN[2][k] - pl[2][k]);
     if (SCHEME == SCH_BMAX || SCHEME == SCH_BMIN) {
       const double s = thb[0] + thb[1] + thb[2] + thb[3];
       for (int k = 0; k < 4; ++k) thb[k] = k == pick ? s : 0.0;
@@ -346,28 +340,40 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
       if (!active[k]) continue;
       const double qq = fabs(rhs1[k]) / den[k];
       rhs1b[k] += thb[k] * sgn(rhs1[k]) / den[k];
-      const double denb = -thb[k] * qq / den[k];
-      for (int i = 0; i < 3; ++i) PNb[i][k] += denb * sgn(PN[i][k]);
+      denb[k] = -thb[k] * qq / den[k];
     }
   }
   double xLb[4] = {0, 0, 0, 0}, xNb[4] = {0, 0, 0, 0}, dWhb[3][4];
   for (int i = 0; i < 3; ++i)
     for (int k = 0; k < 4; ++k) dWhb[i][k] = 0.0;
-  double pNb[3][4];
   for (int i = 0; i < 3; ++i) {
+    double PNb[4], plb[4], pNb[4], yN[4];
     for (int k = 0; k < 4; ++k) {
-      if (STAGE == 1) {
-        pNb[i][k] = PNb[i][k] + kNb[i][k];
+      if (SCHEME == SCH_N) {
+        PNb[k] = ob[i][k];
+        plb[k] = 0.0;
+      } else if (SCHEME == SCH_LDA) {
+        PNb[k] = 0.0;
+        plb[k] = ob[i][k];
       } else {
-        pNb[i][k] = 0.5 * PNb[i][k];
-        s2b->keepN[i][k] = 0.5 * PNb[i][k];
-        s2b->dw[i][k] = s2->mass * s2->idt * PNb[i][k];
+        const unsigned bit = 1u << (4 * i + k);
+        const double sg = (spos & bit) ? 1.0 : ((sneg & bit) ? -1.0 : 0.0);
+        PNb[k] = ob[i][k] * th[k] + denb[k] * sg;
+        plb[k] = ob[i][k] * (1.0 - th[k]);
       }
+      if (STAGE == 1) {
+        pNb[k] = PNb[k] + kNb[i][k];
+      } else {
+        pNb[k] = 0.5 * PNb[k];
+        s2b->keepN[i][k] = 0.5 * PNb[k];
+        s2b->dw[i][k] = s2->mass * s2->idt * PNb[k];
+      }
+      yN[k] = dWh[i][k] + xN[k];
     }
     double yb[4] = {0, 0, 0, 0};
-    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, plb[i], xLb, qb, kb[i], kb[i].l3p, kb[i].h1p,
+    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, plb, xLb, qb, kb[i], kb[i].l3p, kb[i].h1p,
                     kb[i].h2p);
-    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN[i], pNb[i], yb, qb, kb[i], kb[i].l3p, kb[i].h1p,
+    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN, pNb, yb, qb, kb[i], kb[i].l3p, kb[i].h1p,
                     kb[i].h2p);
     for (int k = 0; k < 4; ++k) {
       dWhb[i][k] += yb[k];
@@ -380,9 +386,6 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
     bNb[c] = Ai[0][c] * xNb[0] + Ai[1][c] * xNb[1] + Ai[2][c] * xNb[2] + Ai[3][c] * xNb[3];
     rb[c] = Ai[0][c] * xLb[0] + Ai[1][c] * xLb[1] + Ai[2][c] * xLb[2] + Ai[3][c] * xLb[3];
   }
-  double Ab[4][4];
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) Ab[r][c] = -(bNb[r] * xN[c] + rb[r] * xL[c]);
   for (int k = 0; k < 4; ++k) rhs1b[k] += rb[k];
   double phiTb[4];
   if (STAGE == 1) {
@@ -395,7 +398,7 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
       for (int i = 0; i < 3; ++i) s2b->dw[i][k] += rateb;
     }
   }
-  build_A_bar(q, kc, Ab, qb, kb);
+  build_A_bar(q, kc, bNb, xN, rb, xL, qb, kb);
   for (int i = 1; i < 3; ++i) {
     apply_split_bar(q, kc[i], kc[i].l3m, kc[i].h1m, kc[i].h2m, dWh[i], bNb, dWhb[i], qb, kb[i], kb[i].l3m, kb[i].h1m,
                     kb[i].h2m);
@@ -560,7 +563,8 @@ __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const Adj
   s2.idt = 1.0 / d.dt[0];
   double ob[3][4];
   for (int i = 0; i < 3; ++i) {
-    Zc[i] = d.Z[iv[i]];
+    // W* = W^n at ghosts, whose parameter vectors the stage-1 gather leaves alone
+    Zc[i] = (d.bc && is_ghost(d.bc[iv[i]])) ? a.Zn[iv[i]] : d.Z[iv[i]];
     const D4 dw = ld4<double>(d.dW, iv[i]);
     const D4 kn = ld4<double>(d.keepN, 3 * t + i);
     for (int k = 0; k < 4; ++k) {

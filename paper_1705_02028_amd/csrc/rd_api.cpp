@@ -891,13 +891,16 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     HIPCHK(hipMemcpyAsync(m->adjIn, W_n, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, s));
     src = m->adjIn;
   }
-  HIPCHK(rd::launch_set_state(d, src, 0, s));
-  HIPCHK(rd::launch_copy4(m->adj.Zn, d.Z, nv, s));
+  // parameter vectors at W^n go straight to Zn (read by the stage-1 passes and
+  // the adjoint); the stage-1 gather writes those at W* to the mesh's Z
+  rd::Dev dn = d;
+  dn.Z = m->adj.Zn;
+  HIPCHK(rd::launch_set_state(dn, src, 0, s));
   HIPCHK(rd::launch_set_scalar(d.dt, dt, s));
   const bool rk2 = time == RD_RK2;
   if (rk2) {
-    HIPCHK(rd::launch_wall(d, false, s));
-    HIPCHK(rd::launch_tri(d, 0, scheme, 1, true, false, s));
+    HIPCHK(rd::launch_wall(dn, false, s));
+    HIPCHK(rd::launch_tri(dn, 0, scheme, 1, true, false, s));
     HIPCHK(rd::launch_gather(d, 0, rd::G_STAGE1, nullptr, s));
   }
   const double* lsrc = lam_np1;

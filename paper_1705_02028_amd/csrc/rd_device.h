@@ -271,11 +271,11 @@ __host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x
 
 // Blend of Section 3.3.3: Theta_k = |res_k| / sum_i |N_{i,k}| (0 if the sum is
 // 0, at most 1); BMAX / BMIN use the largest / smallest Theta_k for all k.
+// den_k = sum_i |N_{i,k}| is accumulated by the caller in corner order.
 template <typename R, int SCHEME>
-__host__ __device__ inline void blend_theta(const R res[4], const R n[3][4], R th[4]) {
+__host__ __device__ inline void blend_theta(const R res[4], const R den[4], R th[4]) {
   for (int k = 0; k < 4; ++k) {
-    R den = (R)fabs(n[0][k]) + (R)fabs(n[1][k]) + (R)fabs(n[2][k]);
-    R q = den == R(0) ? R(0) : (R)fabs(res[k]) * rcp(den);
+    R q = den[k] == R(0) ? R(0) : (R)fabs(res[k]) * rcp(den[k]);
     th[k] = q > R(1) ? R(1) : q;
   }
   if (SCHEME == SCH_BMAX || SCHEME == SCH_BMIN) {
@@ -360,6 +360,11 @@ struct GlobalIO {
     reinterpret_cast<Q4<R>*>(d.C)[ip[i]] = q;
   }
   __host__ __device__ void lam(int i, double x) const { d.lam[ip[i]] = x; }
+  // Where the corner coefficients wait while the 4x4 solve runs (kept in
+  // registers here; see CornerLds).
+  template <typename C> __host__ __device__ void park(const C*) const {}
+  template <typename C> __host__ __device__ C corner(const C* k, int i) const { return k[i]; }
+  static constexpr bool kLean = false;
 };
 
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, class IO>
@@ -479,43 +484,58 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     b0[k] = bN[k];
     b1[k] = rhs1[k];
   }
+  io.park(kc);
   solve2(A, b0, b1, xN, xL);
-  if (needN) {
-    for (int i = 0; i < 3; ++i) {
-      R y[4];
-      for (int k = 0; k < 4; ++k) y[k] = dWh[i][k] + xN[k];
-      apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, y, pN[i]);
-    }
-  }
-  if (STAGE == 1 && SAVE) {
-    if (needN)
-      for (int i = 0; i < 3; ++i) st4<R>(d.keepN, 3 * t + i, pN[i]);
-    st4<R>(d.keepT, t, phiT);
-  }
-  if (STAGE == 2 && needN) {
-    // Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2; the
-    // per-vertex differences are reloaded here (cached) to keep them out of
-    // registers across the solve
-    for (int i = 0; i < 3; ++i) {
+  // N part of corner i: phi^N_i, or in stage 2
+  //   Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2
+  // (the per-vertex differences are reloaded here, cached, to keep them out
+  // of registers across the solve)
+  auto n_part = [&](int i, R o[4]) {
+    R y[4];
+    for (int k = 0; k < 4; ++k) y[k] = dWh[i][k] + xN[k];
+    const Corner<R> ki = io.corner(kc, i);
+    apply_split(q, ki, ki.l3p, ki.h1p, ki.h2p, y, o);
+    if (STAGE == 1 && SAVE) st4<R>(d.keepN, 3 * t + i, o);
+    if (STAGE == 2) {
       const Q4<R> kn = ld4<R>(d.keepN, 3 * t + i);
       const Q4<R> dwv = io.dw(i);
-      for (int k = 0; k < 4; ++k) pN[i][k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn.v[k] + pN[i][k]);
+      for (int k = 0; k < 4; ++k) o[k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn.v[k] + o[k]);
+    }
+  };
+  // With a lean IO the blend recomputes each corner's N part instead of
+  // keeping all three (same arithmetic, so the same values).
+  constexpr bool lean = IO::kLean && SCHEME >= SCH_B;
+  R den[4] = {R(0), R(0), R(0), R(0)};
+  if (needN) {
+    for (int i = 0; i < 3; ++i) {
+      R o[4];
+      n_part(i, o);
+      for (int k = 0; k < 4; ++k) {
+        den[k] = den[k] + (R)fabs(o[k]);
+        if (!lean) pN[i][k] = o[k];
+      }
     }
   }
-  // rhs1 is the residual being split (phi^T or Phi^T); pN its N parts
+  if (STAGE == 1 && SAVE) st4<R>(d.keepT, t, phiT);
+  // rhs1 is the residual being split (phi^T or Phi^T)
   R th[4] = {R(0), R(0), R(0), R(0)};
-  if (SCHEME >= SCH_B) blend_theta<R, SCHEME>(rhs1, pN, th);
+  if (SCHEME >= SCH_B) blend_theta<R, SCHEME>(rhs1, den, th);
   for (int i = 0; i < 3; ++i) {
     R out[4];
     if (SCHEME == SCH_N) {
       for (int k = 0; k < 4; ++k) out[k] = pN[i][k];
     } else {
       R pl[4];
-      apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, pl);
+      const Corner<R> ki = io.corner(kc, i);
+      apply_split(q, ki, ki.l3p, ki.h1p, ki.h2p, xL, pl);
       if (SCHEME == SCH_LDA) {
         for (int k = 0; k < 4; ++k) out[k] = pl[k];
       } else {
-        for (int k = 0; k < 4; ++k) out[k] = pl[k] + th[k] * (pN[i][k] - pl[k]);
+        R pn[4];
+        if (lean) n_part(i, pn);
+        else
+          for (int k = 0; k < 4; ++k) pn[k] = pN[i][k];
+        for (int k = 0; k < 4; ++k) out[k] = pl[k] + th[k] * (pn[k] - pl[k]);
       }
     }
     io.part(i, out);

@@ -9,13 +9,58 @@
 
 namespace rd {
 
+// Triangle IO that parks the corner coefficients in LDS (one column per
+// thread, one row per field) while the 4x4 solve runs, so they hold no
+// registers across it.
+template <typename R>
+struct ParkIO : GlobalIO<R> {
+  static constexpr int kRows = 6 * 3;
+  static constexpr bool kLean = false;
+  R* lds;  // [kRows][kBlock]
+  __device__ void park(const Corner<R>* k) const {
+    R* p = lds + threadIdx.x;
+    for (int i = 0; i < 3; ++i) {
+      p[(6 * i + 0) * kBlock] = k[i].nx;
+      p[(6 * i + 1) * kBlock] = k[i].ny;
+      p[(6 * i + 2) * kBlock] = k[i].w;
+      p[(6 * i + 3) * kBlock] = k[i].l3p;
+      p[(6 * i + 4) * kBlock] = k[i].h1p;
+      p[(6 * i + 5) * kBlock] = k[i].h2p;
+    }
+    asm volatile("" ::: "memory");
+  }
+  __device__ Corner<R> corner(const Corner<R>*, int i) const {
+    asm volatile("" ::: "memory");
+    const R* p = lds + threadIdx.x;
+    Corner<R> k;
+    k.nx = p[(6 * i + 0) * kBlock];
+    k.ny = p[(6 * i + 1) * kBlock];
+    k.w = p[(6 * i + 2) * kBlock];
+    k.l3p = p[(6 * i + 3) * kBlock];
+    k.h1p = p[(6 * i + 4) * kBlock];
+    k.h2p = p[(6 * i + 5) * kBlock];
+    return k;
+  }
+};
+
 // One thread per triangle. (A persistent grid with the next triangle's loads
 // software-pipelined was measured slower: fewer waves in flight and, with
 // per-workgroup chunks, scattered working sets.)
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
-__global__ __launch_bounds__(kBlock, TriWaves<R>::value) void k_tri(Dev d) {
+__global__ __launch_bounds__(kBlock, (TriShape<R, SCHEME, STAGE, SAVE>::waves)) void k_tri(Dev d) {
   const int64_t t = xcd_block() * kBlock + threadIdx.x;
-  if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE, CFL>(t, d);
+  if constexpr (TriShape<R, SCHEME, STAGE, SAVE>::park) {
+    __shared__ R park[ParkIO<R>::kRows * kBlock];
+    if (t < d.nt) {
+      TriIn<R> in;
+      tri_load_ids<R>(t, d, in);
+      tri_load_verts<R, CFL>(d, in);
+      const ParkIO<R> io{{d, in.iv, in.ip}, park};
+      tri_compute<R, SCHEME, STAGE, SAVE, CFL>(t, in, d, io);
+    }
+  } else if (t < d.nt) {
+    tri_body<R, SCHEME, STAGE, SAVE, CFL>(t, d);
+  }
 }
 
 template <typename R, int MODE>
@@ -35,22 +80,20 @@ __global__ __launch_bounds__(kBlock) void k_cfl_tri(Dev d) {
   if (t < d.nt) cfl_tri_body(t, d);
 }
 
+// Per-vertex CFL bounds 2 V_i / sum l_max lambda_max (summed from the sliced
+// corner terms, or read from the bounds the tiled passes store) and their
+// block minima.
+template <bool FROM_CFLV>
 __global__ __launch_bounds__(kBlock) void k_cfl_vertex(Dev d, CflPlan p) {
   const int b = blockIdx.x;
   const int64_t v = (int64_t)p.blk_v0[b] + threadIdx.x;
-  const double x = v < p.blk_v1[b] ? cfl_vertex_bound(v, d) : INFINITY;
+  double x = INFINITY;
+  if (v < p.blk_v1[b]) x = FROM_CFLV ? d.cflv[v] : cfl_vertex_bound(v, d);
   const double m = block_min(x);
   if (threadIdx.x == 0) p.part[b] = m;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cfl_vmin(Dev d, CflPlan p) {
-  const int b = blockIdx.x;
-  const int64_t v = (int64_t)p.blk_v0[b] + threadIdx.x;
-  const double x = v < p.blk_v1[b] ? d.cflv[v] : INFINITY;
-  const double m = block_min(x);
-  if (threadIdx.x == 0) p.part[b] = m;
-}
-
+// Per-mesh minimum over the mesh's blocks -> dt.
 __global__ __launch_bounds__(kBlock) void k_cfl_final(Dev d, CflPlan p, double cfl) {
   const int m = blockIdx.x;
   double x = INFINITY;
@@ -224,8 +267,8 @@ hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s, bool tiled) {
 
 hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s) {
   if (part == 0) hipLaunchKernelGGL(k_cfl_tri, dim3(nblk(d.nt)), dim3(kBlock), 0, s, d);
-  else if (part == 1) hipLaunchKernelGGL(k_cfl_vertex, dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
-  else if (part == 3) hipLaunchKernelGGL(k_cfl_vmin, dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else if (part == 1) hipLaunchKernelGGL((k_cfl_vertex<false>), dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else if (part == 3) hipLaunchKernelGGL((k_cfl_vertex<true>), dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
   else hipLaunchKernelGGL(k_cfl_final, dim3(p.nmesh), dim3(kBlock), 0, s, d, p, cfl);
   return hipGetLastError();
 }

@@ -13,8 +13,7 @@
 //           residual R1 (and the CFL bound), stage 2 the new state.
 // Shared vertices are finished by a vertex pass over the shared list. Stage 1
 // never forms W* in HBM: stage 2 (and the wall term at W*) rebuild it as
-// W^n - (dt/V) R1, by the arithmetic of the two-pass gather, so both forms
-// agree bit for bit.
+// W^n - (dt/V) R1, by the arithmetic of the two-pass gather.
 #pragma once
 
 #include "rd_device.h"
@@ -102,6 +101,9 @@ struct TileIO {
     if (dst[i] < 0) L.lam[-1 - dst[i]] = x;
     else lams[dst[i]] = x;
   }
+  template <typename C> __host__ __device__ void park(const C*) const {}
+  template <typename C> __host__ __device__ C corner(const C* k, int i) const { return k[i]; }
+  static constexpr bool kLean = false;
 };
 
 // ---- phase bodies (tile = workgroup id, l / j = local vertex / triangle) --

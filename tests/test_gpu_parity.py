@@ -299,6 +299,33 @@ def test_sod_1024_one_step_full_size(orc, rd):
         assert e64 <= t64 and e32 <= t32
 
 
+@pytest.mark.parametrize("tile", [0, 256])
+def test_sod_1024_device_dt_sequence(orc, rd, tile):
+    """20 steps with the time step reduced on the device (rd_step_cfl) equal
+    20 steps with the oracle's CFL limit of each GPU state passed in from the
+    host: at full size every device reduction gives the oracle's dt."""
+    m = I.split_square(1024, periodic=(False, False), bc=("ghost", "wall"))
+    om = orc.OracleMesh(m)
+    W0 = I.ic_sod(m)
+    g = rd.Mesh(m)
+    g.tile = tile
+    g.set_state(W0)
+    say(f"sod 1024 device dt tile={tile}")
+    g.step_cfl(20, 0.4, rd.B, rd.RK2, rd.FP64)
+    a = g.get_state()
+    g.set_state(W0)
+    W = W0
+    for n in range(20):
+        dt = om.max_dt(W, 0.4)
+        assert abs(g.max_dt(0.4) - dt) <= 1e-14 * dt
+        g.step(dt, rd.B, rd.RK2, rd.FP64)
+        W = g.get_state()
+    g.close()
+    e = err(a, W)
+    say(f"  device-dt vs host-dt run: {e:.2e}")
+    assert e <= 1e-13
+
+
 def test_kh_2048_one_step_full_size(orc, rd):
     """2048x2048 periodic Kelvin-Helmholtz (8,380,418 triangles), B / RK2,
     the launch configuration the benchmark times."""
