@@ -641,14 +641,13 @@ __host__ __device__ inline void wall_bar(const Dev& d, int64_t v, const D4* src,
 __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const AdjDev& a) {
   double zb[4] = {0, 0, 0, 0}, wb[4] = {0, 0, 0, 0};
   const int32_t deg = d.row[v + 1] - d.row[v];
-  for (int32_t j = 0; j < deg; ++j) {
-    const int64_t s = d.sbeg[v] + 64 * (int64_t)j;
-    const D4 cz = a.cZ[s], cw = a.cW[s];
-    for (int k = 0; k < 4; ++k) {
-      zb[k] += cz.v[k];
-      wb[k] += cw.v[k];
-    }
-  }
+  const int64_t s0 = d.sbeg[v];
+  for_loaded(deg, [&](int32_t j) { return a.cZ[s0 + 64 * (int64_t)j]; }, [&](int32_t, const D4& cz) {
+    for (int k = 0; k < 4; ++k) zb[k] += cz.v[k];
+  });
+  for_loaded(deg, [&](int32_t j) { return a.cW[s0 + 64 * (int64_t)j]; }, [&](int32_t, const D4& cw) {
+    for (int k = 0; k < 4; ++k) wb[k] += cw.v[k];
+  });
   const D4 ws = d.Ws[v], l = a.lam[v];
   double ls[4];
   for (int k = 0; k < 4; ++k) ls[k] = l.v[k] + wb[k];
@@ -665,10 +664,10 @@ __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const 
 __host__ __device__ inline void adj_gather1_body(int64_t v, const Dev& d, const AdjDev& a, bool rk2, double* out) {
   double zb[4] = {0, 0, 0, 0};
   const int32_t deg = d.row[v + 1] - d.row[v];
-  for (int32_t j = 0; j < deg; ++j) {
-    const D4 cz = a.cZ[d.sbeg[v] + 64 * (int64_t)j];
+  const int64_t s0 = d.sbeg[v];
+  for_loaded(deg, [&](int32_t j) { return a.cZ[s0 + 64 * (int64_t)j]; }, [&](int32_t, const D4& cz) {
     for (int k = 0; k < 4; ++k) zb[k] += cz.v[k];
-  }
+  });
   const D4 w = d.W[v], ls = a.lamS[v], ln = a.lamN[v];
   double r[4];
   for (int k = 0; k < 4; ++k) r[k] = ln.v[k] + ls.v[k];

@@ -591,14 +591,30 @@ __host__ __device__ inline void vertex_epilogue(const Dev& d, int64_t v, const d
   if (!o.ok) d.flag[0] = 1;
 }
 
+// f(j, get(j)) for j = 0, ..., n-1 in that order. The loads of four
+// consecutive j are issued before any is consumed, so a wavefront keeps
+// several independent loads in flight instead of one.
+template <class Get, class F>
+__host__ __device__ inline void for_loaded(int32_t n, const Get& get, const F& f) {
+  using T = decltype(get(0));
+  for (int32_t j = 0; j < n; j += 4) {
+    T x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j + u < n) x[u] = get(j + u);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j + u < n) f(j + u, x[u]);
+  }
+}
+
 // Sum of a vertex's n parts get(0), ..., get(n-1) in that order, in FP64
 // (Neumaier-compensated when the parts are FP32).
 template <typename R, class Get>
 __host__ __device__ inline void sum_parts(int32_t n, const Get& get, double acc[4]) {
   double cmp[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k = 0; k < 4; ++k) acc[k] = 0.0;
-  for (int32_t j = 0; j < n; ++j) {
-    const Q4<R> c = get(j);
+  for_loaded(n, get, [&](int32_t, const Q4<R>& c) {
     for (int k = 0; k < 4; ++k) {
       if (sizeof(R) == sizeof(double)) {
         acc[k] += (double)c.v[k];
@@ -609,7 +625,7 @@ __host__ __device__ inline void sum_parts(int32_t n, const Get& get, double acc[
         acc[k] = tsum;
       }
     }
-  }
+  });
   if (sizeof(R) != sizeof(double))
     for (int k = 0; k < 4; ++k) acc[k] = acc[k] + cmp[k];
 }
@@ -738,7 +754,7 @@ __host__ __device__ inline double cfl_vertex_bound(int64_t v, const Dev& d) {
   double acc = 0.0;
   const int32_t deg = d.row[v + 1] - d.row[v];
   const int64_t s0 = d.sbeg[v];
-  for (int32_t j = 0; j < deg; ++j) acc += d.lam[s0 + 64 * (int64_t)j];
+  for_loaded(deg, [&](int32_t j) { return d.lam[s0 + 64 * (int64_t)j]; }, [&](int32_t, double x) { acc += x; });
   return 2.0 * d.V[v] / acc;
 }
 

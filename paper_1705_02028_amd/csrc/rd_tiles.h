@@ -216,7 +216,7 @@ __host__ __device__ inline void shared_sum1(int64_t k, const Dev& d, const Tiles
   const int64_t s0 = tl.ssbeg[k];
   if (CFL) {
     double acc = 0.0;
-    for (int32_t j = 0; j < n; ++j) acc += tl.lams[s0 + 64 * (int64_t)j];
+    for_loaded(n, [&](int32_t j) { return tl.lams[s0 + 64 * (int64_t)j]; }, [&](int32_t, double x) { acc += x; });
     d.cflv[v] = 2.0 * d.V[v] / acc;
   }
   const int32_t code = d.bc ? d.bc[v] : -1;
