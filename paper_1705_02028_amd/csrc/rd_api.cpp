@@ -236,7 +236,7 @@ rd_status run_step(rd_mesh* m, int scheme, int time, int fp32, double cfl, hipEv
   HIPCHK(mark(RD_K_SHARED1));
   HIPCHK(mark(RD_K_CFL));
   if (with_cfl) {
-    HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 1, s));
+    HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 1, s, fp32));
     HIPCHK(rd::launch_cfl_part(d, m->cfl, cfl, 2, s));
   }
   HIPCHK(mark(RD_K_GATHER1));

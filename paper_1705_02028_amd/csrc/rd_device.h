@@ -86,7 +86,8 @@ struct Dev {
   void* keepT = nullptr;  // [nt] stage-1 triangle residual (D4 or F4)
   D4* WCn = nullptr;      // [nwv] wall term at W^n
   D4* WCs = nullptr;      // [nwv] wall term at W*
-  double* lam = nullptr;  // [ns] l_max^T lambda_max^T, sliced layout
+  void* lam = nullptr;    // [ns] l_max^T lambda_max^T, sliced layout: float from the FP32 triangle
+                          // passes, double from the FP64 ones and from the CFL-only pass
   double* dt = nullptr;   // [n meshes] time step
   int* flag = nullptr;    // non-physical state latch
   // tiled form
@@ -359,7 +360,7 @@ struct GlobalIO {
     for (int k = 0; k < 4; ++k) q.v[k] = out[k];
     reinterpret_cast<Q4<R>*>(d.C)[ip[i]] = q;
   }
-  __host__ __device__ void lam(int i, double x) const { d.lam[ip[i]] = x; }
+  __host__ __device__ void lam(int i, double x) const { reinterpret_cast<R*>(d.lam)[ip[i]] = (R)x; }
   // Where the corner coefficients wait while the 4x4 solve runs (kept in
   // registers here; see CornerLds).
   template <typename C> __host__ __device__ void park(const C*) const {}
@@ -746,15 +747,17 @@ __host__ __device__ inline void cfl_tri_body(int64_t t, const Dev& d) {
     lam = rmax(lam, d.sig[iv[i]]);
   }
   const double lt = lmax * lam;
-  for (int i = 0; i < 3; ++i) d.lam[d.pos[i * nt + t]] = lt;
+  for (int i = 0; i < 3; ++i) reinterpret_cast<double*>(d.lam)[d.pos[i * nt + t]] = lt;
 }
 
-// 2 V_i / sum_{T ni i} l_max lambda_max of one vertex.
+// 2 V_i / sum_{T ni i} l_max lambda_max of one vertex (terms of type R).
+template <typename R = double>
 __host__ __device__ inline double cfl_vertex_bound(int64_t v, const Dev& d) {
   double acc = 0.0;
   const int32_t deg = d.row[v + 1] - d.row[v];
   const int64_t s0 = d.sbeg[v];
-  for_loaded(deg, [&](int32_t j) { return d.lam[s0 + 64 * (int64_t)j]; }, [&](int32_t, double x) { acc += x; });
+  const R* lam = reinterpret_cast<const R*>(d.lam);
+  for_loaded(deg, [&](int32_t j) { return lam[s0 + 64 * (int64_t)j]; }, [&](int32_t, R x) { acc += (double)x; });
   return 2.0 * d.V[v] / acc;
 }
 

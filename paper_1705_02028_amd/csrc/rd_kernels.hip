@@ -83,12 +83,12 @@ __global__ __launch_bounds__(kBlock) void k_cfl_tri(Dev d) {
 // Per-vertex CFL bounds 2 V_i / sum l_max lambda_max (summed from the sliced
 // corner terms, or read from the bounds the tiled passes store) and their
 // block minima.
-template <bool FROM_CFLV>
+template <bool FROM_CFLV, typename R>
 __global__ __launch_bounds__(kBlock) void k_cfl_vertex(Dev d, CflPlan p) {
   const int b = blockIdx.x;
   const int64_t v = (int64_t)p.blk_v0[b] + threadIdx.x;
   double x = INFINITY;
-  if (v < p.blk_v1[b]) x = FROM_CFLV ? d.cflv[v] : cfl_vertex_bound(v, d);
+  if (v < p.blk_v1[b]) x = FROM_CFLV ? d.cflv[v] : cfl_vertex_bound<R>(v, d);
   const double m = block_min(x);
   if (threadIdx.x == 0) p.part[b] = m;
 }
@@ -265,10 +265,11 @@ hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s, bool tiled) {
   return hipGetLastError();
 }
 
-hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s) {
+hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s, int fp32) {
   if (part == 0) hipLaunchKernelGGL(k_cfl_tri, dim3(nblk(d.nt)), dim3(kBlock), 0, s, d);
-  else if (part == 1) hipLaunchKernelGGL((k_cfl_vertex<false>), dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
-  else if (part == 3) hipLaunchKernelGGL((k_cfl_vertex<true>), dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else if (part == 1 && fp32) hipLaunchKernelGGL((k_cfl_vertex<false, float>), dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else if (part == 1) hipLaunchKernelGGL((k_cfl_vertex<false, double>), dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else if (part == 3) hipLaunchKernelGGL((k_cfl_vertex<true, double>), dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
   else hipLaunchKernelGGL(k_cfl_final, dim3(p.nmesh), dim3(kBlock), 0, s, d, p, cfl);
   return hipGetLastError();
 }

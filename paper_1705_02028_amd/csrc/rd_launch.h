@@ -28,10 +28,11 @@ hipError_t launch_gather(const Dev& d, int fp32, int mode, double* out_soa, hipS
 // tiled: the stage-2 wall term reads W* rebuilt from R1
 hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s, bool tiled = false);
 hipError_t launch_cfl(const Dev& d, const CflPlan& p, double cfl, hipStream_t s);
-// part 0: l_max lambda_max per triangle corner; part 1: per-vertex bounds
-// (sums of the sliced terms) and block minima; part 3: the same from the
-// bounds the tiled passes store in d.cflv; part 2: per-mesh minimum -> d.dt
-hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s);
+// part 0: l_max lambda_max per triangle corner (FP64); part 1: per-vertex
+// bounds (sums of the sliced terms, float when fp32: as the FP32 triangle
+// pass writes them) and block minima; part 3: the same from the bounds the
+// tiled passes store in d.cflv; part 2: per-mesh minimum -> d.dt
+hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s, int fp32 = 0);
 hipError_t launch_set_state(const Dev& d, const double* soa, int fp32, hipStream_t s);
 hipError_t launch_refresh(const Dev& d, int fp32, hipStream_t s);
 hipError_t launch_get_state(const Dev& d, const D4* src, double* soa, hipStream_t s);
