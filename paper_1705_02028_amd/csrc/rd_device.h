@@ -109,8 +109,10 @@ __host__ __device__ inline double unwrap(double d, double period) {
   return d;
 }
 
-template <typename R> __host__ __device__ inline R rmax(R a, R b) { return a < b ? b : a; }
-template <typename R> __host__ __device__ inline R rmin(R a, R b) { return b < a ? b : a; }
+// max / min of non-NaN values (one v_max / v_min instruction; the sign of a
+// zero result is unspecified, which no result depends on).
+template <typename R> __host__ __device__ inline R rmax(R a, R b) { return fmax(a, b); }
+template <typename R> __host__ __device__ inline R rmin(R a, R b) { return fmin(a, b); }
 
 // Reciprocal: IEEE for FP64; the hardware reciprocal (about 1 ulp) for the
 // FP32 algebra, whose error budget is set by FP32 rounding anyway.
