@@ -552,11 +552,11 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
     d.flag = flag;
     m->scratch = scratch;
     // CFL reduction plan: vertex blocks of kBlock, one segment
-    const int32_t nb = (int32_t)((nv + rd::kBlock - 1) / rd::kBlock);
+    const int32_t nb = (int32_t)((nv + rd::kCflSpan - 1) / rd::kCflSpan);
     std::vector<int32_t> v0(nb), v1(nb), b0 = {0, nb};
     for (int32_t b = 0; b < nb; ++b) {
-      v0[b] = b * rd::kBlock;
-      v1[b] = (int32_t)std::min<int64_t>(nv, (int64_t)(b + 1) * rd::kBlock);
+      v0[b] = b * rd::kCflSpan;
+      v1[b] = (int32_t)std::min<int64_t>(nv, (int64_t)(b + 1) * rd::kCflSpan);
     }
     int32_t *pv0, *pv1, *pb0;
     double* part;
@@ -1016,9 +1016,9 @@ RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd
   for (int k = 0; k < n; ++k) {
     for (int64_t i = voff[k]; i < voff[k + 1]; ++i) vm[i] = k;
     for (int64_t t = toff[k]; t < toff[k + 1]; ++t) tm[t] = k;
-    for (int64_t v = voff[k]; v < voff[k + 1]; v += rd::kBlock) {
+    for (int64_t v = voff[k]; v < voff[k + 1]; v += rd::kCflSpan) {
       v0.push_back((int32_t)v);
-      v1.push_back((int32_t)std::min<int64_t>(v + rd::kBlock, voff[k + 1]));
+      v1.push_back((int32_t)std::min<int64_t>(v + rd::kCflSpan, voff[k + 1]));
     }
     b0.push_back((int32_t)v0.size());
   }

@@ -86,9 +86,12 @@ __global__ __launch_bounds__(kBlock) void k_cfl_tri(Dev d) {
 template <bool FROM_CFLV, typename R>
 __global__ __launch_bounds__(kBlock) void k_cfl_vertex(Dev d, CflPlan p) {
   const int b = blockIdx.x;
-  const int64_t v = (int64_t)p.blk_v0[b] + threadIdx.x;
   double x = INFINITY;
-  if (v < p.blk_v1[b]) x = FROM_CFLV ? d.cflv[v] : cfl_vertex_bound<R>(v, d);
+#pragma unroll
+  for (int u = 0; u < kCflSpan / kBlock; ++u) {
+    const int64_t v = (int64_t)p.blk_v0[b] + u * kBlock + threadIdx.x;
+    if (v < p.blk_v1[b]) x = rmin(x, FROM_CFLV ? d.cflv[v] : cfl_vertex_bound<R>(v, d));
+  }
   const double m = block_min(x);
   if (threadIdx.x == 0) p.part[b] = m;
 }

@@ -10,9 +10,10 @@
 namespace rd {
 
 constexpr int kBlock = 256;
+constexpr int kCflSpan = 4 * kBlock;  // vertices per block of the CFL reduction
 
 // Segmented min-reduction layout for the CFL limit: vertex block b covers
-// vertices [blk_v0[b], blk_v1[b]) of one mesh; mesh m owns blocks
+// vertices [blk_v0[b], blk_v1[b]) (at most kCflSpan) of one mesh; mesh m owns blocks
 // [mesh_b0[m], mesh_b0[m+1]).
 struct CflPlan {
   int32_t nblocks = 0, nmesh = 0;
