@@ -1,6 +1,7 @@
-"""Differentiable multi-step rollout on top of the C ABI.
+"""Differentiable steps on top of the C ABI.
 
-``RDRollout.apply(W0, mesh, dt, n_steps, scheme, time, checkpoint_every)``
+``RDStep.apply(W, mesh, dt, scheme, time)`` is one step with its adjoint as
+the backward. ``RDRollout.apply(W0, mesh, dt, n_steps, scheme, time, checkpoint_every)``
 advances the state ``W0`` (a float64 tensor [4, nv] on the GPU) by
 ``n_steps`` steps of fixed size ``dt`` with ``rd_step`` and returns the final
 state. Its backward pass uses ``rd_adjoint_step`` (the hand-written reverse
@@ -23,6 +24,34 @@ def _state(mesh, like):
     out = torch.empty_like(like)
     rd.rd_get_state(mesh.h, out)
     return out
+
+
+class RDStep(torch.autograd.Function):
+    """One step: ``RDStep.apply(W, mesh, dt, scheme, time)`` returns the state
+    after ``rd_step`` (fixed ``dt``, FP64); its backward is ``rd_adjoint_step``
+    at the saved input state."""
+
+    @staticmethod
+    def forward(ctx, W, mesh, dt, scheme=rd.B, time=rd.RK2):
+        if W.dtype != torch.float64 or not W.is_cuda:
+            raise ValueError("W must be a float64 tensor on the GPU")
+        W = W.contiguous()
+        rd.rd_set_state(mesh.h, W)
+        rd.rd_step(mesh.h, dt, scheme, time, rd.FP64)
+        out = _state(mesh, W)
+        ctx.mesh = mesh
+        ctx.args = (float(dt), int(scheme), int(time))
+        ctx.save_for_backward(W)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (W,) = ctx.saved_tensors
+        dt, scheme, time = ctx.args
+        lam = grad_out.contiguous().to(torch.float64)
+        out = torch.empty_like(lam)
+        rd.rd_adjoint_step(ctx.mesh.h, W, dt, scheme, time, lam, out)
+        return out, None, None, None, None
 
 
 class RDRollout(torch.autograd.Function):

@@ -446,6 +446,33 @@ def test_adjoint_dot_product_against_oracle_jvp(orc, rd, case):
     g.close()
 
 
+def test_rdstep_autograd_matches_oracle_jvp(orc, rd):
+    """torch.autograd through RDStep: <grad of <lam, step(W)>, v> equals
+    <lam, J v> from the oracle's exact forward-mode derivative."""
+    import torch
+    from paper_1705_02028_amd.autograd import RDStep
+    m = I.split_square(25, periodic=(True, False), bc=("ghost", "wall"), diagonal="random", seed=3)
+    W0 = I.random_smooth_state(m, seed=7, amp=0.2)
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W0, 0.4)
+    g = rd.Mesh(m)
+    rng = np.random.default_rng(3)
+    for scheme in (rd.N, rd.B):
+        lam = rng.normal(size=W0.shape)
+        v = rng.normal(size=W0.shape) * np.abs(W0).mean(axis=1, keepdims=True)
+        W = torch.tensor(W0, device="cuda", requires_grad=True)
+        out = RDStep.apply(W, g, dt, scheme, rd.RK2)
+        (out * torch.tensor(lam, device="cuda")).sum().backward()
+        a = float(np.sum(W.grad.cpu().numpy() * v))
+        _, Jv = om.step_jvp(W0, v, dt, scheme, orc.RK2)
+        b = float(np.sum(lam * Jv))
+        scale = float(np.sum(np.abs(lam * Jv)))
+        say(f"RDStep scheme={scheme}: {a:.15e} vs {b:.15e}")
+        assert abs(a - b) <= 1e-12 * scale
+        assert err(out.detach().cpu().numpy(), om.step(W0, dt, scheme, orc.RK2)) <= TOL64
+    g.close()
+
+
 @pytest.mark.parametrize("scheme_name", ["B", "LDA"])
 def test_rollout_gradient_checkpointed(orc, rd, scheme_name):
     """Gradient of sum (rho_T - rho_target)^2 with respect to the initial
