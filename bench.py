@@ -285,6 +285,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--timed-reps", type=int, default=5)
+    ap.add_argument("--renumber", choices=["none", "random", "morton"], default="none",
+                    help="vertex and triangle numbering of the mesh (default: the lattice order)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="triangles per tile of the fused step (0: two-pass form; -1: run the autotuner)")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -315,7 +317,7 @@ def main():
     if args.fp32_table:
         print(json.dumps({"fp32_errors": fp32_table(rd, inputs)}), flush=True)
         return
-    mesh = inputs.split_square(args.N)
+    mesh = inputs.split_square(args.N, renumber=None if args.renumber == "none" else args.renumber, seed=0)
     W0 = inputs.ic_kelvin_helmholtz(mesh, seed=0)
     nt, nv = mesh["nt"], mesh["nv"]
 
@@ -342,7 +344,7 @@ def main():
         "config": {"workload": f"Kelvin-Helmholtz shear layer, {args.N}x{args.N} periodic split-square mesh, "
                                f"B scheme, RK2, CFL {args.cfl} (dt on device each step), "
                                "FP32 distribution + FP64 accumulation",
-                   "triangles": nt, "vertices": nv, "seed": 0},
+                   "triangles": nt, "vertices": nv, "seed": 0, "numbering": args.renumber},
         "roofline": roofline_entry(dom32, b32[dom32], per32[dom32]),
         "kernels_ms": {k: round(v, 5) for k, v in per32.items()},
         "kernels_GBps": {k: round(b32[k] / (v * 1e-3) / 1e9, 1) for k, v in per32.items()
