@@ -365,9 +365,6 @@ struct GlobalIO {
   __host__ __device__ void lam(int i, double x) const { reinterpret_cast<R*>(d.lam)[ip[i]] = (R)x; }
   // Where the corner coefficients wait while the 4x4 solve runs (kept in
   // registers here; see CornerLds).
-  template <typename C> __host__ __device__ void park(const C*) const {}
-  template <typename C> __host__ __device__ C corner(const C* k, int i) const { return k[i]; }
-  static constexpr bool kLean = false;
 };
 
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, class IO>
@@ -487,7 +484,6 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     b0[k] = bN[k];
     b1[k] = rhs1[k];
   }
-  io.park(kc);
   solve2(A, b0, b1, xN, xL);
   // N part of corner i: phi^N_i, or in stage 2
   //   Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2
@@ -496,8 +492,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   auto n_part = [&](int i, R o[4]) {
     R y[4];
     for (int k = 0; k < 4; ++k) y[k] = dWh[i][k] + xN[k];
-    const Corner<R> ki = io.corner(kc, i);
-    apply_split(q, ki, ki.l3p, ki.h1p, ki.h2p, y, o);
+    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, y, o);
     if (STAGE == 1 && SAVE) st4<R>(d.keepN, 3 * t + i, o);
     if (STAGE == 2) {
       const Q4<R> kn = ld4<R>(d.keepN, 3 * t + i);
@@ -505,9 +500,6 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
       for (int k = 0; k < 4; ++k) o[k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn.v[k] + o[k]);
     }
   };
-  // With a lean IO the blend recomputes each corner's N part instead of
-  // keeping all three (same arithmetic, so the same values).
-  constexpr bool lean = IO::kLean && SCHEME >= SCH_B;
   R den[4] = {R(0), R(0), R(0), R(0)};
   if (needN) {
     for (int i = 0; i < 3; ++i) {
@@ -515,7 +507,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
       n_part(i, o);
       for (int k = 0; k < 4; ++k) {
         den[k] = den[k] + (R)fabs(o[k]);
-        if (!lean) pN[i][k] = o[k];
+        pN[i][k] = o[k];
       }
     }
   }
@@ -529,16 +521,11 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
       for (int k = 0; k < 4; ++k) out[k] = pN[i][k];
     } else {
       R pl[4];
-      const Corner<R> ki = io.corner(kc, i);
-      apply_split(q, ki, ki.l3p, ki.h1p, ki.h2p, xL, pl);
+      apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, pl);
       if (SCHEME == SCH_LDA) {
         for (int k = 0; k < 4; ++k) out[k] = pl[k];
       } else {
-        R pn[4];
-        if (lean) n_part(i, pn);
-        else
-          for (int k = 0; k < 4; ++k) pn[k] = pN[i][k];
-        for (int k = 0; k < 4; ++k) out[k] = pl[k] + th[k] * (pn[k] - pl[k]);
+        for (int k = 0; k < 4; ++k) out[k] = pl[k] + th[k] * (pN[i][k] - pl[k]);
       }
     }
     io.part(i, out);

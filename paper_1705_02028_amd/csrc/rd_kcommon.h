@@ -17,20 +17,11 @@ __device__ __forceinline__ int64_t xcd_block() {
   return x * q + (x < r ? x : r) + b / 8;
 }
 
-// Minimum waves per SIMD the triangle kernels are compiled for.
+// Minimum waves per SIMD the triangle kernels are compiled for. (FP64 at 3
+// waves, with the corner coefficients parked in LDS across the solve to
+// avoid spills, was measured slower than 2 waves.)
 template <typename R> struct TriWaves { static constexpr int value = 2; };
 template <> struct TriWaves<float> { static constexpr int value = 4; };
-
-// Shape of a two-pass triangle kernel. The FP64 kernels of stage 1 that keep
-// their N parts (RK2), and of stage 2 for N and LDA, park the corner
-// coefficients in LDS across the 4x4 solve, which lets them run 3 waves per
-// SIMD without register spills (the blended stage-2 kernels would spill).
-template <typename R, int SCHEME, int STAGE, bool SAVE>
-struct TriShape {
-  static constexpr bool park =
-      sizeof(R) == sizeof(double) && ((STAGE == 1 && SAVE) || (STAGE == 2 && SCHEME <= SCH_LDA));
-  static constexpr int waves = park ? 3 : TriWaves<R>::value;
-};
 
 // Minimum over a kBlock-thread workgroup (result valid in every thread).
 __device__ __forceinline__ double block_min(double x) {

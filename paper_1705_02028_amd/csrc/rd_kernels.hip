@@ -9,58 +9,13 @@
 
 namespace rd {
 
-// Triangle IO that parks the corner coefficients in LDS (one column per
-// thread, one row per field) while the 4x4 solve runs, so they hold no
-// registers across it.
-template <typename R>
-struct ParkIO : GlobalIO<R> {
-  static constexpr int kRows = 6 * 3;
-  static constexpr bool kLean = false;
-  R* lds;  // [kRows][kBlock]
-  __device__ void park(const Corner<R>* k) const {
-    R* p = lds + threadIdx.x;
-    for (int i = 0; i < 3; ++i) {
-      p[(6 * i + 0) * kBlock] = k[i].nx;
-      p[(6 * i + 1) * kBlock] = k[i].ny;
-      p[(6 * i + 2) * kBlock] = k[i].w;
-      p[(6 * i + 3) * kBlock] = k[i].l3p;
-      p[(6 * i + 4) * kBlock] = k[i].h1p;
-      p[(6 * i + 5) * kBlock] = k[i].h2p;
-    }
-    asm volatile("" ::: "memory");
-  }
-  __device__ Corner<R> corner(const Corner<R>*, int i) const {
-    asm volatile("" ::: "memory");
-    const R* p = lds + threadIdx.x;
-    Corner<R> k;
-    k.nx = p[(6 * i + 0) * kBlock];
-    k.ny = p[(6 * i + 1) * kBlock];
-    k.w = p[(6 * i + 2) * kBlock];
-    k.l3p = p[(6 * i + 3) * kBlock];
-    k.h1p = p[(6 * i + 4) * kBlock];
-    k.h2p = p[(6 * i + 5) * kBlock];
-    return k;
-  }
-};
-
 // One thread per triangle. (A persistent grid with the next triangle's loads
 // software-pipelined was measured slower: fewer waves in flight and, with
 // per-workgroup chunks, scattered working sets.)
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
-__global__ __launch_bounds__(kBlock, (TriShape<R, SCHEME, STAGE, SAVE>::waves)) void k_tri(Dev d) {
+__global__ __launch_bounds__(kBlock, TriWaves<R>::value) void k_tri(Dev d) {
   const int64_t t = xcd_block() * kBlock + threadIdx.x;
-  if constexpr (TriShape<R, SCHEME, STAGE, SAVE>::park) {
-    __shared__ R park[ParkIO<R>::kRows * kBlock];
-    if (t < d.nt) {
-      TriIn<R> in;
-      tri_load_ids<R>(t, d, in);
-      tri_load_verts<R, CFL>(d, in);
-      const ParkIO<R> io{{d, in.iv, in.ip}, park};
-      tri_compute<R, SCHEME, STAGE, SAVE, CFL>(t, in, d, io);
-    }
-  } else if (t < d.nt) {
-    tri_body<R, SCHEME, STAGE, SAVE, CFL>(t, d);
-  }
+  if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE, CFL>(t, d);
 }
 
 template <typename R, int MODE>

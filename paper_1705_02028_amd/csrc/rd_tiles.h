@@ -101,9 +101,6 @@ struct TileIO {
     if (dst[i] < 0) L.lam[-1 - dst[i]] = x;
     else lams[dst[i]] = x;
   }
-  template <typename C> __host__ __device__ void park(const C*) const {}
-  template <typename C> __host__ __device__ C corner(const C* k, int i) const { return k[i]; }
-  static constexpr bool kLean = false;
 };
 
 // ---- phase bodies (tile = workgroup id, l / j = local vertex / triangle) --
