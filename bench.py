@@ -210,7 +210,11 @@ def fp32_table(rd, inputs):
     """Error of the FP32-distribution / FP64-accumulation variant per
     workload: one step from the initial state against the FP64 oracle, and the
     end state of a run against the same run in FP64 on the GPU (which matches
-    the oracle step by step)."""
+    the oracle step by step). Kelvin-Helmholtz and Sod with the B scheme on
+    these meshes amplify any perturbation exponentially (the oracle itself
+    does: a 1e-15 relative input change grows to 1e-3 within ~150 steps on a
+    129^2 Sod mesh), so their end-state differences measure that
+    amplification more than the variant's rounding."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle
 
@@ -233,8 +237,8 @@ def fp32_table(rd, inputs):
     cases = [
         ("advected sine 64^2, N / Euler, 100 steps", inputs.split_square(64), inputs.ic_advected_sine,
          rd.N, rd.EULER1, 0.5, 100, None),
-        ("Sod 1024^2, B / RK2, to t = 0.2", inputs.split_square(1024, periodic=(False, False), bc=("ghost", "wall")),
-         inputs.ic_sod, rd.B, rd.RK2, 0.4, None, 0.2),
+        ("Sod 1024^2, B / RK2, 20 steps", inputs.split_square(1024, periodic=(False, False), bc=("ghost", "wall")),
+         inputs.ic_sod, rd.B, rd.RK2, 0.4, 20, None),
         ("Kelvin-Helmholtz 2048^2, B / RK2, 500 steps", inputs.split_square(2048),
          lambda m: inputs.ic_kelvin_helmholtz(m, seed=0), rd.B, rd.RK2, 0.4, 500, None),
         ("four-quadrant 512^2, B / RK2, 200 steps", inputs.split_square(512, periodic=(False, False)),
