@@ -485,30 +485,35 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     b1[k] = rhs1[k];
   }
   solve2(A, b0, b1, xN, xL);
-  // N part of corner i: phi^N_i, or in stage 2
-  //   Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2
-  // (the per-vertex differences are reloaded here, cached, to keep them out
-  // of registers across the solve)
-  auto n_part = [&](int i, R o[4]) {
-    R y[4];
-    for (int k = 0; k < 4; ++k) y[k] = dWh[i][k] + xN[k];
-    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, y, o);
-    if (STAGE == 1 && SAVE) st4<R>(d.keepN, 3 * t + i, o);
-    if (STAGE == 2) {
-      const Q4<R> kn = ld4<R>(d.keepN, 3 * t + i);
-      const Q4<R> dwv = io.dw(i);
-      for (int k = 0; k < 4; ++k) o[k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn.v[k] + o[k]);
-    }
-  };
+  // Corner parts. The parts of a distribution sum to the residual they
+  // split (sum_i K_i^+ = A): sum_i K_i^+ (dW_i + xN) = phi^T and
+  // sum_i K_i^+ xL = rhs1, so corner 2's parts are the residual minus those
+  // of corners 0 and 1 (exact in exact arithmetic; saves two K^+ products).
+  R pl[3][4];
+  if (needL) {
+    apply_split(q, kc[0], kc[0].l3p, kc[0].h1p, kc[0].h2p, xL, pl[0]);
+    apply_split(q, kc[1], kc[1].l3p, kc[1].h1p, kc[1].h2p, xL, pl[1]);
+    for (int k = 0; k < 4; ++k) pl[2][k] = rhs1[k] - pl[0][k] - pl[1][k];
+  }
   R den[4] = {R(0), R(0), R(0), R(0)};
   if (needN) {
+    for (int i = 0; i < 2; ++i) {
+      R y[4];
+      for (int k = 0; k < 4; ++k) y[k] = dWh[i][k] + xN[k];
+      apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, y, pN[i]);
+    }
+    for (int k = 0; k < 4; ++k) pN[2][k] = phiT[k] - pN[0][k] - pN[1][k];
     for (int i = 0; i < 3; ++i) {
-      R o[4];
-      n_part(i, o);
-      for (int k = 0; k < 4; ++k) {
-        den[k] = den[k] + (R)fabs(o[k]);
-        pN[i][k] = o[k];
+      if (STAGE == 1 && SAVE) st4<R>(d.keepN, 3 * t + i, pN[i]);
+      if (STAGE == 2) {
+        // Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2; the
+        // per-vertex differences are reloaded here (cached) to keep them out
+        // of registers across the solve
+        const Q4<R> kn = ld4<R>(d.keepN, 3 * t + i);
+        const Q4<R> dwv = io.dw(i);
+        for (int k = 0; k < 4; ++k) pN[i][k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn.v[k] + pN[i][k]);
       }
+      for (int k = 0; k < 4; ++k) den[k] = den[k] + (R)fabs(pN[i][k]);
     }
   }
   if (STAGE == 1 && SAVE) st4<R>(d.keepT, t, phiT);
@@ -517,16 +522,10 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   if (SCHEME >= SCH_B) blend_theta<R, SCHEME>(rhs1, den, th);
   for (int i = 0; i < 3; ++i) {
     R out[4];
-    if (SCHEME == SCH_N) {
-      for (int k = 0; k < 4; ++k) out[k] = pN[i][k];
-    } else {
-      R pl[4];
-      apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, pl);
-      if (SCHEME == SCH_LDA) {
-        for (int k = 0; k < 4; ++k) out[k] = pl[k];
-      } else {
-        for (int k = 0; k < 4; ++k) out[k] = pl[k] + th[k] * (pN[i][k] - pl[k]);
-      }
+    for (int k = 0; k < 4; ++k) {
+      if (SCHEME == SCH_N) out[k] = pN[i][k];
+      else if (SCHEME == SCH_LDA) out[k] = pl[i][k];
+      else out[k] = pl[i][k] + th[k] * (pN[i][k] - pl[i][k]);
     }
     io.part(i, out);
   }

@@ -17,11 +17,19 @@ __device__ __forceinline__ int64_t xcd_block() {
   return x * q + (x < r ? x : r) + b / 8;
 }
 
-// Minimum waves per SIMD the triangle kernels are compiled for. (FP64 at 3
-// waves, with the corner coefficients parked in LDS across the solve to
-// avoid spills, was measured slower than 2 waves.)
+// Minimum waves per SIMD the triangle kernels are compiled for: 4 for FP32;
+// for FP64, 3 where the kernel fits 168 VGPRs without spilling (every
+// stage-1 kernel but the N one with both outputs, and the N and LDA stage-2
+// kernels), else 2. (Parking the corner coefficients in LDS across the solve
+// to fit 3 waves was measured slower than 2 waves without it.)
 template <typename R> struct TriWaves { static constexpr int value = 2; };
 template <> struct TriWaves<float> { static constexpr int value = 4; };
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
+struct TriKernelWaves {
+  static constexpr bool three = sizeof(R) == sizeof(double) &&
+                                (STAGE == 1 ? !(SCHEME == SCH_N && SAVE && CFL) : SCHEME <= SCH_LDA);
+  static constexpr int value = three ? 3 : TriWaves<R>::value;
+};
 
 // Minimum over a kBlock-thread workgroup (result valid in every thread).
 __device__ __forceinline__ double block_min(double x) {

@@ -13,7 +13,7 @@ namespace rd {
 // software-pipelined was measured slower: fewer waves in flight and, with
 // per-workgroup chunks, scattered working sets.)
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
-__global__ __launch_bounds__(kBlock, TriWaves<R>::value) void k_tri(Dev d) {
+__global__ __launch_bounds__(kBlock, (TriKernelWaves<R, SCHEME, STAGE, SAVE, CFL>::value)) void k_tri(Dev d) {
   const int64_t t = xcd_block() * kBlock + threadIdx.x;
   if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE, CFL>(t, d);
 }
