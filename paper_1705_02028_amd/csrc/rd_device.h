@@ -275,11 +275,21 @@ __host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x
 // Blend of Section 3.3.3: Theta_k = |res_k| / sum_i |N_{i,k}| (0 if the sum is
 // 0, at most 1); BMAX / BMIN use the largest / smallest Theta_k for all k.
 // den_k = sum_i |N_{i,k}| is accumulated by the caller in corner order.
+// The quotient is a |res_k| times the reciprocal of den_k; where that product
+// is not below 1 (the clamp, or a reciprocal that overflowed because den_k
+// is below ~1/DBL_MAX, as happens at the edge of a uniform state at rest
+// where the parts have decayed to subnormal values) the exact quotient
+// decides.
 template <typename R, int SCHEME>
 __host__ __device__ inline void blend_theta(const R res[4], const R den[4], R th[4]) {
   for (int k = 0; k < 4; ++k) {
-    R q = den[k] == R(0) ? R(0) : (R)fabs(res[k]) * rcp(den[k]);
-    th[k] = q > R(1) ? R(1) : q;
+    const R a = (R)fabs(res[k]);
+    R q = R(0);
+    if (den[k] > R(0) && a > R(0)) {
+      q = a * rcp(den[k]);
+      if (!(q < R(1))) q = a < den[k] ? a / den[k] : R(1);
+    }
+    th[k] = q;
   }
   if (SCHEME == SCH_BMAX || SCHEME == SCH_BMIN) {
     R t = th[0];

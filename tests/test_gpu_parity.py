@@ -222,6 +222,32 @@ def test_all_ghost_and_tiny_meshes(orc, rd):
         assert err(gpu_step(rd, m, W, dt, scheme, 2, rd.FP64), om.step(W, dt, scheme, 2)) <= t64
 
 
+@pytest.mark.parametrize("tile", [0, 32])
+def test_subnormal_momentum_at_rest(orc, rd, tile):
+    """A uniform state at rest with one vertex's momentum subnormal (as the
+    numerical domain of dependence brings into a quiet region): every blend
+    denominator is subnormal and its reciprocal overflows; the step must stay
+    finite and match the oracle."""
+    for m in (I.split_square(9), I.split_square(9, periodic=(False, False), bc=("ghost", "wall"))):
+        W = I.ic_uniform(m, 0.125, 0.0, 0.0, 0.1)
+        om = orc.OracleMesh(m)
+        for mom in (2.6e-307, 1e-310, 3e-320):
+            Wp = W.copy()
+            Wp[1, m["nv"] // 2] = mom
+            ref = om.step(Wp, 1e-3, orc.B, orc.RK2)
+            for prec in (rd.FP64, rd.FP32_ACC64):
+                say(f"subnormal momentum {mom} periodic={m['px'] > 0} prec={prec} tile={tile}")
+                g = rd.Mesh(m)
+                g.tile = tile
+                g.set_state(Wp)
+                g.step(1e-3, rd.B, rd.RK2, prec)
+                g.sync()
+                out = g.get_state()
+                g.close()
+                assert np.isfinite(out).all()
+                assert np.abs(out - ref).max() <= 1e-12
+
+
 def test_device_pointers_and_nonphysical_flag(orc, rd):
     import torch
     m = I.split_square(20)
