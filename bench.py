@@ -237,8 +237,8 @@ def fp32_table(rd, inputs):
     cases = [
         ("advected sine 64^2, N / Euler, 100 steps", inputs.split_square(64), inputs.ic_advected_sine,
          rd.N, rd.EULER1, 0.5, 100, None),
-        ("Sod 1024^2, B / RK2, 20 steps", inputs.split_square(1024, periodic=(False, False), bc=("ghost", "wall")),
-         inputs.ic_sod, rd.B, rd.RK2, 0.4, 20, None),
+        ("Sod 1024^2, B / RK2, to t = 0.2", inputs.split_square(1024, periodic=(False, False), bc=("ghost", "wall")),
+         inputs.ic_sod, rd.B, rd.RK2, 0.4, None, 0.2),
         ("Kelvin-Helmholtz 2048^2, B / RK2, 500 steps", inputs.split_square(2048),
          lambda m: inputs.ic_kelvin_helmholtz(m, seed=0), rd.B, rd.RK2, 0.4, 500, None),
         ("four-quadrant 512^2, B / RK2, 200 steps", inputs.split_square(512, periodic=(False, False)),
