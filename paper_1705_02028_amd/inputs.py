@@ -273,8 +273,8 @@ def quadrant_states(seed, rho=(0.1, 2.0), p=(0.1, 2.0), vmax=1.0):
 
 
 # Draw of the batched four-quadrant problems: no adjacent pair comes near
-# vacuum (|u_L - u_R| <= 1 while 2 (c_L + c_R) / (gamma - 1) >= 5.9), so the
-# B scheme (not positivity preserving) stays physical over long runs.
+# vacuum (|u_L - u_R| <= 1 while 2 (c_L + c_R) / (gamma - 1) >= 5.9), which
+# keeps long B-scheme runs (not positivity preserving) away from it.
 BATCH_QUADRANTS = dict(rho=(0.5, 2.0), p=(0.5, 2.0), vmax=0.5)
 
 
