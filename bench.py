@@ -75,11 +75,47 @@ def algorithmic_bytes_tiled(nt, nv, fp32, info):
     return k
 
 
-def roofline_entry(name, bytes_, ms):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_kh2048.txt")
+
+
+def source_hash():
+    """Hash of the kernel sources: measured traffic is reported only for the
+    kernels it was measured on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1705_02028_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of one kernel (FETCH_SIZE + WRITE_SIZE from
+    rocprofv3 counter runs, scaled by the copy-kernel calibration), from
+    profiles/hbm_traffic_kh2048.txt; None if absent or taken on other kernel
+    sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    v = rec.get("bytes_per_launch", {}).get(key)
+    return None if v is None else int(v)
+
+
+def roofline_entry(name, bytes_, ms, traffic_key=None):
     achieved = bytes_ / (ms * 1e-3)
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": PEAK_HBM / 1e9,
-            "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
+            "traffic": measured_traffic(traffic_key) if traffic_key else None,
             "algorithmic_bytes": int(bytes_), "avg_ms": round(ms, 5)}
+
+
+def form_name(tile):
+    return "two-pass" if tile == 0 else f"tiled-{tile}"
 
 
 def time_variant(rd, torch, mesh, W0, prec, steps, warmup, cfl, timed_reps, tile):
@@ -349,7 +385,9 @@ def main():
                                f"B scheme, RK2, CFL {args.cfl} (dt on device each step), "
                                "FP32 distribution + FP64 accumulation",
                    "triangles": nt, "vertices": nv, "seed": 0, "numbering": args.renumber},
-        "roofline": roofline_entry(dom32, b32[dom32], per32[dom32]),
+        "roofline": roofline_entry(dom32, b32[dom32], per32[dom32],
+                                   f"fp32/{form_name(form32['tile'])}/{dom32}"
+                                   if args.renumber == "none" and args.N == 2048 else None),
         "kernels_ms": {k: round(v, 5) for k, v in per32.items()},
         "kernels_GBps": {k: round(b32[k] / (v * 1e-3) / 1e9, 1) for k, v in per32.items()
                          if v > 0 and b32.get(k)},
@@ -364,7 +402,9 @@ def main():
         dom64 = max(per64, key=per64.get)
         result["fp64"] = {"value": round(nt * args.steps / (ms64 * 1e-3), 1), "unit": "triangle-updates/s",
                           "ms_per_step": round(ms64 / args.steps, 5),
-                          "roofline": roofline_entry(dom64, b64[dom64], per64[dom64]),
+                          "roofline": roofline_entry(dom64, b64[dom64], per64[dom64],
+                                                     f"fp64/{form_name(form64['tile'])}/{dom64}"
+                                                     if args.renumber == "none" and args.N == 2048 else None),
                           "kernels_ms": {k: round(v, 5) for k, v in per64.items()},
                           "kernels_GBps": {k: round(b64[k] / (v * 1e-3) / 1e9, 1)
                                            for k, v in per64.items() if v > 0 and b64.get(k)},
