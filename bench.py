@@ -78,15 +78,19 @@ def algorithmic_bytes_tiled(nt, nv, fp32, info):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_kh2048.txt")
 
 
+# The sources that define the two-pass triangle kernels (their bodies,
+# launch shapes and the translation unit they are compiled in).
+TRI_SOURCES = ("rd_device.h", "rd_kcommon.h", "rd_launch.h", "rd_kernels.hip")
+
+
 def source_hash():
-    """Hash of the kernel sources: measured traffic is reported only for the
-    kernels it was measured on."""
-    import glob
+    """Hash of the triangle kernels' sources: measured traffic is reported only
+    for the kernels it was measured on."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1705_02028_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    for f in TRI_SOURCES:
+        with open(os.path.join(ROOT, "paper_1705_02028_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 

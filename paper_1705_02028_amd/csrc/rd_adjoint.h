@@ -19,13 +19,19 @@
 
 namespace rd {
 
+// Stage-2 corner cotangents of one slot: of Z* and of W* - W^n, side by side
+// so the reverse gather reads one 64-byte record per slot.
+struct alignas(64) ZW {
+  D4 z, w;
+};
+
 struct AdjDev {
   const D4* lam = nullptr;   // [nv] dL/dW^{n+1}
   D4* lamS = nullptr;        // [nv] dL/dW*
   D4* lamN = nullptr;        // [nv] running dL/dW^n (output)
   D4* Zn = nullptr;          // [nv] parameter vectors at W^n
-  D4* cZ = nullptr;          // [ns] corner cotangent of Z (sliced part layout)
-  D4* cW = nullptr;          // [ns] corner cotangent of W* - W^n (sliced part layout)
+  D4* cZ = nullptr;          // [ns] stage-1 corner cotangent of Z (sliced part layout)
+  ZW* cZW = nullptr;         // [ns] stage-2 corner cotangents of Z* and W* - W^n (sliced part layout)
   D4* kN = nullptr;          // [3nt] cotangent of kept stage-1 N parts (triangle order)
   D4* kT = nullptr;          // [nt] cotangent of kept stage-1 residual
   D4* wcbar = nullptr;       // [nwv] cotangent of the wall term at W^n (stage 1 + half of stage 2)
@@ -579,8 +585,12 @@ __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const Adj
   double Zb[3][4];
   tri_adjoint<SCHEME, 2>(Zc, nxd, nyd, d.gamma, ob, nullptr, nullptr, &s2, &s2b, Zb);
   for (int i = 0; i < 3; ++i) {
-    st4<double>(a.cZ, ip[i], Zb[i]);
-    st4<double>(a.cW, ip[i], s2b.dw[i]);
+    ZW c;
+    for (int k = 0; k < 4; ++k) {
+      c.z.v[k] = Zb[i][k];
+      c.w.v[k] = s2b.dw[i][k];
+    }
+    a.cZW[ip[i]] = c;
     st4<double>(a.kN, 3 * t + i, s2b.keepN[i]);
   }
   st4<double>(a.kT, t, s2b.keepT);
@@ -642,11 +652,11 @@ __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const 
   double zb[4] = {0, 0, 0, 0}, wb[4] = {0, 0, 0, 0};
   const int32_t deg = d.row[v + 1] - d.row[v];
   const int64_t s0 = d.sbeg[v];
-  for_loaded(deg, [&](int32_t j) { return a.cZ[s0 + 64 * (int64_t)j]; }, [&](int32_t, const D4& cz) {
-    for (int k = 0; k < 4; ++k) zb[k] += cz.v[k];
-  });
-  for_loaded(deg, [&](int32_t j) { return a.cW[s0 + 64 * (int64_t)j]; }, [&](int32_t, const D4& cw) {
-    for (int k = 0; k < 4; ++k) wb[k] += cw.v[k];
+  for_loaded(deg, [&](int32_t j) { return a.cZW[s0 + 64 * (int64_t)j]; }, [&](int32_t, const ZW& c) {
+    for (int k = 0; k < 4; ++k) {
+      zb[k] += c.z.v[k];
+      wb[k] += c.w.v[k];
+    }
   });
   const D4 ws = d.Ws[v], l = a.lam[v];
   double ls[4];

@@ -863,10 +863,11 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
   const int64_t nv = m->d.nv, nt = m->d.nt;
   if (!m->adjW) {
     rd::AdjDev& a = m->adj;
-    rd::D4 *lamIn, *lamS, *lamN, *Zn, *cZ, *cW, *kN, *kT, *Wa;
+    rd::D4 *lamIn, *lamS, *lamN, *Zn, *cZ, *kN, *kT, *Wa;
+    rd::ZW* cZW;
     double *in, *out;
     if ((st = dalloc(m, &lamIn, nv)) || (st = dalloc(m, &lamS, nv)) || (st = dalloc(m, &lamN, nv)) ||
-        (st = dalloc(m, &Zn, nv)) || (st = dalloc(m, &cZ, m->d.ns)) || (st = dalloc(m, &cW, m->d.ns)) ||
+        (st = dalloc(m, &Zn, nv)) || (st = dalloc(m, &cZ, m->d.ns)) || (st = dalloc(m, &cZW, m->d.ns)) ||
         (st = dalloc(m, &kN, 3 * nt)) || (st = dalloc(m, &kT, nt)) || (st = dalloc(m, &Wa, nv)) ||
         (st = dalloc(m, &in, 4 * nv)) || (st = dalloc(m, &out, 4 * nv)))
       return st;
@@ -875,7 +876,7 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     a.lamN = lamN;
     a.Zn = Zn;
     a.cZ = cZ;
-    a.cW = cW;
+    a.cZW = cZW;
     a.kN = kN;
     a.kT = kT;
     m->adjW = Wa;
