@@ -118,6 +118,19 @@ def roofline_entry(name, bytes_, ms, traffic_key=None):
             "algorithmic_bytes": int(bytes_), "avg_ms": round(ms, 5)}
 
 
+STAGE1 = ("wall1", "tri1", "shared1", "cfl", "gather1")
+
+
+def stage_rates(per, nt):
+    """Per-stage times (the sum of each stage's kernel times; the CFL pass
+    counts with stage 1) and the triangle-updates/s of each stage alone."""
+    s1 = sum(v for k, v in per.items() if k in STAGE1)
+    s2 = sum(v for k, v in per.items() if k not in STAGE1)
+    return {"stage1_ms": round(s1, 5), "stage2_ms": round(s2, 5),
+            "stage1_triangle_updates_per_s": round(nt / (s1 * 1e-3), 1) if s1 > 0 else None,
+            "stage2_triangle_updates_per_s": round(nt / (s2 * 1e-3), 1) if s2 > 0 else None}
+
+
 def form_name(tile):
     return "two-pass" if tile == 0 else f"tiled-{tile}"
 
@@ -392,6 +405,8 @@ def main():
         "roofline": roofline_entry(dom32, b32[dom32], per32[dom32],
                                    f"fp32/{form_name(form32['tile'])}/{dom32}"
                                    if args.renumber == "none" and args.N == 2048 else None),
+        "vertex_updates_per_s": round(nv * args.steps / (ms32 * 1e-3), 1),
+        "stages": stage_rates(per32, nt),
         "kernels_ms": {k: round(v, 5) for k, v in per32.items()},
         "kernels_GBps": {k: round(b32[k] / (v * 1e-3) / 1e9, 1) for k, v in per32.items()
                          if v > 0 and b32.get(k)},
@@ -406,6 +421,8 @@ def main():
         dom64 = max(per64, key=per64.get)
         result["fp64"] = {"value": round(nt * args.steps / (ms64 * 1e-3), 1), "unit": "triangle-updates/s",
                           "ms_per_step": round(ms64 / args.steps, 5),
+                          "vertex_updates_per_s": round(nv * args.steps / (ms64 * 1e-3), 1),
+                          "stages": stage_rates(per64, nt),
                           "roofline": roofline_entry(dom64, b64[dom64], per64[dom64],
                                                      f"fp64/{form_name(form64['tile'])}/{dom64}"
                                                      if args.renumber == "none" and args.N == 2048 else None),
