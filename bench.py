@@ -34,15 +34,15 @@ def algorithmic_bytes(nt, nv, fp32):
     r4 = 4 * q
     k = {}
     # stage 1: corner ids and CSR positions, coordinates, Z and |v|+c in;
-    # parts, kept N parts, phi^T and l_max lambda_max per corner out
-    k["tri1"] = nt * (12 + 12 + 3 * r4 + 3 * r4 + r4 + 24) + nv * (16 + r4 + 8)
+    # parts, kept N parts (corners 0 and 1), phi^T and l_max lambda_max per corner out
+    k["tri1"] = nt * (12 + 12 + 3 * r4 + 2 * r4 + r4 + 24) + nv * (16 + r4 + 8)
     # CFL: CSR rows, V and the per-corner l_max lambda_max in, block minima out
     k["shared1"] = 0
     k["cfl"] = nv * (4 + 8) + nt * 24
     # gather 1: rows, parts in; W, V in; W*, W*-W, Z*, |v|+c out
     k["gather1"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + r4 + 8)
     # stage 2: ids, positions, coordinates, Z*, W*-W, kept N parts, phi^T in; parts out
-    k["tri2"] = nt * (12 + 12 + 3 * r4 + r4 + 3 * r4) + nv * (16 + r4 + r4)
+    k["tri2"] = nt * (12 + 12 + 2 * r4 + r4 + 3 * r4) + nv * (16 + r4 + r4)
     # gather 2: rows, parts in; W*, V in; W, Z, |v|+c out
     k["gather2"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + 8)
     k["wall1"] = k["wall2"] = 0
@@ -61,14 +61,14 @@ def algorithmic_bytes_tiled(nt, nv, fp32, info):
     k = {}
     # tile pass 1: corner tables, vertex records (id, xy, Z, |v|+c) in; kept N parts and phi^T,
     # interior R1 and CFL bound, shared parts and l_max lambda_max out
-    k["tri1"] = nt * (18 + 3 * r4 + r4) + L * (4 + 16 + r4 + 8) + I * (4 + 8 + 32 + 8) + P * (r4 + 8)
+    k["tri1"] = nt * (18 + 2 * r4 + r4) + L * (4 + 16 + r4 + 8) + I * (4 + 8 + 32 + 8) + P * (r4 + 8)
     # shared pass 1: ids, slots, rows, V in; parts and CFL terms in; R1 and CFL bound out
     k["shared1"] = S * (4 + 4 + 8 + 8 + 32 + 8) + P * (r4 + 8)
     k["cfl"] = nv * 8
     k["gather1"] = 0
     # tile pass 2: corner tables, kept N parts and phi^T, vertex records (id, xy, W, R1, V) in;
     # interior W, Z, |v|+c and shared parts out
-    k["tri2"] = nt * (18 + 3 * r4 + r4) + L * (4 + 16 + 32 + 32 + 8) + I * (4 + 32 + r4 + 8) + P * r4
+    k["tri2"] = nt * (18 + 2 * r4 + r4) + L * (4 + 16 + 32 + 32 + 8) + I * (4 + 32 + r4 + 8) + P * r4
     # shared pass 2: ids, slots, rows, V, W, R1, parts in; W, Z, |v|+c out
     k["gather2"] = S * (4 + 4 + 8 + 8 + 32 + 32 + 32 + r4 + 8) + P * r4
     k["wall1"] = k["wall2"] = 0

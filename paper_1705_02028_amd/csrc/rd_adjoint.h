@@ -32,7 +32,7 @@ struct AdjDev {
   D4* Zn = nullptr;          // [nv] parameter vectors at W^n
   D4* cZ = nullptr;          // [ns] stage-1 corner cotangent of Z (sliced part layout)
   ZW* cZW = nullptr;         // [ns] stage-2 corner cotangents of Z* and W* - W^n (sliced part layout)
-  D4* kN = nullptr;          // [3nt] cotangent of kept stage-1 N parts (triangle order)
+  D4* kN = nullptr;          // [2nt] cotangent of the kept stage-1 N parts of corners 0 and 1 (triangle order)
   D4* kT = nullptr;          // [nt] cotangent of kept stage-1 residual
   D4* wcbar = nullptr;       // [nwv] cotangent of the wall term at W^n (stage 1 + half of stage 2)
 };
@@ -568,18 +568,20 @@ __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const Adj
   s2.mass = area / 3.0;
   s2.idt = 1.0 / d.dt[0];
   double ob[3][4];
+  // kept stage-1 N parts: corners 0 and 1 stored, corner 2 formed as the forward pass forms it
+  const D4 kt = ld4<double>(d.keepT, t);
+  D4 kn[3] = {ld4<double>(d.keepN, 2 * t), ld4<double>(d.keepN, 2 * t + 1), kt};
+  for (int k = 0; k < 4; ++k) kn[2].v[k] = kt.v[k] - kn[0].v[k] - kn[1].v[k];
   for (int i = 0; i < 3; ++i) {
     // W* = W^n at ghosts, whose parameter vectors the stage-1 gather leaves alone
     Zc[i] = (d.bc && is_ghost(d.bc[iv[i]])) ? a.Zn[iv[i]] : d.Z[iv[i]];
     const D4 dw = ld4<double>(d.dW, iv[i]);
-    const D4 kn = ld4<double>(d.keepN, 3 * t + i);
     for (int k = 0; k < 4; ++k) {
       s2.dw[i][k] = dw.v[k];
-      s2.keepN[i][k] = SCHEME == SCH_LDA ? 0.0 : kn.v[k];
+      s2.keepN[i][k] = SCHEME == SCH_LDA ? 0.0 : kn[i].v[k];
     }
     mu_of(d, a.lam, iv[i], ob[i]);
   }
-  const D4 kt = ld4<double>(d.keepT, t);
   for (int k = 0; k < 4; ++k) s2.keepT[k] = SCHEME == SCH_N ? 0.0 : kt.v[k];
   Stage2Bar s2b;
   double Zb[3][4];
@@ -591,9 +593,18 @@ __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const Adj
       c.w.v[k] = s2b.dw[i][k];
     }
     a.cZW[ip[i]] = c;
-    st4<double>(a.kN, 3 * t + i, s2b.keepN[i]);
   }
-  st4<double>(a.kT, t, s2b.keepT);
+  // the kept stage-1 values are corners 0 and 1 and phi^T (corner 2 = phi^T
+  // minus the other two), so corner 2's cotangent moves onto those three
+  double b[3][4];
+  for (int k = 0; k < 4; ++k) {
+    b[0][k] = s2b.keepN[0][k] - s2b.keepN[2][k];
+    b[1][k] = s2b.keepN[1][k] - s2b.keepN[2][k];
+    b[2][k] = s2b.keepT[k] + s2b.keepN[2][k];
+  }
+  st4<double>(a.kN, 2 * t, b[0]);
+  st4<double>(a.kN, 2 * t + 1, b[1]);
+  st4<double>(a.kT, t, b[2]);
 }
 
 // Stage-1 reverse of one triangle: cotangents of Z^n (CSR order), from
@@ -613,7 +624,8 @@ __host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const Adj
   for (int i = 0; i < 3; ++i) {
     Zc[i] = a.Zn[iv[i]];
     mu_of(d, a.lamS, iv[i], ob[i]);
-    const D4 kn = rk2 ? a.kN[3 * t + i] : D4{{0.0, 0.0, 0.0, 0.0}};
+    // cotangents of the kept values (corners 0 and 1, and phi^T below)
+    const D4 kn = rk2 && i < 2 ? a.kN[2 * t + i] : D4{{0.0, 0.0, 0.0, 0.0}};
     for (int k = 0; k < 4; ++k) kNb[i][k] = kn.v[k];
   }
   const D4 kt = rk2 ? a.kT[t] : D4{{0.0, 0.0, 0.0, 0.0}};

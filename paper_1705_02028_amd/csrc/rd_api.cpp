@@ -173,7 +173,7 @@ rd_status ensure_prec(rd_mesh* m, int fp32) {
   rd_status st;
   if ((st = dalloc(m, &p, q * m->d.ns)) != RD_OK) return st;
   m->C[fp32] = p;
-  if ((st = dalloc(m, &p, q * 3 * nt)) != RD_OK) return st;
+  if ((st = dalloc(m, &p, q * 2 * nt)) != RD_OK) return st;
   m->keepN[fp32] = p;
   if ((st = dalloc(m, &p, q * nt)) != RD_OK) return st;
   m->keepT[fp32] = p;
@@ -868,7 +868,7 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     double *in, *out;
     if ((st = dalloc(m, &lamIn, nv)) || (st = dalloc(m, &lamS, nv)) || (st = dalloc(m, &lamN, nv)) ||
         (st = dalloc(m, &Zn, nv)) || (st = dalloc(m, &cZ, m->d.ns)) || (st = dalloc(m, &cZW, m->d.ns)) ||
-        (st = dalloc(m, &kN, 3 * nt)) || (st = dalloc(m, &kT, nt)) || (st = dalloc(m, &Wa, nv)) ||
+        (st = dalloc(m, &kN, 2 * nt)) || (st = dalloc(m, &kT, nt)) || (st = dalloc(m, &Wa, nv)) ||
         (st = dalloc(m, &in, 4 * nv)) || (st = dalloc(m, &out, 4 * nv)))
       return st;
     a.lam = lamIn;

@@ -82,7 +82,7 @@ struct Dev {
   double* sig = nullptr;   // [nv] |v| + c
   // triangle buffers
   void* C = nullptr;      // [ns] distributed parts, sliced layout (D4 or F4)
-  void* keepN = nullptr;  // [3nt] stage-1 N parts (D4 or F4)
+  void* keepN = nullptr;  // [2nt] stage-1 N parts of corners 0 and 1 (D4 or F4)
   void* keepT = nullptr;  // [nt] stage-1 triangle residual (D4 or F4)
   D4* WCn = nullptr;      // [nwv] wall term at W^n
   D4* WCs = nullptr;      // [nwv] wall term at W*
@@ -513,18 +513,31 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
       apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, y, pN[i]);
     }
     for (int k = 0; k < 4; ++k) pN[2][k] = phiT[k] - pN[0][k] - pN[1][k];
-    for (int i = 0; i < 3; ++i) {
-      if (STAGE == 1 && SAVE) st4<R>(d.keepN, 3 * t + i, pN[i]);
-      if (STAGE == 2) {
-        // Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2; the
-        // per-vertex differences are reloaded here (cached) to keep them out
-        // of registers across the solve
-        const Q4<R> kn = ld4<R>(d.keepN, 3 * t + i);
-        const Q4<R> dwv = io.dw(i);
-        for (int k = 0; k < 4; ++k) pN[i][k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn.v[k] + pN[i][k]);
-      }
-      for (int k = 0; k < 4; ++k) den[k] = den[k] + (R)fabs(pN[i][k]);
+    // Only corners 0 and 1 of the N parts are kept: corner 2's is phi^T minus
+    // those two, and stage 2 forms it again from the kept phi^T with the same
+    // two subtractions, which gives back the identical value.
+    if (STAGE == 1 && SAVE) {
+      st4<R>(d.keepN, 2 * t, pN[0]);
+      st4<R>(d.keepN, 2 * t + 1, pN[1]);
     }
+    if (STAGE == 2) {
+      // Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2; the
+      // kept parts and per-vertex differences are loaded here (cached) to
+      // keep them out of registers across the solve
+      const Q4<R> k0 = ld4<R>(d.keepN, 2 * t), k1 = ld4<R>(d.keepN, 2 * t + 1), kt = ld4<R>(d.keepT, t);
+      R kn[3][4];
+      for (int k = 0; k < 4; ++k) {
+        kn[0][k] = k0.v[k];
+        kn[1][k] = k1.v[k];
+        kn[2][k] = kt.v[k] - k0.v[k] - k1.v[k];
+      }
+      for (int i = 0; i < 3; ++i) {
+        const Q4<R> dwv = io.dw(i);
+        for (int k = 0; k < 4; ++k) pN[i][k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn[i][k] + pN[i][k]);
+      }
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 4; ++k) den[k] = den[k] + (R)fabs(pN[i][k]);
   }
   if (STAGE == 1 && SAVE) st4<R>(d.keepT, t, phiT);
   // rhs1 is the residual being split (phi^T or Phi^T)
