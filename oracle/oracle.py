@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rd_oracle.cpp")
 LIB = os.environ.get("RDO_LIB") or os.path.join(HERE, "liboracle.so")
 
-N, LDA, B, BMAX, BMIN = 0, 1, 2, 3, 4
+N, LDA, B, BMAX, BMIN, BX = 0, 1, 2, 3, 4, 5
 EULER1, RK2 = 1, 2
 
 
@@ -47,6 +47,9 @@ def lib():
         L.rdo_mesh_new.argtypes = [C.c_int64, C.c_int64, dp, dp, P, C.c_double, C.c_double,
                                    P, C.c_int64, P, C.c_double, C.c_char_p, C.c_int]
         L.rdo_mesh_free.argtypes = [P]
+        L.rdo_set_lumping.argtypes = [P, C.c_int]
+        L.rdo_domain_size.argtypes = [P]
+        L.rdo_domain_size.restype = C.c_double
         L.rdo_geometry.argtypes = [P, dp, dp, dp, dp]
         L.rdo_residual.argtypes = [P, dp, C.c_int, dp, P]
         L.rdo_residual.restype = C.c_int
@@ -102,6 +105,14 @@ class OracleMesh:
         if h and _lib is not None:
             _lib.rdo_mesh_free(h)
             self._h = None
+
+    def set_lumping(self, selective: bool) -> None:
+        """Stage-2 mass term: global lumping (default) or selective lumping."""
+        lib().rdo_set_lumping(self._h, 1 if selective else 0)
+
+    def domain_size(self) -> float:
+        """L of the Bx sensor."""
+        return float(lib().rdo_domain_size(self._h))
 
     def geometry(self):
         area = np.zeros(self.nt)

@@ -42,6 +42,23 @@
 //    and W*. Ghost vertices keep their value.
 //  * Vertex sums run over the triangles of a vertex in ascending triangle
 //    order, then add the wall term.
+//  * Bx (Section 3.3.3, after Dobes): one scalar theta per triangle,
+//    theta = min(1, s^2 h / L) with s = max(0, -L div(v) / (|v|max - |v|min)).
+//    As printed theta = s^2 h has the dimension of a length; h is read in
+//    units of the domain size L (on the unit square this is the printed
+//    formula) and theta is clamped to 1 so that the blend stays convex.
+//    h = sqrt(2|T|) (the leg of a right isosceles triangle of that area);
+//    div(v) is the divergence of the linear interpolant of the vertex
+//    velocities, sum_i v_i . n_i / (2|T|) with the inward scaled normals;
+//    |v|max and |v|min are taken over all vertices of the mesh at the
+//    stage's state (W^n in stage 1, W* in stage 2); s = 0 when they are
+//    equal. L is the larger side of the domain: the period on a periodic
+//    axis, else the extent of the vertex coordinates.
+//  * Selective lumping (Section 3.4): in stage 2 both the N and the LDA
+//    total parts get sum_j (|T| delta_ij / 3 - m^G_ij)(W*_j - W^n_j)/dt
+//    with the Galerkin mass m^G_ij = |T| (1 + delta_ij) / 12, before the
+//    blend (so the B coefficients see the lumped N parts). Off by default
+//    (global lumping); it does nothing in a forward Euler step.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -100,7 +117,7 @@ template <class T> inline T absval(T x) {
 template <class T> inline T pos_part(T x) { return val(x) > 0.0 ? x : T(0.0); }
 template <class T> inline T neg_part(T x) { return val(x) < 0.0 ? x : T(0.0); }
 
-enum { SCHEME_N = 0, SCHEME_LDA = 1, SCHEME_B = 2, SCHEME_BMAX = 3, SCHEME_BMIN = 4 };
+enum { SCHEME_N = 0, SCHEME_LDA = 1, SCHEME_B = 2, SCHEME_BMAX = 3, SCHEME_BMIN = 4, SCHEME_BX = 5 };
 
 // ---------------------------------------------------------------- mesh ----
 
@@ -118,6 +135,8 @@ struct Mesh {
   std::vector<double> lmax;   // longest edge
   std::vector<double> V;      // vertex volume
   std::vector<double> wlen, wnx, wny;  // wall edge length and outward unit normal
+  double L = 0.0;           // domain size (Bx sensor)
+  bool selective = false;   // selective lumping in stage 2
 };
 
 // Minimum-image difference of two coordinates on a periodic axis.
@@ -168,6 +187,17 @@ bool build_geometry(Mesh& m, std::string& err) {
   }
   for (int64_t t = 0; t < m.nt; ++t)
     for (int k = 0; k < 3; ++k) m.V[m.tri[3 * t + k]] += m.area[t] / 3.0;
+  {
+    double x0 = m.x[0], x1 = m.x[0], y0 = m.y[0], y1 = m.y[0];
+    for (int64_t i = 0; i < m.nv; ++i) {
+      x0 = std::min(x0, m.x[i]);
+      x1 = std::max(x1, m.x[i]);
+      y0 = std::min(y0, m.y[i]);
+      y1 = std::max(y1, m.y[i]);
+    }
+    const double lx = m.px > 0.0 ? m.px : x1 - x0, ly = m.py > 0.0 ? m.py : y1 - y0;
+    m.L = std::max(lx, ly);
+  }
   for (int64_t i = 0; i < m.nv; ++i) {
     if (!(m.V[i] > 0.0)) {
       err = "vertex " + std::to_string(i) + " belongs to no triangle";
@@ -375,9 +405,14 @@ template <class T> void blend_theta(const T res[4], const T pn[3][4], int scheme
 // Distributed parts of one triangle for a scheme, given N and LDA parts and
 // the residual they split.
 template <class T>
-void distribute(int scheme, const T res[4], const T pn[3][4], const T pl[3][4], T out[3][4], T theta_out[4]) {
+void distribute(int scheme, const T res[4], const T pn[3][4], const T pl[3][4], T out[3][4], T theta_out[4],
+                T bx = T(0.0)) {
   T theta[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
-  if (scheme == SCHEME_N) {
+  if (scheme == SCHEME_BX) {
+    for (int k = 0; k < 4; ++k) theta[k] = bx;
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 4; ++k) out[i][k] = pl[i][k] + bx * (pn[i][k] - pl[i][k]);
+  } else if (scheme == SCHEME_N) {
     for (int i = 0; i < 3; ++i)
       for (int k = 0; k < 4; ++k) out[i][k] = pn[i][k];
   } else if (scheme == SCHEME_LDA) {
@@ -448,10 +483,39 @@ template <class T> void all_z(const Mesh& m, const std::vector<T>& W, std::vecto
   for (int64_t i = 0; i < m.nv; ++i) w_to_z(&W[4 * i], m.gamma, &Z[4 * i]);
 }
 
+// Smallest and largest flow speed |v| over the vertices of a state (Bx).
+template <class T> void speed_range(const Mesh& m, const std::vector<T>& W, T& vmin, T& vmax) {
+  for (int64_t i = 0; i < m.nv; ++i) {
+    T u = W[4 * i + 1] / W[4 * i], v = W[4 * i + 2] / W[4 * i];
+    T sp = sq_root(u * u + v * v);
+    if (i == 0 || val(sp) < val(vmin)) vmin = sp;
+    if (i == 0 || val(sp) > val(vmax)) vmax = sp;
+  }
+}
+
+// Blend coefficient of the Bx scheme for triangle t at state W (Section
+// 3.3.3): theta = min(1, s^2 h / L), s = (-L div v / (|v|max - |v|min))^+.
+template <class T> T bx_theta(const Mesh& m, const std::vector<T>& W, int64_t t, T vmin, T vmax) {
+  T div = T(0.0);
+  for (int i = 0; i < 3; ++i) {
+    int64_t v = m.tri[3 * t + i];
+    T u = W[4 * v + 1] / W[4 * v], w = W[4 * v + 2] / W[4 * v];
+    div = div + u * m.nrm[6 * t + 2 * i] + w * m.nrm[6 * t + 2 * i + 1];
+  }
+  div = div / (2.0 * m.area[t]);
+  T range = vmax - vmin;
+  T s = val(range) > 0.0 ? pos_part(-m.L * div / range) : T(0.0);
+  const double h = std::sqrt(2.0 * m.area[t]);
+  T theta = s * s * h / m.L;
+  return val(theta) > 1.0 ? T(1.0) : theta;
+}
+
 // Stage-1 spatial parts of every triangle; optionally keeps phi^N and phi^T.
 template <class T>
-void spatial_parts(const Mesh& m, const std::vector<T>& Z, int scheme, std::vector<T>& part,
-                   std::vector<T>* keepN, std::vector<T>* keepT) {
+void spatial_parts(const Mesh& m, const std::vector<T>& W, const std::vector<T>& Z, int scheme,
+                   std::vector<T>& part, std::vector<T>* keepN, std::vector<T>* keepT) {
+  T vmin = T(0.0), vmax = T(0.0);
+  if (scheme == SCHEME_BX) speed_range(m, W, vmin, vmax);
   part.assign(12 * m.nt, T(0.0));
   if (keepN) keepN->assign(12 * m.nt, T(0.0));
   if (keepT) keepT->assign(4 * m.nt, T(0.0));
@@ -466,7 +530,8 @@ void spatial_parts(const Mesh& m, const std::vector<T>& Z, int scheme, std::vect
     T pl[3][4];
     for (int i = 0; i < 3; ++i) matvec(s.Kp[i], s.xL, pl[i]);
     T out[3][4];
-    distribute(scheme, s.phiT, s.phiN, pl, out, (T*)nullptr);
+    const T bx = scheme == SCHEME_BX ? bx_theta(m, W, t, vmin, vmax) : T(0.0);
+    distribute(scheme, s.phiT, s.phiN, pl, out, (T*)nullptr, bx);
     for (int i = 0; i < 3; ++i)
       for (int k = 0; k < 4; ++k) part[12 * t + 4 * i + k] = out[i][k];
     if (keepN)
@@ -482,7 +547,7 @@ void spatial_parts(const Mesh& m, const std::vector<T>& Z, int scheme, std::vect
 template <class T> void step(const Mesh& m, std::vector<T>& W, double dt, int scheme, int time_order) {
   std::vector<T> Z, part, keepN, keepT, R, Wc_n;
   all_z(m, W, Z);
-  spatial_parts<T>(m, Z, scheme, part, time_order == 2 ? &keepN : nullptr, time_order == 2 ? &keepT : nullptr);
+  spatial_parts<T>(m, W, Z, scheme, part, time_order == 2 ? &keepN : nullptr, time_order == 2 ? &keepT : nullptr);
   gather(m, part, R);
   wall_term(m, W, Wc_n);
   std::vector<T> Ws(W);
@@ -499,6 +564,8 @@ template <class T> void step(const Mesh& m, std::vector<T>& W, double dt, int sc
   }
   std::vector<T> Zs;
   all_z(m, Ws, Zs);
+  T vmin = T(0.0), vmax = T(0.0);
+  if (scheme == SCHEME_BX) speed_range(m, Ws, vmin, vmax);
 #pragma omp parallel for schedule(static)
   for (int64_t t = 0; t < m.nt; ++t) {
     T Zc[3][4];
@@ -523,8 +590,23 @@ template <class T> void step(const Mesh& m, std::vector<T>& W, double dt, int sc
     solve4(s.A, PT, x);
     T PL[3][4];
     for (int i = 0; i < 3; ++i) matvec(s.Kp[i], x, PL[i]);
+    if (m.selective) {
+      // selective lumping: + sum_j (|T| delta_ij / 3 - m^G_ij) (W*_j - W^n_j) / dt
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 4; ++k) {
+          T sl = T(0.0);
+          for (int j = 0; j < 3; ++j) {
+            const double mg = m.area[t] * ((i == j ? 1.0 : 0.0) + 1.0) / 12.0;
+            const double ml = i == j ? m.area[t] / 3.0 : 0.0;
+            sl = sl + (ml - mg) * rate[j][k];
+          }
+          PN[i][k] = PN[i][k] + sl;
+          PL[i][k] = PL[i][k] + sl;
+        }
+    }
     T out[3][4];
-    distribute(scheme, PT, PN, PL, out, (T*)nullptr);
+    const T bx = scheme == SCHEME_BX ? bx_theta(m, Ws, t, vmin, vmax) : T(0.0);
+    distribute(scheme, PT, PN, PL, out, (T*)nullptr, bx);
     for (int i = 0; i < 3; ++i)
       for (int k = 0; k < 4; ++k) part[12 * t + 4 * i + k] = out[i][k];
   }
@@ -585,6 +667,12 @@ void* rdo_mesh_new(int64_t nv, int64_t nt, const double* x, const double* y, con
 
 void rdo_mesh_free(void* h) { delete static_cast<Mesh*>(h); }
 
+// Lumping of the stage-2 mass term: 0 global (default), 1 selective.
+void rdo_set_lumping(void* h, int selective) { static_cast<Mesh*>(h)->selective = selective != 0; }
+
+// Domain size L of the Bx sensor.
+double rdo_domain_size(void* h) { return static_cast<Mesh*>(h)->L; }
+
 void rdo_set_threads(int n) {
 #ifdef _OPENMP
   if (n > 0) omp_set_num_threads(n);
@@ -615,11 +703,11 @@ void rdo_geometry(void* h, double* area, double* nrm, double* lmax, double* V) {
 // (may be NULL).
 int rdo_residual(void* h, const double* W_soa, int scheme, double* R_soa, double* phiT_soa) {
   const Mesh& m = *static_cast<Mesh*>(h);
-  if (scheme < 0 || scheme > 4) return 1;
+  if (scheme < 0 || scheme > 5) return 1;
   std::vector<double> W, Z, part, keepT, R, Wc;
   soa_to_aos(m, W_soa, W);
   all_z(m, W, Z);
-  spatial_parts<double>(m, Z, scheme, part, nullptr, &keepT);
+  spatial_parts<double>(m, W, Z, scheme, part, nullptr, &keepT);
   gather(m, part, R);
   wall_term(m, W, Wc);
   for (int64_t i = 0; i < 4 * m.nv; ++i) R[i] = R[i] + Wc[i];
@@ -633,18 +721,18 @@ int rdo_residual(void* h, const double* W_soa, int scheme, double* R_soa, double
 // Per-triangle corner parts of a scheme at a state, [nt][3][4].
 int rdo_parts(void* h, const double* W_soa, int scheme, double* parts) {
   const Mesh& m = *static_cast<Mesh*>(h);
-  if (scheme < 0 || scheme > 4) return 1;
+  if (scheme < 0 || scheme > 5) return 1;
   std::vector<double> W, Z, part;
   soa_to_aos(m, W_soa, W);
   all_z(m, W, Z);
-  spatial_parts<double>(m, Z, scheme, part, nullptr, nullptr);
+  spatial_parts<double>(m, W, Z, scheme, part, nullptr, nullptr);
   std::memcpy(parts, part.data(), sizeof(double) * 12 * m.nt);
   return 0;
 }
 
 int rdo_step(void* h, double* W_soa, double dt, int scheme, int time_order) {
   const Mesh& m = *static_cast<Mesh*>(h);
-  if (scheme < 0 || scheme > 4 || (time_order != 1 && time_order != 2) || !(dt > 0.0)) return 1;
+  if (scheme < 0 || scheme > 5 || (time_order != 1 && time_order != 2) || !(dt > 0.0)) return 1;
   std::vector<double> W;
   soa_to_aos(m, W_soa, W);
   step(m, W, dt, scheme, time_order);
@@ -656,7 +744,7 @@ int rdo_step(void* h, double* W_soa, double dt, int scheme, int time_order) {
 // dW the Jacobian of the step applied to the incoming dW (dt held fixed).
 int rdo_step_jvp(void* h, double* W_soa, double* dW_soa, double dt, int scheme, int time_order) {
   const Mesh& m = *static_cast<Mesh*>(h);
-  if (scheme < 0 || scheme > 4 || (time_order != 1 && time_order != 2) || !(dt > 0.0)) return 1;
+  if (scheme < 0 || scheme > 5 || (time_order != 1 && time_order != 2) || !(dt > 0.0)) return 1;
   std::vector<Dual> W(4 * m.nv);
   for (int64_t i = 0; i < m.nv; ++i)
     for (int k = 0; k < 4; ++k) W[4 * i + k] = Dual(W_soa[k * m.nv + i], dW_soa[k * m.nv + i]);

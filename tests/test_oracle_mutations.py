@@ -33,6 +33,15 @@ MUTANTS = {
                        "    for (int k = 0; k < 4; ++k) {\n      T r = R[4 * i + k] + Wc_n[4 * i + k];"),
     "wall_normal_inward": ("m.wnx[e] = dy / len;", "m.wnx[e] = -dy / len;"),
     "volume_third": ("m.V[m.tri[3 * t + k]] += m.area[t] / 3.0;", "m.V[m.tri[3 * t + k]] += m.area[t] / 2.0;"),
+    "bx_sensor_sign": ("pos_part(-m.L * div / range)", "pos_part(m.L * div / range)"),
+    "bx_h_in_domain_units": ("T theta = s * s * h / m.L;", "T theta = s * s * h;"),
+    "bx_element_size": ("const double h = std::sqrt(2.0 * m.area[t]);", "const double h = std::sqrt(m.area[t]);"),
+    "bx_speed_range": ("T range = vmax - vmin;", "T range = vmax;"),
+    "bx_domain_size": ("m.L = std::max(lx, ly);", "m.L = std::min(lx, ly);"),
+    "lumping_sign": ("sl = sl + (ml - mg) * rate[j][k];", "sl = sl + (mg - ml) * rate[j][k];"),
+    "lumping_galerkin_mass": ("const double mg = m.area[t] * ((i == j ? 1.0 : 0.0) + 1.0) / 12.0;",
+                              "const double mg = m.area[t] * ((i == j ? 1.0 : 0.0) + 1.0) / 6.0;"),
+    "lumping_lda_part": ("          PL[i][k] = PL[i][k] + sl;\n", "\n"),
 }
 
 

@@ -581,3 +581,146 @@ def test_config_sizes():
     assert (m["nv"], m["nt"]) == (3969, 7938)
     m = I.split_square(1024, periodic=(False, False), bc=("ghost", "wall"))
     assert (m["nv"], m["nt"]) == (1048576, 2093058)
+
+
+# ------------------------------------- Bx blend and selective lumping --
+
+def areas_from_coordinates(m):
+    """|T| of every triangle from its corner coordinates (minimum image on
+    periodic axes), computed here, not by the oracle."""
+    t = m["tri"]
+    x, y = m["x"], m["y"]
+
+    def d(a, b, period):
+        r = b - a
+        if period > 0:
+            r = r - period * np.round(r / period)
+        return r
+    x1, y1 = d(x[t[:, 0]], x[t[:, 1]], m["px"]), d(y[t[:, 0]], y[t[:, 1]], m["py"])
+    x2, y2 = d(x[t[:, 0]], x[t[:, 2]], m["px"]), d(y[t[:, 0]], y[t[:, 2]], m["py"])
+    return 0.5 * (x1 * y2 - y1 * x2)
+
+
+def velocity_state(m, u, v, rho=None, p=None, seed=0):
+    """Conserved state with the given vertex velocities; density and
+    pressure seeded and smooth unless given."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if rho is None:
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * m["x"] + rng.uniform(0, 6)) * np.cos(2 * np.pi * m["y"])
+    if p is None:
+        p = 1.0 + 0.1 * np.cos(2 * np.pi * (m["x"] + m["y"]))
+    return I.prim_to_cons(rho, u + 0 * m["x"], v + 0 * m["x"], p)
+
+
+def test_bx_is_lda_where_the_sensor_vanishes(orc):
+    """Bx (Section 3.3.3) blends with theta = s^2 h / L, s = (-L div v /
+    (|v|max - |v|min))^+: a uniform velocity (|v|max = |v|min) and an
+    expanding flow (div v > 0) both give s = 0, i.e. exactly the LDA parts."""
+    m = periodic_mesh(12, diagonal="random", jitter=0.2, seed=21)
+    om = orc.OracleMesh(m)
+    W = velocity_state(m, 0.6, -0.3, seed=1)
+    assert np.array_equal(om.parts(W, orc.BX), om.parts(W, orc.LDA))
+    Wn = om.step(W, 1e-3, orc.BX, orc.EULER1)
+    assert np.array_equal(Wn, om.step(W, 1e-3, orc.LDA, orc.EULER1))
+    m = I.split_square(11, periodic=(False, False), bc=("ghost", "ghost"), diagonal="random", jitter=0.2, seed=22)
+    om = orc.OracleMesh(m)
+    W = velocity_state(m, 0.7 * (m["x"] - 0.4), 0.5 * (m["y"] - 0.6), seed=2)
+    assert np.array_equal(om.parts(W, orc.BX), om.parts(W, orc.LDA))
+
+
+@pytest.mark.parametrize("shape", ["square2", "rect", "periodic_x"])
+def test_bx_theta_closed_form_in_uniform_compression(orc, shape):
+    """u = b - a x, v = 0 has div v = -a everywhere (the linear interpolant
+    is exact) and |v| spans [b - a x_max, b - a x_min], so s = L a / (a (x_max
+    - x_min)) and theta_T = (L / (x_max - x_min))^2 h_T / L, h_T = sqrt(2|T|),
+    L the larger side of the domain. Bx parts = LDA + theta (N - LDA)."""
+    if shape == "square2":
+        m = I.split_square(10, periodic=(False, False), diagonal="random", jitter=0.25, seed=23, length=2.0)
+        L, xs = 2.0, 2.0
+    elif shape == "rect":
+        m = I.split_square(12, periodic=(False, False), diagonal="random", jitter=0.2, seed=24, length=3.0,
+                           Ny=6, ly=1.0)
+        L, xs = 3.0, 3.0
+    else:
+        m = I.split_square(10, periodic=(False, True), bc=("ghost", "ghost"), diagonal="random", seed=25,
+                           length=1.0, Ny=12, ly=2.0)
+        L, xs = 2.0, 1.0  # the period in y is the larger side
+    om = orc.OracleMesh(m)
+    a, b = 0.4, 1.5
+    W = velocity_state(m, b - a * m["x"], 0.0, seed=3)
+    th = np.minimum(1.0, (L / xs) ** 2 * np.sqrt(2.0 * areas_from_coordinates(m)) / L)
+    assert 0.05 < th.min() and th.max() < 1.0
+    pn, pl = om.parts(W, orc.N), om.parts(W, orc.LDA)
+    want = pl + th[:, None, None] * (pn - pl)
+    got = om.parts(W, orc.BX)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(pn).max()
+
+
+def test_bx_is_n_across_a_compressive_jump(orc):
+    """A velocity drop from 1 to 1/4 across x = 1/2 (uniform elsewhere):
+    the triangles across it see div v ~ -(3/4)/h, s ~ L/h and theta clamped
+    at 1 (N parts); the others see div v = 0 up to rounding (LDA parts)."""
+    m = I.split_square(13, periodic=(False, False), diagonal="random", seed=26)
+    om = orc.OracleMesh(m)
+    u = np.where(m["x"] < 0.5, 1.0, 0.25)
+    W = velocity_state(m, u, 0.0, rho=np.ones(m["nv"]), p=np.ones(m["nv"]))
+    pn, pl, got = om.parts(W, orc.N), om.parts(W, orc.LDA), om.parts(W, orc.BX)
+    cross = u[m["tri"]].min(axis=1) != u[m["tri"]].max(axis=1)
+    assert cross.any() and (~cross).any()
+    scale = np.abs(pn).max()
+    assert np.abs(got[cross] - pn[cross]).max() <= 1e-13 * scale
+    assert np.abs(got[~cross] - pl[~cross]).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_selective_lumping_closed_form(orc, scheme):
+    """Section 3.4: selective lumping adds sum_j (|T| delta_ij / 3 - m^G_ij)
+    (W*_j - W^n_j) / dt, m^G_ij = |T| (1 + delta_ij) / 12, to the stage-2
+    parts. For N and LDA the parts are not blended, so the RK2 result moves
+    by -(dt / V_i) sum_T (|T| / 12) (3 r_i - sum_j r_j), r = (W* - W^n) / dt,
+    W* being the forward Euler step; V and |T| are computed here."""
+    for m in (periodic_mesh(11, diagonal="random", jitter=0.2, seed=27),
+              I.split_square(10, periodic=(False, False), bc=("ghost", "wall"), diagonal="random", seed=28)):
+        om = orc.OracleMesh(m)
+        W = I.random_smooth_state(m, seed=13, amp=0.2)
+        dt = om.max_dt(W, 0.4)
+        gl = om.step(W, dt, scheme, orc.RK2)
+        Ws = om.step(W, dt, scheme, orc.EULER1)
+        om.set_lumping(True)
+        sl = om.step(W, dt, scheme, orc.RK2)
+        assert np.array_equal(om.step(W, dt, scheme, orc.EULER1), Ws)  # no stage 2, no change
+        A = areas_from_coordinates(m)
+        V = np.zeros(m["nv"])
+        for k in range(3):
+            np.add.at(V, m["tri"][:, k], A / 3.0)
+        r = (Ws - W) / dt
+        rt = r[:, m["tri"]]                       # [4, nt, 3]
+        corr = (A / 12.0)[None, :, None] * (3.0 * rt - rt.sum(axis=2, keepdims=True))
+        acc = np.zeros_like(W)
+        for k in range(3):
+            for q in range(4):
+                np.add.at(acc[q], m["tri"][:, k], corr[q, :, k])
+        want = gl - dt * acc / V
+        want[:, m["ghost"] != 0] = gl[:, m["ghost"] != 0]
+        assert np.abs(sl - want).max() <= 1e-13 * np.abs(W).max()
+        assert np.abs(sl - gl).max() > 1e-8   # the term is not negligible here
+
+
+@pytest.mark.parametrize("scheme", SCHEMES + [5])
+def test_bx_and_selective_lumping_keep_uniform_states_and_conserve(orc, scheme):
+    m = periodic_mesh(10, diagonal="random", jitter=0.2, seed=29)
+    om = orc.OracleMesh(m)
+    om.set_lumping(True)
+    W = I.ic_uniform(m, 1.1, 0.3, -0.2, 0.9)
+    W1 = W
+    for _ in range(2):
+        W1 = om.step(W1, 1e-3, scheme, orc.RK2)
+    assert np.array_equal(W1, W)
+    V = om.geometry()["V"]
+    W = I.random_smooth_state(m, seed=14, amp=0.2)
+    dt = om.max_dt(W, 0.4)
+    W1 = W
+    for _ in range(4):
+        W1 = om.step(W1, dt, scheme, orc.RK2)
+    tot0, tot1 = (W * V).sum(axis=1), (W1 * V).sum(axis=1)
+    assert np.all(np.abs(tot1 - tot0) <= 1e-14 * np.abs(W * V).sum(axis=1))
