@@ -7,7 +7,9 @@ The headline value is the FP32-distribution / FP64-accumulation variant (the
 configuration's arithmetic); the FP64 variant is timed on the same mesh and
 reported beside it. One step = CFL limit + both Runge-Kutta stages (two
 triangle passes and two vertex gathers). Inputs are resident on the GPU
-before timing starts.
+before timing starts. Also timed on the same workload: the Bx blend and the
+B scheme with selective lumping (`variants`), the adjoint step against the
+forward step, and (with --batch) many meshes in one graph.
 
 Prints one JSON line. `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
@@ -135,30 +137,32 @@ def form_name(tile):
     return "two-pass" if tile == 0 else f"tiled-{tile}"
 
 
-def time_variant(rd, torch, mesh, W0, prec, steps, warmup, cfl, timed_reps, tile):
+def time_variant(rd, torch, mesh, W0, prec, steps, warmup, cfl, timed_reps, tile, scheme=None, lump=0):
+    scheme = rd.B if scheme is None else scheme
     g = rd.Mesh(mesh)
     g.set_state(W0)
+    g.lumping = lump
     tuned = None
     if tile < 0:
-        best, table = g.tune(cfl, rd.B, rd.RK2, prec, n_steps=3)
+        best, table = g.tune(cfl, scheme, rd.RK2, prec, n_steps=3)
         tuned = {"chosen": best, "ms_per_step": {str(k): round(v, 5) for k, v in table.items()}}
     else:
         g.tile = tile
     info = rd.rd_mesh_tile_info(g.h)
     if warmup:
-        g.step_cfl(warmup, cfl, rd.B, rd.RK2, prec)
+        g.step_cfl(warmup, cfl, scheme, rd.RK2, prec)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    g.step_cfl(steps, cfl, rd.B, rd.RK2, prec)
+    g.step_cfl(steps, cfl, scheme, rd.RK2, prec)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     g.sync()
     per = {}
     for _ in range(max(timed_reps, 1)):
-        t = rd.rd_step_timed(g.h, cfl, rd.B, rd.RK2, prec)
+        t = rd.rd_step_timed(g.h, cfl, scheme, rd.RK2, prec)
         for k, v in t.items():
             per[k] = per.get(k, 0.0) + v / max(timed_reps, 1)
     g.sync()
@@ -350,6 +354,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0, metavar="NMESH",
                     help="also time NMESH four-quadrant meshes (32^2..512^2) per instance vs one batched graph")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip timing the Bx blend and selective lumping")
     ap.add_argument("--fp32-table", action="store_true",
                     help="only print the FP32-variant error table per workload (JSON)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -430,6 +436,20 @@ def main():
                           "kernels_GBps": {k: round(b64[k] / (v * 1e-3) / 1e9, 1)
                                            for k, v in per64.items() if v > 0 and b64.get(k)},
                           "form": form64}
+    if not args.no_variants:
+        # the other blends and lumpings of Sections 3.3.3 and 3.4 on the same workload (two-pass form)
+        print("bench: scheme variants", file=sys.stderr, flush=True)
+        variants = {}
+        for name, scheme, lump in (("Bx", rd.BX, 0), ("B, selective lumping", rd.B, 1)):
+            entry = {}
+            for pname, prec in (("fp32", rd.FP32_ACC64), ("fp64", rd.FP64)):
+                ms, per, _ = time_variant(rd, torch, mesh, W0, prec, args.steps, args.warmup, args.cfl,
+                                          args.timed_reps, 0, scheme=scheme, lump=lump)
+                entry[pname] = {"ms_per_step": round(ms / args.steps, 5),
+                                "triangle_updates_per_s": round(nt * args.steps / (ms * 1e-3), 1),
+                                "kernels_ms": {k: round(v, 5) for k, v in per.items()}}
+            variants[name] = entry
+        result["variants"] = variants
     if not args.no_adjoint:
         print("bench: adjoint / forward", file=sys.stderr, flush=True)
         result["adjoint_forward_ratio"] = adjoint_ratio(rd, torch, mesh, W0, args.cfl, 10, args.tile)

@@ -57,8 +57,21 @@ typedef enum {
 } rd_status;
 
 /* Distribution schemes (Section 3.3): N, LDA, and the blend B with its
- * diagonal Theta; BMAX / BMIN set every Theta_kk to the largest / smallest. */
-typedef enum { RD_N = 0, RD_LDA = 1, RD_B = 2, RD_BMAX = 3, RD_BMIN = 4 } rd_scheme;
+ * diagonal Theta; BMAX / BMIN set every Theta_kk to the largest / smallest.
+ * BX is the blend of Section 3.3.3 with one scalar theta per triangle from a
+ * shock sensor: theta = min(1, s^2 h / L), s = max(0, -L div v / (|v|max -
+ * |v|min)), div v of the linear interpolant of the vertex velocities, h =
+ * sqrt(2 |T|), |v|max and |v|min over the mesh's vertices at the stage's
+ * state (s = 0 when they are equal), L the larger side of the domain (the
+ * period on a periodic axis, else the coordinate extent). Two extra
+ * vertex passes per stage find |v|max and |v|min. */
+typedef enum { RD_N = 0, RD_LDA = 1, RD_B = 2, RD_BMAX = 3, RD_BMIN = 4, RD_BX = 5 } rd_scheme;
+
+/* Lumping of the mass term in the second Runge-Kutta stage (Section 3.4):
+ * global (the default), or selective, which adds sum_j (|T| delta_ij / 3 -
+ * m^G_ij) (W*_j - W^n_j) / dt, m^G_ij = |T| (1 + delta_ij) / 12 (Galerkin
+ * mass), to the N and LDA total parts before they are blended. */
+typedef enum { RD_LUMP_GLOBAL = 0, RD_LUMP_SELECTIVE = 1 } rd_lumping;
 
 /* Time integration: forward Euler (the update of Section 3.2) or the
  * two-stage Runge-Kutta scheme of Section 3.4 with global lumping and the
@@ -164,6 +177,12 @@ rd_status rd_step_timed(rd_mesh* mesh, double cfl, int scheme, int time, int pre
  * may use (64 KiB). Waits for the mesh's stream. The default is 0. */
 rd_status rd_mesh_set_tile(rd_mesh* mesh, int tile_triangles);
 rd_status rd_mesh_get_tile(const rd_mesh* mesh, int* tile_triangles);
+/* Lumping of the mesh's RK2 steps (rd_lumping; RD_EINVAL for other values).
+ * Takes effect with the next step; the members of a batch must agree
+ * (rd_batch_run returns RD_EINVAL otherwise). The default is global. */
+rd_status rd_mesh_set_lumping(rd_mesh* mesh, int lumping);
+rd_status rd_mesh_get_lumping(const rd_mesh* mesh, int* lumping);
+
 /* Shape of the current tiling (all zero in the two-pass form): info[0] tiles,
  * info[1] local vertex records over all tiles (vertices on tile borders
  * count once per tile), info[2] shared vertices, info[3] their parts
@@ -188,7 +207,8 @@ rd_status rd_residual(rd_mesh* mesh, int scheme, double* R, double* phiT, int on
 /* Adjoint of one step for a fixed dt (FP64 only): given the state W_n
  * [4][n_vertices] the step started from and lam_np1 = dL/dW^{n+1}, writes
  * lam_n = (dW^{n+1}/dW^n)^T lam_np1. Does not change the mesh's state.
- * Derivatives follow the branch the forward values take; d|x|/dx = 0 at 0. */
+ * Derivatives follow the branch the forward values take; d|x|/dx = 0 at 0.
+ * RD_EUNSUPPORTED for the BX scheme and for RK2 with selective lumping. */
 rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int scheme, int time,
                           const double* lam_np1, double* lam_n, int on_device);
 

@@ -97,6 +97,7 @@ struct rd_mesh {
   std::vector<uint8_t> ghost;
   std::vector<rd::WallEnt> went;
   double px = 0.0, py = 0.0, gamma = 1.4;
+  double Ldom = 0.0;  // domain size of the Bx sensor
   // device buffers
   std::vector<void*> allocs;
   rd::CflPlan cfl;
@@ -228,10 +229,11 @@ rd_status run_step(rd_mesh* m, int scheme, int time, int fp32, double cfl, hipEv
   const rd::Dev d = dev_for(m, fp32);
   hipStream_t s = m->stream;
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
-  const bool with_cfl = cfl > 0.0;
+  const bool with_cfl = cfl > 0.0, bx = scheme == RD_BX;
   HIPCHK(mark(RD_K_WALL1));
   HIPCHK(rd::launch_wall(d, false, s));
   HIPCHK(mark(RD_K_TRI1));
+  if (bx) HIPCHK(rd::launch_vrange(d, m->cfl, 0, s));
   HIPCHK(rd::launch_tri(d, fp32, scheme, 1, time == RD_RK2, with_cfl, s));
   HIPCHK(mark(RD_K_SHARED1));
   HIPCHK(mark(RD_K_CFL));
@@ -245,6 +247,7 @@ rd_status run_step(rd_mesh* m, int scheme, int time, int fp32, double cfl, hipEv
   if (time == RD_RK2) {
     HIPCHK(rd::launch_wall(d, true, s));
     HIPCHK(mark(RD_K_TRI2));
+    if (bx) HIPCHK(rd::launch_vrange(d, m->cfl, 1, s));
     HIPCHK(rd::launch_tri(d, fp32, scheme, 2, false, false, s));
     HIPCHK(mark(RD_K_GATHER2));
     HIPCHK(rd::launch_gather(d, fp32, rd::G_STAGE2, nullptr, s));
@@ -266,10 +269,11 @@ rd_status run_step_tiled(rd_mesh* m, int scheme, int time, int fp32, double cfl,
   const rd::Tiles& tl = m->tiles;
   hipStream_t s = m->stream;
   auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
-  const bool with_cfl = cfl > 0.0, rk2 = time == RD_RK2;
+  const bool with_cfl = cfl > 0.0, rk2 = time == RD_RK2, bx = scheme == RD_BX;
   HIPCHK(mark(RD_K_WALL1));
   HIPCHK(rd::launch_wall(d, false, s));
   HIPCHK(mark(RD_K_TRI1));
+  if (bx) HIPCHK(rd::launch_vrange(d, m->cfl, 0, s));
   HIPCHK(rd::launch_tile(d, tl, fp32, scheme, 1, rk2, with_cfl, s));
   HIPCHK(mark(RD_K_SHARED1));
   HIPCHK(rd::launch_shared(d, tl, fp32, 1, with_cfl, s));
@@ -283,6 +287,7 @@ rd_status run_step_tiled(rd_mesh* m, int scheme, int time, int fp32, double cfl,
   HIPCHK(mark(RD_K_WALL2));
   if (rk2) HIPCHK(rd::launch_wall(d, true, s, true));
   HIPCHK(mark(RD_K_TRI2));
+  if (rk2 && bx) HIPCHK(rd::launch_vrange(d, m->cfl, 2, s));
   if (rk2) HIPCHK(rd::launch_tile(d, tl, fp32, scheme, 2, false, false, s));
   HIPCHK(mark(RD_K_GATHER2));
   if (rk2) HIPCHK(rd::launch_shared(d, tl, fp32, 2, false, s));
@@ -377,7 +382,7 @@ rd_status set_tile(rd_mesh* m, int tt) {
 }
 
 rd_status check_step_args(int scheme, int time, int precision) {
-  if (scheme < RD_N || scheme > RD_BMIN) return fail(RD_EINVAL, "unknown scheme");
+  if (scheme < RD_N || scheme > RD_BX) return fail(RD_EINVAL, "unknown scheme");
   if (time != RD_EULER1 && time != RD_RK2) return fail(RD_EINVAL, "unknown time integration");
   if (precision != RD_FP64 && precision != RD_FP32_ACC64) return fail(RD_EINVAL, "unknown precision");
   return RD_OK;
@@ -559,13 +564,24 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
       v1[b] = (int32_t)std::min<int64_t>(nv, (int64_t)(b + 1) * rd::kCflSpan);
     }
     int32_t *pv0, *pv1, *pb0;
-    double* part;
+    double *part, *vpart, *vr;
+    // domain size L of the Bx sensor: the period on a periodic axis, else the coordinate extent
+    {
+      const auto xr = std::minmax_element(m->x.begin(), m->x.end());
+      const auto yr = std::minmax_element(m->y.begin(), m->y.end());
+      const double lx = m->px > 0.0 ? m->px : *xr.second - *xr.first;
+      const double ly = m->py > 0.0 ? m->py : *yr.second - *yr.first;
+      m->Ldom = std::max(lx, ly);
+    }
+    const std::vector<double> vr0 = {0.0, 0.0, m->Ldom};
     if ((st = upload(m, &pv0, v0)) || (st = upload(m, &pv1, v1)) || (st = upload(m, &pb0, b0)) ||
-        (st = dalloc(m, &part, nb))) {
+        (st = dalloc(m, &part, nb)) || (st = dalloc(m, &vpart, 2 * nb)) || (st = upload(m, &vr, vr0))) {
       free_all(m);
       delete m;
       return st;
     }
+    d.vr = vr;
+    m->cfl.vpart = vpart;
     m->cfl.nblocks = nb;
     m->cfl.nmesh = 1;
     m->cfl.blk_v0 = pv0;
@@ -722,6 +738,19 @@ RD_API rd_status rd_mesh_get_tile(const rd_mesh* m, int* tile_triangles) {
   return RD_OK;
 }
 
+RD_API rd_status rd_mesh_set_lumping(rd_mesh* m, int lumping) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  if (lumping != RD_LUMP_GLOBAL && lumping != RD_LUMP_SELECTIVE) return fail(RD_EINVAL, "unknown lumping");
+  m->d.slump = lumping == RD_LUMP_SELECTIVE;
+  return RD_OK;
+}
+
+RD_API rd_status rd_mesh_get_lumping(const rd_mesh* m, int* lumping) {
+  if (!m || !lumping) return fail(RD_EINVAL, "null argument");
+  *lumping = m->d.slump ? RD_LUMP_SELECTIVE : RD_LUMP_GLOBAL;
+  return RD_OK;
+}
+
 RD_API rd_status rd_mesh_tile_info(const rd_mesh* m, int64_t* info) {
   if (!m || !info) return fail(RD_EINVAL, "null argument");
   for (int k = 0; k < 4; ++k) info[k] = m->tile_info[k];
@@ -829,7 +858,7 @@ RD_API rd_status rd_tune(rd_mesh* m, double cfl, int scheme, int time, int preci
 
 RD_API rd_status rd_residual(rd_mesh* m, int scheme, double* R, double* phiT, int on_device) {
   if (!m || !R) return fail(RD_EINVAL, "null argument");
-  if (scheme < RD_N || scheme > RD_BMIN) return fail(RD_EINVAL, "unknown scheme");
+  if (scheme < RD_N || scheme > RD_BX) return fail(RD_EINVAL, "unknown scheme");
   DeviceGuard g(m->device);
   rd_status st;
   if ((st = ensure_z(m, 0)) != RD_OK) return st;
@@ -837,6 +866,7 @@ RD_API rd_status rd_residual(rd_mesh* m, int scheme, double* R, double* phiT, in
   hipStream_t s = m->stream;
   const int64_t nv = d.nv, nt = d.nt;
   HIPCHK(rd::launch_wall(d, false, s));
+  if (scheme == RD_BX) HIPCHK(rd::launch_vrange(d, m->cfl, 0, s));
   HIPCHK(rd::launch_tri(d, 0, scheme, 1, true, false, s));
   if (on_device) {
     HIPCHK(rd::launch_gather(d, 0, rd::G_RESIDUAL, R, s));
@@ -859,6 +889,9 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RD_EINVAL, "dt must be positive and finite");
   rd_status st = check_step_args(scheme, time, RD_FP64);
   if (st != RD_OK) return st;
+  if (scheme == RD_BX) return fail(RD_EUNSUPPORTED, "the adjoint does not cover the Bx scheme");
+  if (m->d.slump && time == RD_RK2)
+    return fail(RD_EUNSUPPORTED, "the adjoint does not cover selective lumping");
   DeviceGuard g(m->device);
   const int64_t nv = m->d.nv, nt = m->d.nt;
   if (!m->adjW) {
@@ -937,7 +970,7 @@ struct rd_batch {
   hipStream_t own = nullptr;     // the batch's own stream (a null stream cannot be captured)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   struct Graph {
-    int n_steps, scheme, time, fp32;
+    int n_steps, scheme, time, fp32, slump;
     double cfl;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -1024,13 +1057,18 @@ RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd
     b0.push_back((int32_t)v0.size());
   }
   int32_t *pvm, *ptm, *pv0, *pv1, *pb0;
-  double *dt, *part;
+  double *dt, *part, *vpart, *vr;
+  std::vector<double> vr0(3 * n, 0.0);
+  for (int k = 0; k < n; ++k) vr0[3 * k + 2] = meshes[k]->Ldom;  // each member's own domain size
   if ((st = upload(flat, &pvm, vm)) || (st = upload(flat, &ptm, tm)) || (st = upload(flat, &pv0, v0)) ||
       (st = upload(flat, &pv1, v1)) || (st = upload(flat, &pb0, b0)) || (st = dalloc(flat, &dt, n)) ||
-      (st = dalloc(flat, &part, v0.size()))) {
+      (st = dalloc(flat, &part, v0.size())) || (st = dalloc(flat, &vpart, 2 * v0.size())) ||
+      (st = upload(flat, &vr, vr0))) {
     rd_mesh_destroy(flat);
     return st;
   }
+  flat->d.vr = vr;
+  flat->cfl.vpart = vpart;
   flat->voff = voff;
   flat->toff = toff;
   flat->d.vmesh = pvm;
@@ -1061,6 +1099,11 @@ namespace {
 // and copies the members' states in.
 rd_status batch_begin(rd_batch* b, int fp32, std::vector<hipStream_t>& outer) {
   rd_mesh* f = b->flat;
+  // the members' lumping, which must agree
+  for (rd_mesh* m : b->members)
+    if (m->d.slump != b->members[0]->d.slump)
+      return fail(RD_EINVAL, "the meshes of a batch use different lumpings");
+  f->d.slump = b->members[0]->d.slump;
   hipStream_t s = f->stream;  // the batch's own stream
   outer.assign(1, b->stream);
   for (rd_mesh* m : b->members)
@@ -1085,11 +1128,12 @@ rd_status batch_graph(rd_batch* b, int n_steps, double cfl, int scheme, int time
   rd_mesh* f = b->flat;
   hipStream_t s = f->stream;
   for (auto& c : b->graphs)
-    if (c.n_steps == n_steps && c.scheme == scheme && c.time == time && c.fp32 == fp32 && c.cfl == cfl) {
+    if (c.n_steps == n_steps && c.scheme == scheme && c.time == time && c.fp32 == fp32 && c.cfl == cfl &&
+        c.slump == f->d.slump) {
       *exec = c.exec;
       return RD_OK;
     }
-  rd_batch::Graph c{n_steps, scheme, time, fp32, cfl, nullptr, nullptr};
+  rd_batch::Graph c{n_steps, scheme, time, fp32, f->d.slump, cfl, nullptr, nullptr};
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   rd_status rs = RD_OK;
   for (int k = 0; k < n_steps && rs == RD_OK; ++k) rs = run_step(f, scheme, time, fp32, cfl);

@@ -51,7 +51,7 @@ struct alignas(16) WallEnt {
   double nx, ny;  // outward unit normal
 };
 
-enum { SCH_N = 0, SCH_LDA = 1, SCH_B = 2, SCH_BMAX = 3, SCH_BMIN = 4 };
+enum { SCH_N = 0, SCH_LDA = 1, SCH_B = 2, SCH_BMAX = 3, SCH_BMIN = 4, SCH_BX = 5 };
 enum { G_EULER = 0, G_STAGE1 = 1, G_STAGE2 = 2, G_RESIDUAL = 3 };
 
 // Device view of one mesh (or of a batch laid end to end).
@@ -89,6 +89,8 @@ struct Dev {
   void* lam = nullptr;    // [ns] l_max^T lambda_max^T, sliced layout: float from the FP32 triangle
                           // passes, double from the FP64 ones and from the CFL-only pass
   double* dt = nullptr;   // [n meshes] time step
+  double* vr = nullptr;   // [3 per mesh] Bx sensor: smallest and largest |v| at the stage's state, domain size L
+  int slump = 0;          // selective lumping in stage 2 (else global lumping)
   int* flag = nullptr;    // non-physical state latch
   // tiled form
   D4* R1 = nullptr;       // [nv] stage-1 (or Euler) vertex residual, wall term included
@@ -366,6 +368,7 @@ struct GlobalIO {
   const int32_t* iv;
   const int32_t* ip;
   __host__ __device__ R idt(int64_t t) const { return (R)(1.0 / d.dt[d.tmesh ? d.tmesh[t] : 0]); }
+  __host__ __device__ const double* vr(int64_t t) const { return d.vr + 3 * (d.tmesh ? d.tmesh[t] : 0); }
   __host__ __device__ Q4<R> dw(int i) const { return reinterpret_cast<const Q4<R>*>(d.dW)[iv[i]]; }
   __host__ __device__ void part(int i, const R out[4]) const {
     Q4<R> q;
@@ -377,7 +380,8 @@ struct GlobalIO {
   // registers here; see CornerLds).
 };
 
-template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, class IO>
+// LUMP (stage 2 only): selective lumping of Section 3.4 instead of global lumping.
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP = false, class IO>
 __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const Dev& d, const IO& io) {
   const double2 p0 = in.p[0], p1 = in.p[1], p2 = in.p[2];
   const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
@@ -387,6 +391,22 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   const double nyd[3] = {d2x - d1x, -d2x, d1x};
 
   const Q4<R>* Zc = in.Z;
+
+  // Bx blend coefficient (Section 3.3.3): theta = min(1, s^2 h / L) with the
+  // shock sensor s = (-L div v / (|v|max - |v|min))^+, div v that of the
+  // linear interpolant of the corner velocities (u = Z_1 / Z_0, v = Z_2 / Z_0),
+  // h = sqrt(2 |T|); |v|min, |v|max (at this stage's state) and the domain
+  // size L of the triangle's mesh come from io.vr.
+  R bx = R(0);
+  if (SCHEME == SCH_BX) {
+    const double* r = io.vr(t);
+    R div = R(0);
+    for (int i = 0; i < 3; ++i) div = div + (Zc[i].v[1] * (R)nxd[i] + Zc[i].v[2] * (R)nyd[i]) / Zc[i].v[0];
+    const double a2 = d1x * d2y - d1y * d2x;  // 2 |T|
+    const R range = (R)(r[1] - r[0]), L = (R)r[2];
+    const R sn = range > R(0) ? rmax(-(L * div) / ((R)a2 * range), R(0)) : R(0);
+    bx = rmin(sn * sn * (R)sqrt(a2) / L, R(1));
+  }
 
   const R gam = (R)d.gamma;
   Roe<R> q;
@@ -505,6 +525,27 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     apply_split(q, kc[1], kc[1].l3p, kc[1].h1p, kc[1].h2p, xL, pl[1]);
     for (int k = 0; k < 4; ++k) pl[2][k] = rhs1[k] - pl[0][k] - pl[1][k];
   }
+  // Selective lumping (Section 3.4, stage 2): the N and LDA total parts both
+  // get sum_j (|T| delta_ij / 3 - m^G_ij) (W*_j - W^n_j) / dt with the
+  // Galerkin mass m^G_ij = |T| (1 + delta_ij) / 12, that is
+  // (|T| / 12) (3 r_i - r_0 - r_1 - r_2) with r = (W* - W^n) / dt.
+  R sl[3][4];
+  if (STAGE == 2 && LUMP) {
+    R rs[4] = {R(0), R(0), R(0), R(0)};
+    for (int i = 0; i < 3; ++i) {
+      const Q4<R> dwv = io.dw(i);
+      for (int k = 0; k < 4; ++k) {
+        sl[i][k] = dwv.v[k] * idt;
+        rs[k] = rs[k] + sl[i][k];
+      }
+    }
+    const R m12 = mass * R(0.25);
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 4; ++k) sl[i][k] = m12 * (R(3) * sl[i][k] - rs[k]);
+    if (needL)
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 4; ++k) pl[i][k] = pl[i][k] + sl[i][k];
+  }
   R den[4] = {R(0), R(0), R(0), R(0)};
   if (needN) {
     for (int i = 0; i < 2; ++i) {
@@ -535,6 +576,9 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
         const Q4<R> dwv = io.dw(i);
         for (int k = 0; k < 4; ++k) pN[i][k] = mass * (dwv.v[k] * idt) + R(0.5) * (kn[i][k] + pN[i][k]);
       }
+      if (LUMP)
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 4; ++k) pN[i][k] = pN[i][k] + sl[i][k];
     }
     for (int i = 0; i < 3; ++i)
       for (int k = 0; k < 4; ++k) den[k] = den[k] + (R)fabs(pN[i][k]);
@@ -542,7 +586,9 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   if (STAGE == 1 && SAVE) st4<R>(d.keepT, t, phiT);
   // rhs1 is the residual being split (phi^T or Phi^T)
   R th[4] = {R(0), R(0), R(0), R(0)};
-  if (SCHEME >= SCH_B) blend_theta<R, SCHEME>(rhs1, den, th);
+  if (SCHEME >= SCH_B && SCHEME <= SCH_BMIN) blend_theta<R, SCHEME>(rhs1, den, th);
+  if (SCHEME == SCH_BX)
+    for (int k = 0; k < 4; ++k) th[k] = bx;
   for (int i = 0; i < 3; ++i) {
     R out[4];
     for (int k = 0; k < 4; ++k) {
@@ -554,13 +600,19 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   }
 }
 
-template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP = false>
 __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
   TriIn<R> in;
   tri_load_ids<R>(t, d, in);
   tri_load_verts<R, CFL>(d, in);
   const GlobalIO<R> io{d, in.iv, in.ip};
-  tri_compute<R, SCHEME, STAGE, SAVE, CFL>(t, in, d, io);
+  tri_compute<R, SCHEME, STAGE, SAVE, CFL, LUMP>(t, in, d, io);
+}
+
+// Flow speed |v| of a conserved state.
+__host__ __device__ inline double flow_speed(const D4& w) {
+  const double u = w.v[1] / w.v[0], v = w.v[2] / w.v[0];
+  return sqrt(u * u + v * v);
 }
 
 // Parameter vector, signal speed and physicality of one state.

@@ -12,10 +12,10 @@ namespace rd {
 // One thread per triangle. (A persistent grid with the next triangle's loads
 // software-pipelined was measured slower: fewer waves in flight and, with
 // per-workgroup chunks, scattered working sets.)
-template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP>
 __global__ __launch_bounds__(kBlock, (TriKernelWaves<R, SCHEME, STAGE, SAVE, CFL>::value)) void k_tri(Dev d) {
   const int64_t t = xcd_block() * kBlock + threadIdx.x;
-  if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE, CFL>(t, d);
+  if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE, CFL, LUMP>(t, d);
 }
 
 template <typename R, int MODE>
@@ -58,6 +58,49 @@ __global__ __launch_bounds__(kBlock) void k_cfl_final(Dev d, CflPlan p, double c
   for (int b = p.mesh_b0[m] + threadIdx.x; b < p.mesh_b0[m + 1]; b += kBlock) x = rmin(x, p.part[b]);
   x = block_min(x);
   if (threadIdx.x == 0) d.dt[m] = cfl * x;
+}
+
+// Smallest and largest flow speed |v| over each CFL block's vertices (the Bx
+// sensor's range), at W^n (MODE 0), at W* held in Ws (MODE 1) or at W*
+// formed from the stage-1 residual (MODE 2, tiled form); then per mesh.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_vrange(Dev d, CflPlan p) {
+  const int b = blockIdx.x;
+  double lo = INFINITY, hi = 0.0;
+#pragma unroll
+  for (int u = 0; u < kCflSpan / kBlock; ++u) {
+    const int64_t v = (int64_t)p.blk_v0[b] + u * kBlock + threadIdx.x;
+    if (v < p.blk_v1[b]) {
+      const D4 w = MODE == 0 ? d.W[v] : (MODE == 1 ? d.Ws[v] : star_state(d, v, d.bc ? d.bc[v] : -1,
+                                                                            d.vmesh ? d.vmesh[v] : 0));
+      const double sp = flow_speed(w);
+      lo = rmin(lo, sp);
+      hi = rmax(hi, sp);
+    }
+  }
+  lo = block_min(lo);
+  __syncthreads();
+  hi = -block_min(-hi);
+  if (threadIdx.x == 0) {
+    p.vpart[2 * b] = lo;
+    p.vpart[2 * b + 1] = hi;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_vrange_final(Dev d, CflPlan p) {
+  const int m = blockIdx.x;
+  double lo = INFINITY, hi = 0.0;
+  for (int b = p.mesh_b0[m] + threadIdx.x; b < p.mesh_b0[m + 1]; b += kBlock) {
+    lo = rmin(lo, p.vpart[2 * b]);
+    hi = rmax(hi, p.vpart[2 * b + 1]);
+  }
+  lo = block_min(lo);
+  __syncthreads();
+  hi = -block_min(-hi);
+  if (threadIdx.x == 0) {
+    d.vr[3 * m] = lo;
+    d.vr[3 * m + 1] = hi;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_set_state(Dev d, const double* soa, int fp32) {
@@ -164,9 +207,9 @@ hipError_t launch_soa_to_aos(const double* soa, D4* dst, int64_t n, hipStream_t 
   return hipGetLastError();
 }
 
-template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP = false>
 static hipError_t tri_launch(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL((k_tri<R, SCHEME, STAGE, SAVE, CFL>), dim3(nblk(d.nt)), dim3(kBlock), 0, s, d);
+  hipLaunchKernelGGL((k_tri<R, SCHEME, STAGE, SAVE, CFL, LUMP>), dim3(nblk(d.nt)), dim3(kBlock), 0, s, d);
   return hipGetLastError();
 }
 
@@ -176,6 +219,7 @@ static hipError_t tri_dispatch(const Dev& d, int stage, bool save, bool cfl, hip
   if (stage == 1 && save) return tri_launch<R, SCHEME, 1, true, false>(d, s);
   if (stage == 1 && cfl) return tri_launch<R, SCHEME, 1, false, true>(d, s);
   if (stage == 1) return tri_launch<R, SCHEME, 1, false, false>(d, s);
+  if (d.slump) return tri_launch<R, SCHEME, 2, false, false, true>(d, s);
   return tri_launch<R, SCHEME, 2, false, false>(d, s);
 }
 
@@ -187,6 +231,7 @@ static hipError_t tri_scheme(const Dev& d, int scheme, int stage, bool save, boo
     case SCH_B: return tri_dispatch<R, SCH_B>(d, stage, save, cfl, s);
     case SCH_BMAX: return tri_dispatch<R, SCH_BMAX>(d, stage, save, cfl, s);
     case SCH_BMIN: return tri_dispatch<R, SCH_BMIN>(d, stage, save, cfl, s);
+    case SCH_BX: return tri_dispatch<R, SCH_BX>(d, stage, save, cfl, s);
   }
   return hipErrorInvalidValue;
 }
@@ -229,6 +274,16 @@ hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part,
   else if (part == 1) hipLaunchKernelGGL((k_cfl_vertex<false, double>), dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
   else if (part == 3) hipLaunchKernelGGL((k_cfl_vertex<true, double>), dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
   else hipLaunchKernelGGL(k_cfl_final, dim3(p.nmesh), dim3(kBlock), 0, s, d, p, cfl);
+  return hipGetLastError();
+}
+
+hipError_t launch_vrange(const Dev& d, const CflPlan& p, int mode, hipStream_t s) {
+  if (p.nblocks == 0) return hipSuccess;
+  if (mode == 0) hipLaunchKernelGGL(k_vrange<0>, dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else if (mode == 1) hipLaunchKernelGGL(k_vrange<1>, dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else if (mode == 2) hipLaunchKernelGGL(k_vrange<2>, dim3(p.nblocks), dim3(kBlock), 0, s, d, p);
+  else return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_vrange_final, dim3(p.nmesh), dim3(kBlock), 0, s, d, p);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ struct CflPlan {
   const int32_t* blk_v1 = nullptr;
   const int32_t* mesh_b0 = nullptr;
   double* part = nullptr;
+  double* vpart = nullptr;  // [2 nblocks] Bx speed range per block
 };
 
 // cfl: also write l_max lambda_max per corner (stage 1 only)
@@ -29,6 +30,10 @@ hipError_t launch_gather(const Dev& d, int fp32, int mode, double* out_soa, hipS
 // tiled: the stage-2 wall term reads W* rebuilt from R1
 hipError_t launch_wall(const Dev& d, bool stage2, hipStream_t s, bool tiled = false);
 hipError_t launch_cfl(const Dev& d, const CflPlan& p, double cfl, hipStream_t s);
+// Bx sensor range: smallest and largest |v| per mesh -> d.vr, over the same
+// vertex blocks as the CFL reduction; mode 0 at W^n, 1 at W* (Ws), 2 at W*
+// rebuilt from R1 (tiled form)
+hipError_t launch_vrange(const Dev& d, const CflPlan& p, int mode, hipStream_t s);
 // part 0: l_max lambda_max per triangle corner (FP64); part 1: per-vertex
 // bounds (sums of the sliced terms, float when fp32: as the FP32 triangle
 // pass writes them) and block minima; part 3: the same from the bounds the

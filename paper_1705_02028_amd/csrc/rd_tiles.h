@@ -89,7 +89,9 @@ struct TileIO {
   void* Cs;
   double* lams;
   R idt_;
+  const double* vr_;
   __host__ __device__ R idt(int64_t) const { return idt_; }
+  __host__ __device__ const double* vr(int64_t) const { return vr_; }
   __host__ __device__ Q4<R> dw(int i) const { return L.dW[lvi[i]]; }
   __host__ __device__ void part(int i, const R out[4]) const {
     Q4<R> q;
@@ -137,12 +139,12 @@ __host__ __device__ inline void tile_load2(int64_t tile, int32_t l, const Dev& d
   if (l < tl.nvi[tile]) L.Ws[l] = ws;
 }
 
-template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP = false>
 __host__ __device__ inline void tile_tri(int64_t tile, int32_t j, const Dev& d, const Tiles& tl,
                                          const TileLds<R>& L) {
   const int64_t s = (int64_t)tl.tbeg[tile] + j;
   const int64_t nt = d.nt;
-  TileIO<R> io{L, {0, 0, 0}, {0, 0, 0}, tl.Cs, tl.lams, R(0)};
+  TileIO<R> io{L, {0, 0, 0}, {0, 0, 0}, tl.Cs, tl.lams, R(0), d.vr + 3 * tile_mesh(tl, tile)};
   TriIn<R> in;
   for (int i = 0; i < 3; ++i) {
     const int q = tl.lv[i * nt + s];
@@ -153,7 +155,7 @@ __host__ __device__ inline void tile_tri(int64_t tile, int32_t j, const Dev& d, 
     if (CFL) in.sig[i] = L.sig[q];
   }
   if (STAGE == 2) io.idt_ = (R)(1.0 / d.dt[tile_mesh(tl, tile)]);
-  tri_compute<R, SCHEME, STAGE, SAVE, CFL>(s, in, d, io);
+  tri_compute<R, SCHEME, STAGE, SAVE, CFL, LUMP>(s, in, d, io);
 }
 
 // Stage-1 (or Euler) sum of interior vertex l: R1 = sum of parts + wall term,

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kBlock, TriWaves<R>::value) void k_tile1(Dev d, Til
   for (int32_t l = tid; l < nvi; l += nthr) tile_sum1<R, CFL>(tile, l, d, tl, L);
 }
 
-template <typename R, int SCHEME>
+template <typename R, int SCHEME, bool LUMP>
 __global__ __launch_bounds__(kBlock, TriWaves<R>::value) void k_tile2(Dev d, Tiles tl) {
   extern __shared__ D4 lds_raw[];
   const int64_t tile = xcd_block();
@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kBlock, TriWaves<R>::value) void k_tile2(Dev d, Til
   for (int32_t l = tid; l < nlv; l += nthr) tile_load2<R>(tile, l, d, tl, L);
   __syncthreads();
   const int32_t ntri = tl.tbeg[tile + 1] - tl.tbeg[tile];
-  for (int32_t j = tid; j < ntri; j += nthr) tile_tri<R, SCHEME, 2, false, false>(tile, j, d, tl, L);
+  for (int32_t j = tid; j < ntri; j += nthr) tile_tri<R, SCHEME, 2, false, false, LUMP>(tile, j, d, tl, L);
   __syncthreads();
   const int32_t nvi = tl.nvi[tile];
   for (int32_t l = tid; l < nvi; l += nthr) tile_sum2<R>(tile, l, d, tl, L);
@@ -66,7 +66,8 @@ template <typename R, int SCHEME>
 static hipError_t tile_go(const Dev& d, const Tiles& tl, int stage, bool save, bool cfl, hipStream_t s) {
   const dim3 g(tl.ntiles), b(tile_threads(tl));
   const size_t lds = tile_lds<R>(tl, stage, cfl, nullptr, nullptr);
-  if (stage == 2) hipLaunchKernelGGL((k_tile2<R, SCHEME>), g, b, lds, s, d, tl);
+  if (stage == 2 && d.slump) hipLaunchKernelGGL((k_tile2<R, SCHEME, true>), g, b, lds, s, d, tl);
+  else if (stage == 2) hipLaunchKernelGGL((k_tile2<R, SCHEME, false>), g, b, lds, s, d, tl);
   else if (save && cfl) hipLaunchKernelGGL((k_tile1<R, SCHEME, true, true>), g, b, lds, s, d, tl);
   else if (save) hipLaunchKernelGGL((k_tile1<R, SCHEME, true, false>), g, b, lds, s, d, tl);
   else if (cfl) hipLaunchKernelGGL((k_tile1<R, SCHEME, false, true>), g, b, lds, s, d, tl);
@@ -83,6 +84,7 @@ static hipError_t tile_scheme(const Dev& d, const Tiles& tl, int scheme, int sta
     case SCH_B: return tile_go<R, SCH_B>(d, tl, stage, save, cfl, s);
     case SCH_BMAX: return tile_go<R, SCH_BMAX>(d, tl, stage, save, cfl, s);
     case SCH_BMIN: return tile_go<R, SCH_BMIN>(d, tl, stage, save, cfl, s);
+    case SCH_BX: return tile_go<R, SCH_BX>(d, tl, stage, save, cfl, s);
   }
   return hipErrorInvalidValue;
 }

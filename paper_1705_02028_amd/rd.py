@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librd.so")
 
 RD_OK, RD_EINVAL, RD_ENOMEM, RD_EDEVICE, RD_ENONPHYS, RD_EUNSUPPORTED = range(6)
-N, LDA, B, BMAX, BMIN = range(5)
+N, LDA, B, BMAX, BMIN, BX = range(6)
+LUMP_GLOBAL, LUMP_SELECTIVE = 0, 1
 EULER1, RK2 = 1, 2
 FP64, FP32_ACC64 = 0, 1
 
@@ -43,7 +44,7 @@ EXPORTS = ["rd_mesh_validate", "rd_mesh_create", "rd_mesh_destroy", "rd_mesh_inf
            "rd_set_state", "rd_get_state", "rd_max_dt", "rd_step", "rd_step_cfl", "rd_step_timed", "rd_residual",
            "rd_adjoint_step", "rd_batch_create", "rd_batch_run", "rd_batch_destroy", "rd_sync",
            "rd_last_error", "rd_mesh_set_tile", "rd_mesh_get_tile", "rd_mesh_tile_info", "rd_tune",
-           "rd_batch_set_tile", "rd_batch_tune"]
+           "rd_batch_set_tile", "rd_batch_tune", "rd_mesh_set_lumping", "rd_mesh_get_lumping"]
 
 _lib = None
 
@@ -75,6 +76,8 @@ def lib():
             "rd_batch_destroy": [P],
             "rd_sync": [P],
             "rd_mesh_set_tile": [P, I],
+            "rd_mesh_set_lumping": [P, I],
+            "rd_mesh_get_lumping": [P, P],
             "rd_mesh_get_tile": [P, P],
             "rd_mesh_tile_info": [P, P],
             "rd_tune": [P, D, I, I, I, I, P, I, P, P],
@@ -209,6 +212,16 @@ def rd_mesh_get_tile(h) -> int:
     return t.value
 
 
+def rd_mesh_set_lumping(h, lumping: int) -> None:
+    _check(lib().rd_mesh_set_lumping(h, int(lumping)))
+
+
+def rd_mesh_get_lumping(h) -> int:
+    t = C.c_int()
+    _check(lib().rd_mesh_get_lumping(h, C.byref(t)))
+    return t.value
+
+
 def rd_mesh_tile_info(h) -> dict:
     a = (C.c_int64 * 4)()
     _check(lib().rd_mesh_tile_info(h, a))
@@ -326,6 +339,14 @@ class Mesh:
 
     def tune(self, cfl, scheme=B, time=RK2, precision=FP64, n_steps=5, candidates=None):
         return rd_tune(self.h, cfl, scheme, time, precision, n_steps, candidates)
+
+    @property
+    def lumping(self) -> int:
+        return rd_mesh_get_lumping(self.h)
+
+    @lumping.setter
+    def lumping(self, lumping: int):
+        rd_mesh_set_lumping(self.h, lumping)
 
     def residual(self, scheme=B, with_phiT=False):
         R = np.zeros((4, self.nv))
