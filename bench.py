@@ -331,9 +331,25 @@ def cpu_baseline(mesh, W0, cfl):
     t0 = time.perf_counter()
     om.step(W0, dt, oracle.B, oracle.RK2)
     el = time.perf_counter() - t0
-    return {"value": round(mesh["nt"] / el, 1), "unit": "triangle-updates/s", "cores": oracle.max_threads(),
-            "kind": "oracle", "seconds": round(el, 2),
-            "sample": f"one FP64 RK2/B step of the same {mesh['N']}x{mesh['N']} mesh ({mesh['nt']} triangles)"}
+    out = {"value": round(mesh["nt"] / el, 1), "unit": "triangle-updates/s", "cores": oracle.max_threads(),
+           "kind": "oracle", "seconds": round(el, 2), "us_per_triangle_step": round(el * 1e6 / mesh["nt"], 4),
+           "sample": f"one FP64 RK2/B step of the same {mesh['N']}x{mesh['N']} mesh ({mesh['nt']} triangles)"}
+    # one host thread, on a 512x512 mesh of the same workload (about a second of work)
+    from paper_1705_02028_amd import inputs
+    small = inputs.split_square(512)
+    Ws = inputs.ic_kelvin_helmholtz(small, seed=0)
+    os1 = oracle.OracleMesh(small)
+    dts = os1.max_dt(Ws, cfl)
+    threads = oracle.max_threads()
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    os1.step(Ws, dts, oracle.B, oracle.RK2)
+    el1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    out["single_thread"] = {"value": round(small["nt"] / el1, 1), "unit": "triangle-updates/s", "cores": 1,
+                            "us_per_triangle_step": round(el1 * 1e6 / small["nt"], 4),
+                            "sample": f"one FP64 RK2/B step of the 512x512 mesh ({small['nt']} triangles)"}
+    return out
 
 
 def main():

@@ -322,6 +322,47 @@ def random_smooth_state(mesh, seed=0, amp=0.1, u=0.3, v=-0.2, p=1.0):
                         p * (1.0 + amp * fields[3]), mesh["gamma"])
 
 
+def ic_sound_wave(mesh, amp=1e-4):
+    """Right-moving linear sound wave of Section 5.1.1: rho = 1 + amp sin(2 pi x),
+    u = c (rho - 1), p = 1/gamma + c^2 (rho - 1), c = 1, v = 0 (wavelength 1)."""
+    g = mesh["gamma"]
+    d = amp * np.sin(2.0 * np.pi * mesh["x"])
+    return prim_to_cons(1.0 + d, d, 0.0, 1.0 / g + d, g)
+
+
+def ic_isentropic_vortex(mesh, xc=5.0, yc=5.0, beta=5.0, boost=0.0):
+    """Isentropic vortex of Section 5.2.3 (p = rho^gamma far away equal to
+    1): v = Omega(r) (-(y - yc), x - xc) + (boost, 0), Omega = beta
+    exp((1 - r^2)/2) / (2 pi), T = p / rho = 1 - (gamma - 1)/gamma beta^2
+    exp(1 - r^2) / (8 pi^2), rho = T^(1/(gamma - 1)), p = rho^gamma."""
+    g = mesh["gamma"]
+    dx, dy = mesh["x"] - xc, mesh["y"] - yc
+    r2 = dx * dx + dy * dy
+    om = beta * np.exp(0.5 * (1.0 - r2)) / (2.0 * np.pi)
+    T = 1.0 - (g - 1.0) / g * beta * beta * np.exp(1.0 - r2) / (8.0 * np.pi ** 2)
+    rho = T ** (1.0 / (g - 1.0))
+    return prim_to_cons(rho, -om * dy + boost, om * dx, rho ** g, g)
+
+
+def _smooth_step(t):
+    """g(t) of Section 5.2.5: 0 for t <= 0, 1 for t >= 1, smooth between."""
+    t = np.asarray(t, dtype=np.float64)
+    f = lambda s: np.where(s > 0.0, np.exp(-1.0 / np.where(s > 0.0, s, 1.0)), 0.0)  # noqa: E731
+    return f(t) / (f(t) + f(1.0 - t))
+
+
+def ic_kh_smooth(mesh, d=0.25, u0=0.5, rho_l=1.0, rho_h=2.0, p=2.5, amp=1e-3):
+    """Smoothed Kelvin-Helmholtz shear layer of Section 5.2.5 (transition
+    width d) with a transverse velocity amp sin(2 pi x) (the k_x = 2 pi
+    mode; the paper seeds its eigenvector, this seeds the plain sine)."""
+    y = mesh["y"]
+    prof = _smooth_step(0.5 + (y - 0.25) / d) * _smooth_step(0.5 - (y - 0.75) / d)
+    rho = (rho_h - rho_l) * prof + rho_l
+    u = 2.0 * u0 * prof - u0
+    v = amp * np.sin(2.0 * np.pi * mesh["x"])
+    return prim_to_cons(rho, u, v, p, mesh["gamma"])
+
+
 # ------------------------------------------------------------ workloads ----
 
 def batch_sides(seed=0, n=256, lo=32, hi=512):
