@@ -41,8 +41,8 @@ def algorithmic_bytes(nt, nv, fp32):
     # CFL: CSR rows, V and the per-corner l_max lambda_max in, block minima out
     k["shared1"] = 0
     k["cfl"] = nv * (4 + 8) + nt * 24
-    # gather 1: rows, parts in; W, V in; W*, W*-W, Z*, |v|+c out
-    k["gather1"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + r4 + 8)
+    # gather 1: rows, parts in; W, V in; W*, W*-W, Z* out
+    k["gather1"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + r4)
     # stage 2: ids, positions, coordinates, Z*, W*-W, kept N parts, phi^T in; parts out
     k["tri2"] = nt * (12 + 12 + 2 * r4 + r4 + 3 * r4) + nv * (16 + r4 + r4)
     # gather 2: rows, parts in; W*, V in; W, Z, |v|+c out

@@ -647,11 +647,14 @@ __host__ __device__ inline Q4<R> zq(const VertexDerived& o) {
   return q;
 }
 
-__host__ __device__ inline void vertex_epilogue(const Dev& d, int64_t v, const double w[4], bool fp32) {
+// with_sig: also store |v| + c (the CFL limit reads it at the start of a
+// step; the first-stage state W* does not need it)
+__host__ __device__ inline void vertex_epilogue(const Dev& d, int64_t v, const double w[4], bool fp32,
+                                                bool with_sig = true) {
   const VertexDerived o = derive(d.gamma, w);
   if (fp32) d.Zf[v] = zq<float>(o);
   else d.Z[v] = zq<double>(o);
-  d.sig[v] = o.sig;
+  if (with_sig) d.sig[v] = o.sig;
   if (!o.ok) d.flag[0] = 1;
 }
 
@@ -744,7 +747,7 @@ __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out
   } else {
     st4<double>(d.W, v, wo);
   }
-  vertex_epilogue(d, v, wo, sizeof(R) != sizeof(double));
+  vertex_epilogue(d, v, wo, sizeof(R) != sizeof(double), MODE != G_STAGE1);
 }
 
 // The first-stage state W* = W^n - (dt / V) R1 of vertex v in the tiled form

@@ -46,7 +46,9 @@ def test_enum_values_match_header(rd):
     for name, val in [("RD_N", rd.N), ("RD_LDA", rd.LDA), ("RD_B", rd.B), ("RD_BMAX", rd.BMAX),
                       ("RD_BMIN", rd.BMIN), ("RD_EULER1", rd.EULER1), ("RD_RK2", rd.RK2),
                       ("RD_FP64", rd.FP64), ("RD_FP32_ACC64", rd.FP32_ACC64), ("RD_OK", rd.RD_OK),
-                      ("RD_EINVAL", rd.RD_EINVAL), ("RD_ENONPHYS", rd.RD_ENONPHYS)]:
+                      ("RD_EINVAL", rd.RD_EINVAL), ("RD_ENONPHYS", rd.RD_ENONPHYS), ("RD_BX", rd.BX),
+                      ("RD_LUMP_GLOBAL", rd.LUMP_GLOBAL), ("RD_LUMP_SELECTIVE", rd.LUMP_SELECTIVE),
+                      ("RD_EUNSUPPORTED", rd.RD_EUNSUPPORTED)]:
         assert re.search(rf"\b{name}\s*=\s*{val}\b", text), name
 
 
@@ -101,3 +103,15 @@ def test_periodic_unwrap_accepted_by_validation(rd):
     m2["px"] = 0.0  # without the period the seam triangles are inverted
     with pytest.raises(rd.RDError, match="counter-clockwise"):
         rd.rd_mesh_validate(m2)
+
+
+def test_host_validation_rejects_sizes_beyond_32_bit_indices(rd):
+    """3 n_triangles and n_vertices must stay below 2^31 (int32 corner and
+    slot indices); the check runs before any array is read."""
+    for nv, nt in ((16, 2 ** 31 // 3 + 1), (2 ** 31, 16)):
+        d = rd.rd_mesh_desc(nv, nt, None, None, None, 0.0, 0.0, None, 0, None, 1.4)
+        assert rd.lib().rd_mesh_validate(C.byref(d)) == rd.RD_EINVAL
+        assert "too large" in rd.lib().rd_last_error().decode()
+    d = rd.rd_mesh_desc(16, 2 ** 31 // 3, None, None, None, 0.0, 0.0, None, 0, None, 1.4)
+    assert rd.lib().rd_mesh_validate(C.byref(d)) == rd.RD_EINVAL   # passes the size check, then
+    assert "null" in rd.lib().rd_last_error().decode()             # stops at the missing arrays
