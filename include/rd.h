@@ -212,6 +212,28 @@ rd_status rd_residual(rd_mesh* mesh, int scheme, double* R, double* phiT, int on
 rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int scheme, int time,
                           const double* lam_np1, double* lam_n, int on_device);
 
+/* Delaunay triangulation by edge flips (Section 2, the step that ends every
+ * refinement iteration), on the current GPU. Input: n_vertices points (x, y
+ * host arrays) and a triangulation of them, tri [3 * n_triangles] host
+ * (counter-clockwise after minimum-image unwrapping on a periodic axis, as
+ * in rd_mesh_desc); every vertex used, every edge in at most two triangles.
+ * On return tri holds a Delaunay triangulation of the same points with the
+ * same number of triangles (boundary edges, those in one triangle, are kept;
+ * triangle t keeps its index, its corners change): every interior edge has
+ * its opposite vertex on or outside the circumcircle of each of its
+ * triangles, decided by an exact in-circle predicate (FP64 with an error
+ * bound, exact expansion arithmetic when that cannot decide; exact while
+ * nonzero coordinate differences stay between about 2^-200 and 2^250; on a
+ * periodic axis, on the coordinates unwrapped next to each edge's first
+ * vertex as computed in FP64). Edges are flipped in rounds of independent
+ * flips, the lowest-numbered illegal edge first wherever two compete, so the
+ * result is the same on every run. n_flips and n_rounds (may be NULL)
+ * receive the number of flips and rounds. RD_EINVAL for an invalid input
+ * (with the checks of rd_mesh_validate), RD_ENOMEM, RD_EDEVICE. Allocates
+ * device memory for the call, uses a stream of its own and waits for it. */
+rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y, double period_x, double period_y,
+                           int64_t n_triangles, int32_t* tri, int64_t* n_flips, int32_t* n_rounds);
+
 /* Many independent meshes advanced together. The batch keeps its own copy of
  * the meshes' geometry and its own HIP stream (a null stream cannot be
  * captured); rd_batch_run is ordered after pending work on `stream` and on the

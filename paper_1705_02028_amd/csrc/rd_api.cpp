@@ -7,9 +7,11 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "rd.h"
+#include "rd_delaunay.h"
 #include "rd_launch.h"
 #include "rd_tiling.h"
 
@@ -1268,3 +1270,132 @@ RD_API rd_status rd_sync(rd_mesh* m) {
 }
 
 RD_API const char* rd_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------ Delaunay flips --
+//
+// The triangulation is checked as a mesh is (indices, counter-clockwise
+// triangles after unwrapping); the neighbour table is built on the host from
+// sorted vertex pairs; the flip rounds run on the current device (see
+// rd_delaunay.hip), the host reading three counters per round.
+
+RD_API rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y, double period_x,
+                                  double period_y, int64_t n_triangles, int32_t* tri, int64_t* n_flips,
+                                  int32_t* n_rounds) {
+  rd_mesh_desc desc{};
+  desc.n_vertices = n_vertices;
+  desc.n_triangles = n_triangles;
+  desc.x = x;
+  desc.y = y;
+  desc.tri = tri;
+  desc.period_x = period_x;
+  desc.period_y = period_y;
+  desc.gamma = 1.4;  // not used; the check requires a valid value
+  rd_status st = check_desc(&desc, nullptr);
+  if (st != RD_OK) return st;
+  const int64_t nt = n_triangles, nv = n_vertices;
+  std::vector<int32_t> nbr(3 * nt, -1), tsoa(3 * nt);
+  {
+    struct Edge {
+      int64_t key;
+      int32_t t, i;
+    };
+    std::vector<Edge> edges(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+      for (int i = 0; i < 3; ++i) {
+        const int64_t b = tri[3 * t + (i + 1) % 3], c = tri[3 * t + (i + 2) % 3];
+        edges[3 * t + i] = {std::min(b, c) * nv + std::max(b, c), (int32_t)t, i};
+        tsoa[i * nt + t] = tri[3 * t + i];
+      }
+    std::sort(edges.begin(), edges.end(), [](const Edge& p, const Edge& q) { return p.key < q.key; });
+    for (size_t k = 0; k < edges.size();) {
+      size_t l = k + 1;
+      while (l < edges.size() && edges[l].key == edges[k].key) ++l;
+      if (l - k > 2) return fail(RD_EINVAL, "an edge belongs to more than two triangles");
+      if (l - k == 2) {
+        nbr[edges[k].i * nt + edges[k].t] = edges[k + 1].t;
+        nbr[edges[k + 1].i * nt + edges[k + 1].t] = edges[k].t;
+      }
+      k = l;
+    }
+  }
+  std::vector<void*> bufs;
+  auto release = [&]() {
+    for (void* q : bufs) (void)hipFree(q);
+    bufs.clear();
+  };
+  auto get = [&](auto** out, size_t n) -> bool {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(**out)) != hipSuccess) return false;
+    bufs.push_back(q);
+    *out = static_cast<std::remove_reference_t<decltype(*out)>>(q);
+    return true;
+  };
+  rd::dl::Mesh m;
+  m.nt = nt;
+  m.px = period_x;
+  m.py = period_y;
+  double *dx = nullptr, *dy = nullptr;
+  const int64_t cap = 3 * nt / 2 + 1;  // interior edges at most
+  if (!get(&dx, nv) || !get(&dy, nv) || !get(&m.tri, 3 * nt) || !get(&m.nbr, 3 * nt) || !get(&m.claim, nt) ||
+      !get(&m.cand, nt) || !get(&m.flipped, nt) || !get(&m.partner, nt) || !get(&m.count, 3) ||
+      !get(&m.undecided, cap)) {
+    release();
+    return fail(RD_ENOMEM, "device allocation failed");
+  }
+  m.x = dx;
+  m.y = dy;
+  hipStream_t s = nullptr;
+  if (hipStreamCreate(&s) != hipSuccess) {
+    release();
+    return fail(RD_EDEVICE, "hipStreamCreate failed");
+  }
+  auto finish = [&](rd_status r) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    release();
+    return r;
+  };
+  auto ok = [](hipError_t e) { return e == hipSuccess; };
+  int32_t cnt[3] = {0, 0, 0};
+  auto read_counts = [&]() {
+    return ok(hipMemcpyAsync(cnt, m.count, sizeof(cnt), hipMemcpyDeviceToHost, s)) && ok(hipStreamSynchronize(s));
+  };
+  if (!ok(hipMemcpyAsync(dx, x, sizeof(double) * nv, hipMemcpyHostToDevice, s)) ||
+      !ok(hipMemcpyAsync(dy, y, sizeof(double) * nv, hipMemcpyHostToDevice, s)) ||
+      !ok(hipMemcpyAsync(m.tri, tsoa.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s)) ||
+      !ok(hipMemcpyAsync(m.nbr, nbr.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s)) ||
+      !ok(hipMemsetAsync(m.flipped, 0, sizeof(int32_t) * nt, s)))
+    return finish(fail(RD_EDEVICE, "upload failed"));
+  int64_t chunk = 0;  // exact tests per launch; their scratch is allocated on first need
+  int64_t flips = 0;
+  int32_t round = 0;
+  const int32_t kMaxRounds = 1000000;
+  for (;;) {
+    if (!ok(rd::dl::launch_reset(m, s)) || !ok(rd::dl::launch_mark(m, s)) || !read_counts())
+      return finish(fail(RD_EDEVICE, "in-circle pass failed"));
+    if (cnt[2] > 0) {
+      if (!m.work) {
+        chunk = std::min<int64_t>(cap, 4096);
+        if (!get(&m.work, chunk * rd::dl::exact_scratch())) return finish(fail(RD_ENOMEM, "device allocation failed"));
+      }
+      for (int64_t f = 0; f < cnt[2]; f += chunk)
+        if (!ok(rd::dl::launch_exact(m, f, std::min<int64_t>(cnt[2], f + chunk), s)))
+          return finish(fail(RD_EDEVICE, "exact in-circle pass failed"));
+      if (!read_counts()) return finish(fail(RD_EDEVICE, "exact in-circle pass failed"));
+    }
+    if (cnt[1] == 0) break;
+    if (++round > kMaxRounds) return finish(fail(RD_EDEVICE, "flipping did not finish"));
+    if (!ok(rd::dl::launch_flip(m, round, s)) || !ok(rd::dl::launch_fix(m, round, s)) || !read_counts())
+      return finish(fail(RD_EDEVICE, "flip pass failed"));
+    if (cnt[0] < 1) return finish(fail(RD_EDEVICE, "a round flipped no edge"));
+    flips += cnt[0];
+  }
+  if (!ok(hipMemcpyAsync(tsoa.data(), m.tri, sizeof(int32_t) * 3 * nt, hipMemcpyDeviceToHost, s)) ||
+      !ok(hipStreamSynchronize(s)))
+    return finish(fail(RD_EDEVICE, "download failed"));
+  for (int64_t t = 0; t < nt; ++t)
+    for (int i = 0; i < 3; ++i) tri[3 * t + i] = tsoa[i * nt + t];
+  if (n_flips) *n_flips = flips;
+  if (n_rounds) *n_rounds = round;
+  return finish(RD_OK);
+}

@@ -44,7 +44,8 @@ EXPORTS = ["rd_mesh_validate", "rd_mesh_create", "rd_mesh_destroy", "rd_mesh_inf
            "rd_set_state", "rd_get_state", "rd_max_dt", "rd_step", "rd_step_cfl", "rd_step_timed", "rd_residual",
            "rd_adjoint_step", "rd_batch_create", "rd_batch_run", "rd_batch_destroy", "rd_sync",
            "rd_last_error", "rd_mesh_set_tile", "rd_mesh_get_tile", "rd_mesh_tile_info", "rd_tune",
-           "rd_batch_set_tile", "rd_batch_tune", "rd_mesh_set_lumping", "rd_mesh_get_lumping"]
+           "rd_batch_set_tile", "rd_batch_tune", "rd_mesh_set_lumping", "rd_mesh_get_lumping",
+           "rd_delaunay_flip"]
 
 _lib = None
 
@@ -77,6 +78,7 @@ def lib():
             "rd_sync": [P],
             "rd_mesh_set_tile": [P, I],
             "rd_mesh_set_lumping": [P, I],
+            "rd_delaunay_flip": [I64, P, P, D, D, I64, P, P, P],
             "rd_mesh_get_lumping": [P, P],
             "rd_mesh_get_tile": [P, P],
             "rd_mesh_tile_info": [P, P],
@@ -220,6 +222,18 @@ def rd_mesh_get_lumping(h) -> int:
     t = C.c_int()
     _check(lib().rd_mesh_get_lumping(h, C.byref(t)))
     return t.value
+
+
+def rd_delaunay_flip(mesh: dict):
+    """Delaunay triangulation of the mesh's points by GPU edge flips: returns
+    (tri [nt, 3] int32, n_flips, n_rounds); the input dict is not changed."""
+    x = np.ascontiguousarray(mesh["x"], dtype=np.float64)
+    y = np.ascontiguousarray(mesh["y"], dtype=np.float64)
+    tri = np.array(mesh["tri"], dtype=np.int32, order="C", copy=True)
+    nf, nr = C.c_int64(), C.c_int32()
+    _check(lib().rd_delaunay_flip(int(mesh["nv"]), x.ctypes.data, y.ctypes.data, float(mesh["px"]),
+                                  float(mesh["py"]), int(mesh["nt"]), tri.ctypes.data, C.byref(nf), C.byref(nr)))
+    return tri, nf.value, nr.value
 
 
 def rd_mesh_tile_info(h) -> dict:
