@@ -218,6 +218,37 @@ __host__ __device__ inline int incircle_filter(const double* a, const double* b,
   return 0;
 }
 
+// Exact sign of the orientation determinant of (a, b, c): (a - c) x (b - c),
+// positive when a, b, c are counter-clockwise, zero when collinear. FP64 with
+// the error bound (3 + 16 eps) eps (|l| + |r|) of the two products first; when
+// that cannot decide, the coordinate differences as two-term expansions and
+// the determinant as an exact expansion (at most 16 terms).
+__host__ __device__ inline int orient(const double* a, const double* b, const double* c) {
+#pragma clang fp contract(off)
+  const double l = (a[0] - c[0]) * (b[1] - c[1]), r = (a[1] - c[1]) * (b[0] - c[0]);
+  const double det = l - r;
+  const double eps = 1.1102230246251565e-16;
+  const double bound = (3.0 + 16.0 * eps) * eps * (fabs(l) + fabs(r));
+  if (det > bound) return 1;
+  if (-det > bound) return -1;
+  double d[4][2];
+  int n[4];
+  const double v[4][2] = {{a[0], c[0]}, {b[1], c[1]}, {a[1], c[1]}, {b[0], c[0]}};
+  for (int k = 0; k < 4; ++k) {
+    double hi, lo;
+    two_sum(v[k][0], -v[k][1], hi, lo);
+    n[k] = 0;
+    if (lo != 0.0) d[k][n[k]++] = lo;
+    if (hi != 0.0 || n[k] == 0) d[k][n[k]++] = hi;
+  }
+  double t1[8], t2[8], out[16], tmp[40];
+  const int n1 = mul(n[0], d[0], n[1], d[1], t1, tmp);
+  const int n2 = mul(n[2], d[2], n[3], d[3], t2, tmp);
+  negate(n2, t2);
+  const int no = sum(n1, t1, n2, t2, out, tmp);
+  return sign(no, out);
+}
+
 }  // namespace pred
 }  // namespace rd
 

@@ -16,6 +16,8 @@ int rdp_incircle_exact(const double* a, const double* b, const double* c, const 
   return rd::pred::incircle_exact(a, b, c, d, w.data());
 }
 
+int rdp_orient(const double* a, const double* b, const double* c) { return rd::pred::orient(a, b, c); }
+
 // Expansion product and sum of two doubles' products, for the arithmetic checks:
 // out[0..n) = (a0 * a1) * (b0 * b1) as an expansion; returns n.
 int rdp_product4(double a0, double a1, double b0, double b1, double* out) {

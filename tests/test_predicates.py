@@ -26,6 +26,8 @@ def P():
     for n in ("rdp_incircle_filter", "rdp_incircle_exact"):
         getattr(L, n).argtypes = [dp, dp, dp, dp]
         getattr(L, n).restype = C.c_int
+    L.rdp_orient.argtypes = [dp, dp, dp]
+    L.rdp_orient.restype = C.c_int
     L.rdp_product4.argtypes = [C.c_double] * 4 + [dp]
     L.rdp_product4.restype = C.c_int
     return L
@@ -132,3 +134,36 @@ def test_split_square_cells(P):
         for i in (0, 1, N // 3, N - 2):
             a, b, c, d = (i * h, i * h), ((i + 1) * h, i * h), ((i + 1) * h, (i + 1) * h), (i * h, (i + 1) * h)
             check(P, [a, b, c, d])
+
+
+def exact_orient(a, b, c):
+    (ax, ay), (bx, by), (cx, cy) = [tuple(Fraction(float(v)) for v in p) for p in (a, b, c)]
+    det = (ax - cx) * (by - cy) - (ay - cy) * (bx - cx)
+    return (det > 0) - (det < 0)
+
+
+def test_orientation(P):
+    rng = np.random.default_rng(4)
+    cases = []
+    for _ in range(2000):
+        cases.append(rng.uniform(-1, 1, size=(3, 2)) * np.exp2(rng.integers(-20, 20)))
+    # collinear points on lines through exactly representable points, and one-ulp moves off them
+    for _ in range(500):
+        p0 = rng.integers(-1000, 1000, size=2).astype(float)
+        dvec = rng.integers(-50, 50, size=2).astype(float)
+        k1, k2 = rng.integers(-20, 20, size=2)
+        pts = [p0, p0 + k1 * dvec, p0 + k2 * dvec]
+        cases.append(np.array(pts))
+        moved = np.array(pts)
+        moved[2, rng.integers(0, 2)] = np.nextafter(moved[2, rng.integers(0, 2)], np.inf)
+        cases.append(moved)
+    # nearly collinear with inexact differences
+    for _ in range(500):
+        t = rng.uniform(0, 1, size=3)
+        cases.append(np.array([(0.1 + 0.3 * u, 0.7 - 0.2 * u) for u in t]))
+    zero = 0
+    for pts in cases:
+        want = exact_orient(*pts)
+        zero += want == 0
+        assert P.rdp_orient(*[np.ascontiguousarray(p, dtype=np.float64) for p in pts]) == want
+    assert zero > 100
