@@ -224,8 +224,9 @@ rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int schem
  * triangles, decided by an exact in-circle predicate (FP64 with an error
  * bound, exact expansion arithmetic when that cannot decide; exact while
  * nonzero coordinate differences stay between about 2^-200 and 2^250; on a
- * periodic axis, on the coordinates unwrapped next to each edge's first
- * vertex as computed in FP64). Edges are flipped in rounds of independent
+ * periodic axis, on each vertex's image nearest to the edge's first vertex:
+ * its coordinate, or that coordinate plus or minus the period, rounded to
+ * FP64). Edges are flipped in rounds of independent
  * flips, the lowest-numbered illegal edge first wherever two compete, so the
  * result is the same on every run. n_flips and n_rounds (may be NULL)
  * receive the number of flips and rounds. RD_EINVAL for an invalid input
@@ -233,6 +234,44 @@ rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int schem
  * device memory for the call, uses a stream of its own and waits for it. */
 rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y, double period_x, double period_y,
                            int64_t n_triangles, int32_t* tri, int64_t* n_flips, int32_t* n_rounds);
+
+/* Delaunay refinement (Section 2: quality and size tests, point location by
+ * walking with an exact orientation test, encroachment of boundary segments,
+ * insertion, edge flips; Section 4.1: the parallel insertion set), on the
+ * current GPU. Input as rd_delaunay_flip, with room to grow: *n_vertices
+ * points in x, y [max_vertices] and *n_triangles triangles in
+ * tri [3 * max_triangles] (host arrays). A boundary edge (in one triangle)
+ * is a segment that must stay covered by edges; it must be axis-aligned (the
+ * domain is a rectangle, or periodic on one or both axes; coordinates on a
+ * periodic axis in [0, period)). The mesh is first made Delaunay by flips;
+ * then each iteration: every triangle with circumradius r > max_radius
+ * (0: no bound) or r / (shortest edge) > max_ratio (0: no bound, else >= 1;
+ * termination is guaranteed for max_ratio >= sqrt 2) proposes its
+ * circumcentre, and every triangle whose boundary edge it encroaches on (its
+ * opposite corner inside the edge's diametric circle) proposes that edge's
+ * midpoint; a proposed point is located by walking from its triangle; a
+ * point beyond the boundary, or one that encroaches on a boundary edge of a
+ * triangle around the corners of its insertion triangle(s), is moved to that
+ * edge's midpoint; points on a vertex are dropped; every point locks the
+ * triangles whose circumcircle may hold it (its cavity) with a pseudo-random
+ * priority, and the points that hold their whole cavity are inserted; then
+ * flips restore the Delaunay property. Stops when no triangle proposes a
+ * point. Original vertices keep their indices; new vertices and triangles
+ * are appended. On return *n_vertices, *n_triangles, x, y, tri describe the
+ * refined mesh; n_iterations (insertion iterations) and n_flips may be NULL.
+ * The result does not depend on scheduling. RD_EINVAL for invalid input,
+ * capacities or bounds, and (with the mesh reached so far returned) when
+ * more than max_iterations iterations would be needed; RD_ENOMEM when the
+ * refined mesh would exceed a capacity (the mesh reached so far is
+ * returned) or device allocation fails; RD_EUNSUPPORTED when no proposed
+ * point can be inserted, or a circumcentre lies more than a quarter period
+ * away on a periodic axis (mesh so far returned); RD_EDEVICE. Allocates
+ * about 140 bytes of device memory per triangle of capacity, uses a stream
+ * of its own and waits for it. */
+rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, int64_t max_vertices, double period_x,
+                             double period_y, int64_t* n_triangles, int32_t* tri, int64_t max_triangles,
+                             double max_radius, double max_ratio, int32_t max_iterations, int32_t* n_iterations,
+                             int64_t* n_flips);
 
 /* Many independent meshes advanced together. The batch keeps its own copy of
  * the meshes' geometry and its own HIP stream (a null stream cannot be

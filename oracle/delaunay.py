@@ -5,9 +5,11 @@ predicates).
 TEST INFRASTRUCTURE ONLY: imported by the tests, never by the library.
 Every predicate is evaluated in exact rational arithmetic (a double converts
 to a Fraction exactly), so nothing here depends on rounding. On a periodic
-axis the coordinates of an edge's quadrilateral are unwrapped next to its
-first vertex in FP64, as the library does (the reading the predicates are
-exact on).
+axis every other vertex of an edge's quadrilateral is taken at its image
+nearest to the edge's first vertex: its coordinate, or that coordinate plus
+or minus the period, rounded to FP64, as the library does (the reading the
+predicates are exact on; on an axis that is not periodic the stored
+coordinates themselves).
 
 * ``incircle`` / ``orient``: signs of the defining determinants.
 * ``lawson``: Lawson's algorithm, one flip at a time from a stack of edges,
@@ -18,6 +20,12 @@ exact on).
   everywhere is Delaunay for a valid triangulation) plus orientation.
 * ``brute_force``: the triangles whose circumcircle contains no other point,
   by enumeration (tiny point sets only): the definition itself.
+* Refinement (Section 2: quality and size bounds, segments kept, no
+  encroached segment) has no unique result, so its reference is the set of
+  properties a refined mesh must have, each evaluated exactly:
+  ``quality`` (squared circumradius and squared circumradius-to-shortest-edge
+  ratio as rationals), ``encroached`` (boundary edges whose diametric circle
+  strictly holds the opposite corner), ``area`` and ``segments_covered``.
 """
 from __future__ import annotations
 
@@ -51,21 +59,20 @@ def incircle(a, b, c, d) -> int:
     return (det > 0) - (det < 0)
 
 
-def _unwrap(d, period):
+def _image(v, o, period):
+    """The image of coordinate v nearest to o on an axis of the given period."""
     if period > 0:
-        if d > 0.5 * period:
-            d -= period
-        elif d < -0.5 * period:
-            d += period
-    return d
+        if v - o > 0.5 * period:
+            return v - period
+        if v - o < -0.5 * period:
+            return v + period
+    return v
 
 
 def _point(mesh, v, base):
-    """Coordinates of vertex v unwrapped next to vertex base (FP64)."""
+    """Coordinates of vertex v at its image nearest to vertex base (FP64)."""
     ax, ay = float(mesh["x"][base]), float(mesh["y"][base])
-    if v == base:
-        return (ax, ay)
-    return (ax + _unwrap(float(mesh["x"][v]) - ax, mesh["px"]), ay + _unwrap(float(mesh["y"][v]) - ay, mesh["py"]))
+    return (_image(float(mesh["x"][v]), ax, mesh["px"]), _image(float(mesh["y"][v]), ay, mesh["py"]))
 
 
 def _edges(tri):
@@ -160,3 +167,122 @@ def canonical(tri) -> set:
         k = r.index(min(r))
         out.add(tuple(r[k:] + r[:k]))
     return out
+
+
+def _tri_points(mesh, row):
+    p, q, r = (int(v) for v in row)
+    return [tuple(map(_F, _point(mesh, v, p))) for v in (p, q, r)]
+
+
+def quality(mesh, tri):
+    """Per triangle (r^2, beta^2) as exact rationals: r the circumradius,
+    l_a l_b l_c / (2 |det|) with det the orientation determinant, and beta =
+    r / (shortest edge) (Section 2, finding low-quality triangles)."""
+    out = []
+    for row in np.asarray(tri):
+        (ax, ay), (bx, by), (cx, cy) = _tri_points(mesh, row)
+        la2 = (cx - bx) ** 2 + (cy - by) ** 2
+        lb2 = (cx - ax) ** 2 + (cy - ay) ** 2
+        lc2 = (bx - ax) ** 2 + (by - ay) ** 2
+        det = (ax - cx) * (by - cy) - (ay - cy) * (bx - cx)
+        r2 = la2 * lb2 * lc2 / (4 * det * det)
+        out.append((r2, r2 / min(la2, lb2, lc2)))
+    return out
+
+
+def boundary_edges(tri):
+    """Edges in exactly one triangle, as (triangle, corner opposite)."""
+    return [inc[0] for inc in _edges([tuple(int(v) for v in r) for r in np.asarray(tri)]).values() if len(inc) == 1]
+
+
+def encroached(mesh, tri) -> list:
+    """Boundary edges (t, i) whose diametric circle strictly holds the
+    opposite corner: (a - v).(b - v) < 0 (Section 2, encroachment)."""
+    tri = np.asarray(tri)
+    bad = []
+    for t, i in boundary_edges(tri):
+        pts = _tri_points(mesh, tri[t])
+        v, a, b = pts[i], pts[(i + 1) % 3], pts[(i + 2) % 3]
+        if (a[0] - v[0]) * (b[0] - v[0]) + (a[1] - v[1]) * (b[1] - v[1]) < 0:
+            bad.append((t, i))
+    return bad
+
+
+def area(mesh, tri) -> Fraction:
+    """Exact sum of the triangles' signed areas."""
+    total = Fraction(0)
+    for row in np.asarray(tri):
+        (ax, ay), (bx, by), (cx, cy) = _tri_points(mesh, row)
+        total += ((bx - ax) * (cy - ay) - (by - ay) * (cx - ax)) / 2
+    return total
+
+
+def segments_covered(mesh0, mesh1) -> bool:
+    """Every boundary edge of mesh1 lies on a boundary edge (segment) of
+    mesh0, and each segment's length equals the summed length of the edges on
+    it (exact: boundary segments are axis-aligned)."""
+    def segs(mesh):
+        tri = np.asarray(mesh["tri"])
+        out = []
+        for t, i in boundary_edges(tri):
+            pts = _tri_points(mesh, tri[t])
+            out.append((pts[(i + 1) % 3], pts[(i + 2) % 3]))
+        return out
+
+    def on(seg, p):
+        (ax, ay), (bx, by) = seg
+        cross = (bx - ax) * (p[1] - ay) - (by - ay) * (p[0] - ax)
+        dot = (p[0] - ax) * (bx - ax) + (p[1] - ay) * (by - ay)
+        return cross == 0 and 0 <= dot <= (bx - ax) ** 2 + (by - ay) ** 2
+
+    def length(seg):
+        (ax, ay), (bx, by) = seg
+        if ax != bx and ay != by:
+            raise ValueError("segment not axis-aligned")
+        return abs(bx - ax) + abs(by - ay)
+
+    s0 = segs(mesh0)
+    covered = [Fraction(0)] * len(s0)
+    for e in segs(mesh1):
+        hits = [k for k, s in enumerate(s0) if on(s, e[0]) and on(s, e[1])]
+        if not hits:
+            return False
+        covered[hits[0]] += length(e)
+    return all(c == length(s) for c, s in zip(covered, s0))
+
+
+def neighbours(tri):
+    """[nt, 3]: the triangle across the edge opposite each corner (-1 on the
+    boundary), from sorted vertex pairs; raises on an edge in three or more
+    triangles."""
+    tri = np.asarray(tri, dtype=np.int64)
+    nt = len(tri)
+    nv = int(tri.max()) + 1
+    b, c = tri[:, [1, 2, 0]], tri[:, [2, 0, 1]]
+    flat = (np.minimum(b, c) * nv + np.maximum(b, c)).ravel()
+    order = np.argsort(flat, kind="stable")
+    same = flat[order][1:] == flat[order][:-1]
+    if np.any(same[1:] & same[:-1]):
+        raise ValueError("an edge belongs to more than two triangles")
+    nbr = -np.ones(3 * nt, dtype=np.int64)
+    i = np.nonzero(same)[0]
+    nbr[order[i]] = order[i + 1] // 3
+    nbr[order[i + 1]] = order[i] // 3
+    return nbr.reshape(nt, 3)
+
+
+def violations_at(mesh, tri, idx) -> list:
+    """``violations`` restricted to the triangles idx and their edges (for
+    meshes too large to check whole)."""
+    tri = np.asarray(tri)
+    nbr = neighbours(tri)
+    bad = []
+    for t in (int(v) for v in idx):
+        p, q, r = (int(v) for v in tri[t])
+        if orient(_point(mesh, p, p), _point(mesh, q, p), _point(mesh, r, p)) <= 0:
+            bad.append(("orientation", t))
+        for i in range(3):
+            u = int(nbr[t, i])
+            if u >= 0 and (_illegal(mesh, tri, t, i, u) or _illegal(mesh, tri, u, int(np.nonzero(nbr[u] == t)[0][0]), t)):
+                bad.append(("illegal", t, i))
+    return bad

@@ -1271,12 +1271,117 @@ RD_API rd_status rd_sync(rd_mesh* m) {
 
 RD_API const char* rd_last_error(void) { return g_last_error.c_str(); }
 
-// ------------------------------------------------------ Delaunay flips --
+// ---------------------------------------------------- mesh generation --
 //
-// The triangulation is checked as a mesh is (indices, counter-clockwise
+// A triangulation is checked as a mesh is (indices, counter-clockwise
 // triangles after unwrapping); the neighbour table is built on the host from
-// sorted vertex pairs; the flip rounds run on the current device (see
-// rd_delaunay.hip), the host reading three counters per round.
+// sorted vertex pairs; the flip rounds and refinement iterations run on the
+// current device (rd_delaunay.hip), the host reading a few counters per
+// round.
+
+namespace {
+
+// Device buffers of one mesh-generation call, freed together.
+struct DlBuffers {
+  std::vector<void*> p;
+  DlBuffers() = default;
+  DlBuffers(const DlBuffers&) = delete;
+  DlBuffers& operator=(const DlBuffers&) = delete;
+  ~DlBuffers() {
+    for (void* q : p) (void)hipFree(q);
+  }
+  template <class T>
+  bool get(T** out, size_t n) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return false;
+    p.push_back(q);
+    *out = static_cast<T*>(q);
+    return true;
+  }
+};
+
+// Corner and neighbour tables [3][ts] of nt triangles (tri: [nt][3]).
+rd_status dl_tables(int64_t nv, int64_t nt, int64_t ts, const int32_t* tri, std::vector<int32_t>& tsoa,
+                    std::vector<int32_t>& nbr) {
+  tsoa.assign(3 * ts, -1);
+  nbr.assign(3 * ts, -1);
+  struct Edge {
+    int64_t key;
+    int32_t t, i;
+  };
+  std::vector<Edge> edges(3 * nt);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int i = 0; i < 3; ++i) {
+      const int64_t b = tri[3 * t + (i + 1) % 3], c = tri[3 * t + (i + 2) % 3];
+      edges[3 * t + i] = {std::min(b, c) * nv + std::max(b, c), (int32_t)t, i};
+      tsoa[i * ts + t] = tri[3 * t + i];
+    }
+  std::sort(edges.begin(), edges.end(), [](const Edge& p, const Edge& q) { return p.key < q.key; });
+  for (size_t k = 0; k < edges.size();) {
+    size_t l = k + 1;
+    while (l < edges.size() && edges[l].key == edges[k].key) ++l;
+    if (l - k > 2) return fail(RD_EINVAL, "an edge belongs to more than two triangles");
+    if (l - k == 2) {
+      nbr[edges[k].i * ts + edges[k].t] = edges[k + 1].t;
+      nbr[edges[k + 1].i * ts + edges[k + 1].t] = edges[k].t;
+    }
+    k = l;
+  }
+  return RD_OK;
+}
+
+bool hip_ok(hipError_t e) { return e == hipSuccess; }
+
+// Flip rounds until no interior edge of m is illegal. Round numbers continue
+// across calls (*round); m.work is allocated on first need.
+rd_status dl_flip_all(rd::dl::Mesh& m, DlBuffers& b, hipStream_t s, int64_t* flips, int32_t* round) {
+  const int64_t cap = 3 * m.ts / 2 + 1;  // interior edges at most
+  const int64_t chunk = std::min<int64_t>(cap, 4096);  // exact tests per launch
+  int32_t cnt[3] = {0, 0, 0};
+  auto read_counts = [&]() {
+    return hip_ok(hipMemcpyAsync(cnt, m.count, sizeof(cnt), hipMemcpyDeviceToHost, s)) &&
+           hip_ok(hipStreamSynchronize(s));
+  };
+  const int32_t kMaxRounds = 1000000;
+  for (int32_t n = 0;; ++n) {
+    if (!hip_ok(rd::dl::launch_reset(m, s)) || !hip_ok(rd::dl::launch_mark(m, s)) || !read_counts())
+      return fail(RD_EDEVICE, "in-circle pass failed");
+    if (cnt[2] > 0) {
+      if (!m.work && !b.get(&m.work, chunk * rd::dl::exact_scratch()))
+        return fail(RD_ENOMEM, "device allocation failed");
+      for (int64_t f = 0; f < cnt[2]; f += chunk)
+        if (!hip_ok(rd::dl::launch_exact(m, f, std::min<int64_t>(cnt[2], f + chunk), s)))
+          return fail(RD_EDEVICE, "exact in-circle pass failed");
+      if (!read_counts()) return fail(RD_EDEVICE, "exact in-circle pass failed");
+    }
+    if (cnt[1] == 0) return RD_OK;
+    if (n >= kMaxRounds) return fail(RD_EDEVICE, "flipping did not finish");
+    ++*round;
+    if (!hip_ok(rd::dl::launch_flip(m, *round, s)) || !hip_ok(rd::dl::launch_fix(m, *round, s)) || !read_counts())
+      return fail(RD_EDEVICE, "flip pass failed");
+    if (cnt[0] < 1) return fail(RD_EDEVICE, "a round flipped no edge");
+    *flips += cnt[0];
+  }
+}
+
+// Device arrays of the flip passes for a capacity of ts triangles.
+bool dl_flip_arrays(rd::dl::Mesh& m, DlBuffers& b, int64_t ts) {
+  return b.get(&m.tri, 3 * ts) && b.get(&m.nbr, 3 * ts) && b.get(&m.claim, ts) && b.get(&m.cand, ts) &&
+         b.get(&m.flipped, ts) && b.get(&m.partner, ts) && b.get(&m.count, 3) &&
+         b.get(&m.undecided, 3 * ts / 2 + 1);
+}
+
+struct StreamGuard {
+  hipStream_t s = nullptr;
+  ~StreamGuard() {
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  }
+};
+
+}  // namespace
 
 RD_API rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y, double period_x,
                                   double period_y, int64_t n_triangles, int32_t* tri, int64_t* n_flips,
@@ -1293,109 +1398,161 @@ RD_API rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const dou
   rd_status st = check_desc(&desc, nullptr);
   if (st != RD_OK) return st;
   const int64_t nt = n_triangles, nv = n_vertices;
-  std::vector<int32_t> nbr(3 * nt, -1), tsoa(3 * nt);
-  {
-    struct Edge {
-      int64_t key;
-      int32_t t, i;
-    };
-    std::vector<Edge> edges(3 * nt);
-    for (int64_t t = 0; t < nt; ++t)
-      for (int i = 0; i < 3; ++i) {
-        const int64_t b = tri[3 * t + (i + 1) % 3], c = tri[3 * t + (i + 2) % 3];
-        edges[3 * t + i] = {std::min(b, c) * nv + std::max(b, c), (int32_t)t, i};
-        tsoa[i * nt + t] = tri[3 * t + i];
-      }
-    std::sort(edges.begin(), edges.end(), [](const Edge& p, const Edge& q) { return p.key < q.key; });
-    for (size_t k = 0; k < edges.size();) {
-      size_t l = k + 1;
-      while (l < edges.size() && edges[l].key == edges[k].key) ++l;
-      if (l - k > 2) return fail(RD_EINVAL, "an edge belongs to more than two triangles");
-      if (l - k == 2) {
-        nbr[edges[k].i * nt + edges[k].t] = edges[k + 1].t;
-        nbr[edges[k + 1].i * nt + edges[k + 1].t] = edges[k].t;
-      }
-      k = l;
-    }
-  }
-  std::vector<void*> bufs;
-  auto release = [&]() {
-    for (void* q : bufs) (void)hipFree(q);
-    bufs.clear();
-  };
-  auto get = [&](auto** out, size_t n) -> bool {
-    void* q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(**out)) != hipSuccess) return false;
-    bufs.push_back(q);
-    *out = static_cast<std::remove_reference_t<decltype(*out)>>(q);
-    return true;
-  };
+  std::vector<int32_t> nbr, tsoa;
+  if ((st = dl_tables(nv, nt, nt, tri, tsoa, nbr)) != RD_OK) return st;
+  DlBuffers b;
+  StreamGuard g;  // declared after the buffers: the stream is drained before they are freed
   rd::dl::Mesh m;
   m.nt = nt;
+  m.ts = nt;
   m.px = period_x;
   m.py = period_y;
-  double *dx = nullptr, *dy = nullptr;
-  const int64_t cap = 3 * nt / 2 + 1;  // interior edges at most
-  if (!get(&dx, nv) || !get(&dy, nv) || !get(&m.tri, 3 * nt) || !get(&m.nbr, 3 * nt) || !get(&m.claim, nt) ||
-      !get(&m.cand, nt) || !get(&m.flipped, nt) || !get(&m.partner, nt) || !get(&m.count, 3) ||
-      !get(&m.undecided, cap)) {
-    release();
+  if (!b.get(&m.x, nv) || !b.get(&m.y, nv) || !dl_flip_arrays(m, b, nt))
     return fail(RD_ENOMEM, "device allocation failed");
-  }
-  m.x = dx;
-  m.y = dy;
-  hipStream_t s = nullptr;
-  if (hipStreamCreate(&s) != hipSuccess) {
-    release();
-    return fail(RD_EDEVICE, "hipStreamCreate failed");
-  }
-  auto finish = [&](rd_status r) {
-    (void)hipStreamSynchronize(s);
-    (void)hipStreamDestroy(s);
-    release();
-    return r;
-  };
-  auto ok = [](hipError_t e) { return e == hipSuccess; };
-  int32_t cnt[3] = {0, 0, 0};
-  auto read_counts = [&]() {
-    return ok(hipMemcpyAsync(cnt, m.count, sizeof(cnt), hipMemcpyDeviceToHost, s)) && ok(hipStreamSynchronize(s));
-  };
-  if (!ok(hipMemcpyAsync(dx, x, sizeof(double) * nv, hipMemcpyHostToDevice, s)) ||
-      !ok(hipMemcpyAsync(dy, y, sizeof(double) * nv, hipMemcpyHostToDevice, s)) ||
-      !ok(hipMemcpyAsync(m.tri, tsoa.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s)) ||
-      !ok(hipMemcpyAsync(m.nbr, nbr.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s)) ||
-      !ok(hipMemsetAsync(m.flipped, 0, sizeof(int32_t) * nt, s)))
-    return finish(fail(RD_EDEVICE, "upload failed"));
-  int64_t chunk = 0;  // exact tests per launch; their scratch is allocated on first need
+  if (hipStreamCreate(&g.s) != hipSuccess) return fail(RD_EDEVICE, "hipStreamCreate failed");
+  const hipStream_t s = g.s;
+  if (!hip_ok(hipMemcpyAsync(m.x, x, sizeof(double) * nv, hipMemcpyHostToDevice, s)) ||
+      !hip_ok(hipMemcpyAsync(m.y, y, sizeof(double) * nv, hipMemcpyHostToDevice, s)) ||
+      !hip_ok(hipMemcpyAsync(m.tri, tsoa.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s)) ||
+      !hip_ok(hipMemcpyAsync(m.nbr, nbr.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s)) ||
+      !hip_ok(hipMemsetAsync(m.flipped, 0, sizeof(int32_t) * nt, s)))
+    return fail(RD_EDEVICE, "upload failed");
   int64_t flips = 0;
   int32_t round = 0;
-  const int32_t kMaxRounds = 1000000;
-  for (;;) {
-    if (!ok(rd::dl::launch_reset(m, s)) || !ok(rd::dl::launch_mark(m, s)) || !read_counts())
-      return finish(fail(RD_EDEVICE, "in-circle pass failed"));
-    if (cnt[2] > 0) {
-      if (!m.work) {
-        chunk = std::min<int64_t>(cap, 4096);
-        if (!get(&m.work, chunk * rd::dl::exact_scratch())) return finish(fail(RD_ENOMEM, "device allocation failed"));
-      }
-      for (int64_t f = 0; f < cnt[2]; f += chunk)
-        if (!ok(rd::dl::launch_exact(m, f, std::min<int64_t>(cnt[2], f + chunk), s)))
-          return finish(fail(RD_EDEVICE, "exact in-circle pass failed"));
-      if (!read_counts()) return finish(fail(RD_EDEVICE, "exact in-circle pass failed"));
-    }
-    if (cnt[1] == 0) break;
-    if (++round > kMaxRounds) return finish(fail(RD_EDEVICE, "flipping did not finish"));
-    if (!ok(rd::dl::launch_flip(m, round, s)) || !ok(rd::dl::launch_fix(m, round, s)) || !read_counts())
-      return finish(fail(RD_EDEVICE, "flip pass failed"));
-    if (cnt[0] < 1) return finish(fail(RD_EDEVICE, "a round flipped no edge"));
-    flips += cnt[0];
-  }
-  if (!ok(hipMemcpyAsync(tsoa.data(), m.tri, sizeof(int32_t) * 3 * nt, hipMemcpyDeviceToHost, s)) ||
-      !ok(hipStreamSynchronize(s)))
-    return finish(fail(RD_EDEVICE, "download failed"));
+  if ((st = dl_flip_all(m, b, s, &flips, &round)) != RD_OK) return st;
+  if (!hip_ok(hipMemcpyAsync(tsoa.data(), m.tri, sizeof(int32_t) * 3 * nt, hipMemcpyDeviceToHost, s)) ||
+      !hip_ok(hipStreamSynchronize(s)))
+    return fail(RD_EDEVICE, "download failed");
   for (int64_t t = 0; t < nt; ++t)
     for (int i = 0; i < 3; ++i) tri[3 * t + i] = tsoa[i * nt + t];
   if (n_flips) *n_flips = flips;
   if (n_rounds) *n_rounds = round;
-  return finish(RD_OK);
+  return RD_OK;
+}
+
+RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, int64_t max_vertices,
+                                    double period_x, double period_y, int64_t* n_triangles, int32_t* tri,
+                                    int64_t max_triangles, double max_radius, double max_ratio,
+                                    int32_t max_iterations, int32_t* n_iterations, int64_t* n_flips) {
+  if (!n_vertices || !n_triangles) return fail(RD_EINVAL, "null count pointer");
+  const int64_t nv0 = *n_vertices, nt0 = *n_triangles;
+  if (max_vertices < nv0 || max_triangles < nt0) return fail(RD_EINVAL, "capacity below the current size");
+  if (max_vertices >= INT32_MAX || max_triangles >= INT32_MAX / 2)
+    return fail(RD_EINVAL, "capacity beyond the 32-bit index range");
+  if (!(max_radius >= 0.0) || !std::isfinite(max_radius)) return fail(RD_EINVAL, "max_radius must be >= 0");
+  if (!(max_ratio == 0.0 || max_ratio >= 1.0) || !std::isfinite(max_ratio))
+    return fail(RD_EINVAL, "max_ratio must be 0 (no bound) or >= 1");
+  if (max_iterations < 1) return fail(RD_EINVAL, "max_iterations must be >= 1");
+  rd_mesh_desc desc{};
+  desc.n_vertices = nv0;
+  desc.n_triangles = nt0;
+  desc.x = x;
+  desc.y = y;
+  desc.tri = tri;
+  desc.period_x = period_x;
+  desc.period_y = period_y;
+  desc.gamma = 1.4;  // not used; the check requires a valid value
+  rd_status st = check_desc(&desc, nullptr);
+  if (st != RD_OK) return st;
+  for (int64_t v = 0; v < nv0; ++v)
+    if ((period_x > 0.0 && !(x[v] >= 0.0 && x[v] < period_x)) || (period_y > 0.0 && !(y[v] >= 0.0 && y[v] < period_y)))
+      return fail(RD_EINVAL, "a coordinate on a periodic axis is outside [0, period)");
+  const int64_t ts = max_triangles;
+  std::vector<int32_t> nbr, tsoa;
+  if ((st = dl_tables(nv0, nt0, ts, tri, tsoa, nbr)) != RD_OK) return st;
+  for (int64_t t = 0; t < nt0; ++t)
+    for (int i = 0; i < 3; ++i) {
+      if (nbr[i * ts + t] >= 0) continue;
+      const int32_t b = tsoa[((i + 1) % 3) * ts + t], c = tsoa[((i + 2) % 3) * ts + t];
+      if (x[b] != x[c] && y[b] != y[c]) return fail(RD_EINVAL, "a boundary edge is not axis-aligned");
+    }
+  DlBuffers b;
+  StreamGuard g;
+  rd::dl::Mesh m;
+  rd::dl::Refine r;
+  m.nt = nt0;
+  m.ts = ts;
+  m.px = period_x;
+  m.py = period_y;
+  r.nv = nv0;
+  r.r2 = max_radius * max_radius;
+  r.b2 = max_ratio * max_ratio;
+  if (!b.get(&m.x, max_vertices) || !b.get(&m.y, max_vertices) || !dl_flip_arrays(m, b, ts) ||
+      !b.get(&r.prio, ts) || !b.get(&r.px, ts) || !b.get(&r.py, ts) || !b.get(&r.loc, ts) ||
+      !b.get(&r.where, ts) || !b.get(&r.lock, ts) || !b.get(&r.win, ts) || !b.get(&r.wpos, ts) ||
+      !b.get(&r.tnew, ts) || !b.get(&r.tpos, ts) || !b.get(&r.split, ts) || !b.get(&r.child, 2 * ts) ||
+      !b.get(&r.count, 3))
+    return fail(RD_ENOMEM, "device allocation failed");
+  const size_t scan_bytes = rd::dl::scan_tmp_bytes(ts);
+  char* scan_tmp = nullptr;
+  if (!b.get(&scan_tmp, scan_bytes)) return fail(RD_ENOMEM, "device allocation failed");
+  if (hipStreamCreate(&g.s) != hipSuccess) return fail(RD_EDEVICE, "hipStreamCreate failed");
+  const hipStream_t s = g.s;
+  if (!hip_ok(hipMemcpyAsync(m.x, x, sizeof(double) * nv0, hipMemcpyHostToDevice, s)) ||
+      !hip_ok(hipMemcpyAsync(m.y, y, sizeof(double) * nv0, hipMemcpyHostToDevice, s)) ||
+      !hip_ok(hipMemcpyAsync(m.tri, tsoa.data(), sizeof(int32_t) * 3 * ts, hipMemcpyHostToDevice, s)) ||
+      !hip_ok(hipMemcpyAsync(m.nbr, nbr.data(), sizeof(int32_t) * 3 * ts, hipMemcpyHostToDevice, s)) ||
+      !hip_ok(hipMemsetAsync(m.flipped, 0, sizeof(int32_t) * ts, s)) ||
+      !hip_ok(hipMemsetAsync(r.split, 0, sizeof(int32_t) * ts, s)))
+    return fail(RD_EDEVICE, "upload failed");
+  int64_t flips = 0;
+  int32_t round = 0, it = 0;
+  int64_t nv = nv0, nt = nt0;
+  // the mesh reached so far goes back to the caller, also when a limit stops the loop
+  auto download = [&](rd_status result) {
+    if (!hip_ok(hipMemcpyAsync(x, m.x, sizeof(double) * nv, hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipMemcpyAsync(y, m.y, sizeof(double) * nv, hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipMemcpyAsync(tsoa.data(), m.tri, sizeof(int32_t) * 3 * ts, hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipStreamSynchronize(s)))
+      return fail(RD_EDEVICE, "download failed");
+    for (int64_t t = 0; t < nt; ++t)
+      for (int i = 0; i < 3; ++i) tri[3 * t + i] = tsoa[i * ts + t];
+    *n_vertices = nv;
+    *n_triangles = nt;
+    if (n_iterations) *n_iterations = it;
+    if (n_flips) *n_flips = flips;
+    return result;
+  };
+  if ((st = dl_flip_all(m, b, s, &flips, &round)) != RD_OK) return st;
+  int32_t cnt[3];
+  for (;;) {
+    r.seed = 0x9e3779b9u * (uint32_t)(it + 1);
+    if (!hip_ok(hipMemsetAsync(r.count, 0, sizeof(cnt), s)) || !hip_ok(rd::dl::launch_quality(m, r, s)) ||
+        !hip_ok(hipMemcpyAsync(cnt, r.count, sizeof(cnt), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipStreamSynchronize(s)))
+      return fail(RD_EDEVICE, "quality pass failed");
+    if (cnt[0] == 0) {
+      if (cnt[1] > 0)
+        return download(fail(RD_EUNSUPPORTED, "a circumcentre lies more than a quarter period from its triangle"));
+      return download(RD_OK);
+    }
+    if (it >= max_iterations) return download(fail(RD_EINVAL, "refinement needs more than max_iterations iterations"));
+    ++it;
+    if (!hip_ok(rd::dl::launch_locate(m, r, s)) || !hip_ok(rd::dl::launch_lock(m, r, s)) ||
+        !hip_ok(rd::dl::launch_check(m, r, s)) ||
+        !hip_ok(rd::dl::launch_scan(r.win, r.wpos, nt, scan_tmp, scan_bytes, s)) ||
+        !hip_ok(rd::dl::launch_scan(r.tnew, r.tpos, nt, scan_tmp, scan_bytes, s)))
+      return fail(RD_EDEVICE, "insertion-set passes failed");
+    int32_t last[4];
+    if (!hip_ok(hipMemcpyAsync(&last[0], r.win + nt - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipMemcpyAsync(&last[1], r.wpos + nt - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipMemcpyAsync(&last[2], r.tnew + nt - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipMemcpyAsync(&last[3], r.tpos + nt - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipMemcpyAsync(cnt, r.count, sizeof(cnt), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipStreamSynchronize(s)))
+      return fail(RD_EDEVICE, "insertion-set passes failed");
+    const int64_t nwin = (int64_t)last[0] + last[1], nadd = (int64_t)last[2] + last[3];
+    if (nwin == 0)
+      return download(fail(RD_EUNSUPPORTED, "no candidate could be inserted (" + std::to_string(cnt[1]) +
+                                                " not located, " + std::to_string(cnt[2]) + " cavities too large)"));
+    if (nv + nwin > max_vertices || nt + nadd > max_triangles)
+      return download(fail(RD_ENOMEM, "the refined mesh needs more than max_vertices or max_triangles"));
+    r.nv = nv;
+    if (!hip_ok(rd::dl::launch_insert(m, r, it, s)) || !hip_ok(rd::dl::launch_fixsplit(m, r, it, nt + nadd, s)))
+      return fail(RD_EDEVICE, "insertion failed");
+    nv += nwin;
+    nt += nadd;
+    m.nt = nt;
+    if ((st = dl_flip_all(m, b, s, &flips, &round)) != RD_OK) return st;
+  }
 }

@@ -45,7 +45,7 @@ EXPORTS = ["rd_mesh_validate", "rd_mesh_create", "rd_mesh_destroy", "rd_mesh_inf
            "rd_adjoint_step", "rd_batch_create", "rd_batch_run", "rd_batch_destroy", "rd_sync",
            "rd_last_error", "rd_mesh_set_tile", "rd_mesh_get_tile", "rd_mesh_tile_info", "rd_tune",
            "rd_batch_set_tile", "rd_batch_tune", "rd_mesh_set_lumping", "rd_mesh_get_lumping",
-           "rd_delaunay_flip"]
+           "rd_delaunay_flip", "rd_delaunay_refine"]
 
 _lib = None
 
@@ -79,6 +79,7 @@ def lib():
             "rd_mesh_set_tile": [P, I],
             "rd_mesh_set_lumping": [P, I],
             "rd_delaunay_flip": [I64, P, P, D, D, I64, P, P, P],
+            "rd_delaunay_refine": [P, P, P, I64, D, D, P, P, I64, D, D, I, P, P],
             "rd_mesh_get_lumping": [P, P],
             "rd_mesh_get_tile": [P, P],
             "rd_mesh_tile_info": [P, P],
@@ -399,3 +400,39 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def rd_delaunay_refine(mesh: dict, max_radius: float = 0.0, max_ratio: float = 2 ** 0.5,
+                       max_vertices: int | None = None, max_triangles: int | None = None,
+                       max_iterations: int = 1000):
+    """Delaunay refinement of a triangulation on the GPU (rd_delaunay_refine):
+    returns a new mesh dict (x, y, tri, nv, nt, px, py) with the iteration and
+    flip counts (n_iterations, n_flips). Default capacities: room for
+    triangles of circumradius down to max_radius / 3 over the domain's area,
+    or 64 times the input when max_radius is 0."""
+    nv, nt = int(mesh["nv"]), int(mesh["nt"])
+    if max_vertices is None:
+        if max_radius > 0:
+            x, y = np.asarray(mesh["x"]), np.asarray(mesh["y"])
+            w = mesh["px"] or (x.max() - x.min())
+            h = mesh["py"] or (y.max() - y.min())
+            max_vertices = nv + int(4 * w * h / (max_radius / 3) ** 2) + 64
+        else:
+            max_vertices = 64 * nv + 64
+    if max_triangles is None:
+        max_triangles = 2 * max_vertices + nt
+    x = np.zeros(max(max_vertices, nv))
+    y = np.zeros(max(max_vertices, nv))
+    x[:nv] = mesh["x"]
+    y[:nv] = mesh["y"]
+    tri = np.zeros((max(max_triangles, nt), 3), dtype=np.int32)
+    tri[:nt] = mesh["tri"]
+    cv, ct = C.c_int64(nv), C.c_int64(nt)
+    ni, nf = C.c_int32(), C.c_int64()
+    _check(lib().rd_delaunay_refine(C.byref(cv), x.ctypes.data, y.ctypes.data, int(max_vertices),
+                                    float(mesh["px"]), float(mesh["py"]), C.byref(ct), tri.ctypes.data,
+                                    int(max_triangles), float(max_radius), float(max_ratio), int(max_iterations),
+                                    C.byref(ni), C.byref(nf)))
+    nv, nt = cv.value, ct.value
+    return {"x": x[:nv].copy(), "y": y[:nv].copy(), "tri": tri[:nt].copy(), "nv": nv, "nt": nt,
+            "px": float(mesh["px"]), "py": float(mesh["py"]), "n_iterations": ni.value, "n_flips": nf.value}

@@ -1,0 +1,208 @@
+// Host build of the mesh-generation bodies (rd_delaunay_kern.h) for their
+// CPU tests: the same per-element code the GPU kernels run, executed one
+// element at a time in the order of the device driver (each pass reads only
+// what earlier passes wrote, so this sequential run equals the parallel one).
+// Built with g++ and -ffp-contract=off.
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "rd_delaunay_kern.h"
+
+namespace {
+
+using rd::dl::Mesh;
+using rd::dl::Refine;
+
+struct Host {
+  std::vector<double> x, y, work;
+  std::vector<int32_t> tri, nbr, claim, cand, flipped, partner, count{0, 0, 0};
+  std::vector<int64_t> undecided;
+  std::vector<unsigned long long> prio, lock;
+  std::vector<double> px, py;
+  std::vector<int32_t> loc, where, win, wpos, tnew, tpos, split, child, rcount{0, 0, 0};
+};
+
+void tables(int64_t nv, int64_t nt, int64_t ts, const int32_t* tri, Host& h) {
+  h.tri.assign(3 * ts, -1);
+  h.nbr.assign(3 * ts, -1);
+  struct Edge {
+    int64_t key;
+    int32_t t, i;
+  };
+  std::vector<Edge> e(3 * nt);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int i = 0; i < 3; ++i) {
+      const int64_t b = tri[3 * t + (i + 1) % 3], c = tri[3 * t + (i + 2) % 3];
+      e[3 * t + i] = {std::min(b, c) * nv + std::max(b, c), (int32_t)t, i};
+      h.tri[i * ts + t] = tri[3 * t + i];
+    }
+  std::sort(e.begin(), e.end(), [](const Edge& p, const Edge& q) { return p.key < q.key; });
+  for (size_t k = 0; k + 1 < e.size(); ++k)
+    if (e[k].key == e[k + 1].key) {
+      h.nbr[e[k].i * ts + e[k].t] = e[k + 1].t;
+      h.nbr[e[k + 1].i * ts + e[k + 1].t] = e[k].t;
+    }
+}
+
+Mesh view(Host& h, int64_t nt, int64_t ts, double px, double py) {
+  Mesh m;
+  m.nt = nt;
+  m.ts = ts;
+  m.x = h.x.data();
+  m.y = h.y.data();
+  m.px = px;
+  m.py = py;
+  m.tri = h.tri.data();
+  m.nbr = h.nbr.data();
+  m.claim = h.claim.data();
+  m.cand = h.cand.data();
+  m.flipped = h.flipped.data();
+  m.partner = h.partner.data();
+  m.count = h.count.data();
+  m.undecided = h.undecided.data();
+  m.work = h.work.data();
+  return m;
+}
+
+void alloc(Host& h, int64_t ts) {
+  h.claim.assign(ts, 0);
+  h.cand.assign(ts, 0);
+  h.flipped.assign(ts, 0);
+  h.partner.assign(ts, 0);
+  h.undecided.assign(3 * ts / 2 + 1, 0);
+  h.work.assign(rd::pred::kIncircleScratch, 0.0);
+}
+
+int flip_all(Mesh& m, int64_t* flips, int32_t* round) {
+  for (;;) {
+    for (int64_t t = 0; t < std::max<int64_t>(m.nt, 3); ++t) rd::dl::reset_body(m, t);
+    for (int64_t t = 0; t < m.nt; ++t) rd::dl::mark_body(m, t);
+    for (int64_t k = 0; k < m.count[2]; ++k) rd::dl::exact_body(m, k, m.work);
+    if (m.count[1] == 0) return 0;
+    ++*round;
+    for (int64_t t = 0; t < m.nt; ++t) rd::dl::flip_body(m, t, *round);
+    for (int64_t t = 0; t < m.nt; ++t) rd::dl::fix_body(m, t, *round);
+    if (m.count[0] < 1) return 3;
+    *flips += m.count[0];
+  }
+}
+
+void download(Host& h, int64_t nt, int64_t ts, int32_t* tri) {
+  for (int64_t t = 0; t < nt; ++t)
+    for (int i = 0; i < 3; ++i) tri[3 * t + i] = h.tri[i * ts + t];
+}
+
+}  // namespace
+
+extern "C" {
+
+// rd_delaunay_flip's passes; returns 0, or 3 when a round flips nothing.
+int rdl_flip(int64_t nv, const double* x, const double* y, double px, double py, int64_t nt, int32_t* tri,
+             int64_t* n_flips, int32_t* n_rounds) {
+  Host h;
+  h.x.assign(x, x + nv);
+  h.y.assign(y, y + nv);
+  tables(nv, nt, nt, tri, h);
+  alloc(h, nt);
+  Mesh m = view(h, nt, nt, px, py);
+  int64_t flips = 0;
+  int32_t round = 0;
+  const int st = flip_all(m, &flips, &round);
+  download(h, nt, nt, tri);
+  *n_flips = flips;
+  *n_rounds = round;
+  return st;
+}
+
+// rd_delaunay_refine's passes and driver (status codes as the library's:
+// 0 done, 1 iteration limit, 2 capacity, 5 no insertable candidate or a
+// circumcentre too far on a periodic axis, 3 flips stuck).
+int rdl_refine(int64_t* n_vertices, double* x, double* y, int64_t max_v, double px, double py, int64_t* n_triangles,
+               int32_t* tri, int64_t max_t, double max_radius, double max_ratio, int32_t max_iterations,
+               int32_t* n_iterations, int64_t* n_flips) {
+  Host h;
+  const int64_t ts = max_t;
+  int64_t nv = *n_vertices, nt = *n_triangles;
+  h.x.assign(max_v, 0.0);
+  h.y.assign(max_v, 0.0);
+  std::copy(x, x + nv, h.x.begin());
+  std::copy(y, y + nv, h.y.begin());
+  tables(nv, nt, ts, tri, h);
+  alloc(h, ts);
+  h.prio.assign(ts, 0);
+  h.lock.assign(ts, 0);
+  h.px.assign(ts, 0.0);
+  h.py.assign(ts, 0.0);
+  for (auto* v : {&h.loc, &h.where, &h.win, &h.wpos, &h.tnew, &h.tpos, &h.split}) v->assign(ts, 0);
+  h.child.assign(2 * ts, -1);
+  Mesh m = view(h, nt, ts, px, py);
+  Refine r;
+  r.nv = nv;
+  r.r2 = max_radius * max_radius;
+  r.b2 = max_ratio * max_ratio;
+  r.prio = h.prio.data();
+  r.px = h.px.data();
+  r.py = h.py.data();
+  r.loc = h.loc.data();
+  r.where = h.where.data();
+  r.lock = h.lock.data();
+  r.win = h.win.data();
+  r.wpos = h.wpos.data();
+  r.tnew = h.tnew.data();
+  r.tpos = h.tpos.data();
+  r.split = h.split.data();
+  r.child = h.child.data();
+  r.count = h.rcount.data();
+  int64_t flips = 0;
+  int32_t round = 0, it = 0;
+  int st = flip_all(m, &flips, &round);
+  while (st == 0) {
+    r.seed = 0x9e3779b9u * (uint32_t)(it + 1);
+    r.count[0] = r.count[1] = r.count[2] = 0;
+    for (int64_t t = 0; t < nt; ++t) rd::dl::quality_body(m, r, t);
+    if (r.count[0] == 0) {
+      st = r.count[1] > 0 ? 5 : 0;
+      break;
+    }
+    if (it >= max_iterations) {
+      st = 1;
+      break;
+    }
+    ++it;
+    for (int64_t t = 0; t < nt; ++t) rd::dl::locate_body(m, r, t);
+    for (int64_t t = 0; t < nt; ++t) rd::dl::lock_body(m, r, t);
+    for (int64_t t = 0; t < nt; ++t) rd::dl::check_body(m, r, t);
+    int64_t nwin = 0, nadd = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      r.wpos[t] = (int32_t)nwin;
+      r.tpos[t] = (int32_t)nadd;
+      nwin += r.win[t];
+      nadd += r.tnew[t];
+    }
+    if (nwin == 0) {
+      st = 5;
+      break;
+    }
+    if (nv + nwin > max_v || nt + nadd > max_t) {
+      st = 2;
+      break;
+    }
+    r.nv = nv;
+    for (int64_t t = 0; t < nt; ++t) rd::dl::insert_body(m, r, t, it);
+    m.nt = nt + nadd;
+    for (int64_t t = 0; t < nt + nadd; ++t) rd::dl::fixsplit_body(m, r, t, it);
+    nv += nwin;
+    nt += nadd;
+    st = flip_all(m, &flips, &round);
+  }
+  std::copy(h.x.begin(), h.x.begin() + nv, x);
+  std::copy(h.y.begin(), h.y.begin() + nv, y);
+  download(h, nt, ts, tri);
+  *n_vertices = nv;
+  *n_triangles = nt;
+  *n_iterations = it;
+  *n_flips = flips;
+  return st;
+}
+}

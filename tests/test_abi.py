@@ -115,3 +115,26 @@ def test_host_validation_rejects_sizes_beyond_32_bit_indices(rd):
     d = rd.rd_mesh_desc(16, 2 ** 31 // 3, None, None, None, 0.0, 0.0, None, 0, None, 1.4)
     assert rd.lib().rd_mesh_validate(C.byref(d)) == rd.RD_EINVAL   # passes the size check, then
     assert "null" in rd.lib().rd_last_error().decode()             # stops at the missing arrays
+
+
+def test_refinement_input_checks_run_on_the_host(rd):
+    """rd_delaunay_refine refuses invalid bounds, capacities and domains
+    before it touches a device."""
+    sq = {"x": np.array([0.0, 1.0, 1.0, 0.0]), "y": np.array([0.0, 0.0, 1.0, 1.0]),
+          "tri": np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32), "nv": 4, "nt": 2, "px": 0.0, "py": 0.0}
+    skew = dict(sq, x=np.array([0.0, 1.0, 1.2, 0.0]))  # the right side is not axis-aligned
+    per = I.split_square(6, periodic=(True, True), jitter=0.3, seed=1)  # coordinates below 0
+    cases = [
+        (sq, dict(max_ratio=0.5), "max_ratio"),
+        (sq, dict(max_radius=-1.0), "max_radius"),
+        (sq, dict(max_iterations=0), "max_iterations"),
+        (sq, dict(max_vertices=3), "capacity"),
+        (skew, dict(max_radius=0.1), "axis-aligned"),
+        (per, dict(max_radius=0.1), "periodic axis"),
+    ]
+    for mesh, kw, msg in cases:
+        kw = dict(kw)
+        args = dict(max_radius=kw.pop("max_radius", 0.1), max_ratio=kw.pop("max_ratio", 2 ** 0.5))
+        with pytest.raises(rd.RDError, match=msg) as e:
+            rd.rd_delaunay_refine(mesh, **args, **kw)
+        assert e.value.status == rd.RD_EINVAL

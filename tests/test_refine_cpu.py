@@ -1,0 +1,167 @@
+"""Delaunay refinement (Section 2) on the CPU: the library's per-element
+bodies (rd_delaunay_kern.h, the code the GPU kernels run) built with g++ and
+run one element at a time by a host copy of the driver
+(tests/cpp/delaunay_shim.cpp). A refined mesh has no unique form, so the
+reference is the set of properties it must have, each checked exactly by the
+reference module (oracle/delaunay.py): a valid counter-clockwise
+triangulation, Delaunay, every triangle within the size and quality bounds,
+no encroached boundary segment, the input's area, its segments covered by
+boundary edges and its vertices kept."""
+import ctypes as C
+import os
+import subprocess
+import tempfile
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_1705_02028_amd import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SQRT2 = 2 ** 0.5
+
+
+def build_shim():
+    """Build tests/cpp/delaunay_shim.cpp and load it."""
+    out = os.path.join(tempfile.mkdtemp(prefix="dl_"), "libdl.so")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+                    "-Wno-unknown-pragmas", "-I", os.path.join(ROOT, "paper_1705_02028_amd", "csrc"),
+                    os.path.join(HERE, "cpp", "delaunay_shim.cpp"), "-o", out], check=True)
+    L = C.CDLL(out)
+    P = C.c_void_p
+    L.rdl_refine.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_double, P, P, C.c_int64, C.c_double,
+                             C.c_double, C.c_int32, P, P]
+    L.rdl_refine.restype = C.c_int
+    L.rdl_flip.argtypes = [C.c_int64, P, P, C.c_double, C.c_double, C.c_int64, P, P, P]
+    L.rdl_flip.restype = C.c_int
+    return L
+
+
+@pytest.fixture(scope="module")
+def S():
+    return build_shim()
+
+
+@pytest.fixture(scope="module")
+def D():
+    import delaunay
+    return delaunay
+
+
+def host_refine(S, m, R, B, max_vertices=20000, max_iterations=1000):
+    """rdl_refine (sequential run of the library's bodies): (status, mesh)."""
+    nv, nt = int(m["nv"]), int(m["nt"])
+    max_t = 2 * max_vertices + nt
+    x, y = np.zeros(max_vertices), np.zeros(max_vertices)
+    x[:nv], y[:nv] = m["x"], m["y"]
+    tri = np.zeros((max_t, 3), dtype=np.int32)
+    tri[:nt] = m["tri"]
+    cv, ct, ni, nf = C.c_int64(nv), C.c_int64(nt), C.c_int32(), C.c_int64()
+    st = S.rdl_refine(C.byref(cv), x.ctypes.data, y.ctypes.data, max_vertices, float(m["px"]), float(m["py"]),
+                      C.byref(ct), tri.ctypes.data, max_t, R, B, max_iterations, C.byref(ni), C.byref(nf))
+    nv, nt = cv.value, ct.value
+    return st, {"x": x[:nv].copy(), "y": y[:nv].copy(), "tri": tri[:nt].copy(), "nv": nv, "nt": nt,
+                "px": m["px"], "py": m["py"], "n_iterations": ni.value, "n_flips": nf.value}
+
+
+def points_in_box(n, w, h, seed):
+    """Corners of [0, w] x [0, h] and n seeded uniform points inside, with
+    scipy's Delaunay triangulation made counter-clockwise."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    p = np.vstack([[0, 0], [w, 0], [w, h], [0, h], rng.random((n, 2)) * [w, h]])
+    t = Delaunay(p).simplices.astype(np.int32)
+    e1, e2 = p[t[:, 1]] - p[t[:, 0]], p[t[:, 2]] - p[t[:, 0]]
+    neg = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0] < 0
+    t[neg] = t[neg][:, [0, 2, 1]]
+    return {"x": p[:, 0].copy(), "y": p[:, 1].copy(), "tri": t, "nv": len(p), "nt": len(t), "px": 0.0, "py": 0.0}
+
+
+def wrapped(m):
+    """The mesh with coordinates on periodic axes in [0, period)."""
+    m = dict(m)
+    if m["px"] > 0:
+        m["x"] = np.mod(m["x"], m["px"])
+    if m["py"] > 0:
+        m["y"] = np.mod(m["y"], m["py"])
+    return m
+
+
+CASES = {
+    # (input, R, B)
+    "square": (lambda: points_in_box(0, 1.0, 1.0, 0), 0.05, SQRT2),
+    "random_points": (lambda: points_in_box(40, 1.0, 1.0, 1), 0.1, SQRT2),
+    "rectangle_quality_only": (lambda: points_in_box(60, 2.0, 1.0, 2), 0.0, SQRT2),
+    "periodic": (lambda: wrapped(I.split_square(8, periodic=(True, True), jitter=0.3, seed=5)), 0.06, SQRT2),
+    "periodic_x_walls_y": (lambda: wrapped(I.split_square(7, periodic=(True, False), jitter=0.3, seed=6)),
+                           0.08, SQRT2),
+}
+
+
+def check_refined(D, m0, m1, R, B, sample=None, seed=0):
+    """The properties of a refined mesh, exactly (on a seeded sample of
+    `sample` triangles when given); returns a short summary."""
+    tri = np.asarray(m1["tri"])
+    nv0 = int(m0["nv"])
+    assert np.array_equal(m1["x"][:nv0], m0["x"]) and np.array_equal(m1["y"][:nv0], m0["y"])
+    assert tri.min() >= 0 and tri.max() < m1["nv"]
+    # every vertex is used
+    assert len(np.unique(tri)) == m1["nv"]
+    # edges in at most two triangles, Delaunay, counter-clockwise
+    # (violations() checks all three; on a sample, only the sampled triangles' edges)
+    if sample is None or len(tri) <= sample:
+        idx = np.arange(len(tri))
+        assert D.violations(m1, tri) == []
+    else:
+        idx = np.random.default_rng(seed).choice(len(tri), sample, replace=False)
+    slack = 1 + 1e-9  # the library decides the bounds in FP64
+    for r2, b2 in (D.quality(m1, tri[idx])):
+        if R > 0:
+            assert r2 <= Fraction(R * R) * Fraction(slack)
+        if B > 0:
+            assert b2 <= Fraction(B * B) * Fraction(slack)
+    assert D.encroached(m1, tri) == []
+    a0, a1 = D.area(m0, m0["tri"]), D.area(m1, tri)
+    if m0["px"] == 0 and m0["py"] == 0:
+        assert a1 == a0
+        assert D.segments_covered(m0, m1)
+    else:  # images across a periodic seam are rounded
+        assert abs(a1 - a0) <= 1e-12 * a0
+    return f"nv {m0['nv']} -> {m1['nv']}, nt {m0['nt']} -> {m1['nt']}, {m1['n_iterations']} iterations"
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_refined_mesh_properties(S, D, case):
+    make, R, B = CASES[case]
+    m0 = make()
+    st, m1 = host_refine(S, m0, R, B)
+    assert st == 0
+    assert m1["nt"] > m0["nt"]
+    check_refined(D, m0, m1, R, B)
+    # the same result on a second run (no dependence on the order of elements
+    # within a pass is possible here; this checks that nothing else varies)
+    st2, m2 = host_refine(S, m0, R, B)
+    assert st2 == 0 and np.array_equal(m1["tri"], m2["tri"]) and np.array_equal(m1["x"], m2["x"])
+
+
+def test_refinement_reaches_the_size_bound_on_a_lattice(S, D):
+    """From the two triangles of the unit square, circumradius bound R:
+    splitting right isosceles triangles at their hypotenuse midpoints gives
+    the regular split-square lattice, where no edge needs a flip."""
+    st, m1 = host_refine(S, points_in_box(0, 1.0, 1.0, 0), 0.2, SQRT2)
+    assert st == 0 and m1["n_flips"] == 0
+    assert m1["nv"] == 25 and m1["nt"] == 32  # the 5 x 5 lattice
+    assert sorted(set(m1["x"])) == [0, 0.25, 0.5, 0.75, 1.0]
+    check_refined(D, points_in_box(0, 1.0, 1.0, 0), m1, 0.2, SQRT2)
+
+
+def test_limits_return_the_mesh_so_far(S, D):
+    m0 = points_in_box(40, 1.0, 1.0, 1)
+    st, m1 = host_refine(S, m0, 0.02, SQRT2, max_vertices=200)
+    assert st == 2 and m0["nv"] < m1["nv"] <= 200  # capacity
+    assert D.violations(m1, m1["tri"]) == []
+    st, m1 = host_refine(S, m0, 0.02, SQRT2, max_iterations=2)
+    assert st == 1 and m1["n_iterations"] == 2  # iteration limit
+    assert D.violations(m1, m1["tri"]) == []
