@@ -255,9 +255,13 @@ rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y,
  * edge's midpoint; points on a vertex are dropped; every point locks the
  * triangles whose circumcircle may hold it (its cavity) with a pseudo-random
  * priority, and the points that hold their whole cavity are inserted; then
- * flips restore the Delaunay property. Stops when no triangle proposes a
- * point. Original vertices keep their indices; new vertices and triangles
- * are appended. On return *n_vertices, *n_triangles, x, y, tri describe the
+ * flips restore the Delaunay property; with morton = 1 the vertices and
+ * triangles are then renumbered along a Z-order curve (Section 4.1: keys
+ * interleave the coordinates quantised to 32 bits over the period on a
+ * periodic axis, else over the input's extent, x in the even bits; a
+ * triangle's key is its centroid's; stable order for equal keys). Stops when
+ * no triangle proposes a point. With morton = 0 original vertices keep their
+ * indices and new vertices and triangles are appended. On return *n_vertices, *n_triangles, x, y, tri describe the
  * refined mesh; n_iterations (insertion iterations) and n_flips may be NULL.
  * The result does not depend on scheduling. RD_EINVAL for invalid input,
  * capacities or bounds, and (with the mesh reached so far returned) when
@@ -266,12 +270,13 @@ rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y,
  * returned) or device allocation fails; RD_EUNSUPPORTED when no proposed
  * point can be inserted, or a circumcentre lies more than a quarter period
  * away on a periodic axis (mesh so far returned); RD_EDEVICE. Allocates
- * about 140 bytes of device memory per triangle of capacity, uses a stream
+ * about 140 bytes of device memory per triangle of capacity (about 100 more
+ * with morton = 1), uses a stream
  * of its own and waits for it. */
 rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, int64_t max_vertices, double period_x,
                              double period_y, int64_t* n_triangles, int32_t* tri, int64_t max_triangles,
-                             double max_radius, double max_ratio, int32_t max_iterations, int32_t* n_iterations,
-                             int64_t* n_flips);
+                             double max_radius, double max_ratio, int32_t max_iterations, int32_t morton,
+                             int32_t* n_iterations, int64_t* n_flips);
 
 /* Many independent meshes advanced together. The batch keeps its own copy of
  * the meshes' geometry and its own HIP stream (a null stream cannot be

@@ -1371,6 +1371,23 @@ bool dl_flip_arrays(rd::dl::Mesh& m, DlBuffers& b, int64_t ts) {
          b.get(&m.undecided, 3 * ts / 2 + 1);
 }
 
+// Renumber vertices, then triangles, in Morton order (the moved arrays are
+// swapped in: m's and o's pointers trade places).
+rd_status dl_reorder(rd::dl::Mesh& m, rd::dl::Order& o, int64_t nv, void* tmp, size_t tmp_bytes, hipStream_t s) {
+  if (!hip_ok(rd::dl::launch_vkeys(m, o, nv, s)) || !hip_ok(rd::dl::launch_sort(o, nv, tmp, tmp_bytes, s)) ||
+      !hip_ok(rd::dl::launch_invert(o, nv, s)) || !hip_ok(rd::dl::launch_vapply(m, o, nv, s)) ||
+      !hip_ok(rd::dl::launch_vrename(m, o, s)))
+    return fail(RD_EDEVICE, "vertex reordering failed");
+  std::swap(m.x, o.xt);
+  std::swap(m.y, o.yt);
+  if (!hip_ok(rd::dl::launch_tkeys(m, o, s)) || !hip_ok(rd::dl::launch_sort(o, m.nt, tmp, tmp_bytes, s)) ||
+      !hip_ok(rd::dl::launch_invert(o, m.nt, s)) || !hip_ok(rd::dl::launch_tapply(m, o, s)))
+    return fail(RD_EDEVICE, "triangle reordering failed");
+  std::swap(m.tri, o.tt);
+  std::swap(m.nbr, o.nb);
+  return RD_OK;
+}
+
 struct StreamGuard {
   hipStream_t s = nullptr;
   ~StreamGuard() {
@@ -1433,7 +1450,8 @@ RD_API rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const dou
 RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, int64_t max_vertices,
                                     double period_x, double period_y, int64_t* n_triangles, int32_t* tri,
                                     int64_t max_triangles, double max_radius, double max_ratio,
-                                    int32_t max_iterations, int32_t* n_iterations, int64_t* n_flips) {
+                                    int32_t max_iterations, int32_t morton, int32_t* n_iterations,
+                                    int64_t* n_flips) {
   if (!n_vertices || !n_triangles) return fail(RD_EINVAL, "null count pointer");
   const int64_t nv0 = *n_vertices, nt0 = *n_triangles;
   if (max_vertices < nv0 || max_triangles < nt0) return fail(RD_EINVAL, "capacity below the current size");
@@ -1443,6 +1461,7 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
   if (!(max_ratio == 0.0 || max_ratio >= 1.0) || !std::isfinite(max_ratio))
     return fail(RD_EINVAL, "max_ratio must be 0 (no bound) or >= 1");
   if (max_iterations < 1) return fail(RD_EINVAL, "max_iterations must be >= 1");
+  if (morton != 0 && morton != 1) return fail(RD_EINVAL, "morton must be 0 or 1");
   rd_mesh_desc desc{};
   desc.n_vertices = nv0;
   desc.n_triangles = nt0;
@@ -1486,6 +1505,29 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
   const size_t scan_bytes = rd::dl::scan_tmp_bytes(ts);
   char* scan_tmp = nullptr;
   if (!b.get(&scan_tmp, scan_bytes)) return fail(RD_ENOMEM, "device allocation failed");
+  rd::dl::Order o;
+  size_t sort_bytes = 0;
+  char* sort_tmp = nullptr;
+  if (morton) {
+    // Morton frame: the period on a periodic axis, else the input's extent
+    auto frame = [&](const double* c, double period, double& c0, double& sc) {
+      double lo = c[0], hi = c[0];
+      for (int64_t v = 1; v < nv0; ++v) {
+        lo = std::min(lo, c[v]);
+        hi = std::max(hi, c[v]);
+      }
+      c0 = period > 0.0 ? 0.0 : lo;
+      sc = 4294967296.0 / (period > 0.0 ? period : hi - lo);
+    };
+    frame(x, period_x, o.x0, o.sx);
+    frame(y, period_y, o.y0, o.sy);
+    const int64_t n = std::max(max_vertices, ts);
+    sort_bytes = rd::dl::sort_tmp_bytes(n);
+    if (!b.get(&o.key, n) || !b.get(&o.skey, n) || !b.get(&o.idx, n) || !b.get(&o.perm, n) || !b.get(&o.inv, n) ||
+        !b.get(&o.xt, max_vertices) || !b.get(&o.yt, max_vertices) || !b.get(&o.tt, 3 * ts) ||
+        !b.get(&o.nb, 3 * ts) || !b.get(&sort_tmp, sort_bytes))
+      return fail(RD_ENOMEM, "device allocation failed");
+  }
   if (hipStreamCreate(&g.s) != hipSuccess) return fail(RD_EDEVICE, "hipStreamCreate failed");
   const hipStream_t s = g.s;
   if (!hip_ok(hipMemcpyAsync(m.x, x, sizeof(double) * nv0, hipMemcpyHostToDevice, s)) ||
@@ -1554,5 +1596,6 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
     nt += nadd;
     m.nt = nt;
     if ((st = dl_flip_all(m, b, s, &flips, &round)) != RD_OK) return st;
+    if (morton && (st = dl_reorder(m, o, nv, sort_tmp, sort_bytes, s)) != RD_OK) return st;
   }
 }

@@ -35,6 +35,18 @@ hipError_t launch_check(const Mesh& m, const Refine& r, hipStream_t s);
 hipError_t launch_insert(const Mesh& m, const Refine& r, int32_t it, hipStream_t s);
 hipError_t launch_fixsplit(const Mesh& m, const Refine& r, int32_t it, int64_t nt_after, hipStream_t s);
 
+// Morton ordering passes: keys of n vertices or triangles (with o.idx =
+// 0..n-1), the stable sort of (key, idx) into (skey, perm), the inverse
+// permutation, and the moves (into o's buffers; the caller swaps them in).
+hipError_t launch_vkeys(const Mesh& m, const Order& o, int64_t nv, hipStream_t s);
+hipError_t launch_tkeys(const Mesh& m, const Order& o, hipStream_t s);
+size_t sort_tmp_bytes(int64_t n);
+hipError_t launch_sort(const Order& o, int64_t n, void* tmp, size_t tmp_bytes, hipStream_t s);
+hipError_t launch_invert(const Order& o, int64_t n, hipStream_t s);
+hipError_t launch_vapply(const Mesh& m, const Order& o, int64_t nv, hipStream_t s);
+hipError_t launch_vrename(const Mesh& m, const Order& o, hipStream_t s);
+hipError_t launch_tapply(const Mesh& m, const Order& o, hipStream_t s);
+
 // Exclusive prefix sum of n ints (dst may not alias src); tmp of at least
 // scan_tmp_bytes(n) bytes.
 size_t scan_tmp_bytes(int64_t n);

@@ -21,7 +21,8 @@
 // tested for encroachment; each candidate locks its cavity with its priority
 // (atomic maximum), and the candidates that hold their whole cavity are
 // inserted together; prefix sums number the new vertices and triangles, so
-// the result does not depend on scheduling.
+// the result does not depend on scheduling. Optionally the vertices and
+// triangles are then renumbered in Morton order (a stable radix sort).
 #include <hipcub/hipcub.hpp>
 
 #include "rd_delaunay.h"
@@ -86,6 +87,36 @@ __global__ __launch_bounds__(kBlock) void k_fixsplit(Mesh m, Refine r, int32_t i
   if (t < m.nt) fixsplit_body(m, r, t, it);
 }
 
+__global__ __launch_bounds__(kBlock) void k_vkeys(Mesh m, Order o, int64_t nv) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (v < nv) vkey_body(m, o, v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tkeys(Mesh m, Order o) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < m.nt) tkey_body(m, o, t);
+}
+
+__global__ __launch_bounds__(kBlock) void k_invert(Order o, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) invert_body(o, i);
+}
+
+__global__ __launch_bounds__(kBlock) void k_vapply(Mesh m, Order o, int64_t nv) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < nv) vapply_body(m, o, i);
+}
+
+__global__ __launch_bounds__(kBlock) void k_vrename(Mesh m, Order o) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < m.nt) vrename_body(m, o, t);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tapply(Mesh m, Order o) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < m.nt) tapply_body(m, o, i);
+}
+
 static unsigned nblocks(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 int64_t exact_scratch() { return pred::kIncircleScratch; }
@@ -136,6 +167,42 @@ hipError_t launch_fixsplit(const Mesh& m, const Refine& r, int32_t it, int64_t n
   Mesh a = m;
   a.nt = nt_after;
   hipLaunchKernelGGL(k_fixsplit, dim3(nblocks(nt_after)), dim3(kBlock), 0, s, a, r, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_vkeys(const Mesh& m, const Order& o, int64_t nv, hipStream_t s) {
+  hipLaunchKernelGGL(k_vkeys, dim3(nblocks(nv)), dim3(kBlock), 0, s, m, o, nv);
+  return hipGetLastError();
+}
+hipError_t launch_tkeys(const Mesh& m, const Order& o, hipStream_t s) {
+  hipLaunchKernelGGL(k_tkeys, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m, o);
+  return hipGetLastError();
+}
+size_t sort_tmp_bytes(int64_t n) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const unsigned long long*)nullptr,
+                                           (unsigned long long*)nullptr, (const int32_t*)nullptr, (int32_t*)nullptr,
+                                           (int)n);
+  return bytes;
+}
+hipError_t launch_sort(const Order& o, int64_t n, void* tmp, size_t tmp_bytes, hipStream_t s) {
+  size_t bytes = tmp_bytes;
+  return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, o.key, o.skey, o.idx, o.perm, (int)n, 0, 64, s);
+}
+hipError_t launch_invert(const Order& o, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_invert, dim3(nblocks(n)), dim3(kBlock), 0, s, o, n);
+  return hipGetLastError();
+}
+hipError_t launch_vapply(const Mesh& m, const Order& o, int64_t nv, hipStream_t s) {
+  hipLaunchKernelGGL(k_vapply, dim3(nblocks(nv)), dim3(kBlock), 0, s, m, o, nv);
+  return hipGetLastError();
+}
+hipError_t launch_vrename(const Mesh& m, const Order& o, hipStream_t s) {
+  hipLaunchKernelGGL(k_vrename, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m, o);
+  return hipGetLastError();
+}
+hipError_t launch_tapply(const Mesh& m, const Order& o, hipStream_t s) {
+  hipLaunchKernelGGL(k_tapply, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m, o);
   return hipGetLastError();
 }
 

@@ -645,5 +645,87 @@ DL_FN void fixsplit_body(const Mesh& m, const Refine& r, int64_t w, int32_t it) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Morton ordering (Section 4.1: vertices and triangles renumbered along a
+// Z-order curve after each insertion iteration, for locality). A key
+// interleaves the 32-bit quantised coordinates, x in the even bits:
+// q(x) = min(2^32 - 1, floor(max(0, (x - x0) * sx))), likewise for y; a
+// triangle's key is that of its centroid (corners at their images nearest
+// to corner 0, the mean wrapped into the period). Sorting is stable, so
+// equal keys keep their order.
+
+struct Order {
+  double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
+  unsigned long long* key = nullptr;   // [n] keys
+  unsigned long long* skey = nullptr;  // [n] sorted keys
+  int32_t* idx = nullptr;              // [n] 0, 1, ..., n - 1
+  int32_t* perm = nullptr;             // [n] new -> old
+  int32_t* inv = nullptr;              // [n] old -> new
+  double* xt = nullptr;                // [vertex capacity] reordered coordinates
+  double* yt = nullptr;
+  int32_t* tt = nullptr;               // [3][ts] reordered corners
+  int32_t* nb = nullptr;               // [3][ts] reordered neighbours
+};
+
+DL_FN unsigned long long spread_bits(uint32_t v) {
+  unsigned long long x = v;
+  x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+  x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+  x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
+}
+
+DL_FN uint32_t quantise(double v, double v0, double s) {
+#pragma clang fp contract(off)
+  double q = (v - v0) * s;
+  if (!(q > 0.0)) q = 0.0;
+  if (q > 4294967295.0) q = 4294967295.0;
+  return (uint32_t)q;
+}
+
+DL_FN unsigned long long morton_key(const Order& o, double x, double y) {
+  return spread_bits(quantise(x, o.x0, o.sx)) | (spread_bits(quantise(y, o.y0, o.sy)) << 1);
+}
+
+DL_FN void vkey_body(const Mesh& m, const Order& o, int64_t v) {
+  o.key[v] = morton_key(o, m.x[v], m.y[v]);
+  o.idx[v] = (int32_t)v;
+}
+
+DL_FN void tkey_body(const Mesh& m, const Order& o, int64_t t) {
+#pragma clang fp contract(off)
+  double v[3][2];
+  const double a[2] = {m.x[corner(m, 0, t)], m.y[corner(m, 0, t)]};
+  tri_near(m, t, a, v);
+  const double cx = wrap((v[0][0] + v[1][0] + v[2][0]) / 3.0, m.px);
+  const double cy = wrap((v[0][1] + v[1][1] + v[2][1]) / 3.0, m.py);
+  o.key[t] = morton_key(o, cx, cy);
+  o.idx[t] = (int32_t)t;
+}
+
+DL_FN void invert_body(const Order& o, int64_t i) { o.inv[o.perm[i]] = (int32_t)i; }
+
+// Coordinates in the new vertex order (to o.xt, o.yt) and every corner
+// renamed (in place: each triangle its own).
+DL_FN void vapply_body(const Mesh& m, const Order& o, int64_t i) {
+  o.xt[i] = m.x[o.perm[i]];
+  o.yt[i] = m.y[o.perm[i]];
+}
+DL_FN void vrename_body(const Mesh& m, const Order& o, int64_t t) {
+  for (int k = 0; k < 3; ++k) m.tri[k * m.ts + t] = o.inv[m.tri[k * m.ts + t]];
+}
+
+// Triangles in the new order (to o.tt, o.nb), neighbours renamed.
+DL_FN void tapply_body(const Mesh& m, const Order& o, int64_t i) {
+  const int32_t old = o.perm[i];
+  for (int k = 0; k < 3; ++k) {
+    o.tt[k * m.ts + i] = m.tri[k * m.ts + old];
+    const int32_t n = m.nbr[k * m.ts + old];
+    o.nb[k * m.ts + i] = n < 0 ? -1 : o.inv[n];
+  }
+}
+
 }  // namespace dl
 }  // namespace rd

@@ -79,7 +79,7 @@ def lib():
             "rd_mesh_set_tile": [P, I],
             "rd_mesh_set_lumping": [P, I],
             "rd_delaunay_flip": [I64, P, P, D, D, I64, P, P, P],
-            "rd_delaunay_refine": [P, P, P, I64, D, D, P, P, I64, D, D, I, P, P],
+            "rd_delaunay_refine": [P, P, P, I64, D, D, P, P, I64, D, D, I, I, P, P],
             "rd_mesh_get_lumping": [P, P],
             "rd_mesh_get_tile": [P, P],
             "rd_mesh_tile_info": [P, P],
@@ -404,12 +404,13 @@ class Batch:
 
 def rd_delaunay_refine(mesh: dict, max_radius: float = 0.0, max_ratio: float = 2 ** 0.5,
                        max_vertices: int | None = None, max_triangles: int | None = None,
-                       max_iterations: int = 1000):
+                       max_iterations: int = 1000, morton: bool = False):
     """Delaunay refinement of a triangulation on the GPU (rd_delaunay_refine):
     returns a new mesh dict (x, y, tri, nv, nt, px, py) with the iteration and
-    flip counts (n_iterations, n_flips). Default capacities: room for
-    triangles of circumradius down to max_radius / 3 over the domain's area,
-    or 64 times the input when max_radius is 0."""
+    flip counts (n_iterations, n_flips); with morton, vertices and triangles
+    are renumbered in Morton order after every iteration. Default capacities:
+    room for triangles of circumradius down to max_radius / 3 over the
+    domain's area, or 64 times the input when max_radius is 0."""
     nv, nt = int(mesh["nv"]), int(mesh["nt"])
     if max_vertices is None:
         if max_radius > 0:
@@ -432,7 +433,7 @@ def rd_delaunay_refine(mesh: dict, max_radius: float = 0.0, max_ratio: float = 2
     _check(lib().rd_delaunay_refine(C.byref(cv), x.ctypes.data, y.ctypes.data, int(max_vertices),
                                     float(mesh["px"]), float(mesh["py"]), C.byref(ct), tri.ctypes.data,
                                     int(max_triangles), float(max_radius), float(max_ratio), int(max_iterations),
-                                    C.byref(ni), C.byref(nf)))
+                                    int(bool(morton)), C.byref(ni), C.byref(nf)))
     nv, nt = cv.value, ct.value
     return {"x": x[:nv].copy(), "y": y[:nv].copy(), "tri": tri[:nt].copy(), "nv": nv, "nt": nt,
             "px": float(mesh["px"]), "py": float(mesh["py"]), "n_iterations": ni.value, "n_flips": nf.value}

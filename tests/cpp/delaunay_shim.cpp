@@ -88,6 +88,46 @@ int flip_all(Mesh& m, int64_t* flips, int32_t* round) {
   }
 }
 
+// Morton renumbering with the library's bodies; the sort is a stable sort
+// by key, as the device's radix sort is.
+struct Reorder {
+  std::vector<unsigned long long> key;
+  std::vector<int32_t> idx, perm, inv, tt, nb;
+  std::vector<double> xt, yt;
+  rd::dl::Order o;
+};
+
+void sort_perm(Reorder& q, int64_t n) {
+  std::vector<int32_t> p(q.idx.begin(), q.idx.begin() + n);
+  std::stable_sort(p.begin(), p.end(), [&](int32_t a, int32_t b) { return q.key[a] < q.key[b]; });
+  std::copy(p.begin(), p.end(), q.perm.begin());
+}
+
+void reorder(Host& h, Mesh& m, Reorder& q, int64_t nv) {
+  rd::dl::Order& o = q.o;
+  for (int64_t v = 0; v < nv; ++v) rd::dl::vkey_body(m, o, v);
+  sort_perm(q, nv);
+  for (int64_t i = 0; i < nv; ++i) rd::dl::invert_body(o, i);
+  for (int64_t i = 0; i < nv; ++i) rd::dl::vapply_body(m, o, i);
+  for (int64_t t = 0; t < m.nt; ++t) rd::dl::vrename_body(m, o, t);
+  h.x.swap(q.xt);
+  h.y.swap(q.yt);
+  m.x = h.x.data();
+  m.y = h.y.data();
+  o.xt = q.xt.data();
+  o.yt = q.yt.data();
+  for (int64_t t = 0; t < m.nt; ++t) rd::dl::tkey_body(m, o, t);
+  sort_perm(q, m.nt);
+  for (int64_t i = 0; i < m.nt; ++i) rd::dl::invert_body(o, i);
+  for (int64_t i = 0; i < m.nt; ++i) rd::dl::tapply_body(m, o, i);
+  h.tri.swap(q.tt);
+  h.nbr.swap(q.nb);
+  m.tri = h.tri.data();
+  m.nbr = h.nbr.data();
+  o.tt = q.tt.data();
+  o.nb = q.nb.data();
+}
+
 void download(Host& h, int64_t nt, int64_t ts, int32_t* tri) {
   for (int64_t t = 0; t < nt; ++t)
     for (int i = 0; i < 3; ++i) tri[3 * t + i] = h.tri[i * ts + t];
@@ -120,7 +160,7 @@ int rdl_flip(int64_t nv, const double* x, const double* y, double px, double py,
 // circumcentre too far on a periodic axis, 3 flips stuck).
 int rdl_refine(int64_t* n_vertices, double* x, double* y, int64_t max_v, double px, double py, int64_t* n_triangles,
                int32_t* tri, int64_t max_t, double max_radius, double max_ratio, int32_t max_iterations,
-               int32_t* n_iterations, int64_t* n_flips) {
+               int32_t morton, int32_t* n_iterations, int64_t* n_flips) {
   Host h;
   const int64_t ts = max_t;
   int64_t nv = *n_vertices, nt = *n_triangles;
@@ -154,6 +194,37 @@ int rdl_refine(int64_t* n_vertices, double* x, double* y, int64_t max_v, double 
   r.split = h.split.data();
   r.child = h.child.data();
   r.count = h.rcount.data();
+  Reorder q;
+  if (morton) {
+    auto frame = [&](const double* c, double period, double& c0, double& sc) {
+      double lo = c[0], hi = c[0];
+      for (int64_t v = 1; v < nv; ++v) {
+        lo = std::min(lo, c[v]);
+        hi = std::max(hi, c[v]);
+      }
+      c0 = period > 0.0 ? 0.0 : lo;
+      sc = 4294967296.0 / (period > 0.0 ? period : hi - lo);
+    };
+    frame(x, px, q.o.x0, q.o.sx);
+    frame(y, py, q.o.y0, q.o.sy);
+    const int64_t n = std::max(max_v, ts);
+    q.key.assign(n, 0);
+    q.idx.assign(n, 0);
+    q.perm.assign(n, 0);
+    q.inv.assign(n, 0);
+    q.xt.assign(max_v, 0.0);
+    q.yt.assign(max_v, 0.0);
+    q.tt.assign(3 * ts, -1);
+    q.nb.assign(3 * ts, -1);
+    q.o.key = q.key.data();
+    q.o.idx = q.idx.data();
+    q.o.perm = q.perm.data();
+    q.o.inv = q.inv.data();
+    q.o.xt = q.xt.data();
+    q.o.yt = q.yt.data();
+    q.o.tt = q.tt.data();
+    q.o.nb = q.nb.data();
+  }
   int64_t flips = 0;
   int32_t round = 0, it = 0;
   int st = flip_all(m, &flips, &round);
@@ -195,6 +266,7 @@ int rdl_refine(int64_t* n_vertices, double* x, double* y, int64_t max_v, double 
     nv += nwin;
     nt += nadd;
     st = flip_all(m, &flips, &round);
+    if (st == 0 && morton) reorder(h, m, q, nv);
   }
   std::copy(h.x.begin(), h.x.begin() + nv, x);
   std::copy(h.y.begin(), h.y.begin() + nv, y);

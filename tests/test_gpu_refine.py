@@ -46,32 +46,35 @@ def same(a, b):
             and np.array_equal(a["tri"], b["tri"]))
 
 
+@pytest.mark.parametrize("morton", [False, True])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_refinement_properties_and_host_equality(rd, D, S, case):
+def test_refinement_properties_and_host_equality(rd, D, S, case, morton):
     make, R, B = CASES[case]
     m0 = make()
-    say(f"refine case={case} nv={m0['nv']} R={R} B={B}")
-    m1 = rd.rd_delaunay_refine(m0, R, B, max_vertices=20000, max_triangles=2 * 20000 + m0["nt"])
-    say("  " + check_refined(D, m0, m1, R, B))
-    st, h = host_refine(S, m0, R, B)
+    say(f"refine case={case} nv={m0['nv']} R={R} B={B} morton={morton}")
+    m1 = rd.rd_delaunay_refine(m0, R, B, max_vertices=20000, max_triangles=2 * 20000 + m0["nt"], morton=morton)
+    say("  " + check_refined(D, m0, m1, R, B, morton=morton))
+    st, h = host_refine(S, m0, R, B, morton=morton)
     assert st == 0 and same(m1, h)
 
 
-def test_medium_periodic_mesh_equals_host_run(rd, D, S):
+@pytest.mark.parametrize("morton", [False, True])
+def test_medium_periodic_mesh_equals_host_run(rd, D, S, morton):
     m0 = wrapped(I.split_square(16, periodic=(True, True), jitter=0.3, seed=9))
     R = 0.004
-    say(f"refine periodic 16^2 R={R}")
+    say(f"refine periodic 16^2 R={R} morton={morton}")
     t0 = time.perf_counter()
-    m1 = rd.rd_delaunay_refine(m0, R, SQRT2, max_vertices=200000)
+    m1 = rd.rd_delaunay_refine(m0, R, SQRT2, max_vertices=200000, morton=morton)
     el = time.perf_counter() - t0
     say(f"  {m1['nv']} vertices, {m1['nt']} triangles, {m1['n_iterations']} iterations, "
         f"{m1['n_flips']} flips, {el:.2f} s")
-    st, h = host_refine(S, m0, R, SQRT2, max_vertices=200000)
+    st, h = host_refine(S, m0, R, SQRT2, max_vertices=200000, morton=morton)
     assert st == 0 and same(m1, h)
-    say("  " + check_refined(D, m0, m1, R, SQRT2, sample=3000, seed=1))
+    say("  " + check_refined(D, m0, m1, R, SQRT2, sample=3000, seed=1, morton=morton))
 
 
-def test_paper_size_periodic_mesh(rd, D):
+@pytest.mark.parametrize("morton", [False, True])
+def test_paper_size_periodic_mesh(rd, D, morton):
     """A uniform periodic mesh of about 1.3 million vertices (the paper's
     mesh-generation test), refined from a jittered 32 x 32 lattice with the
     quality bound sqrt 2 and a circumradius bound."""
@@ -79,10 +82,10 @@ def test_paper_size_periodic_mesh(rd, D):
     R = 7.3e-4
     rd.rd_delaunay_refine(m0, 0.05, SQRT2)  # first call: module load, allocator
     t0 = time.perf_counter()
-    m1 = rd.rd_delaunay_refine(m0, R, SQRT2, max_vertices=1600000)
+    m1 = rd.rd_delaunay_refine(m0, R, SQRT2, max_vertices=1600000, morton=morton)
     el = time.perf_counter() - t0
-    say(f"refine periodic to {m1['nv']} vertices, {m1['nt']} triangles: {m1['n_iterations']} iterations, "
-        f"{m1['n_flips']} flips, {el:.2f} s")
+    say(f"refine periodic (morton={morton}) to {m1['nv']} vertices, {m1['nt']} triangles: "
+        f"{m1['n_iterations']} iterations, {m1['n_flips']} flips, {el:.2f} s")
     assert 1.1e6 < m1["nv"] < 1.6e6 and m1["nt"] == 2 * m1["nv"]  # a torus: nt = 2 nv
     tri = m1["tri"]
     idx = np.random.default_rng(2).choice(len(tri), 1500, replace=False)

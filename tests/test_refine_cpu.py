@@ -32,7 +32,7 @@ def build_shim():
     L = C.CDLL(out)
     P = C.c_void_p
     L.rdl_refine.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_double, P, P, C.c_int64, C.c_double,
-                             C.c_double, C.c_int32, P, P]
+                             C.c_double, C.c_int32, C.c_int32, P, P]
     L.rdl_refine.restype = C.c_int
     L.rdl_flip.argtypes = [C.c_int64, P, P, C.c_double, C.c_double, C.c_int64, P, P, P]
     L.rdl_flip.restype = C.c_int
@@ -50,7 +50,7 @@ def D():
     return delaunay
 
 
-def host_refine(S, m, R, B, max_vertices=20000, max_iterations=1000):
+def host_refine(S, m, R, B, max_vertices=20000, max_iterations=1000, morton=False):
     """rdl_refine (sequential run of the library's bodies): (status, mesh)."""
     nv, nt = int(m["nv"]), int(m["nt"])
     max_t = 2 * max_vertices + nt
@@ -60,7 +60,8 @@ def host_refine(S, m, R, B, max_vertices=20000, max_iterations=1000):
     tri[:nt] = m["tri"]
     cv, ct, ni, nf = C.c_int64(nv), C.c_int64(nt), C.c_int32(), C.c_int64()
     st = S.rdl_refine(C.byref(cv), x.ctypes.data, y.ctypes.data, max_vertices, float(m["px"]), float(m["py"]),
-                      C.byref(ct), tri.ctypes.data, max_t, R, B, max_iterations, C.byref(ni), C.byref(nf))
+                      C.byref(ct), tri.ctypes.data, max_t, R, B, max_iterations, int(morton), C.byref(ni),
+                      C.byref(nf))
     nv, nt = cv.value, ct.value
     return st, {"x": x[:nv].copy(), "y": y[:nv].copy(), "tri": tri[:nt].copy(), "nv": nv, "nt": nt,
                 "px": m["px"], "py": m["py"], "n_iterations": ni.value, "n_flips": nf.value}
@@ -100,12 +101,16 @@ CASES = {
 }
 
 
-def check_refined(D, m0, m1, R, B, sample=None, seed=0):
+def check_refined(D, m0, m1, R, B, sample=None, seed=0, morton=False):
     """The properties of a refined mesh, exactly (on a seeded sample of
     `sample` triangles when given); returns a short summary."""
     tri = np.asarray(m1["tri"])
     nv0 = int(m0["nv"])
-    assert np.array_equal(m1["x"][:nv0], m0["x"]) and np.array_equal(m1["y"][:nv0], m0["y"])
+    if morton:  # the input points are kept, renumbered
+        out = set(zip(m1["x"].tolist(), m1["y"].tolist()))
+        assert all(p in out for p in zip(m0["x"].tolist(), m0["y"].tolist()))
+    else:
+        assert np.array_equal(m1["x"][:nv0], m0["x"]) and np.array_equal(m1["y"][:nv0], m0["y"])
     assert tri.min() >= 0 and tri.max() < m1["nv"]
     # every vertex is used
     assert len(np.unique(tri)) == m1["nv"]
@@ -165,3 +170,57 @@ def test_limits_return_the_mesh_so_far(S, D):
     st, m1 = host_refine(S, m0, 0.02, SQRT2, max_iterations=2)
     assert st == 1 and m1["n_iterations"] == 2  # iteration limit
     assert D.violations(m1, m1["tri"]) == []
+
+
+def morton_keys(m0, x, y):
+    """Z-order keys as rd_delaunay_refine documents them: coordinates
+    quantised to 32 bits over the period (periodic axis) or the input's
+    extent, bits interleaved with x in the even positions."""
+    def quant(c, c0, period):
+        lo = 0.0 if period > 0 else float(np.min(c0))
+        s = 4294967296.0 / (period if period > 0 else float(np.max(c0)) - float(np.min(c0)))
+        q = np.clip((np.asarray(c) - lo) * s, 0.0, 4294967295.0)
+        return q.astype(np.uint64)
+
+    def spread(v):
+        v = v.copy()
+        for shift, mask in ((16, 0x0000ffff0000ffff), (8, 0x00ff00ff00ff00ff), (4, 0x0f0f0f0f0f0f0f0f),
+                            (2, 0x3333333333333333), (1, 0x5555555555555555)):
+            v = (v | (v << np.uint64(shift))) & np.uint64(mask)
+        return v
+
+    return spread(quant(x, m0["x"], m0["px"])) | (spread(quant(y, m0["y"], m0["py"])) << np.uint64(1))
+
+
+def centroids(m):
+    """Triangle centroids, corners at their images nearest to corner 0, the
+    mean wrapped into the period."""
+    t = np.asarray(m["tri"])
+    out = []
+    for c, per in ((m["x"], m["px"]), (m["y"], m["py"])):
+        a = c[t[:, 0]]
+        v = [a] + [np.where(c[t[:, k]] - a > 0.5 * per, c[t[:, k]] - per,
+                            np.where(c[t[:, k]] - a < -0.5 * per, c[t[:, k]] + per, c[t[:, k]])) if per > 0
+                   else c[t[:, k]] for k in (1, 2)]
+        g = (v[0] + v[1] + v[2]) / 3.0
+        if per > 0:
+            g = np.where(g < 0, g + per, g)
+            g = np.where(g >= per, g - per, g)
+        out.append(g)
+    return out
+
+
+@pytest.mark.parametrize("case", ["random_points", "periodic", "periodic_x_walls_y"])
+def test_morton_renumbering(S, D, case):
+    """With morton = 1 the refined mesh has the same properties, and its
+    vertices and triangles are in non-decreasing Z-order."""
+    make, R, B = CASES[case]
+    m0 = make()
+    st, m1 = host_refine(S, m0, R, B, morton=True)
+    assert st == 0
+    check_refined(D, m0, m1, R, B, morton=True)
+    kv = morton_keys(m0, m1["x"], m1["y"])
+    assert np.all(kv[1:] >= kv[:-1])
+    cx, cy = centroids(m1)
+    kt = morton_keys(m0, cx, cy)
+    assert np.all(kt[1:] >= kt[:-1])
