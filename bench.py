@@ -9,7 +9,9 @@ reported beside it. One step = CFL limit + both Runge-Kutta stages (two
 triangle passes and two vertex gathers). Inputs are resident on the GPU
 before timing starts. Also timed on the same workload: the Bx blend and the
 B scheme with selective lumping (`variants`), the adjoint step against the
-forward step, and (with --batch) many meshes in one graph.
+forward step, the GPU Delaunay refinement of a 1.3-million-vertex periodic
+mesh (`mesh_generation`; alone with --meshgen), and (with --batch) many
+meshes in one graph.
 
 Prints one JSON line. `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
@@ -352,6 +354,31 @@ def cpu_baseline(mesh, W0, cfl):
     return out
 
 
+def meshgen(rd, inputs, reps=3):
+    """Delaunay refinement to a uniform periodic mesh of about 1.3 million
+    vertices (the size of the paper's mesh-generation test) from a jittered
+    32x32 lattice: circumradius bound 7.3e-4, quality bound sqrt 2; whole
+    calls timed on the host (neighbour table, upload, GPU iterations,
+    download), with and without Morton renumbering."""
+    import numpy as np
+    m0 = inputs.split_square(32, periodic=(True, True), jitter=0.3, seed=10)
+    m0["x"], m0["y"] = np.mod(m0["x"], 1.0), np.mod(m0["y"], 1.0)
+    rd.rd_delaunay_refine(m0, 0.05, 2 ** 0.5)  # first call: module load, allocator
+    out = {}
+    for morton in (False, True):
+        best, m1 = None, None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            m1 = rd.rd_delaunay_refine(m0, 7.3e-4, 2 ** 0.5, max_vertices=1600000, morton=morton)
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        out["morton" if morton else "insertion_order"] = {
+            "seconds": round(best, 4), "vertices": m1["nv"], "triangles": m1["nt"],
+            "iterations": m1["n_iterations"], "flips": m1["n_flips"],
+            "vertices_per_s": round(m1["nv"] / best, 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,6 +401,9 @@ def main():
                     help="skip timing the Bx blend and selective lumping")
     ap.add_argument("--fp32-table", action="store_true",
                     help="only print the FP32-variant error table per workload (JSON)")
+    ap.add_argument("--meshgen", action="store_true",
+                    help="only time the GPU Delaunay refinement of a 1.3M-vertex periodic mesh (JSON)")
+    ap.add_argument("--no-meshgen", action="store_true", help="skip the mesh-generation timing")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 512 MiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -395,6 +425,9 @@ def main():
         del src, dst
     if args.fp32_table:
         print(json.dumps({"fp32_errors": fp32_table(rd, inputs)}), flush=True)
+        return
+    if args.meshgen:
+        print(json.dumps({"mesh_generation": meshgen(rd, inputs)}), flush=True)
         return
     mesh = inputs.split_square(args.N, renumber=None if args.renumber == "none" else args.renumber, seed=0)
     W0 = inputs.ic_kelvin_helmholtz(mesh, seed=0)
@@ -472,6 +505,9 @@ def main():
         m256 = inputs.split_square(256)
         result["adjoint_forward_ratio_256"] = adjoint_ratio(rd, torch, m256, inputs.ic_fourier_density(m256, seed=0),
                                                             args.cfl, 20, args.tile)
+    if not args.no_meshgen:
+        print("bench: mesh generation", file=sys.stderr, flush=True)
+        result["mesh_generation"] = meshgen(rd, inputs, reps=2)
     if args.batch:
         print(f"bench: batch of {args.batch} meshes", file=sys.stderr, flush=True)
         result["batch"] = batch_vs_single(rd, torch, inputs, args.batch, args.batch_steps, args.cfl, args.tile)

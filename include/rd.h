@@ -256,9 +256,11 @@ rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y,
  * triangles whose circumcircle may hold it (its cavity) with a pseudo-random
  * priority, and the points that hold their whole cavity are inserted; then
  * flips restore the Delaunay property; with morton = 1 the vertices and
- * triangles are then renumbered along a Z-order curve (Section 4.1: keys
- * interleave the coordinates quantised to 32 bits over the period on a
- * periodic axis, else over the input's extent, x in the even bits; a
+ * triangles are renumbered along a Z-order curve whenever the triangle count
+ * has grown by a quarter since the last renumbering, and at the end
+ * (Section 4.1: keys interleave the coordinates quantised to 32 bits over
+ * the period on a periodic axis, else over the input's extent, x in the even
+ * bits, and elements are ordered by the top 32 bits of the key; a
  * triangle's key is its centroid's; stable order for equal keys). Stops when
  * no triangle proposes a point. With morton = 0 original vertices keep their
  * indices and new vertices and triangles are appended. On return *n_vertices, *n_triangles, x, y, tri describe the

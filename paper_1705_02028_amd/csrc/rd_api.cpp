@@ -1332,9 +1332,10 @@ rd_status dl_tables(int64_t nv, int64_t nt, int64_t ts, const int32_t* tri, std:
 
 bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
-// Flip rounds until no interior edge of m is illegal. Round numbers continue
-// across calls (*round); m.work is allocated on first need.
-rd_status dl_flip_all(rd::dl::Mesh& m, DlBuffers& b, hipStream_t s, int64_t* flips, int32_t* round) {
+// Flip rounds until no interior edge of m is illegal. Round and test-pass
+// numbers continue across calls (*round, *pass: the pass about to run, whose
+// marked triangles' edges are tested); m.work is allocated on first need.
+rd_status dl_flip_all(rd::dl::Mesh& m, DlBuffers& b, hipStream_t s, int64_t* flips, int32_t* round, int32_t* pass) {
   const int64_t cap = 3 * m.ts / 2 + 1;  // interior edges at most
   const int64_t chunk = std::min<int64_t>(cap, 4096);  // exact tests per launch
   int32_t cnt[3] = {0, 0, 0};
@@ -1344,7 +1345,8 @@ rd_status dl_flip_all(rd::dl::Mesh& m, DlBuffers& b, hipStream_t s, int64_t* fli
   };
   const int32_t kMaxRounds = 1000000;
   for (int32_t n = 0;; ++n) {
-    if (!hip_ok(rd::dl::launch_reset(m, s)) || !hip_ok(rd::dl::launch_mark(m, s)) || !read_counts())
+    const int32_t p = (*pass)++;
+    if (!hip_ok(rd::dl::launch_reset(m, s)) || !hip_ok(rd::dl::launch_mark(m, p, s)) || !read_counts())
       return fail(RD_EDEVICE, "in-circle pass failed");
     if (cnt[2] > 0) {
       if (!m.work && !b.get(&m.work, chunk * rd::dl::exact_scratch()))
@@ -1357,7 +1359,8 @@ rd_status dl_flip_all(rd::dl::Mesh& m, DlBuffers& b, hipStream_t s, int64_t* fli
     if (cnt[1] == 0) return RD_OK;
     if (n >= kMaxRounds) return fail(RD_EDEVICE, "flipping did not finish");
     ++*round;
-    if (!hip_ok(rd::dl::launch_flip(m, *round, s)) || !hip_ok(rd::dl::launch_fix(m, *round, s)) || !read_counts())
+    if (!hip_ok(rd::dl::launch_flip(m, *round, p, s)) || !hip_ok(rd::dl::launch_fix(m, *round, s)) ||
+        !read_counts())
       return fail(RD_EDEVICE, "flip pass failed");
     if (cnt[0] < 1) return fail(RD_EDEVICE, "a round flipped no edge");
     *flips += cnt[0];
@@ -1367,7 +1370,7 @@ rd_status dl_flip_all(rd::dl::Mesh& m, DlBuffers& b, hipStream_t s, int64_t* fli
 // Device arrays of the flip passes for a capacity of ts triangles.
 bool dl_flip_arrays(rd::dl::Mesh& m, DlBuffers& b, int64_t ts) {
   return b.get(&m.tri, 3 * ts) && b.get(&m.nbr, 3 * ts) && b.get(&m.claim, ts) && b.get(&m.cand, ts) &&
-         b.get(&m.flipped, ts) && b.get(&m.partner, ts) && b.get(&m.count, 3) &&
+         b.get(&m.flipped, ts) && b.get(&m.partner, ts) && b.get(&m.count, 3) && b.get(&m.mark, ts) &&
          b.get(&m.undecided, 3 * ts / 2 + 1);
 }
 
@@ -1432,11 +1435,12 @@ RD_API rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const dou
       !hip_ok(hipMemcpyAsync(m.y, y, sizeof(double) * nv, hipMemcpyHostToDevice, s)) ||
       !hip_ok(hipMemcpyAsync(m.tri, tsoa.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s)) ||
       !hip_ok(hipMemcpyAsync(m.nbr, nbr.data(), sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice, s)) ||
-      !hip_ok(hipMemsetAsync(m.flipped, 0, sizeof(int32_t) * nt, s)))
+      !hip_ok(hipMemsetAsync(m.flipped, 0, sizeof(int32_t) * nt, s)) ||
+      !hip_ok(hipMemsetAsync(m.mark, 0, sizeof(int32_t) * nt, s)))
     return fail(RD_EDEVICE, "upload failed");
   int64_t flips = 0;
-  int32_t round = 0;
-  if ((st = dl_flip_all(m, b, s, &flips, &round)) != RD_OK) return st;
+  int32_t round = 0, pass = 0;  // every mark is 0: the first pass tests every edge
+  if ((st = dl_flip_all(m, b, s, &flips, &round, &pass)) != RD_OK) return st;
   if (!hip_ok(hipMemcpyAsync(tsoa.data(), m.tri, sizeof(int32_t) * 3 * nt, hipMemcpyDeviceToHost, s)) ||
       !hip_ok(hipStreamSynchronize(s)))
     return fail(RD_EDEVICE, "download failed");
@@ -1535,11 +1539,12 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
       !hip_ok(hipMemcpyAsync(m.tri, tsoa.data(), sizeof(int32_t) * 3 * ts, hipMemcpyHostToDevice, s)) ||
       !hip_ok(hipMemcpyAsync(m.nbr, nbr.data(), sizeof(int32_t) * 3 * ts, hipMemcpyHostToDevice, s)) ||
       !hip_ok(hipMemsetAsync(m.flipped, 0, sizeof(int32_t) * ts, s)) ||
+      !hip_ok(hipMemsetAsync(m.mark, 0, sizeof(int32_t) * ts, s)) ||
       !hip_ok(hipMemsetAsync(r.split, 0, sizeof(int32_t) * ts, s)))
     return fail(RD_EDEVICE, "upload failed");
   int64_t flips = 0;
-  int32_t round = 0, it = 0;
-  int64_t nv = nv0, nt = nt0;
+  int32_t round = 0, it = 0, pass = 0;  // every mark is 0: the first pass tests every edge
+  int64_t nv = nv0, nt = nt0, nt_ordered = nt0;
   // the mesh reached so far goes back to the caller, also when a limit stops the loop
   auto download = [&](rd_status result) {
     if (!hip_ok(hipMemcpyAsync(x, m.x, sizeof(double) * nv, hipMemcpyDeviceToHost, s)) ||
@@ -1555,7 +1560,7 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
     if (n_flips) *n_flips = flips;
     return result;
   };
-  if ((st = dl_flip_all(m, b, s, &flips, &round)) != RD_OK) return st;
+  if ((st = dl_flip_all(m, b, s, &flips, &round, &pass)) != RD_OK) return st;
   int32_t cnt[3];
   for (;;) {
     r.seed = 0x9e3779b9u * (uint32_t)(it + 1);
@@ -1566,6 +1571,7 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
     if (cnt[0] == 0) {
       if (cnt[1] > 0)
         return download(fail(RD_EUNSUPPORTED, "a circumcentre lies more than a quarter period from its triangle"));
+      if (morton && nt != nt_ordered && (st = dl_reorder(m, o, nv, sort_tmp, sort_bytes, s)) != RD_OK) return st;
       return download(RD_OK);
     }
     if (it >= max_iterations) return download(fail(RD_EINVAL, "refinement needs more than max_iterations iterations"));
@@ -1590,12 +1596,16 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
     if (nv + nwin > max_vertices || nt + nadd > max_triangles)
       return download(fail(RD_ENOMEM, "the refined mesh needs more than max_vertices or max_triangles"));
     r.nv = nv;
-    if (!hip_ok(rd::dl::launch_insert(m, r, it, s)) || !hip_ok(rd::dl::launch_fixsplit(m, r, it, nt + nadd, s)))
+    if (!hip_ok(rd::dl::launch_insert(m, r, it, pass, s)) ||
+        !hip_ok(rd::dl::launch_fixsplit(m, r, it, nt + nadd, s)))
       return fail(RD_EDEVICE, "insertion failed");
     nv += nwin;
     nt += nadd;
     m.nt = nt;
-    if ((st = dl_flip_all(m, b, s, &flips, &round)) != RD_OK) return st;
-    if (morton && (st = dl_reorder(m, o, nv, sort_tmp, sort_bytes, s)) != RD_OK) return st;
+    if ((st = dl_flip_all(m, b, s, &flips, &round, &pass)) != RD_OK) return st;
+    if (morton && 4 * nt >= 5 * nt_ordered) {  // renumber after every 25 % of growth, and at the end
+      if ((st = dl_reorder(m, o, nv, sort_tmp, sort_bytes, s)) != RD_OK) return st;
+      nt_ordered = nt;
+    }
   }
 }

@@ -14,14 +14,15 @@ namespace dl {
 // Scratch doubles per thread of the exact in-circle pass.
 int64_t exact_scratch();
 
-// One flip round: reset the claims; test every interior edge in FP64
-// (undecided ones go to m.undecided); test undecided edges [first, last)
-// exactly; flip the edges that hold both claims; repoint neighbours at
-// flipped pairs.
+// One flip round: reset the claims; test in FP64 the interior edges of the
+// triangles marked for test pass `pass` (undecided ones go to m.undecided);
+// test undecided edges [first, last) exactly; flip the edges that hold both
+// claims (marking triangles with an illegal edge, and flipped ones, for
+// pass + 1); repoint neighbours at flipped pairs.
 hipError_t launch_reset(const Mesh& m, hipStream_t s);
-hipError_t launch_mark(const Mesh& m, hipStream_t s);
+hipError_t launch_mark(const Mesh& m, int32_t pass, hipStream_t s);
 hipError_t launch_exact(const Mesh& m, int64_t first, int64_t last, hipStream_t s);
-hipError_t launch_flip(const Mesh& m, int32_t round, hipStream_t s);
+hipError_t launch_flip(const Mesh& m, int32_t round, int32_t pass, hipStream_t s);
 hipError_t launch_fix(const Mesh& m, int32_t round, hipStream_t s);
 
 // One refinement iteration over the m.nt triangles in use: candidates
@@ -32,7 +33,7 @@ hipError_t launch_quality(const Mesh& m, const Refine& r, hipStream_t s);
 hipError_t launch_locate(const Mesh& m, const Refine& r, hipStream_t s);
 hipError_t launch_lock(const Mesh& m, const Refine& r, hipStream_t s);
 hipError_t launch_check(const Mesh& m, const Refine& r, hipStream_t s);
-hipError_t launch_insert(const Mesh& m, const Refine& r, int32_t it, hipStream_t s);
+hipError_t launch_insert(const Mesh& m, const Refine& r, int32_t it, int32_t pass, hipStream_t s);
 hipError_t launch_fixsplit(const Mesh& m, const Refine& r, int32_t it, int64_t nt_after, hipStream_t s);
 
 // Morton ordering passes: keys of n vertices or triangles (with o.idx =

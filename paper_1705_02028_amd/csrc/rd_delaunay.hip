@@ -2,8 +2,9 @@
 // predicates; Section 4.1, its parallel form): one thread per element for
 // every pass; the per-element bodies are in rd_delaunay_kern.h.
 //
-// Flips: rounds of independent flips. Each round: every interior edge is
-// tested once, by its lower-numbered triangle (in-circle test: FP64 with an
+// Flips: rounds of independent flips. Each round: every interior edge that
+// may be illegal (one of its triangles changed since the edge last passed)
+// is tested once, by its lower-numbered triangle (in-circle test: FP64 with an
 // error bound, exact expansion arithmetic for the undecided ones, in a
 // separate pass over a compacted list); every illegal edge claims both its
 // triangles with an integer atomic minimum of its key (3 t + i), so the
@@ -37,19 +38,25 @@ __global__ __launch_bounds__(kBlock) void k_reset(Mesh m) {
   reset_body(m, t);
 }
 
-__global__ __launch_bounds__(kBlock) void k_mark(Mesh m) {
+__global__ __launch_bounds__(kBlock) void k_mark(Mesh m, int32_t pass) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t < m.nt) mark_body(m, t);
+  const int r = t < m.nt ? mark_body(m, t, pass) : 0;
+  for (int i = 0; i < 3; ++i) {
+    wave_add(&m.count[1], (r >> i) & 1);
+    const int k = wave_add(&m.count[2], (r >> (4 + i)) & 1);
+    if ((r >> (4 + i)) & 1) m.undecided[k] = 3 * t + i;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_exact(Mesh m, int64_t first, int64_t last) {
   const int64_t k = first + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k < last) exact_body(m, k, m.work + (k - first) * pred::kIncircleScratch);
+  const bool illegal = k < last && exact_body(m, k, m.work + (k - first) * pred::kIncircleScratch);
+  wave_add(&m.count[1], illegal);
 }
 
-__global__ __launch_bounds__(kBlock) void k_flip(Mesh m, int32_t round) {
+__global__ __launch_bounds__(kBlock) void k_flip(Mesh m, int32_t round, int32_t pass) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t < m.nt) flip_body(m, t, round);
+  wave_add(&m.count[0], t < m.nt && flip_body(m, t, round, pass));
 }
 
 __global__ __launch_bounds__(kBlock) void k_fix(Mesh m, int32_t round) {
@@ -59,7 +66,9 @@ __global__ __launch_bounds__(kBlock) void k_fix(Mesh m, int32_t round) {
 
 __global__ __launch_bounds__(kBlock) void k_quality(Mesh m, Refine r) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t < m.nt) quality_body(m, r, t);
+  const int q = t < m.nt ? quality_body(m, r, t) : kNone;
+  wave_add(&r.count[0], q == kCandidate);
+  wave_add(&r.count[1], q == kTooFar);
 }
 
 __global__ __launch_bounds__(kBlock) void k_locate(Mesh m, Refine r) {
@@ -77,9 +86,9 @@ __global__ __launch_bounds__(kBlock) void k_check(Mesh m, Refine r) {
   if (t < m.nt) check_body(m, r, t);
 }
 
-__global__ __launch_bounds__(kBlock) void k_insert(Mesh m, Refine r, int32_t it) {
+__global__ __launch_bounds__(kBlock) void k_insert(Mesh m, Refine r, int32_t it, int32_t pass) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t < m.nt) insert_body(m, r, t, it);
+  if (t < m.nt) insert_body(m, r, t, it, pass);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fixsplit(Mesh m, Refine r, int32_t it) {
@@ -125,8 +134,8 @@ hipError_t launch_reset(const Mesh& m, hipStream_t s) {
   hipLaunchKernelGGL(k_reset, dim3(nblocks(m.nt > 3 ? m.nt : 3)), dim3(kBlock), 0, s, m);
   return hipGetLastError();
 }
-hipError_t launch_mark(const Mesh& m, hipStream_t s) {
-  hipLaunchKernelGGL(k_mark, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m);
+hipError_t launch_mark(const Mesh& m, int32_t pass, hipStream_t s) {
+  hipLaunchKernelGGL(k_mark, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m, pass);
   return hipGetLastError();
 }
 hipError_t launch_exact(const Mesh& m, int64_t first, int64_t last, hipStream_t s) {
@@ -134,8 +143,8 @@ hipError_t launch_exact(const Mesh& m, int64_t first, int64_t last, hipStream_t 
   hipLaunchKernelGGL(k_exact, dim3(nblocks(last - first)), dim3(kBlock), 0, s, m, first, last);
   return hipGetLastError();
 }
-hipError_t launch_flip(const Mesh& m, int32_t round, hipStream_t s) {
-  hipLaunchKernelGGL(k_flip, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m, round);
+hipError_t launch_flip(const Mesh& m, int32_t round, int32_t pass, hipStream_t s) {
+  hipLaunchKernelGGL(k_flip, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m, round, pass);
   return hipGetLastError();
 }
 hipError_t launch_fix(const Mesh& m, int32_t round, hipStream_t s) {
@@ -159,8 +168,8 @@ hipError_t launch_check(const Mesh& m, const Refine& r, hipStream_t s) {
   hipLaunchKernelGGL(k_check, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m, r);
   return hipGetLastError();
 }
-hipError_t launch_insert(const Mesh& m, const Refine& r, int32_t it, hipStream_t s) {
-  hipLaunchKernelGGL(k_insert, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m, r, it);
+hipError_t launch_insert(const Mesh& m, const Refine& r, int32_t it, int32_t pass, hipStream_t s) {
+  hipLaunchKernelGGL(k_insert, dim3(nblocks(m.nt)), dim3(kBlock), 0, s, m, r, it, pass);
   return hipGetLastError();
 }
 hipError_t launch_fixsplit(const Mesh& m, const Refine& r, int32_t it, int64_t nt_after, hipStream_t s) {
@@ -180,14 +189,13 @@ hipError_t launch_tkeys(const Mesh& m, const Order& o, hipStream_t s) {
 }
 size_t sort_tmp_bytes(int64_t n) {
   size_t bytes = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const unsigned long long*)nullptr,
-                                           (unsigned long long*)nullptr, (const int32_t*)nullptr, (int32_t*)nullptr,
-                                           (int)n);
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)n);
   return bytes;
 }
 hipError_t launch_sort(const Order& o, int64_t n, void* tmp, size_t tmp_bytes, hipStream_t s) {
   size_t bytes = tmp_bytes;
-  return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, o.key, o.skey, o.idx, o.perm, (int)n, 0, 64, s);
+  return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, o.key, o.skey, o.idx, o.perm, (int)n, 0, 32, s);
 }
 hipError_t launch_invert(const Order& o, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_invert, dim3(nblocks(n)), dim3(kBlock), 0, s, o, n);

@@ -65,6 +65,7 @@ struct Mesh {
   int32_t* flipped = nullptr;    // [ts] round of t's last flip (0: never)
   int32_t* partner = nullptr;    // [ts] the other triangle of t's last flip
   int32_t* count = nullptr;      // [0] flips, [1] illegal edges, [2] undecided edges
+  int32_t* mark = nullptr;       // [ts] t's edges are tested in every test pass numbered <= mark[t]
   int64_t* undecided = nullptr;  // keys 3 t + i of the edges the FP64 test could not decide
   double* work = nullptr;        // exact-evaluation scratch, kIncircleScratch doubles per thread
 };
@@ -94,6 +95,28 @@ struct Refine {
 constexpr int kCavity = 64;     // triangles a candidate's cavity may hold
 constexpr int kWalk = 1 << 20;  // steps of one point location
 constexpr int kRing = 256;      // triangles around one vertex
+
+// Counter add aggregated over a wave: every lane of the wave must call it;
+// lanes with pred add one each (one atomic per wave); returns this lane's
+// slot (the counter's old value plus the number of lower lanes with pred).
+#if defined(__HIPCC__)
+DL_FN int wave_add(int* counter, bool pred) {
+  const unsigned long long mask = __ballot(pred);
+  if (!mask) return 0;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+#else
+inline int wave_add(int* counter, bool pred) {
+  const int base = *counter;
+  if (pred) *counter = base + 1;
+  return base;
+}
+#endif
 
 DL_FN double image(double v, double o, double period) {
   if (period > 0.0) {
@@ -155,12 +178,13 @@ DL_FN Quad quad(const Mesh& m, int64_t t, int i) {
   return q;
 }
 
+// Edge i of t is illegal: claim both triangles with its key (flip_body then
+// marks t for the next test pass).
 DL_FN void mark_illegal(const Mesh& m, int64_t t, int i, int32_t u) {
   const int32_t key = (int32_t)(3 * t + i);
   atomicOr(&m.cand[t], 1 << i);
   atomicMin(&m.claim[t], key);
   atomicMin(&m.claim[u], key);
-  atomicAdd(&m.count[1], 1);
 }
 
 DL_FN void reset_body(const Mesh& m, int64_t t) {
@@ -171,36 +195,51 @@ DL_FN void reset_body(const Mesh& m, int64_t t) {
   if (t < 3) m.count[t] = 0;
 }
 
-// FP64 in-circle test of every interior edge, once per edge (by the lower
-// triangle); undecided edges go to the list for the exact pass.
-DL_FN void mark_body(const Mesh& m, int64_t t) {
+// FP64 in-circle test of the interior edges of t that t tests (t the lower
+// triangle of the edge) in test pass `pass`: those with t or its neighbour
+// marked for this pass (every other edge is known to be legal: its two
+// triangles are unchanged since it last passed). Returns the illegal edges
+// (bits 0-2) and the undecided ones, for the exact pass (bits 4-6). Marks
+// are only read here (flip_body writes them), so what a pass tests does not
+// depend on timing.
+DL_FN int mark_body(const Mesh& m, int64_t t, int32_t pass) {
+  int out = 0;
+  const bool mine = m.mark[t] >= pass;
   for (int i = 0; i < 3; ++i) {
     const int32_t u = across(m, i, t);
     if (u <= t) continue;  // boundary, or tested by u
+    if (!mine && m.mark[u] < pass) continue;
     const Quad q = quad(m, t, i);
     const int r = pred::incircle_filter(q.a, q.b, q.c, q.d);
     if (r > 0) {
       mark_illegal(m, t, i, u);
+      out |= 1 << i;
     } else if (r == 0) {
-      const int32_t k = atomicAdd(&m.count[2], 1);
-      m.undecided[k] = 3 * t + i;
+      out |= 16 << i;
     }
   }
+  return out;
 }
 
 // Exact in-circle test of undecided edge k; w: kIncircleScratch doubles.
-DL_FN void exact_body(const Mesh& m, int64_t k, double* w) {
+// Returns whether the edge is illegal.
+DL_FN bool exact_body(const Mesh& m, int64_t k, double* w) {
   const int64_t key = m.undecided[k];
   const int64_t t = key / 3;
   const int i = (int)(key % 3);
   const Quad q = quad(m, t, i);
-  if (pred::incircle_exact(q.a, q.b, q.c, q.d, w) > 0) mark_illegal(m, t, i, q.u);
+  if (pred::incircle_exact(q.a, q.b, q.c, q.d, w) <= 0) return false;
+  mark_illegal(m, t, i, q.u);
+  return true;
 }
 
-// Flip the illegal edge of t that holds the claims of both its triangles.
-DL_FN void flip_body(const Mesh& m, int64_t t, int32_t round) {
+// Flip the illegal edge of t that holds the claims of both its triangles;
+// returns whether it flipped. A triangle with an illegal edge, and both
+// triangles of a flip, are marked for the next test pass.
+DL_FN bool flip_body(const Mesh& m, int64_t t, int32_t round, int32_t pass) {
   const int32_t bits = m.cand[t];
-  if (!bits) return;
+  if (!bits) return false;
+  m.mark[t] = pass + 1;
   const int64_t ts = m.ts;
   for (int i = 0; i < 3; ++i) {
     if (!(bits & (1 << i))) continue;
@@ -241,9 +280,11 @@ DL_FN void flip_body(const Mesh& m, int64_t t, int32_t round) {
     m.flipped[u] = round;
     m.partner[t] = u;
     m.partner[u] = t;
-    atomicAdd(&m.count[0], 1);
-    return;
+    m.mark[t] = pass + 1;
+    m.mark[u] = pass + 1;
+    return true;
   }
+  return false;
 }
 
 // Neighbour entries of w that point at a triangle flipped this round now
@@ -290,12 +331,15 @@ DL_FN void candidate_reset(const Refine& r, int64_t t) {
   r.tnew[t] = 0;
 }
 
+// Result of quality_body.
+constexpr int kNone = 0, kCandidate = 1, kTooFar = 2;
+
 // Does t need a new vertex: a boundary edge it encroaches (its opposite
 // corner inside the edge's diametric circle: the edge is split at its
 // midpoint), or a circumradius r > R, or r / (shortest edge) > B (a vertex at
 // the circumcentre). The circumradius is l_a l_b l_c / (2 |det|) with det the
 // orientation determinant.
-DL_FN void quality_body(const Mesh& m, const Refine& r, int64_t t) {
+DL_FN int quality_body(const Mesh& m, const Refine& r, int64_t t) {
 #pragma clang fp contract(off)
   candidate_reset(r, t);
   double v[3][2];
@@ -312,8 +356,7 @@ DL_FN void quality_body(const Mesh& m, const Refine& r, int64_t t) {
       r.loc[t] = (int32_t)t;
       r.where[t] = 3 + i;
       r.prio[t] = priority(t, r.seed);
-      atomicAdd(&r.count[0], 1);
-      return;
+      return kCandidate;
     }
   }
   const double bx = v[1][0] - v[0][0], by = v[1][1] - v[0][1];
@@ -325,19 +368,17 @@ DL_FN void quality_body(const Mesh& m, const Refine& r, int64_t t) {
   double lmin2 = la2 < lb2 ? la2 : lb2;
   lmin2 = lmin2 < lc2 ? lmin2 : lc2;
   const bool bad = (r.r2 > 0.0 && rad2 > r.r2) || (r.b2 > 0.0 && rad2 > r.b2 * lmin2);
-  if (!bad) return;
+  if (!bad) return kNone;
   // circumcentre, relative to corner 0
   const double ux = (cy * lc2 - by * lb2) / (2.0 * det);
   const double uy = (bx * lb2 - cx * lc2) / (2.0 * det);
-  if ((m.px > 0.0 && fabs(ux) > 0.25 * m.px) || (m.py > 0.0 && fabs(uy) > 0.25 * m.py)) {
-    atomicAdd(&r.count[1], 1);  // too far for one periodic image
-    return;
-  }
+  if ((m.px > 0.0 && fabs(ux) > 0.25 * m.px) || (m.py > 0.0 && fabs(uy) > 0.25 * m.py))
+    return kTooFar;  // too far for one periodic image
   r.px[t] = wrap(v[0][0] + ux, m.px);
   r.py[t] = wrap(v[0][1] + uy, m.py);
   r.loc[t] = (int32_t)t;
   r.prio[t] = priority(t, r.seed);
-  atomicAdd(&r.count[0], 1);
+  return kCandidate;
 }
 
 // Index of vertex v among the corners of t (or -1).
@@ -562,8 +603,9 @@ DL_FN void set_tri(const Mesh& m, int64_t t, int32_t a, int32_t b, int32_t c, in
 // shared by s and u (each becomes two), or on a boundary edge of s (s
 // becomes two). New triangles are numbered from m.nt + tpos[t]; the
 // neighbour entries of the split triangles' outer neighbours are repaired by
-// fixsplit_body.
-DL_FN void insert_body(const Mesh& m, const Refine& r, int64_t t, int32_t it) {
+// fixsplit_body. The split triangles and their children are marked for the
+// next edge-test pass `pass`.
+DL_FN void insert_body(const Mesh& m, const Refine& r, int64_t t, int32_t it, int32_t pass) {
   if (!r.win[t]) return;
   const int32_t pv = (int32_t)(r.nv + r.wpos[t]);
   m.x[pv] = r.px[t];
@@ -579,6 +621,7 @@ DL_FN void insert_body(const Mesh& m, const Refine& r, int64_t t, int32_t it) {
     set_tri(m, s, a, b, pv, t1, t2, n2);
     set_tri(m, t1, b, c, pv, t2, s, n0);
     set_tri(m, t2, c, a, pv, s, t1, n1);
+    m.mark[s] = m.mark[t1] = m.mark[t2] = pass;
     r.split[s] = it;
     r.child[0 * ts + s] = t1;
     r.child[1 * ts + s] = t2;
@@ -590,6 +633,7 @@ DL_FN void insert_body(const Mesh& m, const Refine& r, int64_t t, int32_t it) {
   if (where >= 3) {
     set_tri(m, s, a, b, pv, -1, t1, n_ab);
     set_tri(m, t1, a, pv, c, -1, n_ca, s);
+    m.mark[s] = m.mark[t1] = pass;
     r.split[s] = it;
     r.child[0 * ts + s] = t1;
     r.child[1 * ts + s] = -1;
@@ -608,6 +652,7 @@ DL_FN void insert_body(const Mesh& m, const Refine& r, int64_t t, int32_t it) {
   set_tri(m, t1, a, pv, c, t2, n_ca, s);
   set_tri(m, u, pv, b, d, n_bd, t2, s);
   set_tri(m, t2, c, pv, d, u, n_dc, t1);
+  m.mark[s] = m.mark[t1] = m.mark[u] = m.mark[t2] = pass;
   r.split[s] = it;
   r.child[0 * ts + s] = t1;
   r.child[1 * ts + s] = -1;
@@ -647,17 +692,19 @@ DL_FN void fixsplit_body(const Mesh& m, const Refine& r, int64_t w, int32_t it) 
 
 // ---------------------------------------------------------------------------
 // Morton ordering (Section 4.1: vertices and triangles renumbered along a
-// Z-order curve after each insertion iteration, for locality). A key
-// interleaves the 32-bit quantised coordinates, x in the even bits:
+// Z-order curve as the mesh grows, for locality). A key interleaves the
+// 32-bit quantised coordinates, x in the even bits:
 // q(x) = min(2^32 - 1, floor(max(0, (x - x0) * sx))), likewise for y; a
 // triangle's key is that of its centroid (corners at their images nearest
-// to corner 0, the mean wrapped into the period). Sorting is stable, so
-// equal keys keep their order.
+// to corner 0, the mean wrapped into the period). Elements are ordered by
+// the top 32 bits of the key (a 2^16 x 2^16 grid of cells), which is what
+// is stored and sorted; the sort is stable, so elements in one cell keep
+// their order.
 
 struct Order {
   double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
-  unsigned long long* key = nullptr;   // [n] keys
-  unsigned long long* skey = nullptr;  // [n] sorted keys
+  uint32_t* key = nullptr;             // [n] top 32 bits of the keys
+  uint32_t* skey = nullptr;            // [n] sorted
   int32_t* idx = nullptr;              // [n] 0, 1, ..., n - 1
   int32_t* perm = nullptr;             // [n] new -> old
   int32_t* inv = nullptr;              // [n] old -> new
@@ -690,7 +737,7 @@ DL_FN unsigned long long morton_key(const Order& o, double x, double y) {
 }
 
 DL_FN void vkey_body(const Mesh& m, const Order& o, int64_t v) {
-  o.key[v] = morton_key(o, m.x[v], m.y[v]);
+  o.key[v] = (uint32_t)(morton_key(o, m.x[v], m.y[v]) >> 32);
   o.idx[v] = (int32_t)v;
 }
 
@@ -701,7 +748,7 @@ DL_FN void tkey_body(const Mesh& m, const Order& o, int64_t t) {
   tri_near(m, t, a, v);
   const double cx = wrap((v[0][0] + v[1][0] + v[2][0]) / 3.0, m.px);
   const double cy = wrap((v[0][1] + v[1][1] + v[2][1]) / 3.0, m.py);
-  o.key[t] = morton_key(o, cx, cy);
+  o.key[t] = (uint32_t)(morton_key(o, cx, cy) >> 32);
   o.idx[t] = (int32_t)t;
 }
 

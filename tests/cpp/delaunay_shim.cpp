@@ -16,7 +16,7 @@ using rd::dl::Refine;
 
 struct Host {
   std::vector<double> x, y, work;
-  std::vector<int32_t> tri, nbr, claim, cand, flipped, partner, count{0, 0, 0};
+  std::vector<int32_t> tri, nbr, claim, cand, flipped, partner, mark, count{0, 0, 0};
   std::vector<int64_t> undecided;
   std::vector<unsigned long long> prio, lock;
   std::vector<double> px, py;
@@ -59,6 +59,7 @@ Mesh view(Host& h, int64_t nt, int64_t ts, double px, double py) {
   m.cand = h.cand.data();
   m.flipped = h.flipped.data();
   m.partner = h.partner.data();
+  m.mark = h.mark.data();
   m.count = h.count.data();
   m.undecided = h.undecided.data();
   m.work = h.work.data();
@@ -70,18 +71,28 @@ void alloc(Host& h, int64_t ts) {
   h.cand.assign(ts, 0);
   h.flipped.assign(ts, 0);
   h.partner.assign(ts, 0);
+  h.mark.assign(ts, 0);
   h.undecided.assign(3 * ts / 2 + 1, 0);
   h.work.assign(rd::pred::kIncircleScratch, 0.0);
 }
 
-int flip_all(Mesh& m, int64_t* flips, int32_t* round) {
+// The counters the kernels add with wave_add are added here from the
+// bodies' results.
+int flip_all(Mesh& m, int64_t* flips, int32_t* round, int32_t* pass) {
   for (;;) {
+    const int32_t p = (*pass)++;
     for (int64_t t = 0; t < std::max<int64_t>(m.nt, 3); ++t) rd::dl::reset_body(m, t);
-    for (int64_t t = 0; t < m.nt; ++t) rd::dl::mark_body(m, t);
-    for (int64_t k = 0; k < m.count[2]; ++k) rd::dl::exact_body(m, k, m.work);
+    for (int64_t t = 0; t < m.nt; ++t) {
+      const int r = rd::dl::mark_body(m, t, p);
+      for (int i = 0; i < 3; ++i) {
+        m.count[1] += (r >> i) & 1;
+        if ((r >> (4 + i)) & 1) m.undecided[m.count[2]++] = 3 * t + i;
+      }
+    }
+    for (int64_t k = 0; k < m.count[2]; ++k) m.count[1] += rd::dl::exact_body(m, k, m.work);
     if (m.count[1] == 0) return 0;
     ++*round;
-    for (int64_t t = 0; t < m.nt; ++t) rd::dl::flip_body(m, t, *round);
+    for (int64_t t = 0; t < m.nt; ++t) m.count[0] += rd::dl::flip_body(m, t, *round, p);
     for (int64_t t = 0; t < m.nt; ++t) rd::dl::fix_body(m, t, *round);
     if (m.count[0] < 1) return 3;
     *flips += m.count[0];
@@ -91,7 +102,7 @@ int flip_all(Mesh& m, int64_t* flips, int32_t* round) {
 // Morton renumbering with the library's bodies; the sort is a stable sort
 // by key, as the device's radix sort is.
 struct Reorder {
-  std::vector<unsigned long long> key;
+  std::vector<uint32_t> key;
   std::vector<int32_t> idx, perm, inv, tt, nb;
   std::vector<double> xt, yt;
   rd::dl::Order o;
@@ -147,8 +158,8 @@ int rdl_flip(int64_t nv, const double* x, const double* y, double px, double py,
   alloc(h, nt);
   Mesh m = view(h, nt, nt, px, py);
   int64_t flips = 0;
-  int32_t round = 0;
-  const int st = flip_all(m, &flips, &round);
+  int32_t round = 0, pass = 0;
+  const int st = flip_all(m, &flips, &round, &pass);
   download(h, nt, nt, tri);
   *n_flips = flips;
   *n_rounds = round;
@@ -226,12 +237,17 @@ int rdl_refine(int64_t* n_vertices, double* x, double* y, int64_t max_v, double 
     q.o.nb = q.nb.data();
   }
   int64_t flips = 0;
-  int32_t round = 0, it = 0;
-  int st = flip_all(m, &flips, &round);
+  int32_t round = 0, it = 0, pass = 0;
+  int64_t nt_ordered = nt;
+  int st = flip_all(m, &flips, &round, &pass);
   while (st == 0) {
     r.seed = 0x9e3779b9u * (uint32_t)(it + 1);
     r.count[0] = r.count[1] = r.count[2] = 0;
-    for (int64_t t = 0; t < nt; ++t) rd::dl::quality_body(m, r, t);
+    for (int64_t t = 0; t < nt; ++t) {
+      const int q = rd::dl::quality_body(m, r, t);
+      r.count[0] += q == rd::dl::kCandidate;
+      r.count[1] += q == rd::dl::kTooFar;
+    }
     if (r.count[0] == 0) {
       st = r.count[1] > 0 ? 5 : 0;
       break;
@@ -260,14 +276,18 @@ int rdl_refine(int64_t* n_vertices, double* x, double* y, int64_t max_v, double 
       break;
     }
     r.nv = nv;
-    for (int64_t t = 0; t < nt; ++t) rd::dl::insert_body(m, r, t, it);
+    for (int64_t t = 0; t < nt; ++t) rd::dl::insert_body(m, r, t, it, pass);
     m.nt = nt + nadd;
     for (int64_t t = 0; t < nt + nadd; ++t) rd::dl::fixsplit_body(m, r, t, it);
     nv += nwin;
     nt += nadd;
-    st = flip_all(m, &flips, &round);
-    if (st == 0 && morton) reorder(h, m, q, nv);
+    st = flip_all(m, &flips, &round, &pass);
+    if (st == 0 && morton && 4 * nt >= 5 * nt_ordered) {
+      reorder(h, m, q, nv);
+      nt_ordered = nt;
+    }
   }
+  if (st == 0 && morton && nt != nt_ordered) reorder(h, m, q, nv);
   std::copy(h.x.begin(), h.x.begin() + nv, x);
   std::copy(h.y.begin(), h.y.begin() + nv, y);
   download(h, nt, ts, tri);

@@ -86,6 +86,7 @@ def test_paper_size_periodic_mesh(rd, D, morton):
     el = time.perf_counter() - t0
     say(f"refine periodic (morton={morton}) to {m1['nv']} vertices, {m1['nt']} triangles: "
         f"{m1['n_iterations']} iterations, {m1['n_flips']} flips, {el:.2f} s")
+    assert same(m1, rd.rd_delaunay_refine(m0, R, SQRT2, max_vertices=1600000, morton=morton))  # run to run
     assert 1.1e6 < m1["nv"] < 1.6e6 and m1["nt"] == 2 * m1["nv"]  # a torus: nt = 2 nv
     tri = m1["tri"]
     idx = np.random.default_rng(2).choice(len(tri), 1500, replace=False)

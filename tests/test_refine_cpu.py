@@ -213,14 +213,15 @@ def centroids(m):
 @pytest.mark.parametrize("case", ["random_points", "periodic", "periodic_x_walls_y"])
 def test_morton_renumbering(S, D, case):
     """With morton = 1 the refined mesh has the same properties, and its
-    vertices and triangles are in non-decreasing Z-order."""
+    vertices and triangles end in non-decreasing Z-order."""
     make, R, B = CASES[case]
     m0 = make()
     st, m1 = host_refine(S, m0, R, B, morton=True)
     assert st == 0
     check_refined(D, m0, m1, R, B, morton=True)
-    kv = morton_keys(m0, m1["x"], m1["y"])
+    # ordered by the top 32 bits of the key (a 2^16 x 2^16 grid of cells)
+    kv = morton_keys(m0, m1["x"], m1["y"]) >> np.uint64(32)
     assert np.all(kv[1:] >= kv[:-1])
     cx, cy = centroids(m1)
-    kt = morton_keys(m0, cx, cy)
+    kt = morton_keys(m0, cx, cy) >> np.uint64(32)
     assert np.all(kt[1:] >= kt[:-1])
