@@ -382,3 +382,121 @@ def batch_problem(seed=0, n=256, lo=32, hi=512, sides=None):
         meshes.append(m)
         states.append(ic_quadrants(m, quadrant_states(seed * 100003 + k, **BATCH_QUADRANTS)))
     return meshes, states
+
+
+# ---------------------------------------------------------------- 3D -------
+
+def cube_tets(N: int, periodic=(True, True, True), jitter: float = 0.0, seed: int = 0,
+              length: float = 1.0, renumber: str | None = None) -> dict:
+    """Tetrahedral mesh of the box [0, length]^3: N cells per side, each cell
+    split into the six tetrahedra around its main diagonal (Kuhn's
+    subdivision, conforming across cells); every tetrahedron positively
+    oriented. ``periodic`` per axis (periodic axes have N vertex lines, the
+    others N + 1). ``jitter`` moves every vertex by up to jitter * h per
+    coordinate (vertices on a bounded face stay on it). ``renumber`` None or
+    "morton" (vertices and tetrahedra along a Z-order curve).
+
+    Returns a dict with ``x, y, z`` (float64 [nv]), ``tet`` (int32 [nt, 4]),
+    ``px, py, pz`` (periods, 0 when bounded), ``nv, nt``, ``N``, ``h``,
+    ``gamma``."""
+    per = [bool(p) for p in periodic]
+    if N < (3 if any(per) else 1):
+        raise ValueError("too few cells per side")
+    h = length / N
+    nl = [N if p else N + 1 for p in per]
+    ii, jj, kk = np.meshgrid(np.arange(nl[0]), np.arange(nl[1]), np.arange(nl[2]), indexing="ij")
+    ii, jj, kk = ii.ravel(order="F"), jj.ravel(order="F"), kk.ravel(order="F")
+    x, y, z = ii * h, jj * h, kk * h
+    if jitter > 0:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        d = (rng.random((3, len(x))) * 2.0 - 1.0) * jitter * h
+        for a, (c, n_, p) in enumerate(zip((ii, jj, kk), nl, per)):
+            if not p:  # keep bounded faces flat
+                d[a][(c == 0) | (c == n_ - 1)] = 0.0
+        x, y, z = x + d[0], y + d[1], z + d[2]
+
+    def vid(i, j, k):
+        return (i % nl[0]) + nl[0] * ((j % nl[1]) + nl[1] * (k % nl[2]))
+
+    ci, cj, ck = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    ci, cj, ck = ci.ravel(order="F"), cj.ravel(order="F"), ck.ravel(order="F")
+    tets = []
+    for perm, sign in (((0, 1, 2), 1), ((1, 2, 0), 1), ((2, 0, 1), 1), ((0, 2, 1), -1), ((2, 1, 0), -1),
+                       ((1, 0, 2), -1)):
+        path = [np.zeros(3, dtype=np.int64)]
+        for a in perm:
+            step = path[-1].copy()
+            step[a] += 1
+            path.append(step)
+        corners = [vid(ci + s[0], cj + s[1], ck + s[2]) for s in path]
+        if sign < 0:  # odd permutation: swap two corners for a positive orientation
+            corners[1], corners[2] = corners[2], corners[1]
+        tets.append(np.stack(corners, axis=1))
+    tet = np.concatenate(tets).astype(np.int32)
+    mesh = {"x": x.astype(np.float64), "y": y.astype(np.float64), "z": z.astype(np.float64), "tet": tet,
+            "px": length if per[0] else 0.0, "py": length if per[1] else 0.0, "pz": length if per[2] else 0.0,
+            "nv": len(x), "nt": len(tet), "N": N, "h": h, "gamma": GAMMA}
+    if renumber == "morton":
+        def key3(i, j, k):
+            out = np.zeros(len(i), dtype=np.int64)
+            for b in range(21):
+                out |= (((i >> b) & 1) << (3 * b)) | (((j >> b) & 1) << (3 * b + 1)) | (((k >> b) & 1) << (3 * b + 2))
+            return out
+        vp = np.argsort(key3(ii, jj, kk), kind="stable")
+        inv = np.empty_like(vp)
+        inv[vp] = np.arange(len(vp))
+        for c in ("x", "y", "z"):
+            mesh[c] = np.ascontiguousarray(mesh[c][vp])
+        cell = np.arange(len(tet)) % len(ci)  # tetrahedra come in six blocks of all cells
+        tp = np.argsort(key3(ci[cell], cj[cell], ck[cell]), kind="stable")
+        mesh["tet"] = np.ascontiguousarray(inv[tet][tp]).astype(np.int32)
+    elif renumber is not None:
+        raise ValueError("renumber must be None or 'morton'")
+    return mesh
+
+
+def prim_to_cons3(rho, u, v, w, p, gamma=GAMMA) -> np.ndarray:
+    """Conserved state (rho, rho u, rho v, rho w, e) as a [5, nv] float64
+    array, e = rho |u|^2 / 2 + p / (gamma - 1)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    u, v, w, p = (np.broadcast_to(np.asarray(a, dtype=np.float64), rho.shape) for a in (u, v, w, p))
+    e = 0.5 * rho * (u * u + v * v + w * w) + p / (gamma - 1.0)
+    return np.ascontiguousarray(np.stack([rho, rho * u, rho * v, rho * w, e]))
+
+
+def ic3_uniform(mesh, rho=1.0, u=0.0, v=0.0, w=0.0, p=1.0):
+    return prim_to_cons3(np.full(mesh["nv"], rho), u, v, w, p, mesh["gamma"])
+
+
+def ic3_random_smooth(mesh, seed=0, amp=0.1, u=0.3, v=-0.2, w=0.15, p=1.0, modes=4):
+    """Seeded smooth periodic perturbations of a uniform flow (a few Fourier
+    modes per field, lowest wavenumbers of the box)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = [mesh["px"] or 1.0, mesh["py"] or 1.0, mesh["pz"] or 1.0]
+    X = [mesh["x"] / L[0], mesh["y"] / L[1], mesh["z"] / L[2]]
+
+    def field():
+        f = np.zeros(mesh["nv"])
+        for _ in range(modes):
+            k = rng.integers(-2, 3, size=3)
+            ph = rng.random() * 2 * np.pi
+            f += rng.normal() * np.cos(2 * np.pi * (k[0] * X[0] + k[1] * X[1] + k[2] * X[2]) + ph)
+        return f / modes
+
+    rho = 1.0 + amp * field()
+    return prim_to_cons3(rho, u + amp * field(), v + amp * field(), w + amp * field(), p * (1.0 + amp * field()),
+                         mesh["gamma"])
+
+
+def ic3_kelvin_helmholtz(mesh, seed=0, amp=0.01, rho_in=2.0, rho_out=1.0, u_in=0.5, u_out=-0.5, p=2.5):
+    """Shear layer in a periodic box: the middle half in y (1/4 < y < 3/4)
+    denser and moving with u_in, the rest with u_out; seeded small random
+    velocity perturbations in v and w."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Ly = mesh["py"] or 1.0
+    inner = (mesh["y"] > 0.25 * Ly) & (mesh["y"] < 0.75 * Ly)
+    rho = np.where(inner, rho_in, rho_out)
+    u = np.where(inner, u_in, u_out)
+    v = amp * (rng.random(mesh["nv"]) - 0.5)
+    w = amp * (rng.random(mesh["nv"]) - 0.5)
+    return prim_to_cons3(rho, u, v, w, p, mesh["gamma"])
