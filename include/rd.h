@@ -304,6 +304,54 @@ rd_status rd_batch_tune(rd_batch* batch, double cfl, int scheme, int time, int p
  * runtime error. */
 rd_status rd_sync(rd_mesh* mesh);
 
+/* ---- Three dimensions (tetrahedra) --------------------------------------
+ * The method of Section 3 generalised to three dimensions, as the paper's
+ * closing discussion describes (a row and a column added to every matrix):
+ * state (rho, rho u, rho v, rho w, e), Z = sqrt(rho)(1, u, v, w, h),
+ * K_i = (|n_i| / 3) K(n_i / |n_i|) with n_i the inward normal of the face
+ * opposite corner i scaled by its area; schemes RD_N, RD_LDA, RD_B, RD_BMAX,
+ * RD_BMIN; forward Euler or RK2 (global lumping, vertex volume sum |T| / 4);
+ * FP64; periodic boxes (each axis periodic or not; no wall or ghost
+ * vertices, so a bounded axis is only meaningful for flows that do not
+ * reach it). CFL limit: dt_i = 3 V_i / sum_T S_T lambda_T, S_T the largest
+ * face area, lambda_T the largest |u| + c at the corners. */
+typedef struct rd3_mesh rd3_mesh; /* opaque; owns its device buffers and stream */
+
+typedef struct {
+  int64_t n_vertices;
+  int64_t n_tets;
+  const double* x; /* [n_vertices] host */
+  const double* y;
+  const double* z;
+  const int32_t* tet; /* [n_tets][4] host; positively oriented after minimum-image unwrapping */
+  double period_x;    /* > 0: periodic axis of that length; 0: bounded */
+  double period_y;
+  double period_z;
+  double gamma; /* > 1 */
+} rd3_mesh_desc;
+
+/* Validates (indices, 4 n_tets < 2^31, positive volumes, every vertex used),
+ * precomputes face normals, volumes and the per-vertex slot order of the
+ * sums (ascending tetrahedron), uploads, and creates the mesh's stream.
+ * The state is zero until rd3_set_state. RD_EINVAL, RD_ENOMEM, RD_EDEVICE. */
+rd_status rd3_mesh_create(const rd3_mesh_desc* desc, rd3_mesh** out);
+rd_status rd3_mesh_destroy(rd3_mesh* mesh);
+/* State [5][n_vertices] FP64, host (on_device = 0) or device pointer. */
+rd_status rd3_set_state(rd3_mesh* mesh, const double* W, int on_device);
+rd_status rd3_get_state(rd3_mesh* mesh, double* W, int on_device);
+/* CFL limit of the current state times cfl (waits for the stream). */
+rd_status rd3_max_dt(rd3_mesh* mesh, double cfl, double* dt);
+/* One step with the given dt, or n_steps steps with dt from the CFL limit
+ * computed on the device before each step. Enqueue only. */
+rd_status rd3_step(rd3_mesh* mesh, double dt, int scheme, int time);
+rd_status rd3_step_cfl(rd3_mesh* mesh, int n_steps, double cfl, int scheme, int time);
+/* n_steps CFL steps, each kernel bracketed by HIP events on the mesh's
+ * stream; ms[0..4] receive the average milliseconds per step of the CFL
+ * limit, the first tetrahedron pass, the first vertex pass, the second
+ * tetrahedron pass and the second vertex pass (0 for Euler). Waits. */
+rd_status rd3_step_timed(rd3_mesh* mesh, int n_steps, double cfl, int scheme, int time, double* ms);
+rd_status rd3_sync(rd3_mesh* mesh);
+
 /* Message for the last non-OK status returned on this thread. */
 const char* rd_last_error(void);
 

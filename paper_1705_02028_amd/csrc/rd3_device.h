@@ -1,0 +1,300 @@
+// Three-dimensional residual distribution on tetrahedra (the method of
+// Section 3 with a row and a column added to every matrix, as the paper's
+// closing discussion describes): per-tetrahedron and per-vertex bodies of the
+// gfx950 kernels in rd3_kernels.hip. FP64 throughout.
+//
+// For a unit normal n the flux Jacobian K(n) = R diag(l) R^{-1} of the Euler
+// equations is applied in its rank-two form: with the pressure gradient
+// g = (g1 |u|^2 / 2, -g1 u, g1) (dp = g . dW), the normal-velocity row
+// m = (-u.n, n, 0) (rho du.n = m . dW), r0 = (1, u, H) and s = (0, n, u.n),
+// K x = l3 x + r0 ((l123 / c^2) g.x + (l12 / c) m.x) + s ((l12 / c) g.x + l123 m.x)
+// with l123 = (l1 + l2) / 2 - l3 and l12 = (l1 - l2) / 2 for the eigenvalues
+// l1 = u.n + c, l2 = u.n - c, l3 = u.n (or their positive or negative parts
+// for K^+ and K^-). This is the three-dimensional form of the entries of
+// Appendix A. K_i = (|n_i| / 3) K(n_i / |n_i|) with n_i the inward normal of
+// the face opposite corner i scaled by the face's area.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rd3 {
+
+constexpr int kBlock = 256;
+
+enum { S_N = 0, S_LDA = 1, S_B = 2, S_BMAX = 3, S_BMIN = 4 };
+
+// Device view of a tetrahedral mesh and its state.
+struct Dev3 {
+  int64_t nv = 0, nt = 0, ns = 0;  // vertices, tetrahedra, corner slots (4 nt)
+  double gamma = 1.4;
+  const int32_t* tet = nullptr;    // [4][nt] corners
+  const int32_t* slot = nullptr;   // [4][nt] CSR slot of each corner's part
+  const int32_t* off = nullptr;    // [nv + 1] slots of vertex v: [off[v], off[v+1]), ascending tetrahedron
+  const double* nrm = nullptr;     // [12][nt] inward face normals scaled by area: component k of corner i at 3 i + k
+  const double* vol = nullptr;     // [nt] volume
+  const double* smax = nullptr;    // [nt] largest face area
+  const double* V = nullptr;       // [nv] vertex volume (sum of |T| / 4)
+  double* W = nullptr;             // [5][nv] state
+  double* Ws = nullptr;            // [5][nv] first-stage state
+  double* Z = nullptr;             // [5][nv] parameter vector of the state the next tetrahedron pass reads
+  double* sig = nullptr;           // [nv] |u| + c of W
+  double* part = nullptr;          // [5][ns] distributed parts by slot
+  double* keepN = nullptr;         // [20][nt] stage-1 N parts (component k of corner i at 5 i + k)
+  double* keepT = nullptr;         // [5][nt] stage-1 residual
+  double* cpart = nullptr;         // [ns] CFL parts by slot
+  double* dt = nullptr;            // device scalar: the step's time step
+  double* bmin = nullptr;          // [blocks] partial minima of the CFL limit
+};
+
+__device__ inline void to_z(const double w[5], double gamma, double z[5], double& sig) {
+  const double rho = w[0], iu = 1.0 / rho;
+  const double u = w[1] * iu, v = w[2] * iu, ww = w[3] * iu;
+  const double q2 = u * u + v * v + ww * ww;
+  const double p = (gamma - 1.0) * (w[4] - 0.5 * rho * q2);
+  const double s = sqrt(rho);
+  z[0] = s;
+  z[1] = s * u;
+  z[2] = s * v;
+  z[3] = s * ww;
+  z[4] = s * (w[4] + p) * iu;
+  sig = sqrt(q2) + sqrt(gamma * p * iu);
+}
+
+// Rank-two application y = scale * K(l1, l2, l3) x at one corner.
+struct Corner {
+  double n[3];   // unit normal
+  double un;     // u . n
+  double scale;  // |n_i| / 3
+};
+
+struct Flow {
+  double u[3], H, c, g[5], r0[5];
+};
+
+__device__ inline void kapply(const Flow& f, const Corner& q, double l1, double l2, double l3, const double x[5],
+                              double y[5]) {
+  const double l123 = 0.5 * (l1 + l2) - l3, l12 = 0.5 * (l1 - l2);
+  const double gx = f.g[0] * x[0] + f.g[1] * x[1] + f.g[2] * x[2] + f.g[3] * x[3] + f.g[4] * x[4];
+  const double mx = -q.un * x[0] + q.n[0] * x[1] + q.n[1] * x[2] + q.n[2] * x[3];
+  const double ic = 1.0 / f.c;
+  const double a = (l123 * ic * ic) * gx + (l12 * ic) * mx;
+  const double b = (l12 * ic) * gx + l123 * mx;
+  const double s[5] = {0.0, q.n[0], q.n[1], q.n[2], q.un};
+  for (int k = 0; k < 5; ++k) y[k] = q.scale * (l3 * x[k] + f.r0[k] * a + s[k] * b);
+}
+
+__device__ inline double pos(double x) { return x > 0.0 ? x : 0.0; }
+__device__ inline double neg(double x) { return x < 0.0 ? x : 0.0; }
+
+// A x = b for two right-hand sides, Gaussian elimination with partial
+// pivoting; a column whose best pivot is at most 2^-45 max|A| is skipped
+// (its unknowns are 0).
+__device__ inline void solve5x2(double A[5][5], double b1[5], double b2[5], double x1[5], double x2[5]) {
+  double amax = 0.0;
+  for (int r = 0; r < 5; ++r)
+    for (int q = 0; q < 5; ++q) amax = fmax(amax, fabs(A[r][q]));
+  const double tol = ldexp(amax, -45);
+  int used = 0, prow[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    int r = -1;
+    double best = -1.0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      if (used & (1 << i)) continue;
+      const double a = fabs(A[i][k]);
+      if (a > best) {
+        best = a;
+        r = i;
+      }
+    }
+    prow[k] = -1;
+    if (r < 0 || !(best > tol)) continue;
+    used |= 1 << r;
+    prow[k] = r;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      if (used & (1 << i)) continue;
+      const double fct = A[i][k] / A[r][k];
+#pragma unroll
+      for (int j = 0; j < 5; ++j)
+        if (j >= k) A[i][j] -= fct * A[r][j];
+      b1[i] -= fct * b1[r];
+      b2[i] -= fct * b2[r];
+    }
+  }
+#pragma unroll
+  for (int k = 4; k >= 0; --k) {
+    if (prow[k] < 0) {
+      x1[k] = 0.0;
+      x2[k] = 0.0;
+      continue;
+    }
+    const int r = prow[k];
+    double s1 = b1[r], s2 = b2[r];
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+      if (j > k) {
+        s1 -= A[r][j] * x1[j];
+        s2 -= A[r][j] * x2[j];
+      }
+    x1[k] = s1 / A[r][k];
+    x2[k] = s2 / A[r][k];
+  }
+}
+
+// Blend of the B family (and N, LDA) of parts pn, pl splitting `res`.
+__device__ inline void blend(int scheme, const double res[5], const double pn[4][5], const double pl[4][5],
+                             double out[4][5]) {
+  double th[5];
+  if (scheme == S_N || scheme == S_LDA) {
+    for (int k = 0; k < 5; ++k) th[k] = scheme == S_N ? 1.0 : 0.0;
+  } else {
+    for (int k = 0; k < 5; ++k) {
+      const double den = fabs(pn[0][k]) + fabs(pn[1][k]) + fabs(pn[2][k]) + fabs(pn[3][k]);
+      const double q = den == 0.0 ? 0.0 : fabs(res[k]) / den;
+      th[k] = q > 1.0 ? 1.0 : q;
+    }
+    if (scheme == S_BMAX || scheme == S_BMIN) {
+      int pick = 0;
+      for (int k = 1; k < 5; ++k)
+        if (scheme == S_BMAX ? th[k] > th[pick] : th[k] < th[pick]) pick = k;
+      const double t = th[pick];
+      for (int k = 0; k < 5; ++k) th[k] = t;
+    }
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 5; ++k)
+      out[i][k] = scheme == S_N ? pn[i][k] : scheme == S_LDA ? pl[i][k] : pl[i][k] + th[k] * (pn[i][k] - pl[i][k]);
+}
+
+// One tetrahedron: stage 1 (or Euler) at the Z in d.Z; stage 2 adds the
+// mass term of the first-stage increment and the kept stage-1 parts.
+template <int STAGE>
+__device__ inline void tet_body(const Dev3& d, int64_t t, int scheme, bool keep) {
+  const int64_t nt = d.nt, nv = d.nv;
+  const double g1 = d.gamma - 1.0;
+  int32_t vid[4];
+  double Zc[4][5];
+  for (int i = 0; i < 4; ++i) {
+    vid[i] = d.tet[i * nt + t];
+    for (int k = 0; k < 5; ++k) Zc[i][k] = d.Z[k * nv + vid[i]];
+  }
+  double zb[5];
+  for (int k = 0; k < 5; ++k) zb[k] = 0.25 * (Zc[0][k] + Zc[1][k] + Zc[2][k] + Zc[3][k]);
+  Flow f;
+  const double iz = 1.0 / zb[0];
+  f.u[0] = zb[1] * iz;
+  f.u[1] = zb[2] * iz;
+  f.u[2] = zb[3] * iz;
+  f.H = zb[4] * iz;
+  const double q2 = f.u[0] * f.u[0] + f.u[1] * f.u[1] + f.u[2] * f.u[2];
+  f.c = sqrt(g1 * (f.H - 0.5 * q2));
+  f.g[0] = 0.5 * g1 * q2;
+  f.g[1] = -g1 * f.u[0];
+  f.g[2] = -g1 * f.u[1];
+  f.g[3] = -g1 * f.u[2];
+  f.g[4] = g1;
+  f.r0[0] = 1.0;
+  f.r0[1] = f.u[0];
+  f.r0[2] = f.u[1];
+  f.r0[3] = f.u[2];
+  f.r0[4] = f.H;
+  // state differences M(zbar)(Z_i - Z_0)
+  double dW[4][5];
+  for (int k = 0; k < 5; ++k) dW[0][k] = 0.0;
+  for (int i = 1; i < 4; ++i) {
+    double dz[5];
+    for (int k = 0; k < 5; ++k) dz[k] = Zc[i][k] - Zc[0][k];
+    dW[i][0] = 2.0 * zb[0] * dz[0];
+    for (int k = 1; k < 4; ++k) dW[i][k] = zb[k] * dz[0] + zb[0] * dz[k];
+    dW[i][4] = (zb[4] * dz[0] + g1 * (zb[1] * dz[1] + zb[2] * dz[2] + zb[3] * dz[3]) + zb[0] * dz[4]) / d.gamma;
+  }
+  Corner cn[4];
+  for (int i = 0; i < 4; ++i) {
+    double n[3];
+    for (int k = 0; k < 3; ++k) n[k] = d.nrm[(3 * i + k) * nt + t];
+    const double area = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const double ia = 1.0 / area;
+    for (int k = 0; k < 3; ++k) cn[i].n[k] = n[k] * ia;
+    cn[i].un = f.u[0] * cn[i].n[0] + f.u[1] * cn[i].n[1] + f.u[2] * cn[i].n[2];
+    cn[i].scale = area / 3.0;
+  }
+  // residual and the N right-hand side
+  double phiT[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, bN[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = 1; i < 4; ++i) {
+    const double un = cn[i].un;
+    double y[5];
+    kapply(f, cn[i], un + f.c, un - f.c, un, dW[i], y);
+    for (int k = 0; k < 5; ++k) phiT[k] += y[k];
+    kapply(f, cn[i], neg(un + f.c), neg(un - f.c), neg(un), dW[i], y);
+    for (int k = 0; k < 5; ++k) bN[k] += y[k];
+  }
+  // A = sum_i K_i^+ assembled from the rank-two form
+  double A[5][5];
+  for (int r = 0; r < 5; ++r)
+    for (int q = 0; q < 5; ++q) A[r][q] = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    const double un = cn[i].un;
+    const double l1 = pos(un + f.c), l2 = pos(un - f.c), l3 = pos(un);
+    const double l123 = 0.5 * (l1 + l2) - l3, l12 = 0.5 * (l1 - l2);
+    const double ic = 1.0 / f.c, sc = cn[i].scale;
+    const double m[5] = {-un, cn[i].n[0], cn[i].n[1], cn[i].n[2], 0.0};
+    const double s[5] = {0.0, cn[i].n[0], cn[i].n[1], cn[i].n[2], un};
+    double a[5], b[5];
+    for (int q = 0; q < 5; ++q) {
+      a[q] = sc * ((l123 * ic * ic) * f.g[q] + (l12 * ic) * m[q]);
+      b[q] = sc * ((l12 * ic) * f.g[q] + l123 * m[q]);
+    }
+    for (int r = 0; r < 5; ++r) {
+      A[r][r] += sc * l3;
+      for (int q = 0; q < 5; ++q) A[r][q] += f.r0[r] * a[q] + s[r] * b[q];
+    }
+  }
+  double rhsT[5], PN[4][5], PT[5];
+  if (STAGE == 1) {
+    for (int k = 0; k < 5; ++k) PT[k] = phiT[k];
+  } else {
+    // stage 2: mass |T| / 4 times the first-stage rate, plus the mean of the
+    // kept and the current parts
+    const double idt = 1.0 / *d.dt, mass = 0.25 * d.vol[t];
+    double rate_sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 5; ++k) {
+        const double r = (d.Ws[k * nv + vid[i]] - d.W[k * nv + vid[i]]) * idt;
+        PN[i][k] = mass * r;  // completed below with the N parts
+        rate_sum[k] += r;
+      }
+    for (int k = 0; k < 5; ++k) PT[k] = mass * rate_sum[k] + 0.5 * (d.keepT[k * nt + t] + phiT[k]);
+  }
+  for (int k = 0; k < 5; ++k) rhsT[k] = PT[k];
+  double xN[5], xT[5];
+  solve5x2(A, bN, rhsT, xN, xT);
+  double pn[4][5], pl[4][5];
+  for (int i = 0; i < 4; ++i) {
+    const double un = cn[i].un;
+    const double l1 = pos(un + f.c), l2 = pos(un - f.c), l3 = pos(un);
+    double y[5];
+    for (int k = 0; k < 5; ++k) y[k] = dW[i][k] + xN[k];
+    kapply(f, cn[i], l1, l2, l3, y, pn[i]);
+    kapply(f, cn[i], l1, l2, l3, xT, pl[i]);
+  }
+  if (STAGE == 1 && keep) {
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 5; ++k) d.keepN[(5 * i + k) * nt + t] = pn[i][k];
+    for (int k = 0; k < 5; ++k) d.keepT[k * nt + t] = phiT[k];
+  }
+  if (STAGE == 2)
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 5; ++k) pn[i][k] = PN[i][k] + 0.5 * (d.keepN[(5 * i + k) * nt + t] + pn[i][k]);
+  double out[4][5];
+  blend(scheme, PT, pn, pl, out);
+  for (int i = 0; i < 4; ++i) {
+    const int64_t sl = d.slot[i * nt + t];
+    for (int k = 0; k < 5; ++k) d.part[k * d.ns + sl] = out[i][k];
+  }
+}
+
+}  // namespace rd3

@@ -6,11 +6,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <type_traits>
 #include <vector>
 
 #include "rd.h"
+#include "rd3_launch.h"
 #include "rd_delaunay.h"
 #include "rd_launch.h"
 #include "rd_tiling.h"
@@ -1609,3 +1611,263 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
     }
   }
 }
+
+// --------------------------------------------------------- three dimensions --
+//
+// Host side of the tetrahedral path: validation and geometry (face normals,
+// volumes, vertex volumes), the slot order of the vertex sums, buffers and
+// the launch order of a step (kernels in rd3_kernels.hip).
+
+struct rd3_mesh {
+  rd3::Dev3 d;
+  std::vector<void*> bufs;
+  hipStream_t stream = nullptr;
+  ~rd3_mesh() {
+    if (stream) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipStreamDestroy(stream);
+    }
+    for (void* q : bufs) (void)hipFree(q);
+  }
+};
+
+namespace {
+
+double unwrap3(double d, double period) {
+  if (period > 0.0) {
+    if (d > 0.5 * period) d -= period;
+    else if (d < -0.5 * period) d += period;
+  }
+  return d;
+}
+
+template <class T>
+bool dev_get(rd3_mesh* m, T** out, size_t n) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return false;
+  m->bufs.push_back(q);
+  *out = static_cast<T*>(q);
+  return true;
+}
+
+rd_status rd3_check_step(int scheme, int time) {
+  if (scheme < RD_N || scheme > RD_BMIN) return fail(RD_EINVAL, "unknown scheme for three dimensions");
+  if (time != RD_EULER1 && time != RD_RK2) return fail(RD_EINVAL, "unknown time integration");
+  return RD_OK;
+}
+
+// One step after *d.dt is set on the stream.
+rd_status rd3_stages(rd3_mesh* m, int scheme, int time, hipEvent_t* ev) {
+  const rd3::Dev3& d = m->d;
+  const hipStream_t s = m->stream;
+  auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], s) : hipSuccess; };
+  HIPCHK(rd3::launch3_tet(d, 1, scheme, time == RD_RK2, s));
+  HIPCHK(mark(2));
+  HIPCHK(rd3::launch3_gather(d, time == RD_RK2 ? 1 : 0, s));
+  HIPCHK(mark(3));
+  if (time == RD_RK2) {
+    HIPCHK(rd3::launch3_tet(d, 2, scheme, false, s));
+    HIPCHK(mark(4));
+    HIPCHK(rd3::launch3_gather(d, 2, s));
+    HIPCHK(mark(5));
+  }
+  return RD_OK;
+}
+
+}  // namespace
+
+RD_API rd_status rd3_mesh_create(const rd3_mesh_desc* desc, rd3_mesh** out) {
+  if (!desc || !out) return fail(RD_EINVAL, "null argument");
+  *out = nullptr;
+  const int64_t nv = desc->n_vertices, nt = desc->n_tets;
+  if (nv < 4 || nt < 1) return fail(RD_EINVAL, "empty mesh");
+  if (nv >= INT32_MAX || nt >= INT32_MAX / 4) return fail(RD_EINVAL, "mesh too large for 32-bit indices");
+  if (!desc->x || !desc->y || !desc->z || !desc->tet) return fail(RD_EINVAL, "null array");
+  if (!(desc->gamma > 1.0)) return fail(RD_EINVAL, "gamma must exceed 1");
+  const double per[3] = {desc->period_x, desc->period_y, desc->period_z};
+  for (double p : per)
+    if (!(p >= 0.0) || !std::isfinite(p)) return fail(RD_EINVAL, "invalid period");
+  const double* xyz[3] = {desc->x, desc->y, desc->z};
+  std::vector<double> nrm(12 * nt), vol(nt), smax(nt), V(nv, 0.0);
+  std::vector<int32_t> tsoa(4 * nt), cnt(nv + 1, 0);
+  for (int64_t t = 0; t < nt; ++t) {
+    int32_t v[4];
+    for (int i = 0; i < 4; ++i) {
+      v[i] = desc->tet[4 * t + i];
+      if (v[i] < 0 || v[i] >= nv) return fail(RD_EINVAL, "tetrahedron " + std::to_string(t) + ": index out of range");
+      tsoa[i * nt + t] = v[i];
+    }
+    double p[4][3];
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 3; ++k) p[i][k] = i == 0 ? 0.0 : unwrap3(xyz[k][v[i]] - xyz[k][v[0]], per[k]);
+    auto cr = [](const double* a, const double* b, double* c) {
+      c[0] = a[1] * b[2] - a[2] * b[1];
+      c[1] = a[2] * b[0] - a[0] * b[2];
+      c[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    double c[3];
+    cr(p[2], p[3], c);
+    const double six = p[1][0] * c[0] + p[1][1] * c[1] + p[1][2] * c[2];
+    if (!(six > 0.0)) return fail(RD_EINVAL, "tetrahedron " + std::to_string(t) + " is not positively oriented");
+    vol[t] = six / 6.0;
+    double sm = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      const double* a = p[(i + 1) % 4];
+      const double* b = p[(i + 2) % 4];
+      const double* e = p[(i + 3) % 4];
+      const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+      const double e2[3] = {e[0] - a[0], e[1] - a[1], e[2] - a[2]};
+      double n[3];
+      cr(e1, e2, n);
+      const double to[3] = {p[i][0] - a[0], p[i][1] - a[1], p[i][2] - a[2]};
+      const double sgn = (n[0] * to[0] + n[1] * to[1] + n[2] * to[2]) < 0.0 ? -0.5 : 0.5;
+      for (int k = 0; k < 3; ++k) nrm[(3 * i + k) * nt + t] = sgn * n[k];
+      sm = std::max(sm, 0.5 * std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
+    }
+    smax[t] = sm;
+    for (int i = 0; i < 4; ++i) {
+      V[v[i]] += vol[t] / 4.0;
+      ++cnt[v[i] + 1];
+    }
+  }
+  for (int64_t v = 0; v < nv; ++v)
+    if (!(V[v] > 0.0)) return fail(RD_EINVAL, "vertex " + std::to_string(v) + " belongs to no tetrahedron");
+  for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+  std::vector<int32_t> slot(4 * nt), fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t t = 0; t < nt; ++t)  // ascending tetrahedron within each vertex
+    for (int i = 0; i < 4; ++i) slot[i * nt + t] = fill[tsoa[i * nt + t]]++;
+  std::unique_ptr<rd3_mesh> m(new rd3_mesh());
+  rd3::Dev3& d = m->d;
+  d.nv = nv;
+  d.nt = nt;
+  d.ns = 4 * nt;
+  d.gamma = desc->gamma;
+  int32_t *dtet, *dslot, *doff;
+  double *dnrm, *dvol, *dsmax, *dV;
+  const int nb = rd3::cfl_blocks(nv);
+  if (!dev_get(m.get(), &dtet, 4 * nt) || !dev_get(m.get(), &dslot, 4 * nt) || !dev_get(m.get(), &doff, nv + 1) ||
+      !dev_get(m.get(), &dnrm, 12 * nt) || !dev_get(m.get(), &dvol, nt) || !dev_get(m.get(), &dsmax, nt) ||
+      !dev_get(m.get(), &dV, nv) || !dev_get(m.get(), &d.W, 5 * nv) || !dev_get(m.get(), &d.Ws, 5 * nv) ||
+      !dev_get(m.get(), &d.Z, 5 * nv) || !dev_get(m.get(), &d.sig, nv) || !dev_get(m.get(), &d.part, 5 * 4 * nt) ||
+      !dev_get(m.get(), &d.keepN, 20 * nt) || !dev_get(m.get(), &d.keepT, 5 * nt) ||
+      !dev_get(m.get(), &d.cpart, 4 * nt) || !dev_get(m.get(), &d.dt, 1) || !dev_get(m.get(), &d.bmin, nb))
+    return fail(RD_ENOMEM, "device allocation failed");
+  HIPCHK(hipStreamCreate(&m->stream));
+  const hipStream_t s = m->stream;
+  HIPCHK(hipMemcpyAsync(dtet, tsoa.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dslot, slot.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(doff, cnt.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dnrm, nrm.data(), sizeof(double) * 12 * nt, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dvol, vol.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dsmax, smax.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dV, V.data(), sizeof(double) * nv, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(d.W, 0, sizeof(double) * 5 * nv, s));
+  HIPCHK(hipStreamSynchronize(s));
+  d.tet = dtet;
+  d.slot = dslot;
+  d.off = doff;
+  d.nrm = dnrm;
+  d.vol = dvol;
+  d.smax = dsmax;
+  d.V = dV;
+  *out = m.release();
+  return RD_OK;
+}
+
+RD_API rd_status rd3_mesh_destroy(rd3_mesh* mesh) {
+  delete mesh;
+  return RD_OK;
+}
+
+RD_API rd_status rd3_set_state(rd3_mesh* m, const double* W, int on_device) {
+  if (!m || !W) return fail(RD_EINVAL, "null argument");
+  const int64_t nv = m->d.nv;
+  if (!on_device) {
+    for (int64_t i = 0; i < nv; ++i) {
+      const double rho = W[i], e = W[4 * nv + i];
+      const double q = W[nv + i] * W[nv + i] + W[2 * nv + i] * W[2 * nv + i] + W[3 * nv + i] * W[3 * nv + i];
+      if (!(rho > 0.0) || !std::isfinite(e) || !((m->d.gamma - 1.0) * (e - 0.5 * q / rho) > 0.0))
+        return fail(RD_ENONPHYS, "vertex " + std::to_string(i) + ": rho <= 0, p <= 0 or not finite");
+    }
+  }
+  HIPCHK(hipMemcpyAsync(m->d.W, W, sizeof(double) * 5 * nv, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        m->stream));
+  HIPCHK(rd3::launch3_z(m->d, m->d.W, m->stream));
+  if (!on_device) HIPCHK(hipStreamSynchronize(m->stream));
+  return RD_OK;
+}
+
+RD_API rd_status rd3_get_state(rd3_mesh* m, double* W, int on_device) {
+  if (!m || !W) return fail(RD_EINVAL, "null argument");
+  HIPCHK(hipMemcpyAsync(W, m->d.W, sizeof(double) * 5 * m->d.nv,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return RD_OK;
+}
+
+RD_API rd_status rd3_max_dt(rd3_mesh* m, double cfl, double* dt) {
+  if (!m || !dt) return fail(RD_EINVAL, "null argument");
+  if (!(cfl > 0.0)) return fail(RD_EINVAL, "cfl must be positive");
+  HIPCHK(rd3::launch3_cfl(m->d, cfl, m->stream));
+  HIPCHK(hipMemcpyAsync(dt, m->d.dt, sizeof(double), hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return RD_OK;
+}
+
+RD_API rd_status rd3_step(rd3_mesh* m, double dt, int scheme, int time) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  rd_status st = rd3_check_step(scheme, time);
+  if (st != RD_OK) return st;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RD_EINVAL, "dt must be positive");
+  HIPCHK(rd3::launch3_set_dt(m->d, dt, m->stream));
+  return rd3_stages(m, scheme, time, nullptr);
+}
+
+RD_API rd_status rd3_step_cfl(rd3_mesh* m, int n_steps, double cfl, int scheme, int time) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  rd_status st = rd3_check_step(scheme, time);
+  if (st != RD_OK) return st;
+  if (!(cfl > 0.0) || n_steps < 0) return fail(RD_EINVAL, "cfl must be positive and n_steps >= 0");
+  for (int k = 0; k < n_steps; ++k) {
+    HIPCHK(rd3::launch3_cfl(m->d, cfl, m->stream));
+    if ((st = rd3_stages(m, scheme, time, nullptr)) != RD_OK) return st;
+  }
+  return RD_OK;
+}
+
+RD_API rd_status rd3_step_timed(rd3_mesh* m, int n_steps, double cfl, int scheme, int time, double* ms) {
+  if (!m || !ms) return fail(RD_EINVAL, "null argument");
+  rd_status st = rd3_check_step(scheme, time);
+  if (st != RD_OK) return st;
+  if (!(cfl > 0.0) || n_steps < 1) return fail(RD_EINVAL, "cfl must be positive and n_steps >= 1");
+  hipEvent_t ev[6];
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  struct Free {
+    hipEvent_t* e;
+    ~Free() {
+      for (int k = 0; k < 6; ++k) (void)hipEventDestroy(e[k]);
+    }
+  } guard{ev};
+  for (int k = 0; k < 5; ++k) ms[k] = 0.0;
+  for (int n = 0; n < n_steps; ++n) {
+    HIPCHK(hipEventRecord(ev[0], m->stream));
+    HIPCHK(rd3::launch3_cfl(m->d, cfl, m->stream));
+    HIPCHK(hipEventRecord(ev[1], m->stream));
+    if ((st = rd3_stages(m, scheme, time, ev)) != RD_OK) return st;
+    HIPCHK(hipStreamSynchronize(m->stream));
+    const int last = time == RD_RK2 ? 5 : 3;
+    for (int k = 0; k < last; ++k) {
+      float t = 0.0f;
+      HIPCHK(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+      ms[k] += t / n_steps;
+    }
+  }
+  return RD_OK;
+}
+
+RD_API rd_status rd3_sync(rd3_mesh* m) {
+  if (!m) return fail(RD_EINVAL, "null mesh");
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return RD_OK;
+}
+

@@ -40,12 +40,20 @@ class rd_mesh_desc(C.Structure):
                 ("gamma", C.c_double)]
 
 
+class rd3_mesh_desc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("n_tets", C.c_int64),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("tet", C.c_void_p),
+                ("period_x", C.c_double), ("period_y", C.c_double), ("period_z", C.c_double),
+                ("gamma", C.c_double)]
+
+
 EXPORTS = ["rd_mesh_validate", "rd_mesh_create", "rd_mesh_destroy", "rd_mesh_info", "rd_set_stream",
            "rd_set_state", "rd_get_state", "rd_max_dt", "rd_step", "rd_step_cfl", "rd_step_timed", "rd_residual",
            "rd_adjoint_step", "rd_batch_create", "rd_batch_run", "rd_batch_destroy", "rd_sync",
            "rd_last_error", "rd_mesh_set_tile", "rd_mesh_get_tile", "rd_mesh_tile_info", "rd_tune",
            "rd_batch_set_tile", "rd_batch_tune", "rd_mesh_set_lumping", "rd_mesh_get_lumping",
-           "rd_delaunay_flip", "rd_delaunay_refine"]
+           "rd_delaunay_flip", "rd_delaunay_refine", "rd3_mesh_create", "rd3_mesh_destroy", "rd3_set_state",
+           "rd3_get_state", "rd3_max_dt", "rd3_step", "rd3_step_cfl", "rd3_step_timed", "rd3_sync"]
 
 _lib = None
 
@@ -80,6 +88,15 @@ def lib():
             "rd_mesh_set_lumping": [P, I],
             "rd_delaunay_flip": [I64, P, P, D, D, I64, P, P, P],
             "rd_delaunay_refine": [P, P, P, I64, D, D, P, P, I64, D, D, I, I, P, P],
+            "rd3_mesh_create": [P, P],
+            "rd3_mesh_destroy": [P],
+            "rd3_set_state": [P, P, I],
+            "rd3_get_state": [P, P, I],
+            "rd3_max_dt": [P, D, P],
+            "rd3_step": [P, D, I, I],
+            "rd3_step_cfl": [P, I, D, I, I],
+            "rd3_step_timed": [P, I, D, I, I, P],
+            "rd3_sync": [P],
             "rd_mesh_get_lumping": [P, P],
             "rd_mesh_get_tile": [P, P],
             "rd_mesh_tile_info": [P, P],
@@ -437,3 +454,63 @@ def rd_delaunay_refine(mesh: dict, max_radius: float = 0.0, max_ratio: float = 2
     nv, nt = cv.value, ct.value
     return {"x": x[:nv].copy(), "y": y[:nv].copy(), "tri": tri[:nt].copy(), "nv": nv, "nt": nt,
             "px": float(mesh["px"]), "py": float(mesh["py"]), "n_iterations": ni.value, "n_flips": nf.value}
+
+
+class Mesh3:
+    """A tetrahedral mesh on the current GPU (the rd3_* entry points):
+    states are [5, nv] float64 (rho, rho u, rho v, rho w, e)."""
+
+    def __init__(self, mesh: dict):
+        keep = [np.ascontiguousarray(mesh[k], np.float64) for k in ("x", "y", "z")]
+        tet = np.ascontiguousarray(mesh["tet"], np.int32)
+        d = rd3_mesh_desc(int(mesh["nv"]), int(mesh["nt"]), keep[0].ctypes.data, keep[1].ctypes.data,
+                          keep[2].ctypes.data, tet.ctypes.data, float(mesh["px"]), float(mesh["py"]),
+                          float(mesh["pz"]), float(mesh.get("gamma", 1.4)))
+        h = C.c_void_p()
+        _check(lib().rd3_mesh_create(C.byref(d), C.byref(h)))
+        self.h = h
+        self.nv, self.nt = int(mesh["nv"]), int(mesh["nt"])
+
+    def close(self):
+        if self.h:
+            lib().rd3_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, W):
+        dev = not isinstance(W, np.ndarray)
+        if not dev:
+            W = np.ascontiguousarray(W, np.float64)
+            if W.shape != (5, self.nv):
+                raise ValueError("state must be [5, nv]")
+        _check(lib().rd3_set_state(self.h, W.data_ptr() if dev else W.ctypes.data, int(dev)))
+
+    def get_state(self):
+        out = np.zeros((5, self.nv))
+        _check(lib().rd3_get_state(self.h, out.ctypes.data, 0))
+        return out
+
+    def max_dt(self, cfl):
+        dt = C.c_double()
+        _check(lib().rd3_max_dt(self.h, float(cfl), C.byref(dt)))
+        return dt.value
+
+    def step(self, dt, scheme, time):
+        _check(lib().rd3_step(self.h, float(dt), int(scheme), int(time)))
+
+    def step_cfl(self, n, cfl, scheme, time):
+        _check(lib().rd3_step_cfl(self.h, int(n), float(cfl), int(scheme), int(time)))
+
+    def step_timed(self, n, cfl, scheme, time):
+        ms = np.zeros(5)
+        _check(lib().rd3_step_timed(self.h, int(n), float(cfl), int(scheme), int(time), ms.ctypes.data))
+        return ms
+
+    def sync(self):
+        _check(lib().rd3_sync(self.h))
+

@@ -25,7 +25,7 @@ def rd():
 def declared():
     text = open(os.path.join(ROOT, "include", "rd.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rd_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(rd3?_[a-z_]+)\s*\(", text)))
 
 
 def test_exports_match_header(rd):
@@ -138,3 +138,31 @@ def test_refinement_input_checks_run_on_the_host(rd):
         with pytest.raises(rd.RDError, match=msg) as e:
             rd.rd_delaunay_refine(mesh, **args, **kw)
         assert e.value.status == rd.RD_EINVAL
+
+
+def test_3d_mesh_checks_run_on_the_host(rd):
+    """rd3_mesh_create refuses invalid tetrahedral meshes before it touches a
+    device."""
+    import ctypes as C
+    m = I.cube_tets(3, jitter=0.1, seed=1)
+
+    def create(mesh):
+        keep = [np.ascontiguousarray(mesh[k], np.float64) for k in ("x", "y", "z")]
+        tet = np.ascontiguousarray(mesh["tet"], np.int32)
+        d = rd.rd3_mesh_desc(int(mesh["nv"]), int(mesh["nt"]), keep[0].ctypes.data, keep[1].ctypes.data,
+                             keep[2].ctypes.data, tet.ctypes.data, mesh["px"], mesh["py"], mesh["pz"],
+                             mesh.get("gamma", 1.4))
+        h = C.c_void_p()
+        st = rd.lib().rd3_mesh_create(C.byref(d), C.byref(h))
+        return st, rd.lib().rd_last_error().decode()
+
+    flipped = dict(m, tet=m["tet"][:, [0, 2, 1, 3]])
+    assert create(flipped) == (rd.RD_EINVAL, "tetrahedron 0 is not positively oriented")
+    bad = dict(m, tet=np.where(m["tet"] == 5, m["nv"], m["tet"]))
+    st, msg = create(bad)
+    assert st == rd.RD_EINVAL and "out of range" in msg
+    orphan = dict(m, x=np.append(m["x"], 0.5), y=np.append(m["y"], 0.5), z=np.append(m["z"], 0.5), nv=m["nv"] + 1)
+    st, msg = create(orphan)
+    assert st == rd.RD_EINVAL and "belongs to no tetrahedron" in msg
+    st, msg = create(dict(m, gamma=1.0))
+    assert st == rd.RD_EINVAL and "gamma" in msg
