@@ -10,8 +10,9 @@ triangle passes and two vertex gathers). Inputs are resident on the GPU
 before timing starts. Also timed on the same workload: the Bx blend and the
 B scheme with selective lumping (`variants`), the adjoint step against the
 forward step, the GPU Delaunay refinement of a 1.3-million-vertex periodic
-mesh (`mesh_generation`; alone with --meshgen), and (with --batch) many
-meshes in one graph.
+mesh (`mesh_generation`; alone with --meshgen), the three-dimensional path
+on a 128^3-cell box of tetrahedra (`three_d`; alone with --three-d), and
+(with --batch) many meshes in one graph.
 
 Prints one JSON line. `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
@@ -379,6 +380,62 @@ def meshgen(rd, inputs, reps=3):
     return out
 
 
+def three_d(rd, inputs, N=128, steps=10, warmup=2):
+    """The three-dimensional path (F4): Kelvin-Helmholtz shear layer in a
+    periodic box of N^3 cells split into 6 N^3 tetrahedra (Morton order),
+    B scheme, RK2, CFL 0.4 with dt on the device; FP64. Whole-step
+    throughput from the host clock around `steps` steps (inputs resident),
+    per-kernel times from HIP events; the oracle's single-step rate on a
+    16^3 box beside it."""
+    m = inputs.cube_tets(N, renumber="morton")
+    W = inputs.ic3_kelvin_helmholtz(m, seed=0)
+    g = rd.Mesh3(m)
+    g.set_state(W)
+    g.step_cfl(warmup, 0.4, rd.B, rd.RK2)
+    g.sync()
+    t0 = time.perf_counter()
+    g.step_cfl(steps, 0.4, rd.B, rd.RK2)
+    g.sync()
+    el = time.perf_counter() - t0
+    ms = g.step_timed(3, 0.4, rd.B, rd.RK2)
+    g.close()
+    nt, nv = m["nt"], m["nv"]
+    names = ["cfl", "tet1", "gather1", "tet2", "gather2"]
+    # algorithmic bytes per tetrahedron pass. First: corners and slots (32),
+    # normals (96), the parts (160), the kept N parts and residual (200) per
+    # tetrahedron, Z once per vertex (40). Second: the same without the kept
+    # parts written but read (200), the volume (8), and W, W* besides Z per
+    # vertex (120).
+    b_tet1 = nt * (32 + 96 + 160 + 200) + nv * 40
+    b_tet2 = nt * (32 + 96 + 8 + 200 + 160) + nv * 120
+    dom = 1 if ms[1] >= ms[3] else 3
+    b_dom = b_tet1 if dom == 1 else b_tet2
+    ach = b_dom / (ms[dom] * 1e-3)
+    out = {"value": round(nt * steps / el, 1), "unit": "tetrahedron-updates/s", "ms_per_step": round(el * 1e3 / steps, 4),
+           "workload": f"Kelvin-Helmholtz shear layer, {N}^3-cell periodic box, {nt} tetrahedra, {nv} vertices, "
+                       "B scheme, RK2, CFL 0.4 (dt on device), FP64",
+           "kernels_ms": {k: round(v, 4) for k, v in zip(names, ms)},
+           "roofline": {"kernel": names[dom], "bound": "hbm", "achieved": round(ach / 1e9, 1),
+                        "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": round(ach / PEAK_HBM, 4),
+                        "bytes_per_launch": b_dom}}
+    try:
+        sys.path.insert(0, os.path.join(ROOT, "oracle"))
+        import oracle3
+        small = inputs.cube_tets(16, renumber="morton")
+        Ws = inputs.ic3_kelvin_helmholtz(small, seed=0)
+        om = oracle3.OracleMesh3(small)
+        dts = om.max_dt(Ws, 0.4)
+        t0 = time.perf_counter()
+        om.step(Ws, dts, oracle3.B, oracle3.RK2)
+        el1 = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(small["nt"] / el1, 1), "unit": "tetrahedron-updates/s",
+                               "cores": os.cpu_count(), "kind": "oracle",
+                               "sample": f"one FP64 RK2/B step of the 16^3 box ({small['nt']} tetrahedra)"}
+    except Exception as e:  # the oracle is test infrastructure; report its absence
+        out["cpu_baseline"] = {"error": str(e)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +461,9 @@ def main():
     ap.add_argument("--meshgen", action="store_true",
                     help="only time the GPU Delaunay refinement of a 1.3M-vertex periodic mesh (JSON)")
     ap.add_argument("--no-meshgen", action="store_true", help="skip the mesh-generation timing")
+    ap.add_argument("--three-d", action="store_true",
+                    help="only time the three-dimensional path (128^3-cell box of tetrahedra, JSON)")
+    ap.add_argument("--no-three-d", action="store_true", help="skip the three-dimensional timing")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 512 MiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -428,6 +488,9 @@ def main():
         return
     if args.meshgen:
         print(json.dumps({"mesh_generation": meshgen(rd, inputs)}), flush=True)
+        return
+    if args.three_d:
+        print(json.dumps({"three_d": three_d(rd, inputs)}), flush=True)
         return
     mesh = inputs.split_square(args.N, renumber=None if args.renumber == "none" else args.renumber, seed=0)
     W0 = inputs.ic_kelvin_helmholtz(mesh, seed=0)
@@ -508,6 +571,9 @@ def main():
     if not args.no_meshgen:
         print("bench: mesh generation", file=sys.stderr, flush=True)
         result["mesh_generation"] = meshgen(rd, inputs, reps=2)
+    if not args.no_three_d:
+        print("bench: three dimensions", file=sys.stderr, flush=True)
+        result["three_d"] = three_d(rd, inputs)
     if args.batch:
         print(f"bench: batch of {args.batch} meshes", file=sys.stderr, flush=True)
         result["batch"] = batch_vs_single(rd, torch, inputs, args.batch, args.batch_steps, args.cfl, args.tile)

@@ -27,11 +27,16 @@ enum { S_N = 0, S_LDA = 1, S_B = 2, S_BMAX = 3, S_BMIN = 4 };
 
 // Device view of a tetrahedral mesh and its state.
 struct Dev3 {
-  int64_t nv = 0, nt = 0, ns = 0;  // vertices, tetrahedra, corner slots (4 nt)
+  int64_t nv = 0, nt = 0, ns = 0;  // vertices, tetrahedra, slots (4 nt plus slice padding)
   double gamma = 1.4;
   const int32_t* tet = nullptr;    // [4][nt] corners
-  const int32_t* slot = nullptr;   // [4][nt] CSR slot of each corner's part
-  const int32_t* off = nullptr;    // [nv + 1] slots of vertex v: [off[v], off[v+1]), ascending tetrahedron
+  const int32_t* slot = nullptr;   // [4][nt] slot of each corner's part
+  // Slots in sliced-ELL order: vertices in slices of 64; slice q owns
+  // [sbase[q], sbase[q] + 64 w_q) with w_q its largest degree; the j-th
+  // tetrahedron (ascending) of vertex v has slot sbase[v / 64] + 64 j + v % 64,
+  // so a wave summing its 64 vertices reads consecutive slots.
+  const int32_t* deg = nullptr;    // [nv] tetrahedra of vertex v
+  const int32_t* sbase = nullptr;  // [ceil(nv / 64)]
   const double* nrm = nullptr;     // [12][nt] inward face normals scaled by area: component k of corner i at 3 i + k
   const double* vol = nullptr;     // [nt] volume
   const double* smax = nullptr;    // [nt] largest face area

@@ -33,15 +33,16 @@ __global__ __launch_bounds__(kBlock) void k3_gather(Dev3 d) {
   if (v >= d.nv) return;
   const int64_t nv = d.nv;
   double r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int32_t a = d.off[v], b = d.off[v + 1];
-  for (int32_t s = a; s < b; ++s)
-    for (int k = 0; k < 5; ++k) r[k] += d.part[k * d.ns + s];
+  const int64_t first = d.sbase[v >> 6] + (v & 63);
+  const int32_t n = d.deg[v];
+  for (int32_t j = 0; j < n; ++j)
+    for (int k = 0; k < 5; ++k) r[k] += d.part[k * d.ns + first + 64 * j];
   const double f = *d.dt / d.V[v];
-  const double* base = MODE == 2 ? d.Ws : d.W;
+  const double* src = MODE == 2 ? d.Ws : d.W;
   double* dst = MODE == 1 ? d.Ws : d.W;
   double w[5], z[5], sg;
   for (int k = 0; k < 5; ++k) {
-    w[k] = base[k * nv + v] - f * r[k];
+    w[k] = src[k * nv + v] - f * r[k];
     dst[k * nv + v] = w[k];
   }
   to_z(w, d.gamma, z, sg);
@@ -67,7 +68,8 @@ __global__ __launch_bounds__(kBlock) void k3_cfl_vertex(Dev3 d) {
   double best = INFINITY;
   if (v < d.nv) {
     double acc = 0.0;
-    for (int32_t s = d.off[v]; s < d.off[v + 1]; ++s) acc += d.cpart[s];
+    const int64_t base = d.sbase[v >> 6] + (v & 63);
+    for (int32_t j = 0; j < d.deg[v]; ++j) acc += d.cpart[base + 64 * j];
     best = 3.0 * d.V[v] / acc;
   }
   red[threadIdx.x] = best;

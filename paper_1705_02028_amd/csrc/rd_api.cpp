@@ -1615,8 +1615,8 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
 // --------------------------------------------------------- three dimensions --
 //
 // Host side of the tetrahedral path: validation and geometry (face normals,
-// volumes, vertex volumes), the slot order of the vertex sums, buffers and
-// the launch order of a step (kernels in rd3_kernels.hip).
+// volumes, vertex volumes), the sliced-ELL slot order of the vertex sums,
+// buffers and the launch order of a step (kernels in rd3_kernels.hip).
 
 struct rd3_mesh {
   rd3::Dev3 d;
@@ -1732,31 +1732,49 @@ RD_API rd_status rd3_mesh_create(const rd3_mesh_desc* desc, rd3_mesh** out) {
   }
   for (int64_t v = 0; v < nv; ++v)
     if (!(V[v] > 0.0)) return fail(RD_EINVAL, "vertex " + std::to_string(v) + " belongs to no tetrahedron");
-  for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
-  std::vector<int32_t> slot(4 * nt), fill(cnt.begin(), cnt.end() - 1);
+  // sliced-ELL slots: slices of 64 vertices, each as wide as its largest degree
+  const int64_t nslice = (nv + 63) / 64;
+  std::vector<int32_t> deg(nv), sbase(nslice);
+  int64_t ns = 0;
+  for (int64_t q = 0; q < nslice; ++q) {
+    int32_t w = 0;
+    for (int64_t v = 64 * q; v < std::min(nv, 64 * q + 64); ++v) {
+      deg[v] = cnt[v + 1];
+      w = std::max(w, deg[v]);
+    }
+    sbase[q] = (int32_t)ns;
+    ns += 64 * (int64_t)w;
+  }
+  if (ns >= INT32_MAX) return fail(RD_EINVAL, "mesh too large for 32-bit slot indices");
+  std::vector<int32_t> slot(4 * nt), fill(nv, 0);
   for (int64_t t = 0; t < nt; ++t)  // ascending tetrahedron within each vertex
-    for (int i = 0; i < 4; ++i) slot[i * nt + t] = fill[tsoa[i * nt + t]]++;
+    for (int i = 0; i < 4; ++i) {
+      const int32_t v = tsoa[i * nt + t];
+      slot[i * nt + t] = sbase[v / 64] + 64 * fill[v]++ + v % 64;
+    }
   std::unique_ptr<rd3_mesh> m(new rd3_mesh());
   rd3::Dev3& d = m->d;
   d.nv = nv;
   d.nt = nt;
-  d.ns = 4 * nt;
+  d.ns = ns;
   d.gamma = desc->gamma;
-  int32_t *dtet, *dslot, *doff;
+  int32_t *dtet, *dslot, *ddeg, *dsbase;
   double *dnrm, *dvol, *dsmax, *dV;
   const int nb = rd3::cfl_blocks(nv);
-  if (!dev_get(m.get(), &dtet, 4 * nt) || !dev_get(m.get(), &dslot, 4 * nt) || !dev_get(m.get(), &doff, nv + 1) ||
+  if (!dev_get(m.get(), &dtet, 4 * nt) || !dev_get(m.get(), &dslot, 4 * nt) || !dev_get(m.get(), &ddeg, nv) ||
+      !dev_get(m.get(), &dsbase, nslice) ||
       !dev_get(m.get(), &dnrm, 12 * nt) || !dev_get(m.get(), &dvol, nt) || !dev_get(m.get(), &dsmax, nt) ||
       !dev_get(m.get(), &dV, nv) || !dev_get(m.get(), &d.W, 5 * nv) || !dev_get(m.get(), &d.Ws, 5 * nv) ||
-      !dev_get(m.get(), &d.Z, 5 * nv) || !dev_get(m.get(), &d.sig, nv) || !dev_get(m.get(), &d.part, 5 * 4 * nt) ||
+      !dev_get(m.get(), &d.Z, 5 * nv) || !dev_get(m.get(), &d.sig, nv) || !dev_get(m.get(), &d.part, 5 * ns) ||
       !dev_get(m.get(), &d.keepN, 20 * nt) || !dev_get(m.get(), &d.keepT, 5 * nt) ||
-      !dev_get(m.get(), &d.cpart, 4 * nt) || !dev_get(m.get(), &d.dt, 1) || !dev_get(m.get(), &d.bmin, nb))
+      !dev_get(m.get(), &d.cpart, ns) || !dev_get(m.get(), &d.dt, 1) || !dev_get(m.get(), &d.bmin, nb))
     return fail(RD_ENOMEM, "device allocation failed");
   HIPCHK(hipStreamCreate(&m->stream));
   const hipStream_t s = m->stream;
   HIPCHK(hipMemcpyAsync(dtet, tsoa.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dslot, slot.data(), sizeof(int32_t) * 4 * nt, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(doff, cnt.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ddeg, deg.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dsbase, sbase.data(), sizeof(int32_t) * nslice, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dnrm, nrm.data(), sizeof(double) * 12 * nt, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dvol, vol.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dsmax, smax.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
@@ -1765,7 +1783,8 @@ RD_API rd_status rd3_mesh_create(const rd3_mesh_desc* desc, rd3_mesh** out) {
   HIPCHK(hipStreamSynchronize(s));
   d.tet = dtet;
   d.slot = dslot;
-  d.off = doff;
+  d.deg = ddeg;
+  d.sbase = dsbase;
   d.nrm = dnrm;
   d.vol = dvol;
   d.smax = dsmax;
