@@ -44,6 +44,7 @@ struct Dev3 {
   double* W = nullptr;             // [5][nv] state
   double* Ws = nullptr;            // [5][nv] first-stage state
   double* Z = nullptr;             // [5][nv] parameter vector of the state the next tetrahedron pass reads
+  double* rate = nullptr;          // [5][nv] (W* - W^n) / dt, written by the first vertex pass
   double* sig = nullptr;           // [nv] |u| + c of W
   double* part = nullptr;          // [5][ns] distributed parts by slot
   double* keepN = nullptr;         // [20][nt] stage-1 N parts (component k of corner i at 5 i + k)
@@ -94,85 +95,91 @@ __device__ inline double pos(double x) { return x > 0.0 ? x : 0.0; }
 __device__ inline double neg(double x) { return x < 0.0 ? x : 0.0; }
 
 // A x = b for two right-hand sides, Gaussian elimination with partial
-// pivoting; a column whose best pivot is at most 2^-45 max|A| is skipped
-// (its unknowns are 0).
+// pivoting (the largest magnitude among the rows not yet used, first such
+// row on ties); a column whose best pivot is at most 2^-45 max|A| is skipped
+// (its unknowns are 0). Every array index is a compile-time constant (the
+// pivot row is picked with selects and copied into U), so nothing goes to
+// scratch memory.
 __device__ inline void solve5x2(double A[5][5], double b1[5], double b2[5], double x1[5], double x2[5]) {
   double amax = 0.0;
+#pragma unroll
   for (int r = 0; r < 5; ++r)
+#pragma unroll
     for (int q = 0; q < 5; ++q) amax = fmax(amax, fabs(A[r][q]));
   const double tol = ldexp(amax, -45);
-  int used = 0, prow[5];
+  int used = 0;
+  bool skip[5];
+  double U[5][5], c1[5], c2[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     int r = -1;
     double best = -1.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-      if (used & (1 << i)) continue;
       const double a = fabs(A[i][k]);
-      if (a > best) {
+      if (!(used & (1 << i)) && a > best) {
         best = a;
         r = i;
       }
     }
-    prow[k] = -1;
-    if (r < 0 || !(best > tol)) continue;
+    skip[k] = r < 0 || !(best > tol);
+    double pr[5], pb1 = b1[0], pb2 = b2[0];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) pr[j] = A[0][j];
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      const bool sel = r == i;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) pr[j] = sel ? A[i][j] : pr[j];
+      pb1 = sel ? b1[i] : pb1;
+      pb2 = sel ? b2[i] : pb2;
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) U[k][j] = pr[j];
+    c1[k] = pb1;
+    c2[k] = pb2;
+    if (skip[k]) continue;
     used |= 1 << r;
-    prow[k] = r;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       if (used & (1 << i)) continue;
-      const double fct = A[i][k] / A[r][k];
+      const double fct = A[i][k] / pr[k];
 #pragma unroll
-      for (int j = 0; j < 5; ++j)
-        if (j >= k) A[i][j] -= fct * A[r][j];
-      b1[i] -= fct * b1[r];
-      b2[i] -= fct * b2[r];
+      for (int j = k; j < 5; ++j) A[i][j] -= fct * pr[j];
+      b1[i] -= fct * pb1;
+      b2[i] -= fct * pb2;
     }
   }
 #pragma unroll
   for (int k = 4; k >= 0; --k) {
-    if (prow[k] < 0) {
-      x1[k] = 0.0;
-      x2[k] = 0.0;
-      continue;
-    }
-    const int r = prow[k];
-    double s1 = b1[r], s2 = b2[r];
+    double s1 = c1[k], s2 = c2[k];
 #pragma unroll
-    for (int j = 0; j < 5; ++j)
-      if (j > k) {
-        s1 -= A[r][j] * x1[j];
-        s2 -= A[r][j] * x2[j];
-      }
-    x1[k] = s1 / A[r][k];
-    x2[k] = s2 / A[r][k];
+    for (int j = k + 1; j < 5; ++j) {
+      s1 -= U[k][j] * x1[j];
+      s2 -= U[k][j] * x2[j];
+    }
+    x1[k] = skip[k] ? 0.0 : s1 / U[k][k];
+    x2[k] = skip[k] ? 0.0 : s2 / U[k][k];
   }
 }
 
-// Blend of the B family (and N, LDA) of parts pn, pl splitting `res`.
-__device__ inline void blend(int scheme, const double res[5], const double pn[4][5], const double pl[4][5],
-                             double out[4][5]) {
-  double th[5];
-  if (scheme == S_N || scheme == S_LDA) {
-    for (int k = 0; k < 5; ++k) th[k] = scheme == S_N ? 1.0 : 0.0;
-  } else {
-    for (int k = 0; k < 5; ++k) {
-      const double den = fabs(pn[0][k]) + fabs(pn[1][k]) + fabs(pn[2][k]) + fabs(pn[3][k]);
-      const double q = den == 0.0 ? 0.0 : fabs(res[k]) / den;
-      th[k] = q > 1.0 ? 1.0 : q;
-    }
-    if (scheme == S_BMAX || scheme == S_BMIN) {
-      int pick = 0;
-      for (int k = 1; k < 5; ++k)
-        if (scheme == S_BMAX ? th[k] > th[pick] : th[k] < th[pick]) pick = k;
-      const double t = th[pick];
-      for (int k = 0; k < 5; ++k) th[k] = t;
-    }
+// Blend coefficients of the B family from the residual `res` and the N
+// parts pn: Theta_k = min(1, |res_k| / sum_i |pn_ik|) (0 for a zero sum),
+// one common value for Bmax / Bmin; unused by N and LDA.
+__device__ inline void blend_theta(int scheme, const double res[5], const double pn[4][5], double th[5]) {
+  for (int k = 0; k < 5; ++k) {
+    const double den = fabs(pn[0][k]) + fabs(pn[1][k]) + fabs(pn[2][k]) + fabs(pn[3][k]);
+    const double q = den == 0.0 ? 0.0 : fabs(res[k]) / den;
+    th[k] = q > 1.0 ? 1.0 : q;
   }
-  for (int i = 0; i < 4; ++i)
-    for (int k = 0; k < 5; ++k)
-      out[i][k] = scheme == S_N ? pn[i][k] : scheme == S_LDA ? pl[i][k] : pl[i][k] + th[k] * (pn[i][k] - pl[i][k]);
+  if (scheme == S_BMAX || scheme == S_BMIN) {
+    int pick = 0;
+    for (int k = 1; k < 5; ++k)
+      if (scheme == S_BMAX ? th[k] > th[pick] : th[k] < th[pick]) pick = k;
+    double t = th[0];
+    for (int k = 1; k < 5; ++k) t = pick == k ? th[k] : t;
+    for (int k = 0; k < 5; ++k) th[k] = t;
+  }
 }
 
 // One tetrahedron: stage 1 (or Euler) at the Z in d.Z; stage 2 adds the
@@ -258,47 +265,53 @@ __device__ inline void tet_body(const Dev3& d, int64_t t, int scheme, bool keep)
       for (int q = 0; q < 5; ++q) A[r][q] += f.r0[r] * a[q] + s[r] * b[q];
     }
   }
-  double rhsT[5], PN[4][5], PT[5];
+  double PT[5];
   if (STAGE == 1) {
     for (int k = 0; k < 5; ++k) PT[k] = phiT[k];
   } else {
-    // stage 2: mass |T| / 4 times the first-stage rate, plus the mean of the
-    // kept and the current parts
-    const double idt = 1.0 / *d.dt, mass = 0.25 * d.vol[t];
+    // stage 2: the mass |T| / 4 times the first-stage rate, plus the mean of
+    // the kept and the current residual
+    const double mass = 0.25 * d.vol[t];
     double rate_sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = 0; i < 4; ++i)
-      for (int k = 0; k < 5; ++k) {
-        const double r = (d.Ws[k * nv + vid[i]] - d.W[k * nv + vid[i]]) * idt;
-        PN[i][k] = mass * r;  // completed below with the N parts
-        rate_sum[k] += r;
-      }
+      for (int k = 0; k < 5; ++k) rate_sum[k] += d.rate[k * nv + vid[i]];
     for (int k = 0; k < 5; ++k) PT[k] = mass * rate_sum[k] + 0.5 * (d.keepT[k * nt + t] + phiT[k]);
   }
+  double rhsT[5];
   for (int k = 0; k < 5; ++k) rhsT[k] = PT[k];
   double xN[5], xT[5];
   solve5x2(A, bN, rhsT, xN, xT);
-  double pn[4][5], pl[4][5];
+  // N parts of every corner (the blend needs all of them), then each
+  // corner's LDA part and output
+  double pn[4][5];
   for (int i = 0; i < 4; ++i) {
     const double un = cn[i].un;
-    const double l1 = pos(un + f.c), l2 = pos(un - f.c), l3 = pos(un);
     double y[5];
-    for (int k = 0; k < 5; ++k) y[k] = dW[i][k] + xN[k];
-    kapply(f, cn[i], l1, l2, l3, y, pn[i]);
-    kapply(f, cn[i], l1, l2, l3, xT, pl[i]);
+    for (int k = 0; k < 5; ++k) y[k] = (i == 0 ? 0.0 : dW[i][k]) + xN[k];
+    kapply(f, cn[i], pos(un + f.c), pos(un - f.c), pos(un), y, pn[i]);
   }
   if (STAGE == 1 && keep) {
     for (int i = 0; i < 4; ++i)
       for (int k = 0; k < 5; ++k) d.keepN[(5 * i + k) * nt + t] = pn[i][k];
     for (int k = 0; k < 5; ++k) d.keepT[k * nt + t] = phiT[k];
   }
-  if (STAGE == 2)
+  if (STAGE == 2) {
+    const double mass = 0.25 * d.vol[t];
     for (int i = 0; i < 4; ++i)
-      for (int k = 0; k < 5; ++k) pn[i][k] = PN[i][k] + 0.5 * (d.keepN[(5 * i + k) * nt + t] + pn[i][k]);
-  double out[4][5];
-  blend(scheme, PT, pn, pl, out);
+      for (int k = 0; k < 5; ++k)
+        pn[i][k] = mass * d.rate[k * nv + vid[i]] + 0.5 * (d.keepN[(5 * i + k) * nt + t] + pn[i][k]);
+  }
+  double th[5];
+  blend_theta(scheme, PT, pn, th);
   for (int i = 0; i < 4; ++i) {
+    const double un = cn[i].un;
+    double pl[5];
+    kapply(f, cn[i], pos(un + f.c), pos(un - f.c), pos(un), xT, pl);
     const int64_t sl = d.slot[i * nt + t];
-    for (int k = 0; k < 5; ++k) d.part[k * d.ns + sl] = out[i][k];
+    for (int k = 0; k < 5; ++k) {
+      const double o = scheme == S_N ? pn[i][k] : scheme == S_LDA ? pl[k] : pl[k] + th[k] * (pn[i][k] - pl[k]);
+      d.part[k * d.ns + sl] = o;
+    }
   }
 }
 

@@ -18,8 +18,10 @@ __global__ __launch_bounds__(kBlock) void k3_z(Dev3 d, const double* src) {
   d.sig[v] = sg;
 }
 
+// At most 256 registers per lane (two waves per SIMD): the second stage's
+// extra terms would otherwise take it just past that, to one wave.
 template <int STAGE>
-__global__ __launch_bounds__(kBlock) void k3_tet(Dev3 d, int scheme, int keep) {
+__global__ __launch_bounds__(kBlock, 2) void k3_tet(Dev3 d, int scheme, int keep) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t < d.nt) tet_body<STAGE>(d, t, scheme, keep != 0);
 }
@@ -41,9 +43,12 @@ __global__ __launch_bounds__(kBlock) void k3_gather(Dev3 d) {
   const double* src = MODE == 2 ? d.Ws : d.W;
   double* dst = MODE == 1 ? d.Ws : d.W;
   double w[5], z[5], sg;
+  const double idt = 1.0 / *d.dt;
   for (int k = 0; k < 5; ++k) {
-    w[k] = src[k * nv + v] - f * r[k];
+    const double old = src[k * nv + v];
+    w[k] = old - f * r[k];
     dst[k * nv + v] = w[k];
+    if (MODE == 1) d.rate[k * nv + v] = (w[k] - old) * idt;  // read by the second tetrahedron pass
   }
   to_z(w, d.gamma, z, sg);
   for (int k = 0; k < 5; ++k) d.Z[k * nv + v] = z[k];
