@@ -350,6 +350,9 @@ rd_status rd3_step_cfl(rd3_mesh* mesh, int n_steps, double cfl, int scheme, int 
  * limit, the first tetrahedron pass, the first vertex pass, the second
  * tetrahedron pass and the second vertex pass (0 for Euler). Waits. */
 rd_status rd3_step_timed(rd3_mesh* mesh, int n_steps, double cfl, int scheme, int time, double* ms);
+/* Waits for the mesh's stream. RD_ENONPHYS if a state with rho <= 0, p <= 0
+ * or a non-finite value was produced since the last rd3_set_state (the
+ * latch stays set), RD_EDEVICE on a runtime error. */
 rd_status rd3_sync(rd3_mesh* mesh);
 
 /* Message for the last non-OK status returned on this thread. */

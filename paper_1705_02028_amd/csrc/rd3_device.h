@@ -52,9 +52,12 @@ struct Dev3 {
   double* cpart = nullptr;         // [ns] CFL parts by slot
   double* dt = nullptr;            // device scalar: the step's time step
   double* bmin = nullptr;          // [blocks] partial minima of the CFL limit
+  int* flag = nullptr;             // non-physical state latch (rho <= 0, p <= 0 or not finite)
 };
 
-__device__ inline void to_z(const double w[5], double gamma, double z[5], double& sig) {
+// Z and |u| + c of a state; returns whether it is physical (rho > 0, p > 0,
+// finite).
+__device__ inline bool to_z(const double w[5], double gamma, double z[5], double& sig) {
   const double rho = w[0], iu = 1.0 / rho;
   const double u = w[1] * iu, v = w[2] * iu, ww = w[3] * iu;
   const double q2 = u * u + v * v + ww * ww;
@@ -66,6 +69,7 @@ __device__ inline void to_z(const double w[5], double gamma, double z[5], double
   z[3] = s * ww;
   z[4] = s * (w[4] + p) * iu;
   sig = sqrt(q2) + sqrt(gamma * p * iu);
+  return rho > 0.0 && p > 0.0 && isfinite(sig) && isfinite(z[4]) && isfinite(z[1] + z[2] + z[3]);
 }
 
 // Rank-two application y = scale * K(l1, l2, l3) x at one corner.

@@ -13,7 +13,7 @@ __global__ __launch_bounds__(kBlock) void k3_z(Dev3 d, const double* src) {
   if (v >= d.nv) return;
   double w[5], z[5], sg;
   for (int k = 0; k < 5; ++k) w[k] = src[k * d.nv + v];
-  to_z(w, d.gamma, z, sg);
+  if (!to_z(w, d.gamma, z, sg)) d.flag[0] = 1;
   for (int k = 0; k < 5; ++k) d.Z[k * d.nv + v] = z[k];
   d.sig[v] = sg;
 }
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k3_gather(Dev3 d) {
     dst[k * nv + v] = w[k];
     if (MODE == 1) d.rate[k * nv + v] = (w[k] - old) * idt;  // read by the second tetrahedron pass
   }
-  to_z(w, d.gamma, z, sg);
+  if (!to_z(w, d.gamma, z, sg)) d.flag[0] = 1;
   for (int k = 0; k < 5; ++k) d.Z[k * nv + v] = z[k];
   if (MODE != 1) d.sig[v] = sg;
 }

@@ -1767,7 +1767,8 @@ RD_API rd_status rd3_mesh_create(const rd3_mesh_desc* desc, rd3_mesh** out) {
       !dev_get(m.get(), &dV, nv) || !dev_get(m.get(), &d.W, 5 * nv) || !dev_get(m.get(), &d.Ws, 5 * nv) ||
       !dev_get(m.get(), &d.Z, 5 * nv) || !dev_get(m.get(), &d.rate, 5 * nv) || !dev_get(m.get(), &d.sig, nv) || !dev_get(m.get(), &d.part, 5 * ns) ||
       !dev_get(m.get(), &d.keepN, 20 * nt) || !dev_get(m.get(), &d.keepT, 5 * nt) ||
-      !dev_get(m.get(), &d.cpart, ns) || !dev_get(m.get(), &d.dt, 1) || !dev_get(m.get(), &d.bmin, nb))
+      !dev_get(m.get(), &d.cpart, ns) || !dev_get(m.get(), &d.dt, 1) || !dev_get(m.get(), &d.bmin, nb) ||
+      !dev_get(m.get(), &d.flag, 1))
     return fail(RD_ENOMEM, "device allocation failed");
   HIPCHK(hipStreamCreate(&m->stream));
   const hipStream_t s = m->stream;
@@ -1780,6 +1781,7 @@ RD_API rd_status rd3_mesh_create(const rd3_mesh_desc* desc, rd3_mesh** out) {
   HIPCHK(hipMemcpyAsync(dsmax, smax.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dV, V.data(), sizeof(double) * nv, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(d.W, 0, sizeof(double) * 5 * nv, s));
+  HIPCHK(hipMemsetAsync(d.flag, 0, sizeof(int), s));
   HIPCHK(hipStreamSynchronize(s));
   d.tet = dtet;
   d.slot = dslot;
@@ -1811,6 +1813,7 @@ RD_API rd_status rd3_set_state(rd3_mesh* m, const double* W, int on_device) {
   }
   HIPCHK(hipMemcpyAsync(m->d.W, W, sizeof(double) * 5 * nv, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                         m->stream));
+  HIPCHK(hipMemsetAsync(m->d.flag, 0, sizeof(int), m->stream));
   HIPCHK(rd3::launch3_z(m->d, m->d.W, m->stream));
   if (!on_device) HIPCHK(hipStreamSynchronize(m->stream));
   return RD_OK;
@@ -1886,7 +1889,10 @@ RD_API rd_status rd3_step_timed(rd3_mesh* m, int n_steps, double cfl, int scheme
 
 RD_API rd_status rd3_sync(rd3_mesh* m) {
   if (!m) return fail(RD_EINVAL, "null mesh");
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, m->d.flag, sizeof(int), hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
+  if (flag) return fail(RD_ENONPHYS, "a non-physical state was produced");
   return RD_OK;
 }
 

@@ -134,3 +134,23 @@ def test_fluid_at_rest_singular_sum(rd, O):
             e = rel_err(g.get_state(), om.step(W, dt, s, time))
             assert e <= 1e-12, (name, time, e)
     g.close()
+
+
+def test_nonphysical_latch(rd):
+    """A time step far beyond the CFL limit drives the density negative
+    somewhere: rd3_sync reports RD_ENONPHYS until the next rd3_set_state."""
+    m = I.cube_tets(6, jitter=0.2, seed=12)
+    W = I.ic3_kelvin_helmholtz(m, seed=13)
+    g = rd.Mesh3(m)
+    g.set_state(W)
+    dt = g.max_dt(0.4)
+    g.step(dt, rd.B, rd.RK2)
+    g.sync()  # a normal step is fine
+    for _ in range(3):
+        g.step(200 * dt, rd.N, rd.EULER1)
+    with pytest.raises(rd.RDError) as e:
+        g.sync()
+    assert e.value.status == rd.RD_ENONPHYS
+    g.set_state(W)
+    g.sync()
+    g.close()
