@@ -244,8 +244,9 @@ rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y,
  * is a segment that must stay covered by edges; it must be axis-aligned (the
  * domain is a rectangle, or periodic on one or both axes; coordinates on a
  * periodic axis in [0, period)). The mesh is first made Delaunay by flips;
- * then each iteration: every triangle with circumradius r > max_radius
- * (0: no bound) or r / (shortest edge) > max_ratio (0: no bound, else >= 1;
+ * then each iteration: every triangle with circumradius r > max_radius s(c)
+ * (0: no bound; c its centroid, s the size field below, 1 without one) or
+ * r / (shortest edge) > max_ratio (0: no bound, else >= 1;
  * termination is guaranteed for max_ratio >= sqrt 2) proposes its
  * circumcentre, and every triangle whose boundary edge it encroaches on (its
  * opposite corner inside the edge's diametric circle) proposes that edge's
@@ -262,9 +263,14 @@ rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y,
  * the period on a periodic axis, else over the input's extent, x in the even
  * bits, and elements are ordered by the top 32 bits of the key; a
  * triangle's key is its centroid's; stable order for equal keys). Stops when
- * no triangle proposes a point. With morton = 0 original vertices keep their
- * indices and new vertices and triangles are appended. On return *n_vertices, *n_triangles, x, y, tri describe the
- * refined mesh; n_iterations (insertion iterations) and n_flips may be NULL.
+ * no triangle proposes a point. Size field (Section 2: the size bound may vary in
+ * space): size_grid [grid_ny][grid_nx] host, positive scale factors at the
+ * nodes of a grid over the domain (a periodic axis: grid_n nodes at spacing
+ * period / grid_n from 0, wrapping; a bounded axis: grid_n nodes spanning the
+ * input's extent), interpolated bilinearly; NULL for s = 1. With
+ * morton = 0 original vertices keep their indices and new vertices and
+ * triangles are appended. On return *n_vertices, *n_triangles, x, y, tri
+ * describe the refined mesh; n_iterations (insertion iterations) and n_flips may be NULL.
  * The result does not depend on scheduling. RD_EINVAL for invalid input,
  * capacities or bounds, and (with the mesh reached so far returned) when
  * more than max_iterations iterations would be needed; RD_ENOMEM when the
@@ -277,8 +283,9 @@ rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const double* y,
  * of its own and waits for it. */
 rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, int64_t max_vertices, double period_x,
                              double period_y, int64_t* n_triangles, int32_t* tri, int64_t max_triangles,
-                             double max_radius, double max_ratio, int32_t max_iterations, int32_t morton,
-                             int32_t* n_iterations, int64_t* n_flips);
+                             double max_radius, double max_ratio, const double* size_grid, int32_t grid_nx,
+                             int32_t grid_ny, int32_t max_iterations, int32_t morton, int32_t* n_iterations,
+                             int64_t* n_flips);
 
 /* Many independent meshes advanced together. The batch keeps its own copy of
  * the meshes' geometry and its own HIP stream (a null stream cannot be

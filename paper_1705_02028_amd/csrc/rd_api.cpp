@@ -1456,6 +1456,7 @@ RD_API rd_status rd_delaunay_flip(int64_t n_vertices, const double* x, const dou
 RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, int64_t max_vertices,
                                     double period_x, double period_y, int64_t* n_triangles, int32_t* tri,
                                     int64_t max_triangles, double max_radius, double max_ratio,
+                                    const double* size_grid, int32_t grid_nx, int32_t grid_ny,
                                     int32_t max_iterations, int32_t morton, int32_t* n_iterations,
                                     int64_t* n_flips) {
   if (!n_vertices || !n_triangles) return fail(RD_EINVAL, "null count pointer");
@@ -1468,6 +1469,13 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
     return fail(RD_EINVAL, "max_ratio must be 0 (no bound) or >= 1");
   if (max_iterations < 1) return fail(RD_EINVAL, "max_iterations must be >= 1");
   if (morton != 0 && morton != 1) return fail(RD_EINVAL, "morton must be 0 or 1");
+  if (size_grid) {
+    if (grid_nx < 1 || grid_ny < 1 || (int64_t)grid_nx * grid_ny > (1 << 26))
+      return fail(RD_EINVAL, "size grid dimensions must be >= 1 (at most 2^26 nodes)");
+    for (int64_t k = 0; k < (int64_t)grid_nx * grid_ny; ++k)
+      if (!(size_grid[k] > 0.0) || !std::isfinite(size_grid[k]))
+        return fail(RD_EINVAL, "size grid values must be positive and finite");
+  }
   rd_mesh_desc desc{};
   desc.n_vertices = nv0;
   desc.n_triangles = nt0;
@@ -1508,6 +1516,28 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
       !b.get(&r.tnew, ts) || !b.get(&r.tpos, ts) || !b.get(&r.split, ts) || !b.get(&r.child, 2 * ts) ||
       !b.get(&r.count, 3))
     return fail(RD_ENOMEM, "device allocation failed");
+  if (size_grid) {
+    // grid frame: the period on a periodic axis (nodes wrap), else the input's extent
+    auto frame = [&](const double* c, double period, int32_t n, double& g0, double& gd) {
+      double lo = c[0], hi = c[0];
+      for (int64_t v = 1; v < nv0; ++v) {
+        lo = std::min(lo, c[v]);
+        hi = std::max(hi, c[v]);
+      }
+      g0 = period > 0.0 ? 0.0 : lo;
+      gd = period > 0.0 ? period / n : (n > 1 ? (hi - lo) / (n - 1) : 1.0);
+    };
+    frame(x, period_x, grid_nx, r.gx0, r.gdx);
+    frame(y, period_y, grid_ny, r.gy0, r.gdy);
+    double* g = nullptr;
+    const int64_t ng = (int64_t)grid_nx * grid_ny;
+    if (!b.get(&g, ng)) return fail(RD_ENOMEM, "device allocation failed");
+    if (hipMemcpy(g, size_grid, sizeof(double) * ng, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(RD_EDEVICE, "upload failed");
+    r.sgrid = g;
+    r.gnx = grid_nx;
+    r.gny = grid_ny;
+  }
   const size_t scan_bytes = rd::dl::scan_tmp_bytes(ts);
   char* scan_tmp = nullptr;
   if (!b.get(&scan_tmp, scan_bytes)) return fail(RD_ENOMEM, "device allocation failed");

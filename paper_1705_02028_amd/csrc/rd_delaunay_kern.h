@@ -76,6 +76,13 @@ struct Refine {
   int64_t nv = 0;                // vertices in use
   double r2 = 0.0;               // size bound R^2 on the circumradius (0: none)
   double b2 = 0.0;               // quality bound B^2 on (circumradius / shortest edge)^2 (0: none)
+  // Size field (Section 2: the size bound may vary in space): R(x) = R s(x)
+  // with s bilinear on a gnx x gny grid of node values; a periodic axis has
+  // gn nodes at spacing period / gn (wrapping), a bounded one gn nodes from
+  // g0 at spacing gd. sgrid null: s = 1.
+  const double* sgrid = nullptr;  // [gny][gnx]
+  int32_t gnx = 0, gny = 0;
+  double gx0 = 0.0, gy0 = 0.0, gdx = 0.0, gdy = 0.0;
   uint32_t seed = 0;             // mixes the iteration into the priorities
   unsigned long long* prio = nullptr;  // [ts] priority of t's candidate (0: none)
   double* px = nullptr;          // [ts] candidate point (stored coordinates)
@@ -331,13 +338,50 @@ DL_FN void candidate_reset(const Refine& r, int64_t t) {
   r.tnew[t] = 0;
 }
 
+// One axis of the size grid: node index i0, its neighbour i1 and the weight
+// of i1 for coordinate v.
+DL_FN void grid_axis(double v, double v0, double dv, int32_t n, double period, int32_t& i0, int32_t& i1, double& w) {
+#pragma clang fp contract(off)
+  double q = (v - v0) / dv;
+  if (period > 0.0) {
+    double fl = floor(q);
+    w = q - fl;
+    int64_t k = (int64_t)fl % n;
+    if (k < 0) k += n;
+    i0 = (int32_t)k;
+    i1 = (int32_t)((k + 1) % n);
+    return;
+  }
+  if (q < 0.0) q = 0.0;
+  if (q > (double)(n - 1)) q = (double)(n - 1);
+  double fl = floor(q);
+  if (fl > (double)(n - 2)) fl = (double)(n - 2);
+  if (fl < 0.0) fl = 0.0;
+  i0 = (int32_t)fl;
+  i1 = n > 1 ? i0 + 1 : i0;
+  w = n > 1 ? q - fl : 0.0;
+}
+
+// s(x, y) of the size field (1 without a grid).
+DL_FN double size_scale(const Mesh& m, const Refine& r, double x, double y) {
+#pragma clang fp contract(off)
+  if (!r.sgrid) return 1.0;
+  int32_t x0, x1, y0, y1;
+  double wx, wy;
+  grid_axis(x, r.gx0, r.gdx, r.gnx, m.px, x0, x1, wx);
+  grid_axis(y, r.gy0, r.gdy, r.gny, m.py, y0, y1, wy);
+  const double a = r.sgrid[y0 * r.gnx + x0] * (1.0 - wx) + r.sgrid[y0 * r.gnx + x1] * wx;
+  const double b = r.sgrid[y1 * r.gnx + x0] * (1.0 - wx) + r.sgrid[y1 * r.gnx + x1] * wx;
+  return a * (1.0 - wy) + b * wy;
+}
+
 // Result of quality_body.
 constexpr int kNone = 0, kCandidate = 1, kTooFar = 2;
 
 // Does t need a new vertex: a boundary edge it encroaches (its opposite
 // corner inside the edge's diametric circle: the edge is split at its
-// midpoint), or a circumradius r > R, or r / (shortest edge) > B (a vertex at
-// the circumcentre). The circumradius is l_a l_b l_c / (2 |det|) with det the
+// midpoint), or a circumradius r > R s(centroid), or r / (shortest edge) > B
+// (a vertex at the circumcentre). The circumradius is l_a l_b l_c / (2 |det|) with det the
 // orientation determinant.
 DL_FN int quality_body(const Mesh& m, const Refine& r, int64_t t) {
 #pragma clang fp contract(off)
@@ -367,7 +411,13 @@ DL_FN int quality_body(const Mesh& m, const Refine& r, int64_t t) {
   const double rad2 = la2 * lb2 * lc2 / (4.0 * det * det);
   double lmin2 = la2 < lb2 ? la2 : lb2;
   lmin2 = lmin2 < lc2 ? lmin2 : lc2;
-  const bool bad = (r.r2 > 0.0 && rad2 > r.r2) || (r.b2 > 0.0 && rad2 > r.b2 * lmin2);
+  double rb2 = r.r2;
+  if (r.sgrid && rb2 > 0.0) {  // the size field at the centroid
+    const double sc = size_scale(m, r, wrap((v[0][0] + v[1][0] + v[2][0]) / 3.0, m.px),
+                                 wrap((v[0][1] + v[1][1] + v[2][1]) / 3.0, m.py));
+    rb2 = rb2 * (sc * sc);
+  }
+  const bool bad = (rb2 > 0.0 && rad2 > rb2) || (r.b2 > 0.0 && rad2 > r.b2 * lmin2);
   if (!bad) return kNone;
   // circumcentre, relative to corner 0
   const double ux = (cy * lc2 - by * lb2) / (2.0 * det);

@@ -87,7 +87,7 @@ def lib():
             "rd_mesh_set_tile": [P, I],
             "rd_mesh_set_lumping": [P, I],
             "rd_delaunay_flip": [I64, P, P, D, D, I64, P, P, P],
-            "rd_delaunay_refine": [P, P, P, I64, D, D, P, P, I64, D, D, I, I, P, P],
+            "rd_delaunay_refine": [P, P, P, I64, D, D, P, P, I64, D, D, P, I, I, I, I, P, P],
             "rd3_mesh_create": [P, P],
             "rd3_mesh_destroy": [P],
             "rd3_set_state": [P, P, I],
@@ -421,11 +421,13 @@ class Batch:
 
 def rd_delaunay_refine(mesh: dict, max_radius: float = 0.0, max_ratio: float = 2 ** 0.5,
                        max_vertices: int | None = None, max_triangles: int | None = None,
-                       max_iterations: int = 1000, morton: bool = False):
+                       max_iterations: int = 1000, morton: bool = False, size_grid=None):
     """Delaunay refinement of a triangulation on the GPU (rd_delaunay_refine):
     returns a new mesh dict (x, y, tri, nv, nt, px, py) with the iteration and
     flip counts (n_iterations, n_flips); with morton, vertices and triangles
-    are renumbered in Morton order after every iteration. Default capacities:
+    are renumbered in Morton order as the mesh grows; size_grid ([ny, nx]
+    positive scale factors) makes the size bound max_radius * s(x) with s
+    bilinear on that grid over the domain. Default capacities:
     room for triangles of circumradius down to max_radius / 3 over the
     domain's area, or 64 times the input when max_radius is 0."""
     nv, nt = int(mesh["nv"]), int(mesh["nt"])
@@ -447,10 +449,13 @@ def rd_delaunay_refine(mesh: dict, max_radius: float = 0.0, max_ratio: float = 2
     tri[:nt] = mesh["tri"]
     cv, ct = C.c_int64(nv), C.c_int64(nt)
     ni, nf = C.c_int32(), C.c_int64()
+    grid = None if size_grid is None else np.ascontiguousarray(size_grid, np.float64)
+    gny, gnx = (0, 0) if grid is None else grid.shape
     _check(lib().rd_delaunay_refine(C.byref(cv), x.ctypes.data, y.ctypes.data, int(max_vertices),
                                     float(mesh["px"]), float(mesh["py"]), C.byref(ct), tri.ctypes.data,
-                                    int(max_triangles), float(max_radius), float(max_ratio), int(max_iterations),
-                                    int(bool(morton)), C.byref(ni), C.byref(nf)))
+                                    int(max_triangles), float(max_radius), float(max_ratio),
+                                    None if grid is None else grid.ctypes.data, int(gnx), int(gny),
+                                    int(max_iterations), int(bool(morton)), C.byref(ni), C.byref(nf)))
     nv, nt = cv.value, ct.value
     return {"x": x[:nv].copy(), "y": y[:nv].copy(), "tri": tri[:nt].copy(), "nv": nv, "nt": nt,
             "px": float(mesh["px"]), "py": float(mesh["py"]), "n_iterations": ni.value, "n_flips": nf.value}

@@ -170,8 +170,9 @@ int rdl_flip(int64_t nv, const double* x, const double* y, double px, double py,
 // 0 done, 1 iteration limit, 2 capacity, 5 no insertable candidate or a
 // circumcentre too far on a periodic axis, 3 flips stuck).
 int rdl_refine(int64_t* n_vertices, double* x, double* y, int64_t max_v, double px, double py, int64_t* n_triangles,
-               int32_t* tri, int64_t max_t, double max_radius, double max_ratio, int32_t max_iterations,
-               int32_t morton, int32_t* n_iterations, int64_t* n_flips) {
+               int32_t* tri, int64_t max_t, double max_radius, double max_ratio, const double* size_grid,
+               int32_t grid_nx, int32_t grid_ny, int32_t max_iterations, int32_t morton, int32_t* n_iterations,
+               int64_t* n_flips) {
   Host h;
   const int64_t ts = max_t;
   int64_t nv = *n_vertices, nt = *n_triangles;
@@ -205,6 +206,22 @@ int rdl_refine(int64_t* n_vertices, double* x, double* y, int64_t max_v, double 
   r.split = h.split.data();
   r.child = h.child.data();
   r.count = h.rcount.data();
+  if (size_grid) {  // the library's grid frame
+    auto frame = [&](const double* c, double period, int32_t n, double& g0, double& gd) {
+      double lo = c[0], hi = c[0];
+      for (int64_t v = 1; v < nv; ++v) {
+        lo = std::min(lo, c[v]);
+        hi = std::max(hi, c[v]);
+      }
+      g0 = period > 0.0 ? 0.0 : lo;
+      gd = period > 0.0 ? period / n : (n > 1 ? (hi - lo) / (n - 1) : 1.0);
+    };
+    frame(x, px, grid_nx, r.gx0, r.gdx);
+    frame(y, py, grid_ny, r.gy0, r.gdy);
+    r.sgrid = size_grid;
+    r.gnx = grid_nx;
+    r.gny = grid_ny;
+  }
   Reorder q;
   if (morton) {
     auto frame = [&](const double* c, double period, double& c0, double& sc) {

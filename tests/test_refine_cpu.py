@@ -32,7 +32,7 @@ def build_shim():
     L = C.CDLL(out)
     P = C.c_void_p
     L.rdl_refine.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_double, P, P, C.c_int64, C.c_double,
-                             C.c_double, C.c_int32, C.c_int32, P, P]
+                             C.c_double, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P]
     L.rdl_refine.restype = C.c_int
     L.rdl_flip.argtypes = [C.c_int64, P, P, C.c_double, C.c_double, C.c_int64, P, P, P]
     L.rdl_flip.restype = C.c_int
@@ -50,7 +50,7 @@ def D():
     return delaunay
 
 
-def host_refine(S, m, R, B, max_vertices=20000, max_iterations=1000, morton=False):
+def host_refine(S, m, R, B, max_vertices=20000, max_iterations=1000, morton=False, size_grid=None):
     """rdl_refine (sequential run of the library's bodies): (status, mesh)."""
     nv, nt = int(m["nv"]), int(m["nt"])
     max_t = 2 * max_vertices + nt
@@ -59,9 +59,11 @@ def host_refine(S, m, R, B, max_vertices=20000, max_iterations=1000, morton=Fals
     tri = np.zeros((max_t, 3), dtype=np.int32)
     tri[:nt] = m["tri"]
     cv, ct, ni, nf = C.c_int64(nv), C.c_int64(nt), C.c_int32(), C.c_int64()
+    grid = None if size_grid is None else np.ascontiguousarray(size_grid, np.float64)
+    gny, gnx = (0, 0) if grid is None else grid.shape
     st = S.rdl_refine(C.byref(cv), x.ctypes.data, y.ctypes.data, max_vertices, float(m["px"]), float(m["py"]),
-                      C.byref(ct), tri.ctypes.data, max_t, R, B, max_iterations, int(morton), C.byref(ni),
-                      C.byref(nf))
+                      C.byref(ct), tri.ctypes.data, max_t, R, B, None if grid is None else grid.ctypes.data,
+                      gnx, gny, max_iterations, int(morton), C.byref(ni), C.byref(nf))
     nv, nt = cv.value, ct.value
     return st, {"x": x[:nv].copy(), "y": y[:nv].copy(), "tri": tri[:nt].copy(), "nv": nv, "nt": nt,
                 "px": m["px"], "py": m["py"], "n_iterations": ni.value, "n_flips": nf.value}
@@ -225,3 +227,84 @@ def test_morton_renumbering(S, D, case):
     cx, cy = centroids(m1)
     kt = morton_keys(m0, cx, cy) >> np.uint64(32)
     assert np.all(kt[1:] >= kt[:-1])
+
+
+def size_field(m0, grid, x, y):
+    """The documented size field s at points (x, y): bilinear on the grid's
+    nodes (periodic axis: spacing period / n from 0, wrapping; bounded axis:
+    n nodes spanning the input's extent)."""
+    def axis(v, c0, period, n):
+        if period > 0:
+            q = np.asarray(v) / (period / n)
+            fl = np.floor(q)
+            i0 = np.mod(fl.astype(np.int64), n)
+            return i0, np.mod(i0 + 1, n), q - fl
+        lo, hi = float(np.min(c0)), float(np.max(c0))
+        q = np.clip((np.asarray(v) - lo) / ((hi - lo) / (n - 1)), 0, n - 1)
+        fl = np.clip(np.floor(q), 0, n - 2)
+        return fl.astype(np.int64), fl.astype(np.int64) + 1, q - fl
+
+    x0, x1, wx = axis(x, m0["x"], m0["px"], grid.shape[1])
+    y0, y1, wy = axis(y, m0["y"], m0["py"], grid.shape[0])
+    a = grid[y0, x0] * (1 - wx) + grid[y0, x1] * wx
+    b = grid[y1, x0] * (1 - wx) + grid[y1, x1] * wx
+    return a * (1 - wy) + b * wy
+
+
+def graded_grid(n=9):
+    """Scale factors 0.25 along the horizontal mid-line of the domain rising
+    linearly to 1 at the top and bottom (n x n nodes)."""
+    yy = np.linspace(0.0, 1.0, n)
+    s = 0.25 + 1.5 * np.abs(yy - 0.5)
+    return np.repeat(s[:, None], n, axis=1)
+
+
+def check_size_field(D, m0, m1, R, grid):
+    """Every triangle's circumradius within R s(centroid) (FP64, slack 1e-9),
+    and the mesh denser where s is small."""
+    from fractions import Fraction
+    tri = np.asarray(m1["tri"])
+    x, y = m1["x"], m1["y"]
+    cx = (x[tri[:, 0]] + x[tri[:, 1]] + x[tri[:, 2]]) / 3.0
+    cy = (y[tri[:, 0]] + y[tri[:, 1]] + y[tri[:, 2]]) / 3.0
+    s = size_field(m0, grid, cx, cy)
+    for (r2, _), sc in zip(D.quality(m1, tri), s):
+        assert r2 <= Fraction(R * R * sc * sc) * Fraction(1 + 1e-9)
+    mid = np.abs(cy - 0.5 * (y.max() + y.min())) < 0.1
+    edge = np.abs(cy - 0.5 * (y.max() + y.min())) > 0.4
+    return mid.sum(), edge.sum()
+
+
+def test_size_field_grades_the_mesh(S, D):
+    """A size field 0.25 on the mid-line rising to 1 at the top and bottom:
+    every triangle meets R s(centroid), and the band around the mid-line
+    holds far more triangles than equal-area bands at the edges."""
+    m0 = points_in_box(20, 1.0, 1.0, 3)
+    grid = graded_grid()
+    st, m1 = host_refine(S, m0, 0.08, SQRT2, size_grid=grid)
+    assert st == 0
+    check_refined(D, m0, m1, 0.08, SQRT2)
+    n_mid, n_edge = check_size_field(D, m0, m1, 0.08, grid)
+    assert n_mid > 4 * n_edge
+
+
+
+def test_size_field_on_a_torus(S, D):
+    """The size field wraps on periodic axes: every triangle meets R s(centroid)."""
+    m0 = wrapped(I.split_square(8, periodic=(True, True), jitter=0.3, seed=5))
+    grid = graded_grid(8)
+    st, m1 = host_refine(S, m0, 0.08, SQRT2, size_grid=grid)
+    assert st == 0
+    check_refined(D, m0, m1, 0.08, SQRT2)
+    tri = np.asarray(m1["tri"])
+    from fractions import Fraction
+
+    def img(v, o):
+        return np.where(v - o > 0.5, v - 1.0, np.where(v - o < -0.5, v + 1.0, v))
+
+    x, y = m1["x"], m1["y"]
+    cx = np.mod((x[tri[:, 0]] + img(x[tri[:, 1]], x[tri[:, 0]]) + img(x[tri[:, 2]], x[tri[:, 0]])) / 3.0, 1.0)
+    cy = np.mod((y[tri[:, 0]] + img(y[tri[:, 1]], y[tri[:, 0]]) + img(y[tri[:, 2]], y[tri[:, 0]])) / 3.0, 1.0)
+    s = size_field(m0, grid, cx, cy)
+    for (r2, _), sc in zip(D.quality(m1, tri), s):
+        assert r2 <= Fraction(0.08 * 0.08 * sc * sc) * Fraction(1 + 1e-9)
