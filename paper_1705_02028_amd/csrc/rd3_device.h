@@ -102,8 +102,8 @@ __device__ inline double neg(double x) { return x < 0.0 ? x : 0.0; }
 // pivoting (the largest magnitude among the rows not yet used, first such
 // row on ties); a column whose best pivot is at most 2^-45 max|A| is skipped
 // (its unknowns are 0). Every array index is a compile-time constant (the
-// pivot row is picked with selects and copied into U), so nothing goes to
-// scratch memory.
+// pivot row is picked with selects and copied into U, its diagonal replaced
+// by the pivot's reciprocal), so nothing goes to scratch memory.
 __device__ inline void solve5x2(double A[5][5], double b1[5], double b2[5], double x1[5], double x2[5]) {
   double amax = 0.0;
 #pragma unroll
@@ -144,10 +144,12 @@ __device__ inline void solve5x2(double A[5][5], double b1[5], double b2[5], doub
     c2[k] = pb2;
     if (skip[k]) continue;
     used |= 1 << r;
+    const double ip = 1.0 / pr[k];
+    U[k][k] = ip;  // the back substitution multiplies by it
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       if (used & (1 << i)) continue;
-      const double fct = A[i][k] / pr[k];
+      const double fct = A[i][k] * ip;
 #pragma unroll
       for (int j = k; j < 5; ++j) A[i][j] -= fct * pr[j];
       b1[i] -= fct * pb1;
@@ -162,8 +164,8 @@ __device__ inline void solve5x2(double A[5][5], double b1[5], double b2[5], doub
       s1 -= U[k][j] * x1[j];
       s2 -= U[k][j] * x2[j];
     }
-    x1[k] = skip[k] ? 0.0 : s1 / U[k][k];
-    x2[k] = skip[k] ? 0.0 : s2 / U[k][k];
+    x1[k] = skip[k] ? 0.0 : s1 * U[k][k];
+    x2[k] = skip[k] ? 0.0 : s2 * U[k][k];
   }
 }
 
@@ -220,13 +222,14 @@ __device__ inline void tet_body(const Dev3& d, int64_t t, int scheme, bool keep)
   f.r0[4] = f.H;
   // state differences M(zbar)(Z_i - Z_0)
   double dW[4][5];
+  const double igam = 1.0 / d.gamma;
   for (int k = 0; k < 5; ++k) dW[0][k] = 0.0;
   for (int i = 1; i < 4; ++i) {
     double dz[5];
     for (int k = 0; k < 5; ++k) dz[k] = Zc[i][k] - Zc[0][k];
     dW[i][0] = 2.0 * zb[0] * dz[0];
     for (int k = 1; k < 4; ++k) dW[i][k] = zb[k] * dz[0] + zb[0] * dz[k];
-    dW[i][4] = (zb[4] * dz[0] + g1 * (zb[1] * dz[1] + zb[2] * dz[2] + zb[3] * dz[3]) + zb[0] * dz[4]) / d.gamma;
+    dW[i][4] = (zb[4] * dz[0] + g1 * (zb[1] * dz[1] + zb[2] * dz[2] + zb[3] * dz[3]) + zb[0] * dz[4]) * igam;
   }
   Corner cn[4];
   for (int i = 0; i < 4; ++i) {
@@ -236,7 +239,7 @@ __device__ inline void tet_body(const Dev3& d, int64_t t, int scheme, bool keep)
     const double ia = 1.0 / area;
     for (int k = 0; k < 3; ++k) cn[i].n[k] = n[k] * ia;
     cn[i].un = f.u[0] * cn[i].n[0] + f.u[1] * cn[i].n[1] + f.u[2] * cn[i].n[2];
-    cn[i].scale = area / 3.0;
+    cn[i].scale = area * (1.0 / 3.0);
   }
   // residual and the N right-hand side
   double phiT[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, bN[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -248,26 +251,31 @@ __device__ inline void tet_body(const Dev3& d, int64_t t, int scheme, bool keep)
     kapply(f, cn[i], neg(un + f.c), neg(un - f.c), neg(un), dW[i], y);
     for (int k = 0; k < 5; ++k) bN[k] += y[k];
   }
-  // A = sum_i K_i^+ assembled from the rank-two form
-  double A[5][5];
+  // A = sum_i K_i^+ from the rank-two form: sum_i sc_i l3_i I + r0 (sum_i a_i)^T
+  // + sum_i s_i b_i^T, with s_i = (0, n_i, u.n_i) (its first entry is zero)
+  double A[5][5], abar[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, dsum = 0.0;
   for (int r = 0; r < 5; ++r)
     for (int q = 0; q < 5; ++q) A[r][q] = 0.0;
-  for (int i = 0; i < 4; ++i) {
-    const double un = cn[i].un;
-    const double l1 = pos(un + f.c), l2 = pos(un - f.c), l3 = pos(un);
-    const double l123 = 0.5 * (l1 + l2) - l3, l12 = 0.5 * (l1 - l2);
-    const double ic = 1.0 / f.c, sc = cn[i].scale;
-    const double m[5] = {-un, cn[i].n[0], cn[i].n[1], cn[i].n[2], 0.0};
-    const double s[5] = {0.0, cn[i].n[0], cn[i].n[1], cn[i].n[2], un};
-    double a[5], b[5];
-    for (int q = 0; q < 5; ++q) {
-      a[q] = sc * ((l123 * ic * ic) * f.g[q] + (l12 * ic) * m[q]);
-      b[q] = sc * ((l12 * ic) * f.g[q] + l123 * m[q]);
+  {
+    const double ic = 1.0 / f.c;
+    for (int i = 0; i < 4; ++i) {
+      const double un = cn[i].un;
+      const double l1 = pos(un + f.c), l2 = pos(un - f.c), l3 = pos(un);
+      const double sc = cn[i].scale;
+      const double l123 = sc * (0.5 * (l1 + l2) - l3), l12 = sc * (0.5 * (l1 - l2));
+      const double m[5] = {-un, cn[i].n[0], cn[i].n[1], cn[i].n[2], 0.0};
+      const double s[4] = {cn[i].n[0], cn[i].n[1], cn[i].n[2], un};
+      dsum += sc * l3;
+      for (int q = 0; q < 5; ++q) {
+        abar[q] += (l123 * ic * ic) * f.g[q] + (l12 * ic) * m[q];
+        const double b = (l12 * ic) * f.g[q] + l123 * m[q];
+        for (int r = 1; r < 5; ++r) A[r][q] += s[r - 1] * b;
+      }
     }
-    for (int r = 0; r < 5; ++r) {
-      A[r][r] += sc * l3;
-      for (int q = 0; q < 5; ++q) A[r][q] += f.r0[r] * a[q] + s[r] * b[q];
-    }
+  }
+  for (int r = 0; r < 5; ++r) {
+    A[r][r] += dsum;
+    for (int q = 0; q < 5; ++q) A[r][q] += f.r0[r] * abar[q];
   }
   double PT[5];
   if (STAGE == 1) {
