@@ -14,17 +14,21 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rd3_oracle.cpp")
-LIB = os.path.join(HERE, "liboracle3.so")
+LIB = os.environ.get("RDO3_LIB") or os.path.join(HERE, "liboracle3.so")
 
 N, LDA, B, BMAX, BMIN = 0, 1, 2, 3, 4
 EULER1, RK2 = 1, 2
 
 
+def compile_cmd(src: str, out: str) -> list:
+    return ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+            "-Wall", "-o", out, src]
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ (FP64, no FMA contraction, OpenMP)."""
     if force or not os.path.exists(LIB):
-        subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-                        "-shared", "-Wall", "-o", LIB, SRC], check=True)
+        subprocess.run(compile_cmd(SRC, LIB), check=True)
     return LIB
 
 

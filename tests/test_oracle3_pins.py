@@ -6,7 +6,9 @@ linear (edge-midpoint quadrature, exact for the quadratic flux); the N and
 LDA parts add up to the residual; a supersonic tetrahedron sends everything
 to its one downstream corner; uniform states are steady; periodic boxes
 conserve mass, momentum and energy; the CFL limit has its closed form on
-the regular box."""
+the regular box; stored normals point inwards and a bounded box's residual
+total is its boundary flux; RK2 with the N scheme is Heun's method (two
+forward Euler steps averaged with the start)."""
 import numpy as np
 import pytest
 
@@ -174,3 +176,48 @@ def test_geometry_and_cfl_closed_forms(O):
     U = I.ic3_uniform(m, rho, *u, p)
     lam = np.linalg.norm(u) + np.sqrt(G * p / rho)
     assert om.max_dt(U, 0.5) == pytest.approx(0.5 * h / (4 * np.sqrt(2) * lam), rel=1e-13)
+
+
+def test_inward_normals_and_mesh_residual_total(O):
+    """Each stored face normal points towards its own corner, and on a
+    bounded box the sum of the vertex residuals (all interior faces cancel)
+    equals the sum over tetrahedra of the exact surface integrals of the
+    flux with Z linear (edge-midpoint quadrature)."""
+    m = I.cube_tets(2, periodic=(False, False, False), jitter=0.2, seed=21)
+    om = O.OracleMesh3(m)
+    _, nrm, _, _ = om.geometry()
+    P = np.stack([m["x"], m["y"], m["z"]], axis=1)
+    for t, corners in enumerate(m["tet"]):
+        for i in range(4):
+            face = [corners[q] for q in range(4) if q != i]
+            assert np.dot(nrm[t, i], P[corners[i]] - P[face].mean(axis=0)) > 0
+    W = I.ic3_random_smooth(m, seed=22, amp=0.2)
+    R = om.residual(W, O.N)
+    Z = np.stack([z_from_w(W[:, v]) for v in range(m["nv"])])
+    total = np.zeros(5)
+    for corners in m["tet"]:
+        p = P[corners]
+        for i in range(4):
+            j, k, l = [corners[q] for q in range(4) if q != i]
+            n = 0.5 * np.cross(P[k] - P[j], P[l] - P[j])
+            if np.dot(n, p[i] - P[j]) > 0:
+                n = -n
+            for a, b in ((j, k), (k, l), (l, j)):
+                total += flux_n(w_from_z(0.5 * (Z[a] + Z[b])), n) / 3.0
+    assert np.abs(R.sum(axis=1) - total).max() <= 1e-12 * np.abs(total).max()
+
+
+def test_rk2_with_the_n_scheme_is_heun(O):
+    """With the N scheme and global lumping the two-stage step is Heun's
+    method on dW/dt = -R(W)/V: the stage-2 mass term |T|/4 (W* - W^n)/dt sums
+    to V (W* - W^n)/dt at every vertex, so the RK2 step equals the mean of
+    W^n and two forward Euler steps."""
+    m = I.cube_tets(4, jitter=0.2, seed=23)
+    om = O.OracleMesh3(m)
+    W = I.ic3_random_smooth(m, seed=24)
+    dt = om.max_dt(W, 0.3)
+    heun = 0.5 * (W + om.step(om.step(W, dt, O.N, O.EULER1), dt, O.N, O.EULER1))
+    rk2 = om.step(W, dt, O.N, O.RK2)
+    assert np.abs(rk2 - heun).max() <= 1e-13 * np.abs(W).max()
+    # and the other schemes are not (their stage-2 parts are not per-vertex linear)
+    assert np.abs(om.step(W, dt, O.B, O.RK2) - rk2).max() > 1e-8
