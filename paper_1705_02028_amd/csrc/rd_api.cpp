@@ -1462,7 +1462,7 @@ RD_API rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, i
   if (!n_vertices || !n_triangles) return fail(RD_EINVAL, "null count pointer");
   const int64_t nv0 = *n_vertices, nt0 = *n_triangles;
   if (max_vertices < nv0 || max_triangles < nt0) return fail(RD_EINVAL, "capacity below the current size");
-  if (max_vertices >= INT32_MAX || max_triangles >= INT32_MAX / 2)
+  if (max_vertices >= INT32_MAX || max_triangles >= INT32_MAX / 3)  // edge keys 3 t + i are int32
     return fail(RD_EINVAL, "capacity beyond the 32-bit index range");
   if (!(max_radius >= 0.0) || !std::isfinite(max_radius)) return fail(RD_EINVAL, "max_radius must be >= 0");
   if (!(max_ratio == 0.0 || max_ratio >= 1.0) || !std::isfinite(max_ratio))

@@ -166,3 +166,18 @@ def test_3d_mesh_checks_run_on_the_host(rd):
     assert st == rd.RD_EINVAL and "belongs to no tetrahedron" in msg
     st, msg = create(dict(m, gamma=1.0))
     assert st == rd.RD_EINVAL and "gamma" in msg
+
+
+def test_refinement_capacity_limit_keeps_edge_keys_in_32_bits(rd):
+    """Edge keys 3 t + i are 32-bit: a triangle capacity of 2^31 / 3 or more
+    is refused before anything is allocated."""
+    sq = {"x": np.array([0.0, 1.0, 1.0, 0.0]), "y": np.array([0.0, 0.0, 1.0, 1.0]),
+          "tri": np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32), "nv": 4, "nt": 2, "px": 0.0, "py": 0.0}
+    import ctypes as C
+    x, y = sq["x"].copy(), sq["y"].copy()
+    tri = sq["tri"].copy()
+    nv, nt = C.c_int64(4), C.c_int64(2)
+    st = rd.lib().rd_delaunay_refine(C.byref(nv), x.ctypes.data, y.ctypes.data, 4, 0.0, 0.0, C.byref(nt),
+                                     tri.ctypes.data, (2 ** 31 - 1) // 3, 0.1, 2 ** 0.5, None, 0, 0, 10, 0,
+                                     None, None)
+    assert st == rd.RD_EINVAL and "32-bit" in rd.lib().rd_last_error().decode()
