@@ -296,30 +296,44 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
     xN[r] = Ai[r][0] * bN[0] + Ai[r][1] * bN[1] + Ai[r][2] * bN[2] + Ai[r][3] * bN[3];
     xL[r] = Ai[r][0] * rhs1[0] + Ai[r][1] * rhs1[1] + Ai[r][2] * rhs1[2] + Ai[r][3] * rhs1[3];
   }
-  // per corner: N part pN (stage 2: total PN), LDA part pl; kept are only
-  // the blend's sums and the signs of PN (the reverse recomputes the rest)
+  // per corner: N part pN (stage 2: total PN), LDA part pl. As in the
+  // forward pass, corner 2's parts are the residual being split minus those
+  // of corners 0 and 1 (sum_i K_i^+ (dW_i + xN) = phi^T and
+  // sum_i K_i^+ xL = rhs1), so the reverse differentiates two K^+ products
+  // per corner fewer. Kept are the blend's sums and the signs of PN (the
+  // reverse recomputes the rest).
   double th[4] = {0, 0, 0, 0}, den[4] = {0, 0, 0, 0}, thb[4] = {0, 0, 0, 0};
   unsigned spos = 0, sneg = 0;  // bit 4 i + k: PN_ik > 0, PN_ik < 0
-  for (int i = 0; i < 3; ++i) {
-    double yN[4], pN[4], PN[4], pl[4];
-    for (int k = 0; k < 4; ++k) yN[k] = dWh[i][k] + xN[k];
-    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN, pN);
-    for (int k = 0; k < 4; ++k)
-      PN[k] = STAGE == 1 ? pN[k] : s2->mass * (s2->dw[i][k] * s2->idt) + 0.5 * (s2->keepN[i][k] + pN[k]);
-    apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, pl);
-    for (int k = 0; k < 4; ++k) {
-      den[k] = den[k] + fabs(PN[k]);
-      thb[k] = thb[k] + ob[i][k] * (PN[k] - pl[k]);
-      spos |= (PN[k] > 0.0 ? 1u : 0u) << (4 * i + k);
-      sneg |= (PN[k] < 0.0 ? 1u : 0u) << (4 * i + k);
+  {
+    double pN[3][4], pl[3][4];
+    for (int i = 0; i < 2; ++i) {
+      double yN[4];
+      for (int k = 0; k < 4; ++k) yN[k] = dWh[i][k] + xN[k];
+      apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN, pN[i]);
+      apply_split(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, pl[i]);
     }
+    for (int k = 0; k < 4; ++k) {
+      pN[2][k] = phiT[k] - pN[0][k] - pN[1][k];
+      pl[2][k] = rhs1[k] - pl[0][k] - pl[1][k];
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 4; ++k) {
+        const double PN =
+            STAGE == 1 ? pN[i][k] : s2->mass * (s2->dw[i][k] * s2->idt) + 0.5 * (s2->keepN[i][k] + pN[i][k]);
+        den[k] = den[k] + fabs(PN);
+        thb[k] = thb[k] + ob[i][k] * (PN - pl[i][k]);
+        spos |= (PN > 0.0 ? 1u : 0u) << (4 * i + k);
+        sneg |= (PN < 0.0 ? 1u : 0u) << (4 * i + k);
+      }
   }
   bool active[4] = {false, false, false, false};  // Theta_k = |r_k| / den_k, not 0/0, not clamped
+  double ratio[4] = {0, 0, 0, 0};                    // |r_k| / den_k before the clamp and the Bmax/Bmin pick
   int pick = 0;
   if (SCHEME >= SCH_B) {
     for (int k = 0; k < 4; ++k) {
       const double qq = den[k] == 0.0 ? 0.0 : fabs(rhs1[k]) / den[k];
       active[k] = den[k] != 0.0 && !(qq > 1.0);
+      ratio[k] = qq;
       th[k] = qq > 1.0 ? 1.0 : qq;
     }
     if (SCHEME == SCH_BMAX || SCHEME == SCH_BMIN) {
@@ -344,42 +358,55 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
     }
     for (int k = 0; k < 4; ++k) {
       if (!active[k]) continue;
-      const double qq = fabs(rhs1[k]) / den[k];
-      rhs1b[k] += thb[k] * sgn(rhs1[k]) / den[k];
-      denb[k] = -thb[k] * qq / den[k];
+      const double id = 1.0 / den[k];
+      rhs1b[k] += thb[k] * sgn(rhs1[k]) * id;
+      denb[k] = -thb[k] * ratio[k] * id;
     }
   }
   double xLb[4] = {0, 0, 0, 0}, xNb[4] = {0, 0, 0, 0}, dWhb[3][4];
   for (int i = 0; i < 3; ++i)
     for (int k = 0; k < 4; ++k) dWhb[i][k] = 0.0;
+  double plb[3][4], pNb[3][4];
   for (int i = 0; i < 3; ++i) {
-    double PNb[4], plb[4], pNb[4], yN[4];
     for (int k = 0; k < 4; ++k) {
+      double PNb;
       if (SCHEME == SCH_N) {
-        PNb[k] = ob[i][k];
-        plb[k] = 0.0;
+        PNb = ob[i][k];
+        plb[i][k] = 0.0;
       } else if (SCHEME == SCH_LDA) {
-        PNb[k] = 0.0;
-        plb[k] = ob[i][k];
+        PNb = 0.0;
+        plb[i][k] = ob[i][k];
       } else {
         const unsigned bit = 1u << (4 * i + k);
         const double sg = (spos & bit) ? 1.0 : ((sneg & bit) ? -1.0 : 0.0);
-        PNb[k] = ob[i][k] * th[k] + denb[k] * sg;
-        plb[k] = ob[i][k] * (1.0 - th[k]);
+        PNb = ob[i][k] * th[k] + denb[k] * sg;
+        plb[i][k] = ob[i][k] * (1.0 - th[k]);
       }
       if (STAGE == 1) {
-        pNb[k] = PNb[k] + kNb[i][k];
+        pNb[i][k] = PNb + kNb[i][k];
       } else {
-        pNb[k] = 0.5 * PNb[k];
-        s2b->keepN[i][k] = 0.5 * PNb[k];
-        s2b->dw[i][k] = s2->mass * s2->idt * PNb[k];
+        pNb[i][k] = 0.5 * PNb;
+        s2b->keepN[i][k] = 0.5 * PNb;
+        s2b->dw[i][k] = s2->mass * s2->idt * PNb;
       }
-      yN[k] = dWh[i][k] + xN[k];
     }
-    double yb[4] = {0, 0, 0, 0};
-    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, plb, xLb, qb, kb[i], kb[i].l3p, kb[i].h1p,
+  }
+  // corner 2's parts: rhs1 and phi^T minus those of corners 0 and 1
+  double phiTb[4];
+  for (int k = 0; k < 4; ++k) {
+    rhs1b[k] += plb[2][k];
+    phiTb[k] = pNb[2][k];
+    for (int i = 0; i < 2; ++i) {
+      plb[i][k] -= plb[2][k];
+      pNb[i][k] -= pNb[2][k];
+    }
+  }
+  for (int i = 0; i < 2; ++i) {
+    double yN[4], yb[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) yN[k] = dWh[i][k] + xN[k];
+    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, xL, plb[i], xLb, qb, kb[i], kb[i].l3p, kb[i].h1p,
                     kb[i].h2p);
-    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN, pNb, yb, qb, kb[i], kb[i].l3p, kb[i].h1p,
+    apply_split_bar(q, kc[i], kc[i].l3p, kc[i].h1p, kc[i].h2p, yN, pNb[i], yb, qb, kb[i], kb[i].l3p, kb[i].h1p,
                     kb[i].h2p);
     for (int k = 0; k < 4; ++k) {
       dWhb[i][k] += yb[k];
@@ -393,12 +420,11 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
     rb[c] = Ai[0][c] * xLb[0] + Ai[1][c] * xLb[1] + Ai[2][c] * xLb[2] + Ai[3][c] * xLb[3];
   }
   for (int k = 0; k < 4; ++k) rhs1b[k] += rb[k];
-  double phiTb[4];
   if (STAGE == 1) {
-    for (int k = 0; k < 4; ++k) phiTb[k] = rhs1b[k] + kTb[k];
+    for (int k = 0; k < 4; ++k) phiTb[k] += rhs1b[k] + kTb[k];
   } else {
     for (int k = 0; k < 4; ++k) {
-      phiTb[k] = 0.5 * rhs1b[k];
+      phiTb[k] += 0.5 * rhs1b[k];
       s2b->keepT[k] = 0.5 * rhs1b[k];
       const double rateb = s2->mass * rhs1b[k] * s2->idt;
       for (int i = 0; i < 3; ++i) s2b->dw[i][k] += rateb;
