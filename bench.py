@@ -39,11 +39,12 @@ def algorithmic_bytes(nt, nv, fp32):
     r4 = 4 * q
     k = {}
     # stage 1: corner ids and CSR positions, coordinates, Z and |v|+c in;
-    # parts, kept N parts (corners 0 and 1), phi^T and l_max lambda_max per corner out
-    k["tri1"] = nt * (12 + 12 + 3 * r4 + 2 * r4 + r4 + 24) + nv * (16 + r4 + 8)
+    # parts, kept N parts (corners 0 and 1), phi^T and l_max lambda_max per
+    # corner out (the CFL terms in the triangle algebra's precision)
+    k["tri1"] = nt * (12 + 12 + 3 * r4 + 2 * r4 + r4 + 3 * q) + nv * (16 + r4 + 8)
     # CFL: CSR rows, V and the per-corner l_max lambda_max in, block minima out
     k["shared1"] = 0
-    k["cfl"] = nv * (4 + 8) + nt * 24
+    k["cfl"] = nv * (4 + 8) + nt * 3 * q
     # gather 1: rows, parts in; W, V in; W*, W*-W, Z* out
     k["gather1"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + r4)
     # stage 2: ids, positions, coordinates, Z*, W*-W, kept N parts, phi^T in; parts out

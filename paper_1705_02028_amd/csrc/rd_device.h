@@ -317,6 +317,21 @@ __host__ __device__ inline void st4(void* base, int64_t i, const R a[4]) {
   reinterpret_cast<Q4<R>*>(base)[i] = q;
 }
 
+// The same as a non-temporal store: for records read back only much later
+// (the kept stage-1 parts, read by the stage-2 pass after the gather), so
+// that they do not evict from the caches the parts and parameter vectors the
+// next kernel reads.
+template <typename R>
+__host__ __device__ inline void st4_stream(void* base, int64_t i, const R a[4]) {
+#ifdef __HIP_DEVICE_COMPILE__
+  typedef R V4 __attribute__((ext_vector_type(4)));
+  const V4 q = {a[0], a[1], a[2], a[3]};
+  __builtin_nontemporal_store(q, reinterpret_cast<V4*>(base) + i);
+#else
+  st4<R>(base, i, a);
+#endif
+}
+
 template <typename R> __host__ __device__ inline const Q4<R>* zbuf(const Dev& d);
 template <> __host__ __device__ inline const Q4<double>* zbuf<double>(const Dev& d) { return d.Z; }
 template <> __host__ __device__ inline const Q4<float>* zbuf<float>(const Dev& d) { return d.Zf; }
@@ -558,8 +573,8 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     // those two, and stage 2 forms it again from the kept phi^T with the same
     // two subtractions, which gives back the identical value.
     if (STAGE == 1 && SAVE) {
-      st4<R>(d.keepN, 2 * t, pN[0]);
-      st4<R>(d.keepN, 2 * t + 1, pN[1]);
+      st4_stream<R>(d.keepN, 2 * t, pN[0]);
+      st4_stream<R>(d.keepN, 2 * t + 1, pN[1]);
     }
     if (STAGE == 2) {
       // Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2; the
@@ -583,7 +598,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     for (int i = 0; i < 3; ++i)
       for (int k = 0; k < 4; ++k) den[k] = den[k] + (R)fabs(pN[i][k]);
   }
-  if (STAGE == 1 && SAVE) st4<R>(d.keepT, t, phiT);
+  if (STAGE == 1 && SAVE) st4_stream<R>(d.keepT, t, phiT);
   // rhs1 is the residual being split (phi^T or Phi^T)
   R th[4] = {R(0), R(0), R(0), R(0)};
   if (SCHEME >= SCH_B && SCHEME <= SCH_BMIN) blend_theta<R, SCHEME>(rhs1, den, th);
