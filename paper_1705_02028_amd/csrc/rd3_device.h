@@ -303,9 +303,11 @@ __device__ inline void tet_body(const Dev3& d, int64_t t, int scheme, bool keep)
     kapply(f, cn[i], pos(un + f.c), pos(un - f.c), pos(un), y, pn[i]);
   }
   if (STAGE == 1 && keep) {
+    // read back only by the stage-2 pass after the gather: stored with the
+    // non-temporal hint so they do not evict what the gather reads next
     for (int i = 0; i < 4; ++i)
-      for (int k = 0; k < 5; ++k) d.keepN[(5 * i + k) * nt + t] = pn[i][k];
-    for (int k = 0; k < 5; ++k) d.keepT[k * nt + t] = phiT[k];
+      for (int k = 0; k < 5; ++k) __builtin_nontemporal_store(pn[i][k], &d.keepN[(5 * i + k) * nt + t]);
+    for (int k = 0; k < 5; ++k) __builtin_nontemporal_store(phiT[k], &d.keepT[k * nt + t]);
   }
   if (STAGE == 2) {
     const double mass = 0.25 * d.vol[t];
