@@ -472,6 +472,32 @@ def test_adjoint_dot_product_against_oracle_jvp(orc, rd, case):
     g.close()
 
 
+def test_adjoint_kh_2048_full_size(orc, rd):
+    """The adjoint at the benchmark's size and configuration (2048x2048
+    periodic Kelvin-Helmholtz, 8,380,418 triangles, FP64 B / RK2, fixed dt):
+    <lam, J v> from the oracle's exact forward-mode derivative equals
+    <J^T lam, v> from rd_adjoint_step."""
+    m = I.split_square(2048)
+    W = I.ic_kelvin_helmholtz(m, seed=0)
+    om = orc.OracleMesh(m)
+    dt = om.max_dt(W, 0.4)
+    rng = np.random.default_rng(17)
+    v = rng.normal(size=W.shape) * np.abs(W).mean(axis=1, keepdims=True)
+    lam = rng.normal(size=W.shape)
+    say("adjoint kh 2048: oracle jvp")
+    _, Jv = om.step_jvp(W, v, dt, orc.B, orc.RK2)
+    say("adjoint kh 2048: gpu adjoint")
+    g = rd.Mesh(m)
+    g.set_state(W)
+    JTl = np.zeros_like(W)
+    rd.rd_adjoint_step(g.h, W, dt, rd.B, rd.RK2, lam, JTl)
+    g.close()
+    a, b = float(np.sum(lam * Jv)), float(np.sum(JTl * v))
+    scale = float(np.sum(np.abs(lam * Jv)))
+    say(f"  <lam,Jv> {a:.15e}  <J^T lam,v> {b:.15e}  rel {abs(a - b) / scale:.2e}")
+    assert abs(a - b) <= 1e-12 * scale
+
+
 def test_rdstep_autograd_matches_oracle_jvp(orc, rd):
     """torch.autograd through RDStep: <grad of <lam, step(W)>, v> equals
     <lam, J v> from the oracle's exact forward-mode derivative."""
