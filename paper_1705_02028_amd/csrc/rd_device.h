@@ -127,6 +127,22 @@ __host__ __device__ inline float rcp(float x) {
 #endif
 }
 
+// Length L = sqrt(e2) and its reciprocal: IEEE square root and division
+// for FP64; one hardware reciprocal square root (about 1 ulp) for FP32.
+__host__ __device__ inline void len_rcp(double e2, double& L, double& iL) {
+  L = sqrt(e2);
+  iL = 1.0 / L;
+}
+__host__ __device__ inline void len_rcp(float e2, float& L, float& iL) {
+#ifdef __HIP_DEVICE_COMPILE__
+  iL = __builtin_amdgcn_rsqf(e2);
+  L = e2 * iL;
+#else
+  L = sqrtf(e2);
+  iL = 1.0f / L;
+#endif
+}
+
 template <typename R>
 __host__ __device__ inline R sel4(int r, R a0, R a1, R a2, R a3) {
   R t = r == 1 ? a1 : a0;
@@ -434,8 +450,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   q.v = zb[2] * iz;
   q.h = zb[3] * iz;
   const R q2 = q.u * q.u + q.v * q.v;
-  q.c = (R)sqrt(q.g1 * (q.h - R(0.5) * q2));
-  q.ic = rcp(q.c);
+  len_rcp(q.g1 * (q.h - R(0.5) * q2), q.c, q.ic);
   q.ac = R(0.5) * q.g1 * q2 * q.ic;
   q.uc = q.u * q.ic;
   q.vc = q.v * q.ic;
@@ -459,9 +474,9 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   for (int i = 0; i < 3; ++i) {
     // edge geometry in the algebra's precision, from FP64 coordinate differences
     const R ex = (R)nxd[i], ey = (R)nyd[i];
-    const R L = (R)sqrt(ex * ex + ey * ey);
+    R L, iL;
+    len_rcp(ex * ex + ey * ey, L, iL);
     lmax = rmax(lmax, L);
-    const R iL = rcp(L);
     Corner<R>& k = kc[i];
     k.nx = ex * iL;
     k.ny = ey * iL;
