@@ -14,7 +14,7 @@ mesh (`mesh_generation`; alone with --meshgen), the three-dimensional path
 on a 128^3-cell box of tetrahedra (`three_d`; alone with --three-d), and
 (with --batch) many meshes in one graph.
 
-Prints one JSON line. `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line. `--gpus N` with N > 1 exits: the library runs on one GPU.
 """
 import argparse
 import json
@@ -469,7 +469,7 @@ def main():
                     help="first run one 512 MiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch

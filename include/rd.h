@@ -53,7 +53,7 @@ typedef enum {
   RD_ENOMEM = 2,        /* device or host allocation failed */
   RD_EDEVICE = 3,       /* a HIP runtime call failed */
   RD_ENONPHYS = 4,      /* a state with rho <= 0, p <= 0 or a non-finite value */
-  RD_EUNSUPPORTED = 5   /* valid request this build does not provide */
+  RD_EUNSUPPORTED = 5   /* valid request the library does not provide */
 } rd_status;
 
 /* Distribution schemes (Section 3.3): N, LDA, and the blend B with its

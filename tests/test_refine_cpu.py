@@ -1,6 +1,6 @@
 """Delaunay refinement (Section 2) on the CPU: the library's per-element
 bodies (rd_delaunay_kern.h, the code the GPU kernels run) built with g++ and
-run one element at a time by a host copy of the driver
+run one element at a time by a host copy of the refinement loop
 (tests/cpp/delaunay_shim.cpp). A refined mesh has no unique form, so the
 reference is the set of properties it must have, each checked exactly by the
 reference module (oracle/delaunay.py): a valid counter-clockwise
