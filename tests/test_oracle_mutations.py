@@ -32,6 +32,11 @@ MUTANTS = {
     "ghosts_updated": ("    if (m.ghost[i]) continue;\n    for (int k = 0; k < 4; ++k) {\n      T r = R[4 * i + k] + Wc_n[4 * i + k];",
                        "    for (int k = 0; k < 4; ++k) {\n      T r = R[4 * i + k] + Wc_n[4 * i + k];"),
     "wall_normal_inward": ("m.wnx[e] = dy / len;", "m.wnx[e] = -dy / len;"),
+    "wall_split_roles_swapped": ("out[4 * ab[0] + k] += hl * (alpha * F[0][k] + (1.0 - alpha) * F[1][k]);\n"
+                                 "      out[4 * ab[1] + k] += hl * ((1.0 - alpha) * F[0][k] + alpha * F[1][k]);",
+                                 "out[4 * ab[0] + k] += hl * ((1.0 - alpha) * F[0][k] + alpha * F[1][k]);\n"
+                                 "      out[4 * ab[1] + k] += hl * (alpha * F[0][k] + (1.0 - alpha) * F[1][k]);"),
+    "wall_split_half": ("const double alpha = 0.75, g1 = m.gamma - 1.0;", "const double alpha = 0.5, g1 = m.gamma - 1.0;"),
     "volume_third": ("m.V[m.tri[3 * t + k]] += m.area[t] / 3.0;", "m.V[m.tri[3 * t + k]] += m.area[t] / 2.0;"),
     "bx_sensor_sign": ("pos_part(-m.L * div / range)", "pos_part(m.L * div / range)"),
     "bx_h_in_domain_units": ("T theta = s * s * h / m.L;", "T theta = s * s * h;"),

@@ -356,6 +356,33 @@ def test_wall_term_closed_form(orc):
     assert np.array_equal(R2, np.zeros_like(R2))
 
 
+def test_wall_split_golden(orc):
+    """Section 3.5's split of a wall edge's flux between its two ends, on
+    fluxes that differ along the wall (hand-worked values in
+    tests/golden/wall_split.json): each end takes alpha = 3/4 of its own flux
+    and 1/4 of the other end's. The wall term is the residual minus the sum of
+    the triangles' parts at each vertex."""
+    gold = json.load(open(os.path.join(HERE, "golden", "wall_split.json")))
+    mg = gold["mesh"]
+    m = I.split_square(mg["N"], periodic=tuple(mg["periodic"]), bc=tuple(mg["bc"]))
+    assert np.array_equal(np.stack([m["x"], m["y"]], 1), np.array(gold["vertices_xy"], float))
+    assert np.array_equal(m["wall"], np.array(gold["wall_edges"]))
+    prim = np.array(gold["primitive_rho_u_v_p"], float)
+    W = I.prim_to_cons(prim[:, 0], prim[:, 1], prim[:, 2], prim[:, 3], gold["gamma"])
+    om = orc.OracleMesh(m)
+    for scheme in (orc.N, orc.LDA, orc.B):
+        R = om.residual(W, scheme)
+        parts = om.parts(W, scheme)
+        tri_sum = np.zeros_like(R)
+        for i in range(3):
+            np.add.at(tri_sum.T, m["tri"][:, i], parts[:, i, :])
+        wall = R - tri_sum
+        scale = np.abs(R).max()
+        for v in range(m["nv"]):
+            expect = np.array(gold["wall_term"].get(str(v), [0.0] * 4))
+            assert np.max(np.abs(wall[:, v] - expect)) <= 1e-14 * scale, (scheme, v, wall[:, v], expect)
+
+
 def test_cfl_closed_form(orc):
     """Split-square mesh: 6 triangles per vertex, longest edge sqrt(2) h,
     V = h^2; a uniform state gives dt = cfl 2 h^2 / (6 sqrt(2) h (|v|+c))."""
