@@ -208,7 +208,16 @@ rd_status rd_residual(rd_mesh* mesh, int scheme, double* R, double* phiT, int on
  * [4][n_vertices] the step started from and lam_np1 = dL/dW^{n+1}, writes
  * lam_n = (dW^{n+1}/dW^n)^T lam_np1. Does not change the mesh's state.
  * Derivatives follow the branch the forward values take; d|x|/dx = 0 at 0.
- * RD_EUNSUPPORTED for the BX scheme and for RK2 with selective lumping. */
+ * RD_EUNSUPPORTED for the BX scheme and for RK2 with selective lumping.
+ * The step is recomputed on the adjoint's own buffers: the mesh's state,
+ * signal speeds and non-physical latch are not touched. Two conditions are
+ * latched on the device instead: W_n (or its recomputed first stage) is
+ * non-physical (RD_ENONPHYS), or a triangle's pivoted solve skipped a column
+ * (an exactly stagnant triangle, Section 3.3.1, where the solve is not an
+ * inverse and lam_n is not the derivative: RD_EUNSUPPORTED). With
+ * on_device = 0 the call waits and returns that status; with on_device = 1
+ * it only enqueues and the next rd_sync returns it. Either way the latch is
+ * cleared once reported. */
 rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int scheme, int time,
                           const double* lam_np1, double* lam_n, int on_device);
 
@@ -308,7 +317,8 @@ rd_status rd_batch_tune(rd_batch* batch, double cfl, int scheme, int time, int p
 
 /* Waits for the mesh's stream. RD_ENONPHYS if a non-physical state was
  * produced since the last rd_set_state (the flag stays set), RD_EDEVICE on a
- * runtime error. */
+ * runtime error; otherwise the adjoint's latched status since it was last
+ * reported (see rd_adjoint_step), which is then cleared. */
 rd_status rd_sync(rd_mesh* mesh);
 
 /* ---- Three dimensions (tetrahedra) --------------------------------------

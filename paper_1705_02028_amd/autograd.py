@@ -51,6 +51,7 @@ class RDStep(torch.autograd.Function):
         lam = grad_out.contiguous().to(torch.float64)
         out = torch.empty_like(lam)
         rd.rd_adjoint_step(ctx.mesh.h, W, dt, scheme, time, lam, out)
+        rd.rd_sync(ctx.mesh.h)  # raises on a latched non-physical or singular (stagnant) case
         return out, None, None, None, None
 
 
@@ -91,6 +92,7 @@ class RDRollout(torch.autograd.Function):
                 rd.rd_adjoint_step(mesh.h, states[s - s0], dt, scheme, time, lam, nxt)
                 lam, nxt = nxt, lam
         ctx.ckpts = None
+        rd.rd_sync(mesh.h)  # raises on a latched non-physical or singular (stagnant) case
         return lam, None, None, None, None, None, None
 
 

@@ -11,8 +11,10 @@
 // CSR in fixed order and mapped through dZ/dW. Branches follow the forward
 // values: max/min of eigenvalues, pivot order, |.| (derivative 0 at 0), the
 // 0/0 and clamped cases of the blend, the component Bmax/Bmin selects.
-// The pivoted solve is differentiated as x = A^{-1} b, so the adjoint
-// assumes no column of A was skipped (no exactly stagnant triangle).
+// The pivoted solve is differentiated as x = A^{-1} b, which needs every
+// column of A to have its pivot; a triangle whose solve skips a column (an
+// exactly stagnant triangle, Section 3.3.1) is reported through the
+// adjoint's flag instead (flag[1]), and the call's result is not used.
 #pragma once
 
 #include "rd_device.h"
@@ -35,6 +37,7 @@ struct AdjDev {
   D4* kN = nullptr;          // [2nt] cotangent of the kept stage-1 N parts of corners 0 and 1 (triangle order)
   D4* kT = nullptr;          // [nt] cotangent of kept stage-1 residual
   D4* wcbar = nullptr;       // [nwv] cotangent of the wall term at W^n (stage 1 + half of stage 2)
+  int* flag = nullptr;       // [2]: [0] the recomputed step went non-physical, [1] a solve skipped a column
 };
 
 // Cotangents of the quantities shared by all corners of a triangle.
@@ -204,8 +207,10 @@ struct Stage2Bar {
 // corner i. Stage 1 also takes the cotangents of the kept N parts (kNb) and
 // residual (kTb); stage 2 takes its extra inputs in s2 and returns theirs in
 // s2b. Returns the corner cotangents of Z in Zb.
+// Returns true when the pivoted solve skipped a column (A singular), where
+// the cotangents are not the derivative.
 template <int SCHEME, int STAGE>
-__host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3], const double nyd[3], double gamma,
+__host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3], const double nyd[3], double gamma,
                                             const double ob[3][4], const double kNb[3][4], const double kTb[4],
                                             const Stage2In* s2, Stage2Bar* s2b, double Zb[3][4]) {
   // ---------------- forward (recomputed, as in tri_compute) ----------------
@@ -276,6 +281,7 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
   }
   // A^{-1} (columns from unit right-hand sides) and the two solutions
   double Ai[4][4];
+  bool singular = false;
   {
     double e0[4], e1[4], x0[4], x1[4], Aw[4][4];
     for (int c2 = 0; c2 < 4; c2 += 2) {
@@ -284,7 +290,9 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
         e1[r] = r == c2 + 1 ? 1.0 : 0.0;
         for (int c = 0; c < 4; ++c) Aw[r][c] = A[r][c];
       }
-      solve2(Aw, e0, e1, x0, x1);
+      bool skipped;
+      solve2(Aw, e0, e1, x0, x1, skipped);
+      singular = singular || skipped;
       for (int r = 0; r < 4; ++r) {
         Ai[r][c2] = x0[r];
         Ai[r][c2 + 1] = x1[r];
@@ -516,6 +524,7 @@ __host__ __device__ inline void tri_adjoint(const D4 Zc[3], const double nxd[3],
       Zb[i][k] += dzb[i][k];
       Zb[0][k] -= dzb[i][k];
     }
+  return singular;
 }
 
 // Transpose of W -> Z at one state: Wb += (dZ/dW)^T Zb.
@@ -611,7 +620,7 @@ __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const Adj
   for (int k = 0; k < 4; ++k) s2.keepT[k] = SCHEME == SCH_N ? 0.0 : kt.v[k];
   Stage2Bar s2b;
   double Zb[3][4];
-  tri_adjoint<SCHEME, 2>(Zc, nxd, nyd, d.gamma, ob, nullptr, nullptr, &s2, &s2b, Zb);
+  if (tri_adjoint<SCHEME, 2>(Zc, nxd, nyd, d.gamma, ob, nullptr, nullptr, &s2, &s2b, Zb)) a.flag[1] = 1;
   for (int i = 0; i < 3; ++i) {
     ZW c;
     for (int k = 0; k < 4; ++k) {
@@ -657,7 +666,7 @@ __host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const Adj
   const D4 kt = rk2 ? a.kT[t] : D4{{0.0, 0.0, 0.0, 0.0}};
   for (int k = 0; k < 4; ++k) kTb[k] = kt.v[k];
   double Zb[3][4];
-  tri_adjoint<SCHEME, 1>(Zc, nxd, nyd, d.gamma, ob, kNb, kTb, nullptr, nullptr, Zb);
+  if (tri_adjoint<SCHEME, 1>(Zc, nxd, nyd, d.gamma, ob, kNb, kTb, nullptr, nullptr, Zb)) a.flag[1] = 1;
   for (int i = 0; i < 3; ++i) st4<double>(a.cZ, ip[i], Zb[i]);
 }
 

@@ -114,6 +114,7 @@ struct rd_mesh {
   // adjoint buffers, allocated on first use
   rd::AdjDev adj;
   rd::D4* adjW = nullptr;     // W^n of the step being reversed
+  double* adjSig = nullptr;   // [nv] signal speeds of the recomputation (the mesh's stay with its state)
   double* adjIn = nullptr;    // [4 nv] host staging (W^n, then dL/dW^{n+1})
   double* adjOut = nullptr;   // [4 nv] dL/dW^n
   hipEvent_t events[RD_NKERNELS + 1] = {};
@@ -675,6 +676,12 @@ RD_API rd_status rd_max_dt(rd_mesh* m, double cfl, double* dt_out) {
   if (!m || !dt_out) return fail(RD_EINVAL, "null argument");
   if (!(cfl > 0.0)) return fail(RD_EINVAL, "cfl must be positive");
   DeviceGuard g(m->device);
+  // the signal speeds are valid for the state whenever the parameter vectors
+  // are; after a tune, a batch run or an adjoint step they are refreshed first
+  if (m->zprec < 0) {
+    rd_status st = ensure_z(m, 0);
+    if (st != RD_OK) return st;
+  }
   HIPCHK(rd::launch_cfl(m->d, m->cfl, cfl, m->stream));
   HIPCHK(hipMemcpyAsync(dt_out, m->d.dt, sizeof(double), hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
@@ -887,6 +894,26 @@ RD_API rd_status rd_residual(rd_mesh* m, int scheme, double* R, double* phiT, in
   return RD_OK;
 }
 
+namespace {
+
+// Waits for the mesh's stream and reports (then clears) the adjoint's latches:
+// a non-physical recomputed step, or a triangle whose solve skipped a column.
+rd_status adjoint_status(rd_mesh* m) {
+  int flag[2] = {0, 0};
+  if (m->adj.flag) HIPCHK(hipMemcpyAsync(flag, m->adj.flag, sizeof(flag), hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if (!flag[0] && !flag[1]) return RD_OK;
+  HIPCHK(rd::launch_set_int(m->adj.flag, 0, m->stream));
+  HIPCHK(rd::launch_set_int(m->adj.flag + 1, 0, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  if (flag[0]) return fail(RD_ENONPHYS, "the adjoint's input state W_n or its recomputed first stage is non-physical");
+  return fail(RD_EUNSUPPORTED,
+              "the adjoint met a triangle whose pivoted solve skipped a column (exact stagnation, Section 3.3.1); "
+              "the gradient of that branch is not computed");
+}
+
+}  // namespace
+
 RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int scheme, int time,
                                  const double* lam_np1, double* lam_n, int on_device) {
   if (!m || !W_n || !lam_np1 || !lam_n) return fail(RD_EINVAL, "null argument");
@@ -902,12 +929,18 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     rd::AdjDev& a = m->adj;
     rd::D4 *lamIn, *lamS, *lamN, *Zn, *cZ, *kN, *kT, *Wa;
     rd::ZW* cZW;
-    double *in, *out;
+    double *in, *out, *sig;
+    int* flag;
     if ((st = dalloc(m, &lamIn, nv)) || (st = dalloc(m, &lamS, nv)) || (st = dalloc(m, &lamN, nv)) ||
         (st = dalloc(m, &Zn, nv)) || (st = dalloc(m, &cZ, m->d.ns)) || (st = dalloc(m, &cZW, m->d.ns)) ||
         (st = dalloc(m, &kN, 2 * nt)) || (st = dalloc(m, &kT, nt)) || (st = dalloc(m, &Wa, nv)) ||
-        (st = dalloc(m, &in, 4 * nv)) || (st = dalloc(m, &out, 4 * nv)))
+        (st = dalloc(m, &in, 4 * nv)) || (st = dalloc(m, &out, 4 * nv)) || (st = dalloc(m, &sig, nv)) ||
+        (st = dalloc(m, &flag, 2)))
       return st;
+    HIPCHK(rd::launch_set_int(flag, 0, m->stream));
+    HIPCHK(rd::launch_set_int(flag + 1, 0, m->stream));
+    a.flag = flag;
+    m->adjSig = sig;
     a.lam = lamIn;
     a.lamS = lamS;
     a.lamN = lamN;
@@ -921,9 +954,12 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     m->adjOut = out;
   }
   hipStream_t s = m->stream;
-  // the step is recomputed on private state; the mesh's own W is untouched
+  // the step is recomputed on private state, signal speeds and flag; the
+  // mesh's own W, |v| + c and non-physical latch are untouched
   rd::Dev d = dev_for(m, 0);
   d.W = m->adjW;
+  d.sig = m->adjSig;
+  d.flag = m->adj.flag;
   const double* src = W_n;
   if (!on_device) {
     HIPCHK(hipMemcpyAsync(m->adjIn, W_n, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, s));
@@ -952,7 +988,7 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
   m->zprec = -1;  // the parameter-vector buffer now holds the recomputation's values
   if (!on_device) {
     HIPCHK(hipMemcpyAsync(lam_n, m->adjOut, sizeof(double) * 4 * nv, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    return adjoint_status(m);
   }
   return RD_OK;
 }
@@ -1268,7 +1304,7 @@ RD_API rd_status rd_sync(rd_mesh* m) {
   HIPCHK(hipMemcpyAsync(&flag, m->d.flag, sizeof(int), hipMemcpyDeviceToHost, m->stream));
   HIPCHK(hipStreamSynchronize(m->stream));
   if (flag) return fail(RD_ENONPHYS, "a non-physical state was produced");
-  return RD_OK;
+  return adjoint_status(m);
 }
 
 RD_API const char* rd_last_error(void) { return g_last_error.c_str(); }

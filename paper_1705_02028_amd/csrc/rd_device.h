@@ -238,8 +238,9 @@ __host__ __device__ inline void build_A(const Roe<R>& q, const Corner<R> k[3], R
 // Pivot: largest |entry| among rows not yet used, lowest row on ties; a
 // column whose best pivot is at most 2^-45 max|A| is skipped and its unknown
 // set to 0 (A is singular at stagnation; the K^+ x products stay unique).
+// `skipped` reports whether any column was skipped.
 template <typename R>
-__host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x1[4]) {
+__host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x1[4], bool& skipped) {
   R amax = R(0);
   for (int r = 0; r < 4; ++r)
     for (int c = 0; c < 4; ++c) amax = rmax(amax, (R)fabs(A[r][c]));
@@ -288,6 +289,13 @@ __host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x
     x0[k] = OK[k] ? s0 * PI[k] : R(0);
     x1[k] = OK[k] ? s1 * PI[k] : R(0);
   }
+  skipped = !(OK[0] && OK[1] && OK[2] && OK[3]);
+}
+
+template <typename R>
+__host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x1[4]) {
+  bool skipped;
+  solve2(A, b0, b1, x0, x1, skipped);
 }
 
 // Blend of Section 3.3.3: Theta_k = |res_k| / sum_i |N_{i,k}| (0 if the sum is
