@@ -30,9 +30,31 @@ PEAK_FP64 = 78.6e12      # flop/s, vector FP64
 PEAK_FP32 = 157.3e12     # flop/s, vector FP32
 
 
+def method_bytes(nt, fp32):
+    """The method's algorithmic HBM bytes per pass of an RK2/B step, per the
+    cost model of the hot-path scope: ideal vertex reuse (half a vertex
+    record per triangle), indices int32, reals of the triangle algebra's
+    precision q (8 FP64, 4 FP32). Per triangle:
+      triangle pass: corner ids 12 + coordinates 8 + Z 4q/2 + parts 12q,
+        stage 1 also saves the N parts 12q, stage 2 reads them 12q and W^n 16;
+      gather / update pass: CSR 14 + parts 12q + W read and written 32 +
+        1/V 4 + Z written 4q/2.
+    FP64: 228 / 244 B (stages 1 / 2), 162 B per gather; FP32 distribution:
+    124 / 140 B, 106 B per gather; about 800 and 480 B per triangle-step.
+    The CFL and wall passes are not in the model (0)."""
+    q = 4 if fp32 else 8
+    tri = 12 + 8 + 2 * q + 12 * q
+    gat = 14 + 12 * q + 32 + 4 + 2 * q
+    k = {"tri1": nt * (tri + 12 * q), "tri2": nt * (tri + 12 * q + 16), "gather1": nt * gat, "gather2": nt * gat,
+         "shared1": 0, "cfl": 0, "wall1": 0, "wall2": 0}
+    return k
+
+
 def algorithmic_bytes(nt, nv, fp32):
-    """Bytes each kernel of an RK2/B step with the CFL limit must move at
-    least once, with every vertex record read once per pass (ideal reuse).
+    """Implementation bytes: what each kernel of this library's RK2/B step
+    with the CFL limit moves at least once, with every vertex record read once
+    per pass (ideal reuse). Larger than method_bytes by the library's own
+    records (CSR slot positions, CFL terms per corner, the kept residual).
     q = bytes per real of the triangle algebra; a part or parameter vector is
     4 reals; parts live in vertex-CSR order (one record per corner)."""
     q = 4 if fp32 else 8
@@ -116,12 +138,26 @@ def measured_traffic(key):
     return None if v is None else int(v)
 
 
-def roofline_entry(name, bytes_, ms, traffic_key=None):
-    achieved = bytes_ / (ms * 1e-3)
+def roofline_entry(name, mbytes, ibytes, ms, traffic_key=None):
+    """Roofline of one kernel: `achieved` and `frac` from the method's
+    algorithmic bytes (method_bytes) over the kernel's average duration; the
+    implementation's own byte count beside it."""
+    achieved = mbytes / (ms * 1e-3)
+    impl = ibytes / (ms * 1e-3)
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": PEAK_HBM / 1e9,
             "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
             "traffic": measured_traffic(traffic_key) if traffic_key else None,
-            "algorithmic_bytes": int(bytes_), "avg_ms": round(ms, 5)}
+            "algorithmic_bytes": int(mbytes), "avg_ms": round(ms, 5),
+            "implementation": {"bytes": int(ibytes), "achieved": round(impl / 1e9, 1),
+                               "frac": round(impl / PEAK_HBM, 4)}}
+
+
+def step_roofline(nt, fp32, ms_step):
+    """The whole step against HBM: the method's bytes of all four passes over
+    the measured time per step."""
+    b = sum(method_bytes(nt, fp32).values())
+    return {"bytes": int(b), "achieved": round(b / (ms_step * 1e-3) / 1e9, 1),
+            "frac": round(b / (ms_step * 1e-3) / PEAK_HBM, 4)}
 
 
 STAGE1 = ("wall1", "tri1", "shared1", "cfl", "gather1")
@@ -211,9 +247,14 @@ def adjoint_ratio(rd, torch, mesh, W0, cfl, reps, tile):
 
 
 def batch_vs_single(rd, torch, inputs, n_meshes, steps, cfl, tile, seed=0):
-    """Four-quadrant problems of uneven size: per-mesh rd_step_cfl launches vs
-    one rd_batch_run graph, FP64, B / RK2, the same tile size for both (the
-    batch autotuner's choice when tile < 0); results are bitwise equal."""
+    """Four-quadrant problems of uneven size (side N ~ U{32..512}; rho, p ~
+    U[0.1, 2], |u| <= 1 per quadrant): per-mesh rd_step_cfl launches vs one
+    rd_batch_run graph, FP64, B / RK2, the same tile size for both (the batch
+    autotuner's choice, timed on 20-step graphs, when tile < 0). Equal
+    accuracy: every member's final state is bitwise the one its own run
+    gives. The B scheme is not positivity preserving and some members of
+    this draw go non-physical; they are listed (each member has its own
+    latch), and both forms must agree on which."""
     import numpy as np
     meshes, states = inputs.batch_problem(seed=seed, n=n_meshes)
     nt = sum(m["nt"] for m in meshes)
@@ -223,7 +264,7 @@ def batch_vs_single(rd, torch, inputs, n_meshes, steps, cfl, tile, seed=0):
     if tile < 0:
         for g, W in zip(gm, states):
             g.set_state(W)
-        tile, table = b.tune(cfl, rd.B, rd.RK2, rd.FP64, n_steps=steps)
+        tile, table = b.tune(cfl, rd.B, rd.RK2, rd.FP64, n_steps=20)
         tuned = {str(k): round(v, 5) for k, v in table.items()}
     else:
         b.set_tile(tile)
@@ -241,7 +282,23 @@ def batch_vs_single(rd, torch, inputs, n_meshes, steps, cfl, tile, seed=0):
         g.step_cfl(steps, cfl, rd.B, rd.RK2, rd.FP64)
     torch.cuda.synchronize()
     single = time.perf_counter() - t0
-    ref = [g.get_state() for g in gm]
+
+    def finish():
+        # final states (bit patterns, so NaNs compare too) and the members
+        # whose latch is set; the copy is made even when the latch is set
+        out, bad = [], []
+        for k, g in enumerate(gm):
+            st = np.zeros((4, g.nv))
+            try:
+                g.get_state(st)
+            except rd.RDError as e:
+                if e.status != rd.RD_ENONPHYS:
+                    raise
+                bad.append(k)
+            out.append(st.view(np.uint64))
+        return out, bad
+
+    ref, bad_single = finish()
     for g, W in zip(gm, states):
         g.set_state(W)
     b.run(steps, cfl, rd.B, rd.RK2, rd.FP64)       # captures the graph
@@ -252,13 +309,16 @@ def batch_vs_single(rd, torch, inputs, n_meshes, steps, cfl, tile, seed=0):
     b.run(steps, cfl, rd.B, rd.RK2, rd.FP64)
     torch.cuda.synchronize()
     batched = time.perf_counter() - t0
-    equal = all(np.array_equal(g.get_state(), r) for g, r in zip(gm, ref))
+    got, bad_batch = finish()
+    equal = all(np.array_equal(a, r) for a, r in zip(got, ref))
     b.close()
     for g in gm:
         g.close()
     return {"meshes": n_meshes, "triangles": nt, "steps": steps,
+            "draw": "rho, p ~ U[0.1, 2], |u| <= 1 per quadrant, side N ~ U{32..512}, seed %d" % seed,
             "per_instance_s": round(single, 4), "batched_graph_s": round(batched, 4),
             "speedup": round(single / batched, 3), "bitwise_equal": bool(equal),
+            "nonphysical_members": bad_batch, "nonphysical_agree": bad_batch == bad_single,
             "batched_value": round(nt * steps / batched, 1), "tile": tile, "tuner_ms_per_step": tuned}
 
 
@@ -303,7 +363,7 @@ def fp32_table(rd, inputs):
         ("Kelvin-Helmholtz 2048^2, B / RK2, 500 steps", inputs.split_square(2048),
          lambda m: inputs.ic_kelvin_helmholtz(m, seed=0), rd.B, rd.RK2, 0.4, 500, None),
         ("four-quadrant 512^2, B / RK2, 200 steps", inputs.split_square(512, periodic=(False, False)),
-         lambda m: inputs.ic_quadrants(m, inputs.quadrant_states(0, **inputs.BATCH_QUADRANTS)), rd.B, rd.RK2, 0.4, 200, None),
+         lambda m: inputs.ic_quadrants(m, inputs.quadrant_states(0, **inputs.NARROW_QUADRANTS)), rd.B, rd.RK2, 0.4, 200, None),
         ("Fourier density 256^2, B / RK2, 200 steps", inputs.split_square(256),
          lambda m: inputs.ic_fourier_density(m, seed=0), rd.B, rd.RK2, 0.4, 200, None),
     ]
@@ -452,8 +512,8 @@ def main():
     ap.add_argument("--tile", type=int, default=-1,
                     help="triangles per tile of the fused step (0: two-pass form; -1: run the autotuner)")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--batch", type=int, default=0, metavar="NMESH",
-                    help="also time NMESH four-quadrant meshes (32^2..512^2) per instance vs one batched graph")
+    ap.add_argument("--batch", type=int, default=256, metavar="NMESH",
+                    help="time NMESH four-quadrant meshes (32^2..512^2) per instance vs one batched graph (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-variants", action="store_true",
                     help="skip timing the Bx blend and selective lumping")
@@ -466,7 +526,7 @@ def main():
                     help="only time the three-dimensional path (128^3-cell box of tetrahedra, JSON)")
     ap.add_argument("--no-three-d", action="store_true", help="skip the three-dimensional timing")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run one 512 MiB device-to-device copy (known bytes) for counter calibration")
+                    help="first run one elementwise kernel of known traffic (2 GiB read, 2 GiB written) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path", file=sys.stderr)
@@ -478,12 +538,16 @@ def main():
     torch.cuda.set_device(0)
     rd.lib()
     if args.calibrate_copy:
-        src = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+        # counter calibration: one elementwise kernel that reads 2 GiB and
+        # writes 2 GiB, run after 1 GiB of other writes has replaced the
+        # source in the 256 MB Infinity Cache
+        src = torch.ones(256 * 2 ** 20, dtype=torch.float64, device="cuda")
+        flush = torch.ones(128 * 2 ** 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, flush
     if args.fp32_table:
         print(json.dumps({"fp32_errors": fp32_table(rd, inputs)}), flush=True)
         return
@@ -521,9 +585,10 @@ def main():
                                f"B scheme, RK2, CFL {args.cfl} (dt on device each step), "
                                "FP32 distribution + FP64 accumulation",
                    "triangles": nt, "vertices": nv, "seed": 0, "numbering": args.renumber},
-        "roofline": roofline_entry(dom32, b32[dom32], per32[dom32],
+        "roofline": roofline_entry(dom32, method_bytes(nt, True)[dom32], b32[dom32], per32[dom32],
                                    f"fp32/{form_name(form32['tile'])}/{dom32}"
                                    if args.renumber == "none" and args.N == 2048 else None),
+        "step_roofline": step_roofline(nt, True, ms32 / args.steps),
         "vertex_updates_per_s": round(nv * args.steps / (ms32 * 1e-3), 1),
         "stages": stage_rates(per32, nt),
         "kernels_ms": {k: round(v, 5) for k, v in per32.items()},
@@ -542,9 +607,10 @@ def main():
                           "ms_per_step": round(ms64 / args.steps, 5),
                           "vertex_updates_per_s": round(nv * args.steps / (ms64 * 1e-3), 1),
                           "stages": stage_rates(per64, nt),
-                          "roofline": roofline_entry(dom64, b64[dom64], per64[dom64],
+                          "roofline": roofline_entry(dom64, method_bytes(nt, False)[dom64], b64[dom64], per64[dom64],
                                                      f"fp64/{form_name(form64['tile'])}/{dom64}"
                                                      if args.renumber == "none" and args.N == 2048 else None),
+                          "step_roofline": step_roofline(nt, False, ms64 / args.steps),
                           "kernels_ms": {k: round(v, 5) for k, v in per64.items()},
                           "kernels_GBps": {k: round(b64[k] / (v * 1e-3) / 1e9, 1)
                                            for k, v in per64.items() if v > 0 and b64.get(k)},

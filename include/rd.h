@@ -194,7 +194,11 @@ rd_status rd_mesh_tile_info(const rd_mesh* mesh, int64_t info[4]);
  * one warm-up step and n_steps >= 1 timed steps (dt from `cfl`, as
  * rd_step_cfl), writes milliseconds per step to ms_per_step (may be NULL,
  * else n_candidates entries), selects the fastest size for the mesh and
- * returns it in *best. The mesh's state is restored afterwards. Waits. */
+ * returns it in *best; candidates are taken in the given order and a later
+ * one replaces the size kept so far only when it is more than 2% faster
+ * (about the spread of one timing), so the first candidate (the two-pass
+ * form by default) wins near-ties. The mesh's state is restored afterwards.
+ * Waits. */
 rd_status rd_tune(rd_mesh* mesh, double cfl, int scheme, int time, int precision, int n_steps,
                   const int* candidates, int n_candidates, double* ms_per_step, int* best);
 
@@ -303,7 +307,9 @@ rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, int64_t 
  * captured HIP graph (per-mesh CFL dt each step, computed on the device),
  * writes the states back to the meshes, and makes those streams wait for it.
  * Enqueues only. Meshes must share gamma and device and must not be periodic;
- * each mesh's result is bitwise what its own rd_step_cfl would give. */
+ * each mesh's result is bitwise what its own rd_step_cfl would give. A member
+ * whose state goes non-physical during the run has its own latch set
+ * (reported by rd_sync or rd_get_state on that mesh); the others do not. */
 rd_status rd_batch_create(rd_mesh* const* meshes, int n_meshes, void* stream, rd_batch** out);
 rd_status rd_batch_run(rd_batch* batch, int n_steps, double cfl, int scheme, int time, int precision);
 rd_status rd_batch_destroy(rd_batch* batch);

@@ -91,7 +91,7 @@ struct Dev {
   double* dt = nullptr;   // [n meshes] time step
   double* vr = nullptr;   // [3 per mesh] Bx sensor: smallest and largest |v| at the stage's state, domain size L
   int slump = 0;          // selective lumping in stage 2 (else global lumping)
-  int* flag = nullptr;    // non-physical state latch
+  int* flag = nullptr;    // non-physical state latch, one per mesh (batch) or one
   // tiled form
   D4* R1 = nullptr;       // [nv] stage-1 (or Euler) vertex residual, wall term included
   double* cflv = nullptr; // [nv] 2 V_i / sum_T l_max^T lambda_max^T
@@ -693,7 +693,7 @@ __host__ __device__ inline void vertex_epilogue(const Dev& d, int64_t v, const d
   if (fp32) d.Zf[v] = zq<float>(o);
   else d.Z[v] = zq<double>(o);
   if (with_sig) d.sig[v] = o.sig;
-  if (!o.ok) d.flag[0] = 1;
+  if (!o.ok) d.flag[d.vmesh ? d.vmesh[v] : 0] = 1;
 }
 
 // f(j, get(j)) for j = 0, ..., n-1 in that order. The loads of four

@@ -128,6 +128,10 @@ __global__ __launch_bounds__(kBlock) void k_aos_to_soa(const D4* src, double* so
 __global__ void k_set_scalar(double* p, double v) { p[0] = v; }
 __global__ void k_set_int(int* p, int v) { p[0] = v; }
 __global__ void k_or_int(int* dst, const int* src) { dst[0] = dst[0] | src[0]; }
+__global__ __launch_bounds__(kBlock) void k_fill_int(int* p, int v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
 
 
 __global__ __launch_bounds__(kBlock) void k_copy4(D4* dst, const D4* src, int64_t n) {
@@ -323,6 +327,12 @@ hipError_t launch_set_scalar(double* p, double v, hipStream_t s) {
 
 hipError_t launch_set_int(int* p, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3(nblk(n)), dim3(kBlock), 0, s, p, v, n);
   return hipGetLastError();
 }
 

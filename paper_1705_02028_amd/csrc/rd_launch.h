@@ -45,6 +45,8 @@ hipError_t launch_get_state(const Dev& d, const D4* src, double* soa, hipStream_
 hipError_t launch_aos_to_soa(const D4* src, double* soa, int64_t n, hipStream_t s);
 hipError_t launch_set_scalar(double* p, double v, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
+// p[0..n) = v
+hipError_t launch_fill_int(int* p, int v, int64_t n, hipStream_t s);
 // *dst |= *src
 hipError_t launch_or_int(int* dst, const int* src, hipStream_t s);
 hipError_t launch_copy4(D4* dst, const D4* src, int64_t n, hipStream_t s);

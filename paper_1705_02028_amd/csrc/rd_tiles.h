@@ -135,7 +135,7 @@ __host__ __device__ inline void tile_load2(int64_t tile, int32_t l, const Dev& d
   L.dW[l] = dw;
   const VertexDerived o = derive(d.gamma, ws.v);
   L.Z[l] = zq<R>(o);
-  if (!o.ok) d.flag[0] = 1;
+  if (!o.ok) d.flag[tile_mesh(tl, tile)] = 1;
   if (l < tl.nvi[tile]) L.Ws[l] = ws;
 }
 

@@ -23,3 +23,38 @@ def test_vertex_terms_and_precision_split():
     # the FP64 model is never smaller than the FP32 one, kernel by kernel
     a, b = bench.algorithmic_bytes(1000, 500, True), bench.algorithmic_bytes(1000, 500, False)
     assert all(b[n] >= a[n] for n in a)
+
+
+def test_method_bytes_from_the_arrays_of_a_periodic_mesh():
+    """The headline byte model (the method's traffic at ideal reuse) equals
+    the sizes of the arrays each pass must touch once on a periodic
+    split-square mesh, where every vertex has six triangles (nv = nt / 2):
+    int32 corner ids [3, nt]; float64 coordinates [2, nv]; parameter vectors
+    and states [4, nv]; parts [3, nt, 4] (and the saved stage-1 N parts);
+    CSR row pointers [nv] and slot indices [3, nt]; 1/V [nv] float64."""
+    import numpy as np
+    from paper_1705_02028_amd import inputs as I
+    m = I.split_square(33)
+    nt, nv = m["nt"], m["nv"]
+    assert 2 * nv == nt
+    ids = np.asarray(m["tri"], np.int32).nbytes
+    xy = 2 * nv * 8
+    for fp32, q in ((True, 4), (False, 8)):
+        z = 4 * nv * q                 # parameter vectors in the algebra's precision
+        parts = 3 * nt * 4 * q
+        w = 4 * nv * 8                 # conserved state, FP64
+        csr = nv * 4 + 3 * nt * 4
+        k = bench.method_bytes(nt, fp32)
+        assert k["tri1"] == ids + xy + z + parts + parts
+        assert k["tri2"] == ids + xy + z + parts + parts + w
+        assert k["gather1"] == k["gather2"] == csr + parts + 2 * w + nv * 8 + z
+
+
+def test_method_bytes_per_triangle_step():
+    """About 800 B per triangle-step for FP64 RK2/B and 480 B for the FP32
+    distribution; a forward-Euler N step (one triangle pass without the saved
+    parts, one gather) is 294 B in FP64."""
+    k64, k32 = bench.method_bytes(1, False), bench.method_bytes(1, True)
+    assert sum(k64.values()) == 796 and sum(k32.values()) == 476
+    assert (k64["tri1"] - 96) + k64["gather1"] == 294
+    assert (k64["tri1"], k64["tri2"], k32["tri1"]) == (228, 244, 124)

@@ -383,7 +383,7 @@ def test_batch_bitwise_equals_single_runs(orc, rd):
     one captured graph give, mesh by mesh, bitwise the result of each mesh's
     own run, and match the oracle."""
     sides = [17, 33, 9, 40, 24, 3, 50]
-    meshes, states = I.batch_problem(seed=3, sides=sides)
+    meshes, states = I.batch_problem(seed=3, sides=sides, draw=I.NARROW_QUADRANTS)
     for prec in (rd.FP64, rd.FP32_ACC64):
         singles = []
         for m, W in zip(meshes, states):
@@ -420,6 +420,93 @@ def test_batch_bitwise_equals_single_runs(orc, rd):
     assert err(g.get_state(), ref) <= 1e-11
     b.close()
     g.close()
+
+
+def _physical(W, gamma=1.4):
+    rho = W[0]
+    p = (gamma - 1.0) * (W[3] - 0.5 * (W[1] ** 2 + W[2] ** 2) / rho)
+    return bool(np.all(np.isfinite(W)) and np.all(rho > 0) and np.all(p > 0))
+
+
+def test_batch_draw_nonphysical_member_agrees_with_oracle(orc, rd):
+    """The batch workload's draw (rho, p ~ U[0.1, 2], |u| <= 1 per quadrant,
+    seed 0) includes problems on which the B scheme (not positivity
+    preserving) goes non-physical: member 6 (68^2 vertices) does so in its
+    6th RK2 step. The GPU and the oracle agree step by step up to that point
+    (same CFL dt, 1e-12) and on the step at which the state stops being
+    physical; in a batch only that member's latch is set, and every member,
+    that one included, is bitwise its own single run."""
+    sides = I.batch_sides(0, 256)
+    k = 6
+    assert sides[k] == 68
+    m = I.split_square(sides[k], periodic=(False, False), bc=("ghost", "ghost"))
+    W0 = I.ic_quadrants(m, I.quadrant_states(k, **I.BATCH_QUADRANTS))
+    om = orc.OracleMesh(m)
+    g = rd.Mesh(m)
+    g.set_state(W0)
+    Wo = W0
+    first_o = first_g = None
+    for s in range(12):
+        dt_o = om.max_dt(Wo, 0.4)
+        dt_g = g.max_dt(0.4)
+        assert abs(dt_g - dt_o) <= 1e-13 * dt_o
+        Wo = om.step(Wo, dt_o, orc.B, orc.RK2)
+        g.step(dt_g, rd.B, rd.RK2, rd.FP64)
+        Wg = np.zeros_like(W0)
+        try:
+            g.get_state(Wg)
+            ok_g = True
+        except rd.RDError as e:
+            assert e.status == rd.RD_ENONPHYS
+            ok_g = False
+        ok_o = _physical(Wo)
+        say(f"member {k} step {s + 1}: oracle physical {ok_o}, gpu physical {ok_g}")
+        if ok_o and ok_g:
+            assert err(Wg, Wo) <= TOL64
+        if not ok_o and first_o is None:
+            first_o = s
+        if not ok_g and first_g is None:
+            first_g = s
+        if first_o is not None and first_g is not None:
+            break
+    g.close()
+    assert first_o == first_g == 5
+    # a batch of three members of the same draw, one of which goes non-physical
+    idx = [3, 6, 11]
+    ms = [I.split_square(sides[j] if j == 6 else 20 + j, periodic=(False, False), bc=("ghost", "ghost"))
+          for j in idx]
+    Ws = [I.ic_quadrants(mm, I.quadrant_states(j, **I.BATCH_QUADRANTS)) for j, mm in zip(idx, ms)]
+    singles, bad_single = [], []
+    for j, mm, W in zip(idx, ms, Ws):
+        gg = rd.Mesh(mm)
+        gg.set_state(W)
+        gg.step_cfl(8, 0.4, rd.B, rd.RK2, rd.FP64)
+        out = np.zeros_like(W)
+        try:
+            gg.get_state(out)
+        except rd.RDError:
+            bad_single.append(j)
+        singles.append(out.view(np.uint64).copy())
+        gg.close()
+    gm = [rd.Mesh(mm) for mm in ms]
+    for gg, W in zip(gm, Ws):
+        gg.set_state(W)
+    b = rd.Batch(gm)
+    say("batch of the draw's members 3, 6, 11")
+    b.run(8, 0.4, rd.B, rd.RK2, rd.FP64)
+    bad_batch = []
+    for j, gg, ref in zip(idx, gm, singles):
+        out = np.zeros((4, gg.nv))
+        try:
+            gg.get_state(out)
+        except rd.RDError as e:
+            assert e.status == rd.RD_ENONPHYS
+            bad_batch.append(j)
+        assert np.array_equal(out.view(np.uint64), ref)
+    b.close()
+    for gg in gm:
+        gg.close()
+    assert bad_batch == bad_single == [6]
 
 
 def test_batch_rejects_periodic_and_empty(rd):

@@ -156,7 +156,7 @@ def test_tune_restores_state(orc, rd):
 
 def test_tiled_batch_bitwise_equals_single_runs(orc, rd):
     sides = [17, 33, 9, 40, 24, 3, 50]
-    meshes, states = I.batch_problem(seed=3, sides=sides)
+    meshes, states = I.batch_problem(seed=3, sides=sides, draw=I.NARROW_QUADRANTS)
     for prec in (rd.FP64, rd.FP32_ACC64):
         singles = [run(rd, m, W, 0.0, rd.B, rd.RK2, prec, 64, n=6, cfl=0.4) for m, W in zip(meshes, states)]
         gm = [rd.Mesh(m) for m in meshes]

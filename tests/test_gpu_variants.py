@@ -112,7 +112,7 @@ def test_variants_in_batches(orc, rd):
     """Per-mesh speed ranges and domain sizes: each batch member equals its
     own run bitwise; members with different lumpings are refused."""
     sides = [17, 33, 9, 40, 24]
-    meshes, states = I.batch_problem(seed=4, sides=sides)
+    meshes, states = I.batch_problem(seed=4, sides=sides, draw=I.NARROW_QUADRANTS)
     for scheme, lump in ((rd.BX, 0), (rd.B, 1), (rd.BX, 1)):
         for tile in (0, 64):
             prec = rd.FP64
