@@ -225,6 +225,27 @@ rd_status rd_residual(rd_mesh* mesh, int scheme, double* R, double* phiT, int on
 rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int scheme, int time,
                           const double* lam_np1, double* lam_n, int on_device);
 
+/* Allocation-free form of rd_adjoint_step, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation. Same arguments and result as rd_adjoint_step with
+ * on_device = 1 (W_n, lam_np1 and lam_n are device pointers [4][n_vertices],
+ * stream-ordered on the mesh's stream), computed by the same kernels; it
+ * calls no allocator. Its workspace is one fixed array of 128 MiB per GPU
+ * (held by the process from its first use on that GPU until exit), which
+ * fits meshes of about 130,000 vertices / 260,000 triangles; a larger mesh
+ * gives RD_EINVAL with the sizes in rd_last_error. flags: device int[2],
+ * cleared by the call, then set by the kernels: flags[0] = 1 when W_n or its
+ * recomputed first stage is non-physical, flags[1] = 1 when a triangle's
+ * solve skipped a column (exact stagnation, where lam_n is not the
+ * derivative); both 0 means lam_n is valid. Only enqueues and returns RD_OK
+ * (or an argument error: null pointer, dt, scheme, RD_EUNSUPPORTED for Bx
+ * and selective lumping); does not wait. Every call on one GPU shares that
+ * GPU's workspace, which keeps the last call's contents: calls that overlap
+ * on one GPU (different streams, or threads) race and must be serialised by
+ * the caller. */
+rd_status rd_adjoint_step_noalloc(rd_mesh* mesh, const double* W_n, double dt, int scheme, int time,
+                                  const double* lam_np1, double* lam_n, int* flags);
+
 /* Delaunay triangulation by edge flips (Section 2, the step that ends every
  * refinement iteration), on the current GPU. Input: n_vertices points (x, y
  * host arrays) and a triangulation of them, tri [3 * n_triangles] host

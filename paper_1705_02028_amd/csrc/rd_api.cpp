@@ -15,6 +15,7 @@
 #include "rd3_launch.h"
 #include "rd_delaunay.h"
 #include "rd_launch.h"
+#include "rd_noalloc.h"
 #include "rd_tiling.h"
 
 #define RD_API extern "C" __attribute__((visibility("default")))
@@ -115,8 +116,8 @@ struct rd_mesh {
   rd::AdjDev adj;
   rd::D4* adjW = nullptr;     // W^n of the step being reversed
   double* adjSig = nullptr;   // [nv] signal speeds of the recomputation (the mesh's stay with its state)
-  double* adjIn = nullptr;    // [4 nv] host staging (W^n, then dL/dW^{n+1})
-  double* adjOut = nullptr;   // [4 nv] dL/dW^n
+  double* adjIn = nullptr;    // [4 nv] host staging: W^n in, then dL/dW^n out
+  double* adjOut = nullptr;   // [4 nv] host staging: dL/dW^{n+1} in
   hipEvent_t events[RD_NKERNELS + 1] = {};
   // tiled form
   int tile = 0;                     // triangles per tile, 0: two-pass form
@@ -918,15 +919,54 @@ rd_status adjoint_status(rd_mesh* m) {
 
 }  // namespace
 
-RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int scheme, int time,
-                                 const double* lam_np1, double* lam_n, int on_device) {
-  if (!m || !W_n || !lam_np1 || !lam_n) return fail(RD_EINVAL, "null argument");
+namespace {
+
+rd_status adjoint_args(rd_mesh* m, double dt, int scheme, int time) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RD_EINVAL, "dt must be positive and finite");
   rd_status st = check_step_args(scheme, time, RD_FP64);
   if (st != RD_OK) return st;
   if (scheme == RD_BX) return fail(RD_EUNSUPPORTED, "the adjoint does not cover the Bx scheme");
   if (m->d.slump && time == RD_RK2)
     return fail(RD_EUNSUPPORTED, "the adjoint does not cover selective lumping");
+  return RD_OK;
+}
+
+// Enqueues the reverse of one step on the mesh's stream, all pointers on the
+// device: the step from W_n is recomputed on the buffers of `a` (W^n copy Wa,
+// signal speeds sig, latches a.flag) and the mesh's stage buffers; the mesh's
+// own state, signal speeds and latch are not touched.
+rd_status adjoint_enqueue(rd_mesh* m, const rd::AdjDev& a, rd::D4* Wa, double* sig, const double* W_n,
+                          double dt, int scheme, int time, const double* lam_np1, double* lam_n) {
+  hipStream_t s = m->stream;
+  rd::Dev d = dev_for(m, 0);
+  d.W = Wa;
+  d.sig = sig;
+  d.flag = a.flag;
+  // parameter vectors at W^n go straight to Zn (read by the stage-1 passes and
+  // the adjoint); the stage-1 gather writes those at W* to the mesh's Z
+  rd::Dev dn = d;
+  dn.Z = a.Zn;
+  HIPCHK(rd::launch_set_state(dn, W_n, 0, s));
+  HIPCHK(rd::launch_set_scalar(d.dt, dt, s));
+  const bool rk2 = time == RD_RK2;
+  if (rk2) {
+    HIPCHK(rd::launch_wall(dn, false, s));
+    HIPCHK(rd::launch_tri(dn, 0, scheme, 1, true, false, s));
+    HIPCHK(rd::launch_gather(d, 0, rd::G_STAGE1, nullptr, s));
+  }
+  HIPCHK(rd::launch_soa_to_aos(lam_np1, const_cast<rd::D4*>(a.lam), m->d.nv, s));
+  HIPCHK(rd::launch_adjoint(d, a, scheme, rk2 ? 1 : 0, lam_n, s));
+  m->zprec = -1;  // the parameter-vector buffer now holds the recomputation's values
+  return RD_OK;
+}
+
+}  // namespace
+
+RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int scheme, int time,
+                                 const double* lam_np1, double* lam_n, int on_device) {
+  if (!m || !W_n || !lam_np1 || !lam_n) return fail(RD_EINVAL, "null argument");
+  rd_status st = adjoint_args(m, dt, scheme, time);
+  if (st != RD_OK) return st;
   DeviceGuard g(m->device);
   const int64_t nv = m->d.nv, nt = m->d.nt;
   if (!m->adjW) {
@@ -958,43 +998,66 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     m->adjOut = out;
   }
   hipStream_t s = m->stream;
-  // the step is recomputed on private state, signal speeds and flag; the
-  // mesh's own W, |v| + c and non-physical latch are untouched
-  rd::Dev d = dev_for(m, 0);
-  d.W = m->adjW;
-  d.sig = m->adjSig;
-  d.flag = m->adj.flag;
   const double* src = W_n;
   if (!on_device) {
     HIPCHK(hipMemcpyAsync(m->adjIn, W_n, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, s));
     src = m->adjIn;
   }
-  // parameter vectors at W^n go straight to Zn (read by the stage-1 passes and
-  // the adjoint); the stage-1 gather writes those at W* to the mesh's Z
-  rd::Dev dn = d;
-  dn.Z = m->adj.Zn;
-  HIPCHK(rd::launch_set_state(dn, src, 0, s));
-  HIPCHK(rd::launch_set_scalar(d.dt, dt, s));
-  const bool rk2 = time == RD_RK2;
-  if (rk2) {
-    HIPCHK(rd::launch_wall(dn, false, s));
-    HIPCHK(rd::launch_tri(dn, 0, scheme, 1, true, false, s));
-    HIPCHK(rd::launch_gather(d, 0, rd::G_STAGE1, nullptr, s));
-  }
+  // dL/dW^n is written back to adjIn: its copy of W^n is consumed by the first
+  // kernel of the recomputation, which runs before (stream order)
   const double* lsrc = lam_np1;
   if (!on_device) {
-    HIPCHK(hipMemcpyAsync(m->adjIn, lam_np1, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, s));
-    lsrc = m->adjIn;
+    HIPCHK(hipMemcpyAsync(m->adjOut, lam_np1, sizeof(double) * 4 * nv, hipMemcpyHostToDevice, s));
+    lsrc = m->adjOut;
   }
-  HIPCHK(rd::launch_soa_to_aos(lsrc, const_cast<rd::D4*>(m->adj.lam), nv, s));
-  double* out = on_device ? lam_n : m->adjOut;
-  HIPCHK(rd::launch_adjoint(d, m->adj, scheme, rk2 ? 1 : 0, out, s));
-  m->zprec = -1;  // the parameter-vector buffer now holds the recomputation's values
+  double* out = on_device ? lam_n : m->adjIn;
+  if ((st = adjoint_enqueue(m, m->adj, m->adjW, m->adjSig, src, dt, scheme, time, lsrc, out)) != RD_OK) return st;
   if (!on_device) {
-    HIPCHK(hipMemcpyAsync(lam_n, m->adjOut, sizeof(double) * 4 * nv, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(lam_n, m->adjIn, sizeof(double) * 4 * nv, hipMemcpyDeviceToHost, s));
     return adjoint_status(m);
   }
   return RD_OK;
+}
+
+RD_API rd_status rd_adjoint_step_noalloc(rd_mesh* m, const double* W_n, double dt, int scheme, int time,
+                                         const double* lam_np1, double* lam_n, int* flags) {
+  if (!m || !W_n || !lam_np1 || !lam_n || !flags) return fail(RD_EINVAL, "null argument");
+  rd_status st = adjoint_args(m, dt, scheme, time);
+  if (st != RD_OK) return st;
+  const int64_t nv = m->d.nv, nt = m->d.nt, ns = m->d.ns;
+  // workspace layout: every buffer starts on a 256-byte boundary
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~size_t(255);
+    return at;
+  };
+  const size_t oLam = take(sizeof(rd::D4) * nv), oLamS = take(sizeof(rd::D4) * nv),
+               oLamN = take(sizeof(rd::D4) * nv), oZn = take(sizeof(rd::D4) * nv), oWa = take(sizeof(rd::D4) * nv),
+               oSig = take(sizeof(double) * nv), oCZ = take(sizeof(rd::D4) * ns), oCZW = take(sizeof(rd::ZW) * ns),
+               oKN = take(sizeof(rd::D4) * 2 * nt), oKT = take(sizeof(rd::D4) * nt);
+  if (off > rd::kNoallocScratchBytes)
+    return fail(RD_EINVAL, "mesh too large for the allocation-free adjoint: it needs " + std::to_string(off) +
+                               " bytes of workspace, the fixed workspace holds " +
+                               std::to_string(rd::kNoallocScratchBytes));
+  DeviceGuard g(m->device);
+  void* base = nullptr;
+  HIPCHK(rd::noalloc_scratch(&base));
+  char* p = static_cast<char*>(base);
+  rd::AdjDev a;
+  a.lam = reinterpret_cast<rd::D4*>(p + oLam);
+  a.lamS = reinterpret_cast<rd::D4*>(p + oLamS);
+  a.lamN = reinterpret_cast<rd::D4*>(p + oLamN);
+  a.Zn = reinterpret_cast<rd::D4*>(p + oZn);
+  a.cZ = reinterpret_cast<rd::D4*>(p + oCZ);
+  a.cZW = reinterpret_cast<rd::ZW*>(p + oCZW);
+  a.kN = reinterpret_cast<rd::D4*>(p + oKN);
+  a.kT = reinterpret_cast<rd::D4*>(p + oKT);
+  a.flag = flags;
+  // the latches start cleared on every call (a fill kernel, so the call can be captured)
+  HIPCHK(rd::launch_fill_int(flags, 0, 2, m->stream));
+  return adjoint_enqueue(m, a, reinterpret_cast<rd::D4*>(p + oWa), reinterpret_cast<double*>(p + oSig), W_n, dt,
+                         scheme, time, lam_np1, lam_n);
 }
 
 // ------------------------------------------------------------- batches --

@@ -49,7 +49,7 @@ class rd3_mesh_desc(C.Structure):
 
 EXPORTS = ["rd_mesh_validate", "rd_mesh_create", "rd_mesh_destroy", "rd_mesh_info", "rd_set_stream",
            "rd_set_state", "rd_get_state", "rd_max_dt", "rd_step", "rd_step_cfl", "rd_step_timed", "rd_residual",
-           "rd_adjoint_step", "rd_batch_create", "rd_batch_run", "rd_batch_destroy", "rd_sync",
+           "rd_adjoint_step", "rd_adjoint_step_noalloc", "rd_batch_create", "rd_batch_run", "rd_batch_destroy", "rd_sync",
            "rd_last_error", "rd_mesh_set_tile", "rd_mesh_get_tile", "rd_mesh_tile_info", "rd_tune",
            "rd_batch_set_tile", "rd_batch_tune", "rd_mesh_set_lumping", "rd_mesh_get_lumping",
            "rd_delaunay_flip", "rd_delaunay_refine", "rd3_mesh_create", "rd3_mesh_destroy", "rd3_set_state",
@@ -80,6 +80,7 @@ def lib():
             "rd_step_timed": [P, D, I, I, I, P],
             "rd_residual": [P, I, P, P, I],
             "rd_adjoint_step": [P, P, D, I, I, P, P, I],
+            "rd_adjoint_step_noalloc": [P, P, D, I, I, P, P, P],
             "rd_batch_create": [P, I, P, P],
             "rd_batch_run": [P, I, D, I, I, I],
             "rd_batch_destroy": [P],
@@ -295,6 +296,16 @@ def rd_adjoint_step(h, W_n, dt: float, scheme: int, time: int, lam_np1, lam_n) -
     dev = _is_torch(lam_n)
     _check(lib().rd_adjoint_step(h, _ptr(W_n, dev), float(dt), int(scheme), int(time),
                                  _ptr(lam_np1, dev), _ptr(lam_n, dev), int(dev)))
+
+
+def rd_adjoint_step_noalloc(h, W_n, dt: float, scheme: int, time: int, lam_np1, lam_n, flags) -> None:
+    """Device tensors only: W_n, lam_np1, lam_n float64 [4, nv]; flags int32 [2]
+    (set on the device: non-physical, skipped solve column)."""
+    if not (_is_torch(flags) and flags.is_cuda and str(flags.dtype) == "torch.int32" and flags.numel() >= 2
+            and flags.is_contiguous()):
+        raise ValueError("flags must be a contiguous int32 tensor of 2 elements on the GPU")
+    _check(lib().rd_adjoint_step_noalloc(h, _ptr(W_n, True), float(dt), int(scheme), int(time),
+                                         _ptr(lam_np1, True), _ptr(lam_n, True), flags.data_ptr()))
 
 
 def rd_batch_create(handles, stream=None):
