@@ -20,9 +20,17 @@ N, LDA, B, BMAX, BMIN, BX = 0, 1, 2, 3, 4, 5
 EULER1, RK2 = 1, 2
 
 
+def host_sanitize_flags() -> list:
+    """AddressSanitizer and UndefinedBehaviorSanitizer flags for a host build
+    when RD_HOST_SANITIZE is set (the process must then preload libasan)."""
+    if not os.environ.get("RD_HOST_SANITIZE"):
+        return []
+    return ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=all", "-g"]
+
+
 def compile_cmd(src: str, out: str) -> list:
     return ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
-            "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", out, src]
+            "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", out, src] + host_sanitize_flags()
 
 
 def build(force: bool = True) -> str:

@@ -38,7 +38,9 @@ void tiling_sizes(int64_t* out) {
 void tiling_arrays(int32_t* order, int32_t* tbeg, int32_t* vbeg, int32_t* nvi, int32_t* lpb, int32_t* lp, int32_t* tvl,
                    uint16_t* lv, int32_t* dst, int32_t* tmesh, int32_t* sv, int32_t* ssbeg) {
   const rd::TilePlan& P = g_plan;
-  auto cp = [](auto* out, const auto& v) { std::memcpy(out, v.data(), v.size() * sizeof(v[0])); };
+  auto cp = [](auto* out, const auto& v) {
+    if (!v.empty()) std::memcpy(out, v.data(), v.size() * sizeof(v[0]));
+  };
   cp(order, P.order);
   cp(tbeg, P.tbeg);
   cp(vbeg, P.vbeg);

@@ -16,6 +16,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
+import oracle
 from paper_1705_02028_amd import inputs as I
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,7 +29,8 @@ def build_shim():
     out = os.path.join(tempfile.mkdtemp(prefix="dl_"), "libdl.so")
     subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
                     "-Wno-unknown-pragmas", "-I", os.path.join(ROOT, "paper_1705_02028_amd", "csrc"),
-                    os.path.join(HERE, "cpp", "delaunay_shim.cpp"), "-o", out], check=True)
+                    os.path.join(HERE, "cpp", "delaunay_shim.cpp"), "-o", out] + oracle.host_sanitize_flags(),
+                   check=True)
     L = C.CDLL(out)
     P = C.c_void_p
     L.rdl_refine.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_double, P, P, C.c_int64, C.c_double,

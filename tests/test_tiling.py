@@ -15,6 +15,7 @@ import tempfile
 import numpy as np
 import pytest
 
+import oracle
 from paper_1705_02028_amd import inputs as I
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,7 +27,8 @@ def shim():
     out = os.path.join(tempfile.mkdtemp(prefix="tiling_"), "libtiling.so")
     subprocess.run(["g++", "-std=c++17", "-O1", "-fPIC", "-shared", "-Wall",
                     "-I", os.path.join(ROOT, "paper_1705_02028_amd", "csrc"),
-                    os.path.join(HERE, "cpp", "tiling_shim.cpp"), "-o", out], check=True)
+                    os.path.join(HERE, "cpp", "tiling_shim.cpp"), "-o", out] + oracle.host_sanitize_flags(),
+                   check=True)
     L = C.CDLL(out)
     L.tiling_build.restype = C.c_int
     L.tiling_build.argtypes = [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
