@@ -78,7 +78,7 @@ def test_cfl_steps_match_the_oracle(rd, O):
         ref = om.step(ref, om.max_dt(ref, 0.4), O.B, O.RK2)
     e = rel_err(got, ref)
     say(f"3d KH 6^3 cells, 10 CFL steps B/RK2: {e:.2e}")
-    assert e <= 1e-11
+    assert e <= 1e-12
     g.close()
 
 

@@ -3,14 +3,18 @@
 Tolerances, in the max field-normwise relative error
 max_i |a_i - b_i| / max_i |b_i| per field, per step from identical inputs,
 use the oracle's own sensitivity s(u): how far one oracle step moves when
-its input is perturbed by random relative amounts of size u.
-  * FP64: 1e-12, or 10 s(2^-52) when larger. s(2^-52) is ~1e-14 for N, LDA
-    and B; the Bmax/Bmin blends take one Theta for all four equations from a
-    ratio that can be dominated by rounding in one equation, and there it
-    reaches ~1e-12.
-  * FP32 distribution / FP64 accumulation: 10 s(2^-24) (at least 1e-6): the
-    parameter vectors enter the triangle algebra rounded to FP32 (relative
-    2^-24), and the algebra's own rounding is of the same order.
+its input is perturbed by random relative amounts of size u (four draws).
+  * FP64: 1e-12, or 3 s(2^-52) where that is larger. s(2^-52) is below
+    3.3e-13 for N, LDA and B on smooth states (the bar is then 1e-12); the
+    exceptions are the Bmax/Bmin blends, which take one Theta for all four
+    equations from a ratio that rounding in one equation can dominate
+    (s up to 1.6e-12 on the Kelvin-Helmholtz case), and states with
+    triangles at or near rest, where the pivoted solve is ill-conditioned
+    (the Sod tube's exact solution at t = 0.1: s ~ 1e-10).
+  * FP32 distribution / FP64 accumulation: 2 s(2^-24): the parameter vectors
+    enter the triangle algebra rounded to FP32 (relative 2^-24), and the
+    algebra's own rounding is of the same order. Measured errors are
+    0.11-0.78 s(2^-24) on every per-step case.
 Measured errors and bars are printed.
 """
 import os
@@ -38,7 +42,7 @@ def err(a, b):
     return max(np.abs(a[k] - b[k]).max() / max(np.abs(b[k]).max(), 1e-300) for k in range(4))
 
 
-def sensitivity(om, W, dt, scheme, time, rel=2.0 ** -52, reps=3, seed=0, ref=None):
+def sensitivity(om, W, dt, scheme, time, rel=2.0 ** -52, reps=4, seed=0, ref=None):
     """How far one oracle step moves under random relative input noise."""
     rng = np.random.default_rng(seed)
     if ref is None:
@@ -54,7 +58,7 @@ def tols(om, W, dt, scheme, time, ref=None):
     """(FP64 bar, FP32 bar) for one step of this case."""
     s64 = sensitivity(om, W, dt, scheme, time, 2.0 ** -52, ref=ref)
     s32 = sensitivity(om, W, dt, scheme, time, 2.0 ** -24, ref=ref)
-    return max(TOL64, 10.0 * s64), max(1e-6, 10.0 * s32)
+    return max(TOL64, 3.0 * s64), 2.0 * s32
 
 
 def say(*a):
@@ -128,7 +132,7 @@ def test_advected_sine_trajectory_n_euler(orc, rd):
         g.step(dts[n], rd.N, rd.EULER1, rd.FP64)
     e = err(g.get_state(), states[-1])
     say(f"advected sine 100-step end-state error {e:.2e}")
-    assert e <= 1e-11
+    assert e <= 1e-12
     g.close()
 
 
@@ -144,7 +148,7 @@ def test_step_cfl_matches_oracle_trajectory(orc, rd):
     g.step_cfl(10, 0.4, rd.B, rd.RK2, rd.FP64)
     e = err(g.get_state(), ref)
     say(f"step_cfl 10 steps error {e:.2e}")
-    assert e <= 1e-11
+    assert e <= 1e-12
     g.close()
 
 
@@ -417,7 +421,7 @@ def test_batch_bitwise_equals_single_runs(orc, rd):
     g.set_state(W)
     b = rd.Batch([g])
     b.run(6, 0.4, rd.B, rd.RK2, rd.FP64)
-    assert err(g.get_state(), ref) <= 1e-11
+    assert err(g.get_state(), ref) <= 1e-12
     b.close()
     g.close()
 

@@ -1,8 +1,8 @@
 """GPU parity of the Bx blend (Section 3.3.3) and of selective lumping
 (Section 3.4) against the CPU oracle, through the C ABI, in the two-pass and
 the tiled form, per step and over CFL-limited runs, alone and in batches.
-Bars as in test_gpu_parity: FP64 max(1e-12, 10 s(2^-52)), FP32_ACC64
-max(1e-6, 10 s(2^-24)), s the oracle's own sensitivity on the case.
+Bars as in test_gpu_parity: FP64 max(1e-12, 3 s(2^-52)), FP32_ACC64
+2 s(2^-24), s the oracle's own sensitivity on the case.
 """
 import numpy as np
 import pytest
@@ -91,7 +91,7 @@ def test_bx_and_lumping_cfl_runs(orc, rd):
         for _ in range(10):
             ref = om.step(ref, om.max_dt(ref, 0.4), scheme, orc.RK2)
         for tile in (0, 128):
-            for prec, bar in ((rd.FP64, 1e-11), (rd.FP32_ACC64, 1e-5)):
+            for prec, bar in ((rd.FP64, 1e-12), (rd.FP32_ACC64, 2e-7)):
                 say(f"cfl run scheme={scheme} lump={lump} tile={tile} prec={prec}")
                 e = err(run(rd, m, W, 0.0, scheme, rd.RK2, prec, tile, lump, n=10, cfl=0.4), ref)
                 say(f"  err {e:.2e}")
@@ -140,7 +140,7 @@ def test_variants_in_batches(orc, rd):
     ref = W
     for _ in range(5):
         ref = om.step(ref, om.max_dt(ref, 0.4), orc.BX, orc.RK2)
-    assert err(run(rd, m, W, 0.0, rd.BX, rd.RK2, rd.FP64, 0, 0, n=5, cfl=0.4), ref) <= 1e-11
+    assert err(run(rd, m, W, 0.0, rd.BX, rd.RK2, rd.FP64, 0, 0, n=5, cfl=0.4), ref) <= 1e-12
 
 
 def test_adjoint_refuses_bx_and_selective_lumping(rd):
