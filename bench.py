@@ -54,23 +54,26 @@ def algorithmic_bytes(nt, nv, fp32):
     """Implementation bytes: what each kernel of this library's RK2/B step
     with the CFL limit moves at least once, with every vertex record read once
     per pass (ideal reuse). Larger than method_bytes by the library's own
-    records (CSR slot positions, CFL terms per corner, the kept residual).
-    q = bytes per real of the triangle algebra; a part or parameter vector is
-    4 reals; parts live in vertex-CSR order (one record per corner)."""
+    records (the packed slot ranks, the CFL term per triangle, the triangle
+    of every part slot, the kept residual). q = bytes per real of the
+    triangle algebra; a part or parameter vector is 4 reals; parts live in
+    vertex-CSR order (one record per corner). The slice bases (4 bytes per
+    64 vertices) are left out."""
     q = 4 if fp32 else 8
     r4 = 4 * q
     k = {}
-    # stage 1: corner ids and CSR positions, coordinates, Z and |v|+c in;
+    # stage 1: corner ids and packed slot ranks, coordinates, Z and |v|+c in;
     # parts, kept N parts (corners 0 and 1), phi^T and l_max lambda_max per
-    # corner out (the CFL terms in the triangle algebra's precision)
-    k["tri1"] = nt * (12 + 12 + 3 * r4 + 2 * r4 + r4 + 3 * q) + nv * (16 + r4 + 8)
-    # CFL: CSR rows, V and the per-corner l_max lambda_max in, block minima out
+    # triangle out (the CFL term in the triangle algebra's precision)
+    k["tri1"] = nt * (12 + 4 + 3 * r4 + 2 * r4 + r4 + q) + nv * (16 + r4 + 8)
+    # CFL: CSR rows, V, the triangle of each of a vertex's slots and the
+    # triangles' l_max lambda_max in, block minima out
     k["shared1"] = 0
-    k["cfl"] = nv * (4 + 8) + nt * 3 * q
+    k["cfl"] = nv * (4 + 8) + nt * (3 * 4 + q)
     # gather 1: rows, parts in; W, V in; W*, W*-W, Z* out
     k["gather1"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + r4)
-    # stage 2: ids, positions, coordinates, Z*, W*-W, kept N parts, phi^T in; parts out
-    k["tri2"] = nt * (12 + 12 + 2 * r4 + r4 + 3 * r4) + nv * (16 + r4 + r4)
+    # stage 2: ids, ranks, coordinates, Z*, W*-W, kept N parts, phi^T in; parts out
+    k["tri2"] = nt * (12 + 4 + 2 * r4 + r4 + 3 * r4) + nv * (16 + r4 + r4)
     # gather 2: rows, parts in; W*, V in; W, Z, |v|+c out
     k["gather2"] = nt * 3 * r4 + nv * (4 + 32 + 8 + 32 + r4 + 8)
     k["wall1"] = k["wall2"] = 0

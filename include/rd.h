@@ -100,8 +100,8 @@ typedef struct {
 } rd_mesh_desc;
 
 /* Checks a mesh description on the host only (no GPU needed): indices in
- * range, positive unwrapped areas, every vertex in some triangle, valid wall
- * edges. RD_OK or RD_EINVAL. */
+ * range, positive unwrapped areas, every vertex in at least one and at most
+ * 1023 triangles, valid wall edges. RD_OK or RD_EINVAL. */
 rd_status rd_mesh_validate(const rd_mesh_desc* desc);
 
 /* Validates `desc`, precomputes vertex volumes V_i = sum |T|/3 (median dual,

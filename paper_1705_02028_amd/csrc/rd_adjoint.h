@@ -592,9 +592,10 @@ template <int SCHEME>
 __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const AdjDev& a) {
   const int64_t nt = d.nt;
   int32_t iv[3], ip[3];
+  const uint32_t rk = d.rk[t];
   for (int i = 0; i < 3; ++i) {
     iv[i] = d.tv[i * nt + t];
-    ip[i] = d.pos[i * nt + t];
+    ip[i] = corner_slot(d, iv[i], rk, i);
   }
   double nxd[3], nyd[3], area;
   tri_normals(d, iv, nxd, nyd, &area);
@@ -648,9 +649,10 @@ template <int SCHEME>
 __host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const AdjDev& a, bool rk2) {
   const int64_t nt = d.nt;
   int32_t iv[3], ip[3];
+  const uint32_t rk = d.rk[t];
   for (int i = 0; i < 3; ++i) {
     iv[i] = d.tv[i * nt + t];
-    ip[i] = d.pos[i * nt + t];
+    ip[i] = corner_slot(d, iv[i], rk, i);
   }
   double nxd[3], nyd[3];
   tri_normals(d, iv, nxd, nyd, nullptr);
@@ -698,7 +700,7 @@ __host__ __device__ inline void wall_bar(const Dev& d, int64_t v, const D4* src,
 __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const AdjDev& a) {
   double zb[4] = {0, 0, 0, 0}, wb[4] = {0, 0, 0, 0};
   const int32_t deg = d.row[v + 1] - d.row[v];
-  const int64_t s0 = d.sbeg[v];
+  const int64_t s0 = vslot(d, v);
   for_loaded(deg, [&](int32_t j) { return a.cZW[s0 + 64 * (int64_t)j]; }, [&](int32_t, const ZW& c) {
     for (int k = 0; k < 4; ++k) {
       zb[k] += c.z.v[k];
@@ -721,7 +723,7 @@ __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const 
 __host__ __device__ inline void adj_gather1_body(int64_t v, const Dev& d, const AdjDev& a, bool rk2, double* out) {
   double zb[4] = {0, 0, 0, 0};
   const int32_t deg = d.row[v + 1] - d.row[v];
-  const int64_t s0 = d.sbeg[v];
+  const int64_t s0 = vslot(d, v);
   for_loaded(deg, [&](int32_t j) { return a.cZ[s0 + 64 * (int64_t)j]; }, [&](int32_t, const D4& cz) {
     for (int k = 0; k < 4; ++k) zb[k] += cz.v[k];
   });

@@ -44,6 +44,11 @@ double unwrap_h(double d, double period) {
   return d;
 }
 
+// Largest vertex degree (triangles per vertex) a mesh may have: the rank of
+// a triangle among the triangles of each of its corner vertices is packed in
+// 10 bits.
+constexpr int32_t kMaxDegree = 1023;
+
 // Geometry the device does not recompute: vertex volumes (median dual).
 // Also the checks of rd_mesh_validate.
 struct HostGeom {
@@ -77,10 +82,19 @@ rd_status check_desc(const rd_mesh_desc* d, HostGeom* out) {
       return fail(RD_EINVAL, "triangle " + std::to_string(t) + " is not counter-clockwise with positive area");
     area[t] = a;
   }
+  std::vector<int32_t> deg(nv, 0);
   for (int64_t t = 0; t < nt; ++t)
-    for (int k = 0; k < 3; ++k) V[d->tri[3 * t + k]] += area[t] / 3.0;
-  for (int64_t i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) {
+      V[d->tri[3 * t + k]] += area[t] / 3.0;
+      ++deg[d->tri[3 * t + k]];
+    }
+  for (int64_t i = 0; i < nv; ++i) {
     if (!(V[i] > 0.0)) return fail(RD_EINVAL, "vertex " + std::to_string(i) + " belongs to no triangle");
+    // a triangle's rank among the triangles of each corner vertex is packed in 10 bits
+    if (deg[i] > kMaxDegree)
+      return fail(RD_EINVAL, "vertex " + std::to_string(i) + " belongs to " + std::to_string(deg[i]) +
+                                 " triangles; at most " + std::to_string(kMaxDegree) + " are supported");
+  }
   for (int64_t e = 0; e < d->n_wall_edges; ++e) {
     const int32_t a = d->wall_edges[2 * e], b = d->wall_edges[2 * e + 1];
     if (a < 0 || a >= nv || b < 0 || b >= nv || a == b)
@@ -478,40 +492,59 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
   d.nt = nt;
   d.nwv = (int32_t)m->wv.size();
   d.gamma = m->gamma;
+  d.igamma = 1.0 / m->gamma;
   d.px = m->px;
   d.py = m->py;
   {
     DeviceGuard g(m->device);
     std::vector<double2> xy(nv);
     for (int64_t i = 0; i < nv; ++i) xy[i] = make_double2(m->x[i], m->y[i]);
-    std::vector<int32_t> tv(3 * nt), pos(3 * nt), sbeg(nv);
+    std::vector<int32_t> tv(3 * nt);
+    std::vector<uint32_t> rk(nt, 0u);
     for (int64_t t = 0; t < nt; ++t)
       for (int k = 0; k < 3; ++k) tv[k * nt + t] = m->tri[3 * t + k];
-    // sliced part layout: 64-vertex slices, each as wide as its largest degree
+    // sliced part layout: 64-vertex slices, each as wide as its largest
+    // degree; the j-th part of vertex v sits at sbase[v / 64] + v % 64 + 64 j
+    const int64_t nsl = (nv + 63) / 64;
+    std::vector<int32_t> sbase(nsl);
     int64_t base = 0;
+    int32_t maxdeg = 0;
     for (int64_t g0 = 0; g0 < nv; g0 += 64) {
       const int64_t g1 = std::min<int64_t>(g0 + 64, nv);
       int32_t width = 0;
       for (int64_t v = g0; v < g1; ++v) width = std::max(width, m->row[v + 1] - m->row[v]);
-      for (int64_t v = g0; v < g1; ++v) sbeg[v] = (int32_t)(base + (v - g0));
+      sbase[g0 / 64] = (int32_t)std::min<int64_t>(base, INT32_MAX);
       base += 64 * (int64_t)width;
+      maxdeg = std::max(maxdeg, width);
     }
     if (base >= (int64_t(1) << 31)) {
       free_all(m);
       delete m;
       return fail(RD_EINVAL, "mesh too large for 32-bit part slots");
     }
+    if (maxdeg > kMaxDegree) {  // rd_mesh_validate's check has run; kept as a guard
+      free_all(m);
+      delete m;
+      return fail(RD_EINVAL, "a vertex belongs to " + std::to_string(maxdeg) + " triangles; at most " +
+                                 std::to_string(kMaxDegree) + " are supported");
+    }
     d.ns = base;
+    // rank of each triangle among the triangles of each of its corner vertices
+    // (10 bits per corner), and the triangle of every part slot
+    std::vector<int32_t> vtri(std::max<int64_t>(base, 1), -1);
     for (int64_t v = 0; v < nv; ++v)
       for (int32_t j = 0; j < m->row[v + 1] - m->row[v]; ++j) {
         const int32_t cs = m->slot[m->row[v] + j];  // corner 3 t + k is the j-th part of v
-        pos[(cs % 3) * nt + cs / 3] = sbeg[v] + 64 * j;
+        rk[cs / 3] |= (uint32_t)j << (10 * (cs % 3));
+        vtri[sbase[v / 64] + v % 64 + 64 * (int64_t)j] = cs / 3;
       }
     double2* pxy;
     double* pV;
-    int32_t *prow, *ptv, *ppos, *psbeg;
+    int32_t *prow, *ptv, *psbase, *pvtri;
+    uint32_t* prk;
     if ((st = upload(m, &pxy, xy)) || (st = upload(m, &pV, m->V)) || (st = upload(m, &prow, m->row)) ||
-        (st = upload(m, &ptv, tv)) || (st = upload(m, &ppos, pos)) || (st = upload(m, &psbeg, sbeg))) {
+        (st = upload(m, &ptv, tv)) || (st = upload(m, &prk, rk)) || (st = upload(m, &psbase, sbase)) ||
+        (st = upload(m, &pvtri, vtri))) {
       free_all(m);
       delete m;
       return st;
@@ -520,8 +553,9 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
     d.V = pV;
     d.row = prow;
     d.tv = ptv;
-    d.pos = ppos;
-    d.sbeg = psbeg;
+    d.rk = prk;
+    d.sbase = psbase;
+    d.vtri = pvtri;
     if (has_bc) {
       int32_t *pbc, *pwv, *pwptr;
       rd::WallEnt* pwent;
@@ -548,7 +582,7 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
     double *sig, *lam, *dt, *scratch;
     int* flag;
     if ((st = dalloc(m, &W, nv)) || (st = dalloc(m, &Ws, nv)) || (st = dalloc(m, &Z, nv)) ||
-        (st = dalloc(m, &sig, nv)) || (st = dalloc(m, &lam, d.ns)) || (st = dalloc(m, &dt, 1)) ||
+        (st = dalloc(m, &sig, nv)) || (st = dalloc(m, &lam, nt)) || (st = dalloc(m, &dt, 1)) ||
         (st = dalloc(m, &flag, 1)) || (st = dalloc(m, &scratch, 4 * std::max(nv, nt)))) {
       free_all(m);
       delete m;

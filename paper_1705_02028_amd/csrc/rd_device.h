@@ -14,7 +14,11 @@
 // part (ascending triangle order) of the slice's l-th vertex sits at
 // slice_base + 64 j + l. The triangle passes write each corner's part
 // straight to its slot; the gather's j-th load is then one contiguous,
-// fully coalesced read across the wavefront.
+// fully coalesced read across the wavefront. A corner's slot is formed from
+// its vertex v (slice v / 64, lane v % 64) and the rank j of the triangle
+// among v's triangles; the three ranks of a triangle are packed 10 bits
+// each into one word, so a triangle pass reads 4 bytes of slot data per
+// triangle instead of three 32-bit slot positions.
 //
 // Algebra used on the GPU (equal in exact arithmetic to Appendix A's explicit
 // entries): with unit normal n, Roe state (u, v, h, c), w = u n_x + v n_y,
@@ -59,15 +63,17 @@ struct Dev {
   int64_t nv = 0, nt = 0;
   int32_t nwv = 0;
   double gamma = 1.4, px = 0.0, py = 0.0;
+  double igamma = 1.0 / 1.4;  // 1 / gamma (set with gamma on the host)
   // geometry and connectivity
   const double2* xy = nullptr;   // [nv]
   const double* V = nullptr;     // [nv] vertex volume
   const int32_t* row = nullptr;  // [nv+1] CSR row pointers (row[v+1] - row[v] = degree of v)
-  const int32_t* sbeg = nullptr; // [nv] first part slot of v; its j-th part is at sbeg[v] + 64 j
+  const int32_t* sbase = nullptr; // [ceil(nv/64)] first part slot of each 64-vertex slice
   int64_t ns = 0;                // part slots, including the padding of the 64-vertex slices
+  const int32_t* vtri = nullptr; // [ns] triangle of each part slot (padding slots unused)
   const int32_t* bc = nullptr;   // [nv] or null: boundary code, see is_ghost / wall_index
   const int32_t* tv = nullptr;   // [3][nt] corner vertex ids
-  const int32_t* pos = nullptr;  // [3][nt] part slot of corner (t, i)
+  const uint32_t* rk = nullptr;  // [nt] rank of t among the triangles of corner i's vertex, bits 10 i .. 10 i + 9
   const int32_t* wv = nullptr;   // [nwv] wall vertex ids
   const int32_t* wptr = nullptr; // [nwv+1]
   const WallEnt* went = nullptr; // wall incidences, ascending edge id per vertex
@@ -86,7 +92,7 @@ struct Dev {
   void* keepT = nullptr;  // [nt] stage-1 triangle residual (D4 or F4)
   D4* WCn = nullptr;      // [nwv] wall term at W^n
   D4* WCs = nullptr;      // [nwv] wall term at W*
-  void* lam = nullptr;    // [ns] l_max^T lambda_max^T, sliced layout: float from the FP32 triangle
+  void* lam = nullptr;    // [nt] l_max^T lambda_max^T per triangle: float from the FP32 triangle
                           // passes, double from the FP64 ones and from the CFL-only pass
   double* dt = nullptr;   // [n meshes] time step
   double* vr = nullptr;   // [3 per mesh] Bx sensor: smallest and largest |v| at the stage's state, domain size L
@@ -102,6 +108,14 @@ struct Dev {
 // but its state enters its neighbours' wall terms).
 __host__ __device__ inline bool is_ghost(int32_t bc) { return bc == -2 || bc <= -3; }
 __host__ __device__ inline int32_t wall_index(int32_t bc) { return bc >= 0 ? bc : (bc <= -3 ? -3 - bc : -1); }
+
+// First part slot of vertex v: its j-th part is at vslot(d, v) + 64 j.
+__host__ __device__ inline int64_t vslot(const Dev& d, int64_t v) { return (int64_t)d.sbase[v >> 6] + (v & 63); }
+
+// Part slot of corner i (vertex v) of a triangle with rank word rk.
+__host__ __device__ inline int32_t corner_slot(const Dev& d, int32_t v, uint32_t rk, int i) {
+  return d.sbase[v >> 6] + (v & 63) + 64 * (int32_t)((rk >> (10 * i)) & 1023u);
+}
 
 __host__ __device__ inline double unwrap(double d, double period) {
   if (period > 0.0) {
@@ -373,6 +387,7 @@ template <> __host__ __device__ inline const Q4<float>* zbuf<float>(const Dev& d
 template <typename R>
 struct TriIn {
   int32_t iv[3], ip[3];
+  uint32_t rk;
   double2 p[3];
   Q4<R> Z[3];
   double sig[3];
@@ -381,10 +396,8 @@ struct TriIn {
 template <typename R>
 __host__ __device__ inline void tri_load_ids(int64_t t, const Dev& d, TriIn<R>& in) {
   const int64_t nt = d.nt;
-  for (int i = 0; i < 3; ++i) {
-    in.iv[i] = d.tv[i * nt + t];
-    in.ip[i] = d.pos[i * nt + t];
-  }
+  for (int i = 0; i < 3; ++i) in.iv[i] = d.tv[i * nt + t];
+  in.rk = d.rk[t];
 }
 
 template <typename R, bool CFL>
@@ -394,6 +407,7 @@ __host__ __device__ inline void tri_load_verts(const Dev& d, TriIn<R>& in) {
     in.p[i] = d.xy[in.iv[i]];
     in.Z[i] = Zp[in.iv[i]];
     if (CFL) in.sig[i] = d.sig[in.iv[i]];
+    in.ip[i] = corner_slot(d, in.iv[i], in.rk, i);
   }
 }
 
@@ -414,7 +428,7 @@ struct GlobalIO {
     for (int k = 0; k < 4; ++k) q.v[k] = out[k];
     reinterpret_cast<Q4<R>*>(d.C)[ip[i]] = q;
   }
-  __host__ __device__ void lam(int i, double x) const { reinterpret_cast<R*>(d.lam)[ip[i]] = (R)x; }
+  __host__ __device__ void cfl(int64_t t, double x) const { reinterpret_cast<R*>(d.lam)[t] = (R)x; }
   // Where the corner coefficients wait while the 4x4 solve runs (kept in
   // registers here; see CornerLds).
 };
@@ -465,7 +479,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
 
   // dW_i = M(Zbar)(Z_i - Z_0), M = dW/dZ
   R dWh[3][4];
-  const R igam = (R)(1.0 / d.gamma);
+  const R igam = (R)d.igamma;
   for (int k = 0; k < 4; ++k) dWh[0][k] = R(0);
   for (int i = 1; i < 3; ++i) {
     R dz[4];
@@ -503,11 +517,10 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   }
 
   if (CFL) {
-    // CFL limit of Section 3.2: l_max^T max_j(|v_j| + c_j), one copy per corner
+    // CFL limit of Section 3.2: l_max^T max_j(|v_j| + c_j) of the triangle
     double lam = 0.0;
     for (int i = 0; i < 3; ++i) lam = rmax(lam, in.sig[i]);
-    const double lt = (double)lmax * lam;
-    for (int i = 0; i < 3; ++i) io.lam(i, lt);
+    io.cfl(t, (double)lmax * lam);
   }
 
   // triangle residual and the N right-hand side
@@ -534,7 +547,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     for (int k = 0; k < 4; ++k) rhs1[k] = phiT[k];
   } else {
     idt = io.idt(t);
-    mass = (R)((0.5 * (d1x * d2y - d1y * d2x)) / 3.0);
+    mass = (R)((0.5 * (d1x * d2y - d1y * d2x)) * (1.0 / 3.0));
     if (needL) {
       R srate[4] = {R(0), R(0), R(0), R(0)};
       for (int i = 0; i < 3; ++i) {
@@ -757,7 +770,7 @@ __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out
   }
   double acc[4];
   const int32_t deg = d.row[v + 1] - d.row[v];
-  const int64_t s0 = d.sbeg[v];
+  const int64_t s0 = vslot(d, v);
   sum_parts<R>(deg, [&](int32_t j) { return ld4<R>(d.C, s0 + 64 * (int64_t)j); }, acc);
   if (b >= 0) {
     const D4 wn = d.WCn[b];
@@ -835,8 +848,8 @@ __host__ __device__ inline void wall_body(int64_t b, const Dev& d) {
   st4<double>(STAGE2 ? d.WCs : d.WCn, b, acc);
 }
 
-// l_max^T lambda_max^T of one triangle, written to its three CSR positions
-// (the same arithmetic as the fused form in tri_body).
+// l_max^T lambda_max^T of one triangle (the same arithmetic as the fused form
+// in tri_body).
 __host__ __device__ inline void cfl_tri_body(int64_t t, const Dev& d) {
   const int64_t nt = d.nt;
   const int32_t iv[3] = {d.tv[t], d.tv[nt + t], d.tv[2 * nt + t]};
@@ -850,18 +863,19 @@ __host__ __device__ inline void cfl_tri_body(int64_t t, const Dev& d) {
     lmax = rmax(lmax, (double)sqrt(nxd[i] * nxd[i] + nyd[i] * nyd[i]));
     lam = rmax(lam, d.sig[iv[i]]);
   }
-  const double lt = lmax * lam;
-  for (int i = 0; i < 3; ++i) reinterpret_cast<double*>(d.lam)[d.pos[i * nt + t]] = lt;
+  reinterpret_cast<double*>(d.lam)[t] = lmax * lam;
 }
 
-// 2 V_i / sum_{T ni i} l_max lambda_max of one vertex (terms of type R).
+// 2 V_i / sum_{T ni i} l_max lambda_max of one vertex (terms of type R), its
+// triangles taken in ascending order.
 template <typename R = double>
 __host__ __device__ inline double cfl_vertex_bound(int64_t v, const Dev& d) {
   double acc = 0.0;
   const int32_t deg = d.row[v + 1] - d.row[v];
-  const int64_t s0 = d.sbeg[v];
+  const int64_t s0 = vslot(d, v);
   const R* lam = reinterpret_cast<const R*>(d.lam);
-  for_loaded(deg, [&](int32_t j) { return lam[s0 + 64 * (int64_t)j]; }, [&](int32_t, R x) { acc += (double)x; });
+  for_loaded(deg, [&](int32_t j) { return d.vtri[s0 + 64 * (int64_t)j]; },
+             [&](int32_t, int32_t t) { acc += (double)lam[t]; });
   return 2.0 * d.V[v] / acc;
 }
 

@@ -35,9 +35,9 @@ __global__ __launch_bounds__(kBlock) void k_cfl_tri(Dev d) {
   if (t < d.nt) cfl_tri_body(t, d);
 }
 
-// Per-vertex CFL bounds 2 V_i / sum l_max lambda_max (summed from the sliced
-// corner terms, or read from the bounds the tiled passes store) and their
-// block minima.
+// Per-vertex CFL bounds 2 V_i / sum l_max lambda_max (summed over the terms of
+// the vertex's triangles, or read from the bounds the tiled passes store) and
+// their block minima.
 template <bool FROM_CFLV, typename R>
 __global__ __launch_bounds__(kBlock) void k_cfl_vertex(Dev d, CflPlan p) {
   const int b = blockIdx.x;

@@ -34,9 +34,9 @@ hipError_t launch_cfl(const Dev& d, const CflPlan& p, double cfl, hipStream_t s)
 // vertex blocks as the CFL reduction; mode 0 at W^n, 1 at W* (Ws), 2 at W*
 // rebuilt from R1 (tiled form)
 hipError_t launch_vrange(const Dev& d, const CflPlan& p, int mode, hipStream_t s);
-// part 0: l_max lambda_max per triangle corner (FP64); part 1: per-vertex
-// bounds (sums of the sliced terms, float when fp32: as the FP32 triangle
-// pass writes them) and block minima; part 3: the same from the bounds the
+// part 0: l_max lambda_max per triangle (FP64); part 1: per-vertex bounds
+// (sums of the terms of the vertex's triangles, float when fp32: as the FP32
+// triangle pass writes them) and block minima; part 3: the same from the bounds the
 // tiled passes store in d.cflv; part 2: per-mesh minimum -> d.dt
 hipError_t launch_cfl_part(const Dev& d, const CflPlan& p, double cfl, int part, hipStream_t s, int fp32 = 0);
 hipError_t launch_set_state(const Dev& d, const double* soa, int fp32, hipStream_t s);

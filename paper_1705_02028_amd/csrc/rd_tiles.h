@@ -99,9 +99,13 @@ struct TileIO {
     if (dst[i] < 0) L.P[-1 - dst[i]] = q;
     else reinterpret_cast<Q4<R>*>(Cs)[dst[i]] = q;
   }
-  __host__ __device__ void lam(int i, double x) const {
-    if (dst[i] < 0) L.lam[-1 - dst[i]] = x;
-    else lams[dst[i]] = x;
+  // the triangle's CFL term goes to each of its corners (interior corners in
+  // LDS, shared ones to the shared-slot buffer)
+  __host__ __device__ void cfl(int64_t, double x) const {
+    for (int i = 0; i < 3; ++i) {
+      if (dst[i] < 0) L.lam[-1 - dst[i]] = x;
+      else lams[dst[i]] = x;
+    }
   }
 };
 

@@ -105,6 +105,25 @@ def test_periodic_unwrap_accepted_by_validation(rd):
         rd.rd_mesh_validate(m2)
 
 
+def test_host_validation_limits_vertex_degree(rd):
+    """A vertex may belong to at most 1023 triangles (the triangle's rank
+    among a corner vertex's triangles is packed in 10 bits): a fan of n
+    triangles around one centre vertex is accepted for n = 1023 and refused
+    for n = 1024."""
+    for n, ok in ((1023, True), (1024, False)):
+        a = 2 * np.pi * np.arange(n) / n
+        x = np.concatenate([[0.0], np.cos(a)])
+        y = np.concatenate([[0.0], np.sin(a)])
+        tri = np.array([[0, 1 + k, 1 + (k + 1) % n] for k in range(n)], dtype=np.int32)
+        m = {"x": x, "y": y, "tri": tri, "nv": n + 1, "nt": n, "px": 0.0, "py": 0.0}
+        if ok:
+            rd.rd_mesh_validate(m)
+        else:
+            with pytest.raises(rd.RDError, match="at most 1023") as e:
+                rd.rd_mesh_validate(m)
+            assert e.value.status == rd.RD_EINVAL
+
+
 def test_host_validation_rejects_sizes_beyond_32_bit_indices(rd):
     """3 n_triangles and n_vertices must stay below 2^31 (int32 corner and
     slot indices); the check runs before any array is read."""
