@@ -327,8 +327,12 @@ rd_status rd_delaunay_refine(int64_t* n_vertices, double* x, double* y, int64_t 
  * members' streams, takes each mesh's current state, runs n_steps steps in one
  * captured HIP graph (per-mesh CFL dt each step, computed on the device),
  * writes the states back to the meshes, and makes those streams wait for it.
- * Enqueues only. Meshes must share gamma and device and must not be periodic;
- * each mesh's result is bitwise what its own rd_step_cfl would give. A member
+ * Enqueues only. Meshes must share gamma and device; members periodic on an
+ * axis must share the period on that axis, and a member that is not periodic
+ * on such an axis must have an extent of at most that period and no triangle or
+ * wall edge spanning more than half of it along the axis (RD_EINVAL
+ * otherwise). Each mesh's result is bitwise what its own rd_step_cfl would
+ * give. A member
  * whose state goes non-physical during the run has its own latch set
  * (reported by rd_sync or rd_get_state on that mesh); the others do not. */
 rd_status rd_batch_create(rd_mesh* const* meshes, int n_meshes, void* stream, rd_batch** out);

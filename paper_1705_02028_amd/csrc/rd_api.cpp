@@ -1136,14 +1136,49 @@ RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd
   *out = nullptr;
   if (!meshes || n <= 0) return fail(RD_EINVAL, "empty batch");
   const double gamma = meshes[0] ? meshes[0]->gamma : 0.0;
+  // The batch unwraps triangles with one period per axis: the members that
+  // are periodic on an axis must share their period there. A member that is
+  // not periodic on that axis is laid out as it is; unwrapping leaves its
+  // triangles and wall edges alone when every coordinate difference along
+  // them is at most half the period, and its tiles' centroids (strictly
+  // inside its extent) stay put when that extent is at most the period (both
+  // checked).
+  double bp[2] = {0.0, 0.0};
+  for (int k = 0; k < n; ++k) {
+    const rd_mesh* m = meshes[k];
+    if (!m) return fail(RD_EINVAL, "null mesh in batch");
+    const double mp[2] = {m->px, m->py};
+    for (int a = 0; a < 2; ++a)
+      if (mp[a] > 0.0) {
+        if (bp[a] == 0.0) bp[a] = mp[a];
+        else if (mp[a] != bp[a])
+          return fail(RD_EINVAL, "batched meshes periodic on the same axis must share the period");
+      }
+  }
+  for (int k = 0; k < n; ++k) {
+    const rd_mesh* m = meshes[k];
+    const double mp[2] = {m->px, m->py};
+    const std::vector<double>* c[2] = {&m->x, &m->y};
+    for (int a = 0; a < 2; ++a) {
+      if (bp[a] == 0.0 || mp[a] > 0.0) continue;
+      const std::vector<double>& q = *c[a];
+      const auto r = std::minmax_element(q.begin(), q.end());
+      bool ok = *r.second - *r.first <= bp[a];
+      for (size_t t = 0; ok && t < m->tri.size(); t += 3)
+        for (int i = 1; i < 3; ++i) ok = ok && std::fabs(q[m->tri[t + i]] - q[m->tri[t]]) <= 0.5 * bp[a];
+      for (size_t e = 0; ok && e < m->wall.size(); e += 2)
+        ok = std::fabs(q[m->wall[e + 1]] - q[m->wall[e]]) <= 0.5 * bp[a];
+      if (!ok)
+        return fail(RD_EINVAL, "batched mesh " + std::to_string(k) + " is not periodic on an axis where others are, "
+                               "and its extent or a triangle's extent along that axis is too large for their period");
+    }
+  }
   std::vector<double> x, y;
   std::vector<int32_t> tri, wall;
   std::vector<uint8_t> ghost;
   std::vector<int64_t> voff{0}, toff{0};
   for (int k = 0; k < n; ++k) {
     const rd_mesh* m = meshes[k];
-    if (!m) return fail(RD_EINVAL, "null mesh in batch");
-    if (m->px != 0.0 || m->py != 0.0) return fail(RD_EINVAL, "batched meshes must not be periodic");
     if (m->gamma != gamma) return fail(RD_EINVAL, "batched meshes must share gamma");
     if (m->device != meshes[0]->device) return fail(RD_EINVAL, "batched meshes must live on one device");
     const int32_t vo = (int32_t)voff.back();
@@ -1163,8 +1198,8 @@ RD_API rd_status rd_batch_create(rd_mesh* const* meshes, int n, void* stream, rd
   desc.x = x.data();
   desc.y = y.data();
   desc.tri = tri.data();
-  desc.period_x = 0.0;
-  desc.period_y = 0.0;
+  desc.period_x = bp[0];
+  desc.period_y = bp[1];
   desc.ghost = ghost.data();
   desc.n_wall_edges = (int64_t)wall.size() / 2;
   desc.wall_edges = wall.empty() ? nullptr : wall.data();

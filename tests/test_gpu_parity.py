@@ -513,14 +513,88 @@ def test_batch_draw_nonphysical_member_agrees_with_oracle(orc, rd):
     assert bad_batch == bad_single == [6]
 
 
-def test_batch_rejects_periodic_and_empty(rd):
-    g = rd.Mesh(I.split_square(8))
-    with pytest.raises(rd.RDError) as e:
-        rd.Batch([g])
-    assert e.value.status == rd.RD_EINVAL
+def test_batch_with_periodic_members(orc, rd):
+    """Members periodic on both axes (Kelvin-Helmholtz and Fourier-density
+    problems of different sizes on the unit square), one periodic on x only
+    (a channel with walls) and one bounded four-quadrant member advance
+    together in one graph: each is bitwise equal to its own run, and the
+    periodic ones match the oracle."""
+    ms = [I.split_square(24), I.split_square(33, diagonal="random", seed=2),
+          I.split_square(30, periodic=(True, False), bc=("ghost", "wall"), diagonal="random", seed=5),
+          I.split_square(40, periodic=(False, False), bc=("ghost", "ghost"))]
+    Ws = [I.ic_kelvin_helmholtz(ms[0], seed=1), I.ic_fourier_density(ms[1], seed=0),
+          I.random_smooth_state(ms[2], seed=4, amp=0.2),
+          I.ic_quadrants(ms[3], I.quadrant_states(4, **I.NARROW_QUADRANTS))]
+    for prec in (rd.FP64, rd.FP32_ACC64):
+        singles = []
+        for m, W in zip(ms, Ws):
+            say(f"periodic batch single nt={m['nt']} prec={prec}")
+            g = rd.Mesh(m)
+            g.set_state(W)
+            g.step_cfl(6, 0.4, rd.B, rd.RK2, prec)
+            singles.append(g.get_state())
+            g.close()
+        gm = [rd.Mesh(m) for m in ms]
+        for g, W in zip(gm, Ws):
+            g.set_state(W)
+        b = rd.Batch(gm)
+        say(f"periodic batch run prec={prec}")
+        b.run(6, 0.4, rd.B, rd.RK2, prec)
+        for g, ref in zip(gm, singles):
+            assert np.array_equal(g.get_state().view(np.uint64), ref.view(np.uint64))
+        b.close()
+        for g in gm:
+            g.close()
+        if prec == rd.FP64:
+            # the tiled form: its results do not depend on the tiling, so the
+            # batch's own tiles give each member's tiled single run bitwise
+            tiled = []
+            for m, W in zip(ms, Ws):
+                g = rd.Mesh(m)
+                g.tile = 64
+                g.set_state(W)
+                g.step_cfl(6, 0.4, rd.B, rd.RK2, prec)
+                tiled.append(g.get_state())
+                g.close()
+            gm = [rd.Mesh(m) for m in ms]
+            for g, W in zip(gm, Ws):
+                g.set_state(W)
+            b = rd.Batch(gm)
+            b.set_tile(128)
+            say("periodic batch run, tiles of 128")
+            b.run(6, 0.4, rd.B, rd.RK2, prec)
+            for g, ref in zip(gm, tiled):
+                assert np.array_equal(g.get_state().view(np.uint64), ref.view(np.uint64))
+            b.close()
+            for g in gm:
+                g.close()
+            for k in (0, 1, 2):
+                om = orc.OracleMesh(ms[k])
+                ref = Ws[k]
+                for _ in range(6):
+                    ref = om.step(ref, om.max_dt(ref, 0.4), orc.B, orc.RK2)
+                e = err(singles[k], ref)
+                say(f"  member {k} vs oracle {e:.2e}")
+                assert e <= TOL64
+
+
+def test_batch_refuses_mixed_periods_and_empty(rd):
+    """One period per axis: members periodic on an axis must share it, and a
+    bounded member next to them must be fine enough that unwrapping leaves it
+    alone."""
+    a = rd.Mesh(I.split_square(16))
+    b = rd.Mesh(I.split_square(16, length=2.0))            # period 2 on both axes
+    c = rd.Mesh(I.split_square(2, periodic=(False, False)))  # one cell: triangles span the whole unit square
+    d = rd.Mesh(I.split_square(8, periodic=(False, False)))  # fine enough
+    for members, msg in (([a, b], "share the period"), ([a, c], "too large")):
+        with pytest.raises(rd.RDError, match=msg) as e:
+            rd.Batch(members)
+        assert e.value.status == rd.RD_EINVAL
+    rd.Batch([a, d]).close()
     with pytest.raises(rd.RDError):
         rd.rd_batch_create([])
-    g.close()
+    for g in (a, b, c, d):
+        g.close()
 
 
 # ------------------------------------------------------------- adjoint ---
