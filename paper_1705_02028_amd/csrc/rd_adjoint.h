@@ -38,6 +38,7 @@ struct AdjDev {
   D4* kT = nullptr;          // [nt] cotangent of kept stage-1 residual
   D4* wcbar = nullptr;       // [nwv] cotangent of the wall term at W^n (stage 1 + half of stage 2)
   int* flag = nullptr;       // [2]: [0] the recomputed step went non-physical, [1] a solve skipped a column
+  double idt = 0.0;          // 1 / dt of the step being reversed
 };
 
 // Cotangents of the quantities shared by all corners of a triangle.
@@ -189,12 +190,14 @@ __host__ __device__ inline void build_A_bar(const Roe<double>& q, const Corner<d
   qb.ic += q.g1 * Gb[3];
 }
 
-// Inputs of the stage-2 function of one triangle besides its parameter vectors.
+// Inputs of the stage-2 function of one triangle besides its parameter
+// vectors: the records are read where they are used (not held in registers
+// across the triangle's forward recomputation).
 struct Stage2In {
   double mass = 0.0, idt = 0.0;
-  double dw[3][4];     // W*_i - W^n_i
-  double keepN[3][4];  // stage-1 N parts
-  double keepT[4];     // stage-1 residual
+  const D4* dw[3] = {nullptr, nullptr, nullptr};  // W*_i - W^n_i
+  const D4* kn[2] = {nullptr, nullptr};           // stage-1 N parts of corners 0 and 1
+  const D4* kt = nullptr;                         // stage-1 residual
 };
 struct Stage2Bar {
   double dw[3][4];
@@ -204,19 +207,21 @@ struct Stage2Bar {
 
 // Reverse of one triangle. Zc: corner parameter vectors; geometry from the
 // unwrapped normals (nxd, nyd). ob[i]: cotangent of the scheme's part of
-// corner i. Stage 1 also takes the cotangents of the kept N parts (kNb) and
-// residual (kTb); stage 2 takes its extra inputs in s2 and returns theirs in
+// corner i. Stage 1 also takes the cotangents of the kept N parts of corners
+// 0 and 1 (kNs, two records) and of the kept residual (kTs), or null for a
+// forward Euler step; stage 2 takes its extra inputs in s2 and returns theirs in
 // s2b. Returns the corner cotangents of Z in Zb.
 // Returns true when the pivoted solve skipped a column (A singular), where
 // the cotangents are not the derivative.
 template <int SCHEME, int STAGE>
 __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3], const double nyd[3], double gamma,
-                                            const double ob[3][4], const double kNb[3][4], const double kTb[4],
+                                            double igamma,
+                                            const double ob[3][4], const D4* kNs, const D4* kTs,
                                             const Stage2In* s2, Stage2Bar* s2b, double Zb[3][4]) {
   // ---------------- forward (recomputed, as in tri_compute) ----------------
   Roe<double> q;
   q.g1 = gamma - 1.0;
-  const double third = 1.0 / 3.0, igam = 1.0 / gamma;
+  const double third = 1.0 / 3.0, igam = igamma;
   double zb[4];
   for (int k = 0; k < 4; ++k) zb[k] = (Zc[0].v[k] + Zc[1].v[k] + Zc[2].v[k]) * third;
   const double iz = 1.0 / zb[0];
@@ -239,7 +244,6 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
     dWh[i][3] = (zb[3] * dz[i][0] + q.g1 * (zb[1] * dz[i][1] + zb[2] * dz[i][2]) + zb[0] * dz[i][3]) * igam;
   }
   Corner<double> kc[3];
-  double lam[3][3];  // l1, l2, l3 per corner
   const double hic = 0.5 * q.ic;
   for (int i = 0; i < 3; ++i) {
     const double L = sqrt(nxd[i] * nxd[i] + nyd[i] * nyd[i]);
@@ -249,11 +253,9 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
     k.ny = nyd[i] * iL;
     k.s = 0.5 * L;
     k.w = q.u * k.nx + q.v * k.ny;
-    lam[i][0] = k.w + q.c;
-    lam[i][1] = k.w - q.c;
-    lam[i][2] = k.w;
-    const double p1 = rmax(lam[i][0], 0.0), p2 = rmax(lam[i][1], 0.0), p3 = rmax(lam[i][2], 0.0);
-    const double m1 = rmin(lam[i][0], 0.0), m2 = rmin(lam[i][1], 0.0), m3 = rmin(lam[i][2], 0.0);
+    const double l1 = k.w + q.c, l2 = k.w - q.c, l3 = k.w;
+    const double p1 = rmax(l1, 0.0), p2 = rmax(l2, 0.0), p3 = rmax(l3, 0.0);
+    const double m1 = rmin(l1, 0.0), m2 = rmin(l2, 0.0), m3 = rmin(l3, 0.0);
     const double sh = k.s * hic;
     k.l3p = k.s * p3;
     k.h1p = sh * (p1 - p3);
@@ -275,9 +277,12 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
   if (STAGE == 1) {
     for (int k = 0; k < 4; ++k) rhs1[k] = phiT[k];
   } else {
-    for (int i = 0; i < 3; ++i)
-      for (int k = 0; k < 4; ++k) srate[k] += s2->dw[i][k] * s2->idt;
-    for (int k = 0; k < 4; ++k) rhs1[k] = s2->mass * srate[k] + 0.5 * (s2->keepT[k] + phiT[k]);
+    for (int i = 0; i < 3; ++i) {
+      const D4 w = *s2->dw[i];
+      for (int k = 0; k < 4; ++k) srate[k] += w.v[k] * s2->idt;
+    }
+    const D4 kt = SCHEME == SCH_N ? D4{{0.0, 0.0, 0.0, 0.0}} : *s2->kt;
+    for (int k = 0; k < 4; ++k) rhs1[k] = s2->mass * srate[k] + 0.5 * (kt.v[k] + phiT[k]);
   }
   // A^{-1} (columns from unit right-hand sides) and the two solutions
   double Ai[4][4];
@@ -324,10 +329,26 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
       pN[2][k] = phiT[k] - pN[0][k] - pN[1][k];
       pl[2][k] = rhs1[k] - pl[0][k] - pl[1][k];
     }
+    // stage 2: the kept stage-1 N parts (corner 2's formed as the forward
+    // pass forms it, phi^T(n) minus corners 0 and 1) and W* - W^n
+    double kn[3][4], dw[3][4];
+    if (STAGE == 2) {
+      const D4 z = {{0.0, 0.0, 0.0, 0.0}};
+      const bool keep = SCHEME != SCH_LDA;
+      const D4 k0 = keep ? *s2->kn[0] : z, k1 = keep ? *s2->kn[1] : z, kt = keep ? *s2->kt : z;
+      for (int k = 0; k < 4; ++k) {
+        kn[0][k] = k0.v[k];
+        kn[1][k] = k1.v[k];
+        kn[2][k] = kt.v[k] - k0.v[k] - k1.v[k];
+      }
+      for (int i = 0; i < 3; ++i) {
+        const D4 w = *s2->dw[i];
+        for (int k = 0; k < 4; ++k) dw[i][k] = w.v[k];
+      }
+    }
     for (int i = 0; i < 3; ++i)
       for (int k = 0; k < 4; ++k) {
-        const double PN =
-            STAGE == 1 ? pN[i][k] : s2->mass * (s2->dw[i][k] * s2->idt) + 0.5 * (s2->keepN[i][k] + pN[i][k]);
+        const double PN = STAGE == 1 ? pN[i][k] : s2->mass * (dw[i][k] * s2->idt) + 0.5 * (kn[i][k] + pN[i][k]);
         den[k] = den[k] + fabs(PN);
         thb[k] = thb[k] + ob[i][k] * (PN - pl[i][k]);
         spos |= (PN > 0.0 ? 1u : 0u) << (4 * i + k);
@@ -335,11 +356,15 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
       }
   }
   bool active[4] = {false, false, false, false};  // Theta_k = |r_k| / den_k, not 0/0, not clamped
+  double idn[4] = {0, 0, 0, 0};                    // 1 / den_k (0 where den_k = 0)
   double ratio[4] = {0, 0, 0, 0};                    // |r_k| / den_k before the clamp and the Bmax/Bmin pick
   int pick = 0;
   if (SCHEME >= SCH_B) {
     for (int k = 0; k < 4; ++k) {
-      const double qq = den[k] == 0.0 ? 0.0 : fabs(rhs1[k]) / den[k];
+      // the forward pass's quotient: |r_k| times the reciprocal of den_k
+      // (the reciprocal is kept for the reverse)
+      idn[k] = den[k] == 0.0 ? 0.0 : 1.0 / den[k];
+      const double qq = fabs(rhs1[k]) * idn[k];
       active[k] = den[k] != 0.0 && !(qq > 1.0);
       ratio[k] = qq;
       th[k] = qq > 1.0 ? 1.0 : qq;
@@ -366,9 +391,8 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
     }
     for (int k = 0; k < 4; ++k) {
       if (!active[k]) continue;
-      const double id = 1.0 / den[k];
-      rhs1b[k] += thb[k] * sgn(rhs1[k]) * id;
-      denb[k] = -thb[k] * ratio[k] * id;
+      rhs1b[k] += thb[k] * sgn(rhs1[k]) * idn[k];
+      denb[k] = -thb[k] * ratio[k] * idn[k];
     }
   }
   double xLb[4] = {0, 0, 0, 0}, xNb[4] = {0, 0, 0, 0}, dWhb[3][4];
@@ -391,12 +415,20 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
         plb[i][k] = ob[i][k] * (1.0 - th[k]);
       }
       if (STAGE == 1) {
-        pNb[i][k] = PNb + kNb[i][k];
+        pNb[i][k] = PNb;
       } else {
         pNb[i][k] = 0.5 * PNb;
         s2b->keepN[i][k] = 0.5 * PNb;
         s2b->dw[i][k] = s2->mass * s2->idt * PNb;
       }
+    }
+  }
+  if (STAGE == 1 && kNs) {
+    // cotangents of the kept stage-1 N parts of corners 0 and 1
+    const D4 c0 = kNs[0], c1 = kNs[1];
+    for (int k = 0; k < 4; ++k) {
+      pNb[0][k] += c0.v[k];
+      pNb[1][k] += c1.v[k];
     }
   }
   // corner 2's parts: rhs1 and phi^T minus those of corners 0 and 1
@@ -429,7 +461,8 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
   }
   for (int k = 0; k < 4; ++k) rhs1b[k] += rb[k];
   if (STAGE == 1) {
-    for (int k = 0; k < 4; ++k) phiTb[k] += rhs1b[k] + kTb[k];
+    const D4 ct = kTs ? *kTs : D4{{0.0, 0.0, 0.0, 0.0}};
+    for (int k = 0; k < 4; ++k) phiTb[k] += rhs1b[k] + ct.v[k];
   } else {
     for (int k = 0; k < 4; ++k) {
       phiTb[k] += 0.5 * rhs1b[k];
@@ -438,17 +471,16 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
       for (int i = 0; i < 3; ++i) s2b->dw[i][k] += rateb;
     }
   }
-  build_A_bar(q, kc, bNb, xN, rb, xL, qb, kb);
-  for (int i = 1; i < 3; ++i) {
-    apply_split_bar(q, kc[i], kc[i].l3m, kc[i].h1m, kc[i].h2m, dWh[i], bNb, dWhb[i], qb, kb[i], kb[i].l3m, kb[i].h1m,
-                    kb[i].h2m);
-    apply_full_bar(q, kc[i], dWh[i], phiTb, dWhb[i], qb, kb[i]);
-  }
-  // corners: (l3, h1, h2)^{+-} from the eigenvalues, w = u nx + v ny
-  for (int i = 0; i < 3; ++i) {
+  // corners: (l3, h1, h2)^{+-} from the eigenvalues, w = u nx + v ny; a
+  // corner's coefficients are reversed as soon as its cotangents are complete
+  // (corner 0 after the matrix A, corners 1 and 2 after their K^- and K
+  // products), which ends their live ranges early
+  auto corner_bar = [&](int i) {
     const Corner<double>& k = kc[i];
-    const double p[3] = {rmax(lam[i][0], 0.0), rmax(lam[i][1], 0.0), rmax(lam[i][2], 0.0)};
-    const double m[3] = {rmin(lam[i][0], 0.0), rmin(lam[i][1], 0.0), rmin(lam[i][2], 0.0)};
+    // the eigenvalues again, as the forward part forms them
+    const double l[3] = {k.w + q.c, k.w - q.c, k.w};
+    const double p[3] = {rmax(l[0], 0.0), rmax(l[1], 0.0), rmax(l[2], 0.0)};
+    const double m[3] = {rmin(l[0], 0.0), rmin(l[1], 0.0), rmin(l[2], 0.0)};
     const double sh = k.s * hic;
     double pb[3] = {0, 0, 0}, mb[3] = {0, 0, 0};
     pb[2] += k.s * kb[i].l3p;
@@ -465,11 +497,19 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
                        kb[i].h2m * (m[1] - m[2]);
     qb.ic += 0.5 * k.s * shb;
     double lb[3];
-    for (int j = 0; j < 3; ++j) lb[j] = (lam[i][j] > 0.0 ? pb[j] : 0.0) + (lam[i][j] < 0.0 ? mb[j] : 0.0);
+    for (int j = 0; j < 3; ++j) lb[j] = (l[j] > 0.0 ? pb[j] : 0.0) + (l[j] < 0.0 ? mb[j] : 0.0);
     const double wb = kb[i].w + lb[0] + lb[1] + lb[2];
     qb.c += lb[0] - lb[1];
     qb.u += wb * k.nx;
     qb.v += wb * k.ny;
+  };
+  build_A_bar(q, kc, bNb, xN, rb, xL, qb, kb);
+  corner_bar(0);
+  for (int i = 1; i < 3; ++i) {
+    apply_split_bar(q, kc[i], kc[i].l3m, kc[i].h1m, kc[i].h2m, dWh[i], bNb, dWhb[i], qb, kb[i], kb[i].l3m, kb[i].h1m,
+                    kb[i].h2m);
+    apply_full_bar(q, kc[i], dWh[i], phiTb, dWhb[i], qb, kb[i]);
+    corner_bar(i);
   }
   // Roe average and dW = M(zbar)(Z_i - Z_0)
   double zbb[4] = {0, 0, 0, 0}, dzb[3][4];
@@ -506,7 +546,7 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
   qb.v += q.ic * qb.vc;
   qb.ic += q.v * qb.vc;
   qb.c += -q.ic * q.ic * qb.ic;
-  const double c2b = qb.c / (2.0 * q.c);
+  const double c2b = 0.5 * qb.c * q.ic;
   qb.h += q.g1 * c2b;
   q2b += -0.5 * q.g1 * c2b;
   qb.u += 2.0 * q.u * q2b;
@@ -601,27 +641,22 @@ __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const Adj
   tri_normals(d, iv, nxd, nyd, &area);
   D4 Zc[3];
   Stage2In s2;
-  s2.mass = area / 3.0;
-  s2.idt = 1.0 / d.dt[0];
+  s2.mass = area * (1.0 / 3.0);
+  s2.idt = a.idt;
+  const D4* keepN = reinterpret_cast<const D4*>(d.keepN);
+  s2.kn[0] = keepN + 2 * t;
+  s2.kn[1] = keepN + 2 * t + 1;
+  s2.kt = reinterpret_cast<const D4*>(d.keepT) + t;
   double ob[3][4];
-  // kept stage-1 N parts: corners 0 and 1 stored, corner 2 formed as the forward pass forms it
-  const D4 kt = ld4<double>(d.keepT, t);
-  D4 kn[3] = {ld4<double>(d.keepN, 2 * t), ld4<double>(d.keepN, 2 * t + 1), kt};
-  for (int k = 0; k < 4; ++k) kn[2].v[k] = kt.v[k] - kn[0].v[k] - kn[1].v[k];
   for (int i = 0; i < 3; ++i) {
     // W* = W^n at ghosts, whose parameter vectors the stage-1 gather leaves alone
     Zc[i] = (d.bc && is_ghost(d.bc[iv[i]])) ? a.Zn[iv[i]] : d.Z[iv[i]];
-    const D4 dw = ld4<double>(d.dW, iv[i]);
-    for (int k = 0; k < 4; ++k) {
-      s2.dw[i][k] = dw.v[k];
-      s2.keepN[i][k] = SCHEME == SCH_LDA ? 0.0 : kn[i].v[k];
-    }
+    s2.dw[i] = reinterpret_cast<const D4*>(d.dW) + iv[i];
     mu_of(d, a.lam, iv[i], ob[i]);
   }
-  for (int k = 0; k < 4; ++k) s2.keepT[k] = SCHEME == SCH_N ? 0.0 : kt.v[k];
   Stage2Bar s2b;
   double Zb[3][4];
-  if (tri_adjoint<SCHEME, 2>(Zc, nxd, nyd, d.gamma, ob, nullptr, nullptr, &s2, &s2b, Zb)) a.flag[1] = 1;
+  if (tri_adjoint<SCHEME, 2>(Zc, nxd, nyd, d.gamma, d.igamma, ob, nullptr, nullptr, &s2, &s2b, Zb)) a.flag[1] = 1;
   for (int i = 0; i < 3; ++i) {
     ZW c;
     for (int k = 0; k < 4; ++k) {
@@ -657,18 +692,17 @@ __host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const Adj
   double nxd[3], nyd[3];
   tri_normals(d, iv, nxd, nyd, nullptr);
   D4 Zc[3];
-  double ob[3][4], kNb[3][4], kTb[4];
+  double ob[3][4];
   for (int i = 0; i < 3; ++i) {
     Zc[i] = a.Zn[iv[i]];
     mu_of(d, a.lamS, iv[i], ob[i]);
-    // cotangents of the kept values (corners 0 and 1, and phi^T below)
-    const D4 kn = rk2 && i < 2 ? a.kN[2 * t + i] : D4{{0.0, 0.0, 0.0, 0.0}};
-    for (int k = 0; k < 4; ++k) kNb[i][k] = kn.v[k];
   }
-  const D4 kt = rk2 ? a.kT[t] : D4{{0.0, 0.0, 0.0, 0.0}};
-  for (int k = 0; k < 4; ++k) kTb[k] = kt.v[k];
+  // cotangents of the kept values (N parts of corners 0 and 1, phi^T), read
+  // where the reverse needs them
+  const D4* kNs = rk2 ? a.kN + 2 * t : nullptr;
+  const D4* kTs = rk2 ? a.kT + t : nullptr;
   double Zb[3][4];
-  if (tri_adjoint<SCHEME, 1>(Zc, nxd, nyd, d.gamma, ob, kNb, kTb, nullptr, nullptr, Zb)) a.flag[1] = 1;
+  if (tri_adjoint<SCHEME, 1>(Zc, nxd, nyd, d.gamma, d.igamma, ob, kNs, kTs, nullptr, nullptr, Zb)) a.flag[1] = 1;
   for (int i = 0; i < 3; ++i) st4<double>(a.cZ, ip[i], Zb[i]);
 }
 

@@ -989,7 +989,9 @@ rd_status adjoint_enqueue(rd_mesh* m, const rd::AdjDev& a, rd::D4* Wa, double* s
     HIPCHK(rd::launch_gather(d, 0, rd::G_STAGE1, nullptr, s));
   }
   HIPCHK(rd::launch_soa_to_aos(lam_np1, const_cast<rd::D4*>(a.lam), m->d.nv, s));
-  HIPCHK(rd::launch_adjoint(d, a, scheme, rk2 ? 1 : 0, lam_n, s));
+  rd::AdjDev ad = a;
+  ad.idt = 1.0 / dt;
+  HIPCHK(rd::launch_adjoint(d, ad, scheme, rk2 ? 1 : 0, lam_n, s));
   m->zprec = -1;  // the parameter-vector buffer now holds the recomputation's values
   return RD_OK;
 }
