@@ -109,9 +109,9 @@ def algorithmic_bytes_tiled(nt, nv, fp32, info):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_kh2048.txt")
 
 
-# The sources that define the two-pass triangle kernels (their bodies,
-# launch shapes and the translation unit they are compiled in).
-TRI_SOURCES = ("rd_device.h", "rd_kcommon.h", "rd_launch.h", "rd_kernels.hip")
+# The sources that define the triangle kernels of both forms (their bodies,
+# launch shapes and the translation units they are compiled in).
+TRI_SOURCES = ("rd_device.h", "rd_kcommon.h", "rd_launch.h", "rd_kernels.hip", "rd_tiles.h", "rd_tiles.hip")
 
 
 def source_hash():

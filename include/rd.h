@@ -221,7 +221,8 @@ rd_status rd_residual(rd_mesh* mesh, int scheme, double* R, double* phiT, int on
  * inverse and lam_n is not the derivative: RD_EUNSUPPORTED). With
  * on_device = 0 the call waits and returns that status; with on_device = 1
  * it only enqueues and the next rd_sync returns it. Either way the latch is
- * cleared once reported. */
+ * cleared once reported. lam_n must not overlap lam_np1 (lam_np1 is read
+ * while lam_n is written). */
 rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int scheme, int time,
                           const double* lam_np1, double* lam_n, int on_device);
 

@@ -27,8 +27,20 @@ struct alignas(64) ZW {
   D4 z, w;
 };
 
+// A field of cotangents, one 4-vector per vertex: records (AoS) or the
+// caller's structure-of-arrays layout [4][n].
+struct LamAoS {
+  const D4* p = nullptr;
+  __host__ __device__ D4 at(int64_t v) const { return p[v]; }
+};
+struct LamSoA {
+  const double* p = nullptr;
+  int64_t n = 0;
+  __host__ __device__ D4 at(int64_t v) const { return D4{{p[v], p[n + v], p[2 * n + v], p[3 * n + v]}}; }
+};
+
 struct AdjDev {
-  const D4* lam = nullptr;   // [nv] dL/dW^{n+1}
+  LamSoA lam;                // dL/dW^{n+1}, the caller's [4][nv]
   D4* lamS = nullptr;        // [nv] dL/dW*
   D4* lamN = nullptr;        // [nv] running dL/dW^n (output)
   D4* Zn = nullptr;          // [nv] parameter vectors at W^n
@@ -605,10 +617,11 @@ __host__ __device__ inline void wall_flux_bar(const double w[4], double gamma, d
 namespace rd {
 
 // mu = -(dt / V) lam at a vertex whose update uses its residual (0 at ghosts).
-__host__ __device__ inline void mu_of(const Dev& d, const D4* lam, int64_t v, double mu[4]) {
+template <class L>
+__host__ __device__ inline void mu_of(const Dev& d, const L& lam, int64_t v, double mu[4]) {
   const bool ghost = d.bc && is_ghost(d.bc[v]);
   const double f = ghost ? 0.0 : -d.dt[0] / d.V[v];
-  const D4 l = lam[v];
+  const D4 l = lam.at(v);
   for (int k = 0; k < 4; ++k) mu[k] = f * l.v[k];
 }
 
@@ -695,7 +708,7 @@ __host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const Adj
   double ob[3][4];
   for (int i = 0; i < 3; ++i) {
     Zc[i] = a.Zn[iv[i]];
-    mu_of(d, a.lamS, iv[i], ob[i]);
+    mu_of(d, LamAoS{a.lamS}, iv[i], ob[i]);
   }
   // cotangents of the kept values (N parts of corners 0 and 1, phi^T), read
   // where the reverse needs them
@@ -708,22 +721,23 @@ __host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const Adj
 
 // Wall-term transpose at one wall vertex b: sum over its wall edges of
 // (dF_v/dW_v)^T (|e|/2)(alpha mu_v + (1 - alpha) mu_other), mu = cotangent of
-// the wall term (mu_of(lamA) * sa + mu_of(lamB) * sb).
-__host__ __device__ inline void wall_bar(const Dev& d, int64_t v, const D4* src, const D4* lamA, double sa,
-                                         const D4* lamB, double sb, double Wb[4]) {
+// the wall term (mu_of(lamA) * sa, plus mu_of(lamB) * sb when useB).
+template <class LA, class LB>
+__host__ __device__ inline void wall_bar(const Dev& d, int64_t v, const D4* src, const LA& lamA, double sa,
+                                         const LB& lamB, double sb, bool useB, double Wb[4]) {
   const int32_t b = d.bc ? wall_index(d.bc[v]) : -1;
   if (b < 0) return;
   const double alpha = 0.75;
   const D4 wv = src[v];
   double ms[4], mo[4], t1[4], t2[4];
   mu_of(d, lamA, v, t1);
-  if (lamB) mu_of(d, lamB, v, t2);
-  for (int k = 0; k < 4; ++k) ms[k] = sa * t1[k] + (lamB ? sb * t2[k] : 0.0);
+  if (useB) mu_of(d, lamB, v, t2);
+  for (int k = 0; k < 4; ++k) ms[k] = sa * t1[k] + (useB ? sb * t2[k] : 0.0);
   for (int32_t e = d.wptr[b]; e < d.wptr[b + 1]; ++e) {
     const WallEnt we = d.went[e];
     mu_of(d, lamA, we.other, t1);
-    if (lamB) mu_of(d, lamB, we.other, t2);
-    for (int k = 0; k < 4; ++k) mo[k] = sa * t1[k] + (lamB ? sb * t2[k] : 0.0);
+    if (useB) mu_of(d, lamB, we.other, t2);
+    for (int k = 0; k < 4; ++k) mo[k] = sa * t1[k] + (useB ? sb * t2[k] : 0.0);
     double Fb[4];
     for (int k = 0; k < 4; ++k) Fb[k] = we.hl * (alpha * ms[k] + (1.0 - alpha) * mo[k]);
     wall_flux_bar(wv.v, d.gamma, we.nx, we.ny, Fb, Wb);
@@ -741,11 +755,11 @@ __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const 
       wb[k] += c.w.v[k];
     }
   });
-  const D4 ws = d.Ws[v], l = a.lam[v];
+  const D4 ws = d.Ws[v], l = a.lam.at(v);
   double ls[4];
   for (int k = 0; k < 4; ++k) ls[k] = l.v[k] + wb[k];
   z_of_w_bar(ws.v, d.gamma, zb, ls);
-  wall_bar(d, v, d.Ws, a.lam, 0.5, nullptr, 0.0, ls);
+  wall_bar(d, v, d.Ws, a.lam, 0.5, a.lam, 0.0, false, ls);
   st4<double>(a.lamS, v, ls);
   double ln[4];
   for (int k = 0; k < 4; ++k) ln[k] = -wb[k];
@@ -766,7 +780,7 @@ __host__ __device__ inline void adj_gather1_body(int64_t v, const Dev& d, const 
   for (int k = 0; k < 4; ++k) r[k] = ln.v[k] + ls.v[k];
   z_of_w_bar(w.v, d.gamma, zb, r);
   // wall term at W^n: cotangent mu1 (stage 1) + mu2 / 2 (stage 2)
-  wall_bar(d, v, d.W, a.lamS, 1.0, rk2 ? a.lam : nullptr, 0.5, r);
+  wall_bar(d, v, d.W, LamAoS{a.lamS}, 1.0, a.lam, 0.5, rk2, r);
   for (int k = 0; k < 4; ++k) out[k * d.nv + v] = r[k];
 }
 

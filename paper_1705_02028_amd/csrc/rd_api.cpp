@@ -988,8 +988,8 @@ rd_status adjoint_enqueue(rd_mesh* m, const rd::AdjDev& a, rd::D4* Wa, double* s
     HIPCHK(rd::launch_tri(dn, 0, scheme, 1, true, false, s));
     HIPCHK(rd::launch_gather(d, 0, rd::G_STAGE1, nullptr, s));
   }
-  HIPCHK(rd::launch_soa_to_aos(lam_np1, const_cast<rd::D4*>(a.lam), m->d.nv, s));
   rd::AdjDev ad = a;
+  ad.lam = rd::LamSoA{lam_np1, m->d.nv};  // read in the caller's layout
   ad.idt = 1.0 / dt;
   HIPCHK(rd::launch_adjoint(d, ad, scheme, rk2 ? 1 : 0, lam_n, s));
   m->zprec = -1;  // the parameter-vector buffer now holds the recomputation's values
@@ -1007,11 +1007,11 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
   const int64_t nv = m->d.nv, nt = m->d.nt;
   if (!m->adjW) {
     rd::AdjDev& a = m->adj;
-    rd::D4 *lamIn, *lamS, *lamN, *Zn, *cZ, *kN, *kT, *Wa;
+    rd::D4 *lamS, *lamN, *Zn, *cZ, *kN, *kT, *Wa;
     rd::ZW* cZW;
     double *in, *out, *sig;
     int* flag;
-    if ((st = dalloc(m, &lamIn, nv)) || (st = dalloc(m, &lamS, nv)) || (st = dalloc(m, &lamN, nv)) ||
+    if ((st = dalloc(m, &lamS, nv)) || (st = dalloc(m, &lamN, nv)) ||
         (st = dalloc(m, &Zn, nv)) || (st = dalloc(m, &cZ, m->d.ns)) || (st = dalloc(m, &cZW, m->d.ns)) ||
         (st = dalloc(m, &kN, 2 * nt)) || (st = dalloc(m, &kT, nt)) || (st = dalloc(m, &Wa, nv)) ||
         (st = dalloc(m, &in, 4 * nv)) || (st = dalloc(m, &out, 4 * nv)) || (st = dalloc(m, &sig, nv)) ||
@@ -1021,7 +1021,6 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     HIPCHK(rd::launch_set_int(flag + 1, 0, m->stream));
     a.flag = flag;
     m->adjSig = sig;
-    a.lam = lamIn;
     a.lamS = lamS;
     a.lamN = lamN;
     a.Zn = Zn;
@@ -1068,7 +1067,7 @@ RD_API rd_status rd_adjoint_step_noalloc(rd_mesh* m, const double* W_n, double d
     off += (bytes + 255) & ~size_t(255);
     return at;
   };
-  const size_t oLam = take(sizeof(rd::D4) * nv), oLamS = take(sizeof(rd::D4) * nv),
+  const size_t oLamS = take(sizeof(rd::D4) * nv),
                oLamN = take(sizeof(rd::D4) * nv), oZn = take(sizeof(rd::D4) * nv), oWa = take(sizeof(rd::D4) * nv),
                oSig = take(sizeof(double) * nv), oCZ = take(sizeof(rd::D4) * ns), oCZW = take(sizeof(rd::ZW) * ns),
                oKN = take(sizeof(rd::D4) * 2 * nt), oKT = take(sizeof(rd::D4) * nt);
@@ -1081,7 +1080,6 @@ RD_API rd_status rd_adjoint_step_noalloc(rd_mesh* m, const double* W_n, double d
   HIPCHK(rd::noalloc_scratch(&base));
   char* p = static_cast<char*>(base);
   rd::AdjDev a;
-  a.lam = reinterpret_cast<rd::D4*>(p + oLam);
   a.lamS = reinterpret_cast<rd::D4*>(p + oLamS);
   a.lamN = reinterpret_cast<rd::D4*>(p + oLamN);
   a.Zn = reinterpret_cast<rd::D4*>(p + oZn);

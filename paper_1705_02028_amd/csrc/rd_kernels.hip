@@ -141,15 +141,20 @@ __global__ __launch_bounds__(kBlock) void k_copy4(D4* dst, const D4* src, int64_
 
 // ------------------------------------------------------------- adjoint --
 
+// The reverse triangle kernels run one wavefront per SIMD (their registers
+// fill the SIMD); one-wavefront workgroups let each SIMD start its next
+// wavefront as soon as its own finishes.
+constexpr int kAdjBlock = 64;
+
 template <int SCHEME>
-__global__ __launch_bounds__(kBlock) void k_adj_tri2(Dev d, AdjDev a) {
-  const int64_t t = xcd_block() * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kAdjBlock) void k_adj_tri2(Dev d, AdjDev a) {
+  const int64_t t = xcd_block() * kAdjBlock + threadIdx.x;
   if (t < d.nt) adj_tri2_body<SCHEME>(t, d, a);
 }
 
 template <int SCHEME>
-__global__ __launch_bounds__(kBlock) void k_adj_tri1(Dev d, AdjDev a, int rk2) {
-  const int64_t t = xcd_block() * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kAdjBlock) void k_adj_tri1(Dev d, AdjDev a, int rk2) {
+  const int64_t t = xcd_block() * kAdjBlock + threadIdx.x;
   if (t < d.nt) adj_tri1_body<SCHEME>(t, d, a, rk2 != 0);
 }
 
@@ -179,8 +184,9 @@ __global__ __launch_bounds__(kBlock) void k_zero4(D4* dst, int64_t n) {
 
 template <int SCHEME>
 static void adj_tris(const Dev& d, const AdjDev& a, int stage, int rk2, hipStream_t s) {
-  if (stage == 2) hipLaunchKernelGGL((k_adj_tri2<SCHEME>), dim3(nblk(d.nt)), dim3(kBlock), 0, s, d, a);
-  else hipLaunchKernelGGL((k_adj_tri1<SCHEME>), dim3(nblk(d.nt)), dim3(kBlock), 0, s, d, a, rk2);
+  const unsigned g = (unsigned)((d.nt + kAdjBlock - 1) / kAdjBlock);
+  if (stage == 2) hipLaunchKernelGGL((k_adj_tri2<SCHEME>), dim3(g), dim3(kAdjBlock), 0, s, d, a);
+  else hipLaunchKernelGGL((k_adj_tri1<SCHEME>), dim3(g), dim3(kAdjBlock), 0, s, d, a, rk2);
 }
 
 hipError_t launch_adjoint(const Dev& d, const AdjDev& a, int scheme, int rk2, double* out, hipStream_t s) {
@@ -197,7 +203,7 @@ hipError_t launch_adjoint(const Dev& d, const AdjDev& a, int scheme, int rk2, do
     tris(2);
     hipLaunchKernelGGL(k_adj_gather2, dim3(nblk(d.nv)), dim3(kBlock), 0, s, d, a);
   } else {
-    hipLaunchKernelGGL(k_copy4, dim3(nblk(d.nv)), dim3(kBlock), 0, s, a.lamS, a.lam, d.nv);
+    hipLaunchKernelGGL(k_soa_to_aos, dim3(nblk(d.nv)), dim3(kBlock), 0, s, a.lam.p, a.lamS, d.nv);
     hipLaunchKernelGGL(k_zero4, dim3(nblk(d.nv)), dim3(kBlock), 0, s, a.lamN, d.nv);
   }
   tris(1);
