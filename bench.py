@@ -466,12 +466,12 @@ def three_d(rd, inputs, N=128, steps=10, warmup=2):
     nt, nv = m["nt"], m["nv"]
     names = ["cfl", "tet1", "gather1", "tet2", "gather2"]
     # algorithmic bytes per tetrahedron pass. First: corners and slots (32),
-    # normals (96), the parts (160), the kept N parts and residual (200) per
-    # tetrahedron, Z once per vertex (40). Second: the same with the kept
-    # parts read instead of written (200), the volume (8), and the
-    # first-stage rate besides Z per vertex (80).
-    b_tet1 = nt * (32 + 96 + 160 + 200) + nv * 40
-    b_tet2 = nt * (32 + 96 + 8 + 200 + 160) + nv * 80
+    # normals (96), the parts (160), the kept N parts of three corners and the
+    # residual (160) per tetrahedron, Z once per vertex (40). Second: the same
+    # with the kept values read instead of written (160), the volume (8), and
+    # the first-stage rate besides Z per vertex (80).
+    b_tet1 = nt * (32 + 96 + 160 + 160) + nv * 40
+    b_tet2 = nt * (32 + 96 + 8 + 160 + 160) + nv * 80
     dom = 1 if ms[1] >= ms[3] else 3
     b_dom = b_tet1 if dom == 1 else b_tet2
     ach = b_dom / (ms[dom] * 1e-3)

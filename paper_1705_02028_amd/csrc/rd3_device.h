@@ -47,7 +47,8 @@ struct Dev3 {
   double* rate = nullptr;          // [5][nv] (W* - W^n) / dt, written by the first vertex pass
   double* sig = nullptr;           // [nv] |u| + c of W
   double* part = nullptr;          // [5][ns] distributed parts by slot
-  double* keepN = nullptr;         // [20][nt] stage-1 N parts (component k of corner i at 5 i + k)
+  double* keepN = nullptr;         // [15][nt] stage-1 N parts of corners 0-2 (component k of corner i at 5 i + k);
+                                   // corner 3's is the kept residual minus those three
   double* keepT = nullptr;         // [5][nt] stage-1 residual
   double* cpart = nullptr;         // [ns] CFL parts by slot
   double* dt = nullptr;            // device scalar: the step's time step
@@ -190,8 +191,9 @@ __device__ inline void blend_theta(int scheme, const double res[5], const double
 
 // One tetrahedron: stage 1 (or Euler) at the Z in d.Z; stage 2 adds the
 // mass term of the first-stage increment and the kept stage-1 parts.
-template <int STAGE>
-__device__ inline void tet_body(const Dev3& d, int64_t t, int scheme, bool keep) {
+template <int STAGE, int SCHEME>
+__device__ inline void tet_body(const Dev3& d, int64_t t, bool keep) {
+  constexpr int scheme = SCHEME;
   const int64_t nt = d.nt, nv = d.nv;
   const double g1 = d.gamma - 1.0;
   int32_t vid[4];
@@ -294,33 +296,46 @@ __device__ inline void tet_body(const Dev3& d, int64_t t, int scheme, bool keep)
   double xN[5], xT[5];
   solve5x2(A, bN, rhsT, xN, xT);
   // N parts of every corner (the blend needs all of them), then each
-  // corner's LDA part and output
+  // corner's LDA part and output. The parts of a distribution add up to the
+  // residual they split (sum_i K_i^+ (dW_i + xN) = phi^T, sum_i K_i^+ xT =
+  // PT), so corner 3's are that residual minus those of corners 0-2.
   double pn[4][5];
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 3; ++i) {
     const double un = cn[i].un;
     double y[5];
     for (int k = 0; k < 5; ++k) y[k] = (i == 0 ? 0.0 : dW[i][k]) + xN[k];
     kapply(f, cn[i], pos(un + f.c), pos(un - f.c), pos(un), y, pn[i]);
   }
+  for (int k = 0; k < 5; ++k) pn[3][k] = phiT[k] - pn[0][k] - pn[1][k] - pn[2][k];
   if (STAGE == 1 && keep) {
     // read back only by the stage-2 pass after the gather: stored with the
-    // non-temporal hint so they do not evict what the gather reads next
-    for (int i = 0; i < 4; ++i)
+    // non-temporal hint so they do not evict what the gather reads next;
+    // corner 3's part is formed again from the residual in stage 2
+    for (int i = 0; i < 3; ++i)
       for (int k = 0; k < 5; ++k) __builtin_nontemporal_store(pn[i][k], &d.keepN[(5 * i + k) * nt + t]);
     for (int k = 0; k < 5; ++k) __builtin_nontemporal_store(phiT[k], &d.keepT[k * nt + t]);
   }
   if (STAGE == 2) {
     const double mass = 0.25 * d.vol[t];
-    for (int i = 0; i < 4; ++i)
-      for (int k = 0; k < 5; ++k)
-        pn[i][k] = mass * d.rate[k * nv + vid[i]] + 0.5 * (d.keepN[(5 * i + k) * nt + t] + pn[i][k]);
+    for (int k = 0; k < 5; ++k) {
+      double kn[4];
+      for (int i = 0; i < 3; ++i) kn[i] = d.keepN[(5 * i + k) * nt + t];
+      kn[3] = d.keepT[k * nt + t] - kn[0] - kn[1] - kn[2];
+      for (int i = 0; i < 4; ++i) pn[i][k] = mass * d.rate[k * nv + vid[i]] + 0.5 * (kn[i] + pn[i][k]);
+    }
   }
   double th[5];
   blend_theta(scheme, PT, pn, th);
+  double lsum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int i = 0; i < 4; ++i) {
-    const double un = cn[i].un;
     double pl[5];
-    kapply(f, cn[i], pos(un + f.c), pos(un - f.c), pos(un), xT, pl);
+    if (i < 3) {
+      const double un = cn[i].un;
+      kapply(f, cn[i], pos(un + f.c), pos(un - f.c), pos(un), xT, pl);
+      for (int k = 0; k < 5; ++k) lsum[k] += pl[k];
+    } else {
+      for (int k = 0; k < 5; ++k) pl[k] = PT[k] - lsum[k];
+    }
     const int64_t sl = d.slot[i * nt + t];
     for (int k = 0; k < 5; ++k) {
       const double o = scheme == S_N ? pn[i][k] : scheme == S_LDA ? pl[k] : pl[k] + th[k] * (pn[i][k] - pl[k]);

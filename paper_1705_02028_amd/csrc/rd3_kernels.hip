@@ -20,10 +20,10 @@ __global__ __launch_bounds__(kBlock) void k3_z(Dev3 d, const double* src) {
 
 // At most 256 registers per lane (two waves per SIMD): the second stage's
 // extra terms would otherwise take it just past that, to one wave.
-template <int STAGE>
-__global__ __launch_bounds__(kBlock, 2) void k3_tet(Dev3 d, int scheme, int keep) {
+template <int STAGE, int SCHEME>
+__global__ __launch_bounds__(kBlock, 2) void k3_tet(Dev3 d, int keep) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t < d.nt) tet_body<STAGE>(d, t, scheme, keep != 0);
+  if (t < d.nt) tet_body<STAGE, SCHEME>(d, t, keep != 0);
 }
 
 // mode 0: Euler (W <- W - dt/V R, then Z, sig of W); 1: first stage
@@ -110,11 +110,23 @@ hipError_t launch3_z(const Dev3& d, const double* src, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch3_tet(const Dev3& d, int stage, int scheme, bool keep, hipStream_t s) {
+template <int SCHEME>
+static void tet_launch(const Dev3& d, int stage, bool keep, hipStream_t s) {
   if (stage == 1)
-    hipLaunchKernelGGL(k3_tet<1>, dim3(blocks(d.nt)), dim3(kBlock), 0, s, d, scheme, keep ? 1 : 0);
+    hipLaunchKernelGGL((k3_tet<1, SCHEME>), dim3(blocks(d.nt)), dim3(kBlock), 0, s, d, keep ? 1 : 0);
   else
-    hipLaunchKernelGGL(k3_tet<2>, dim3(blocks(d.nt)), dim3(kBlock), 0, s, d, scheme, 0);
+    hipLaunchKernelGGL((k3_tet<2, SCHEME>), dim3(blocks(d.nt)), dim3(kBlock), 0, s, d, 0);
+}
+
+hipError_t launch3_tet(const Dev3& d, int stage, int scheme, bool keep, hipStream_t s) {
+  switch (scheme) {
+    case S_N: tet_launch<S_N>(d, stage, keep, s); break;
+    case S_LDA: tet_launch<S_LDA>(d, stage, keep, s); break;
+    case S_B: tet_launch<S_B>(d, stage, keep, s); break;
+    case S_BMAX: tet_launch<S_BMAX>(d, stage, keep, s); break;
+    case S_BMIN: tet_launch<S_BMIN>(d, stage, keep, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -1970,7 +1970,7 @@ RD_API rd_status rd3_mesh_create(const rd3_mesh_desc* desc, rd3_mesh** out) {
       !dev_get(m.get(), &dnrm, 12 * nt) || !dev_get(m.get(), &dvol, nt) || !dev_get(m.get(), &dsmax, nt) ||
       !dev_get(m.get(), &dV, nv) || !dev_get(m.get(), &d.W, 5 * nv) || !dev_get(m.get(), &d.Ws, 5 * nv) ||
       !dev_get(m.get(), &d.Z, 5 * nv) || !dev_get(m.get(), &d.rate, 5 * nv) || !dev_get(m.get(), &d.sig, nv) || !dev_get(m.get(), &d.part, 5 * ns) ||
-      !dev_get(m.get(), &d.keepN, 20 * nt) || !dev_get(m.get(), &d.keepT, 5 * nt) ||
+      !dev_get(m.get(), &d.keepN, 15 * nt) || !dev_get(m.get(), &d.keepT, 5 * nt) ||
       !dev_get(m.get(), &d.cpart, ns) || !dev_get(m.get(), &d.dt, 1) || !dev_get(m.get(), &d.bmin, nb) ||
       !dev_get(m.get(), &d.flag, 1))
     return fail(RD_ENOMEM, "device allocation failed");
