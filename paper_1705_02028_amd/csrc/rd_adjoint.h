@@ -39,8 +39,22 @@ struct LamSoA {
   __host__ __device__ D4 at(int64_t v) const { return D4{{p[v], p[n + v], p[2 * n + v], p[3 * n + v]}}; }
 };
 
+// Per-vertex inputs of the reverse triangle passes, packed so that a pass
+// reads each corner's inputs as one contiguous record: for stage 2 the
+// parameter vector at W* (at W^n on ghosts), W* - W^n and mu2 = -(dt/V)
+// dL/dW^{n+1}; for stage 1 the parameter vector at W^n and mu1 = -(dt/V)
+// dL/dW* (mu is 0 on ghosts, whose update ignores their residual).
+struct alignas(32) AdjRec2 {
+  D4 zc, dw, mu;
+};
+struct alignas(32) AdjRec1 {
+  D4 zn, mu;
+};
+
 struct AdjDev {
   LamSoA lam;                // dL/dW^{n+1}, the caller's [4][nv]
+  AdjRec2* r2 = nullptr;     // [nv] stage-2 reverse inputs
+  AdjRec1* r1 = nullptr;     // [nv] stage-1 reverse inputs
   D4* lamS = nullptr;        // [nv] dL/dW*
   D4* lamN = nullptr;        // [nv] running dL/dW^n (output)
   D4* Zn = nullptr;          // [nv] parameter vectors at W^n
@@ -625,11 +639,12 @@ __host__ __device__ inline void mu_of(const Dev& d, const L& lam, int64_t v, dou
   for (int k = 0; k < 4; ++k) mu[k] = f * l.v[k];
 }
 
-__host__ __device__ inline void tri_normals(const Dev& d, const int32_t iv[3], double nxd[3], double nyd[3],
-                                            double* area) {
-  const double2 p0 = d.xy[iv[0]], p1 = d.xy[iv[1]], p2 = d.xy[iv[2]];
-  const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
-  const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
+// Unwrapped inward normals (scaled by edge length) and area of a triangle
+// from its corner coordinates.
+__host__ __device__ inline void tri_normals_p(const Dev& d, const double2 p[3], double nxd[3], double nyd[3],
+                                              double* area) {
+  const double d1x = unwrap(p[1].x - p[0].x, d.px), d1y = unwrap(p[1].y - p[0].y, d.py);
+  const double d2x = unwrap(p[2].x - p[0].x, d.px), d2y = unwrap(p[2].y - p[0].y, d.py);
   nxd[0] = -(d2y - d1y);
   nxd[1] = d2y;
   nxd[2] = -d1y;
@@ -639,44 +654,48 @@ __host__ __device__ inline void tri_normals(const Dev& d, const int32_t iv[3], d
   if (area) *area = 0.5 * (d1x * d2y - d1y * d2x);
 }
 
+// Inputs of one triangle's reverse: corner ids and slot ranks, corner
+// coordinates, parameter vectors and mu; for stage 2 the records W* - W^n
+// and the kept stage-1 N parts of corners 0, 1 and residual; for stage 1
+// (after a stage 2) the cotangents of those kept values. The records are
+// addressed through pointers, read where the reverse uses them.
+struct AdjTriIn {
+  int32_t iv[3];
+  uint32_t rk;
+  double2 p[3];
+  D4 z[3], mu[3];
+  const D4* dw[3];
+  const D4* kn;  // two records
+  const D4* kt;
+};
+
 // Stage-2 reverse of one triangle: cotangents of Z*, W* - W^n (CSR order) and
-// of the kept stage-1 parts (triangle order), from lam = dL/dW^{n+1}.
+// of the kept stage-1 parts (triangle order), from mu2 = -(dt/V) dL/dW^{n+1}.
 template <int SCHEME>
-__host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const AdjDev& a) {
-  const int64_t nt = d.nt;
-  int32_t iv[3], ip[3];
-  const uint32_t rk = d.rk[t];
-  for (int i = 0; i < 3; ++i) {
-    iv[i] = d.tv[i * nt + t];
-    ip[i] = corner_slot(d, iv[i], rk, i);
-  }
+__host__ __device__ inline void adj_tri2_compute(int64_t t, const Dev& d, const AdjDev& a, const AdjTriIn& in) {
   double nxd[3], nyd[3], area;
-  tri_normals(d, iv, nxd, nyd, &area);
-  D4 Zc[3];
+  tri_normals_p(d, in.p, nxd, nyd, &area);
   Stage2In s2;
   s2.mass = area * (1.0 / 3.0);
   s2.idt = a.idt;
-  const D4* keepN = reinterpret_cast<const D4*>(d.keepN);
-  s2.kn[0] = keepN + 2 * t;
-  s2.kn[1] = keepN + 2 * t + 1;
-  s2.kt = reinterpret_cast<const D4*>(d.keepT) + t;
+  s2.kn[0] = in.kn;
+  s2.kn[1] = in.kn + 1;
+  s2.kt = in.kt;
   double ob[3][4];
   for (int i = 0; i < 3; ++i) {
-    // W* = W^n at ghosts, whose parameter vectors the stage-1 gather leaves alone
-    Zc[i] = (d.bc && is_ghost(d.bc[iv[i]])) ? a.Zn[iv[i]] : d.Z[iv[i]];
-    s2.dw[i] = reinterpret_cast<const D4*>(d.dW) + iv[i];
-    mu_of(d, a.lam, iv[i], ob[i]);
+    s2.dw[i] = in.dw[i];
+    for (int k = 0; k < 4; ++k) ob[i][k] = in.mu[i].v[k];
   }
   Stage2Bar s2b;
   double Zb[3][4];
-  if (tri_adjoint<SCHEME, 2>(Zc, nxd, nyd, d.gamma, d.igamma, ob, nullptr, nullptr, &s2, &s2b, Zb)) a.flag[1] = 1;
+  if (tri_adjoint<SCHEME, 2>(in.z, nxd, nyd, d.gamma, d.igamma, ob, nullptr, nullptr, &s2, &s2b, Zb)) a.flag[1] = 1;
   for (int i = 0; i < 3; ++i) {
     ZW c;
     for (int k = 0; k < 4; ++k) {
       c.z.v[k] = Zb[i][k];
       c.w.v[k] = s2b.dw[i][k];
     }
-    a.cZW[ip[i]] = c;
+    a.cZW[corner_slot(d, in.iv[i], in.rk, i)] = c;
   }
   // the kept stage-1 values are corners 0 and 1 and phi^T (corner 2 = phi^T
   // minus the other two), so corner 2's cotangent moves onto those three
@@ -692,31 +711,53 @@ __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const Adj
 }
 
 // Stage-1 reverse of one triangle: cotangents of Z^n (CSR order), from
-// mu1 = -(dt/V) dL/dW* and the cotangents of the kept parts.
+// mu1 = -(dt/V) dL/dW* and the cotangents of the kept parts (in.kn, in.kt;
+// null after a forward Euler step).
+template <int SCHEME>
+__host__ __device__ inline void adj_tri1_compute(int64_t, const Dev& d, const AdjDev& a, const AdjTriIn& in) {
+  double nxd[3], nyd[3];
+  tri_normals_p(d, in.p, nxd, nyd, nullptr);
+  double ob[3][4];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 4; ++k) ob[i][k] = in.mu[i].v[k];
+  double Zb[3][4];
+  if (tri_adjoint<SCHEME, 1>(in.z, nxd, nyd, d.gamma, d.igamma, ob, in.kn, in.kt, nullptr, nullptr, Zb)) a.flag[1] = 1;
+  for (int i = 0; i < 3; ++i) st4<double>(a.cZ, corner_slot(d, in.iv[i], in.rk, i), Zb[i]);
+}
+
+// The same two bodies reading their inputs straight from memory.
+template <int SCHEME>
+__host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const AdjDev& a) {
+  AdjTriIn in;
+  in.rk = d.rk[t];
+  for (int i = 0; i < 3; ++i) {
+    in.iv[i] = d.tv[i * d.nt + t];
+    in.p[i] = d.xy[in.iv[i]];
+    const AdjRec2& r = a.r2[in.iv[i]];
+    in.z[i] = r.zc;
+    in.mu[i] = r.mu;
+    in.dw[i] = &r.dw;
+  }
+  in.kn = reinterpret_cast<const D4*>(d.keepN) + 2 * t;
+  in.kt = reinterpret_cast<const D4*>(d.keepT) + t;
+  adj_tri2_compute<SCHEME>(t, d, a, in);
+}
+
 template <int SCHEME>
 __host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const AdjDev& a, bool rk2) {
-  const int64_t nt = d.nt;
-  int32_t iv[3], ip[3];
-  const uint32_t rk = d.rk[t];
+  AdjTriIn in;
+  in.rk = d.rk[t];
   for (int i = 0; i < 3; ++i) {
-    iv[i] = d.tv[i * nt + t];
-    ip[i] = corner_slot(d, iv[i], rk, i);
+    in.iv[i] = d.tv[i * d.nt + t];
+    in.p[i] = d.xy[in.iv[i]];
+    const AdjRec1 r = a.r1[in.iv[i]];
+    in.z[i] = r.zn;
+    in.mu[i] = r.mu;
+    in.dw[i] = nullptr;
   }
-  double nxd[3], nyd[3];
-  tri_normals(d, iv, nxd, nyd, nullptr);
-  D4 Zc[3];
-  double ob[3][4];
-  for (int i = 0; i < 3; ++i) {
-    Zc[i] = a.Zn[iv[i]];
-    mu_of(d, LamAoS{a.lamS}, iv[i], ob[i]);
-  }
-  // cotangents of the kept values (N parts of corners 0 and 1, phi^T), read
-  // where the reverse needs them
-  const D4* kNs = rk2 ? a.kN + 2 * t : nullptr;
-  const D4* kTs = rk2 ? a.kT + t : nullptr;
-  double Zb[3][4];
-  if (tri_adjoint<SCHEME, 1>(Zc, nxd, nyd, d.gamma, d.igamma, ob, kNs, kTs, nullptr, nullptr, Zb)) a.flag[1] = 1;
-  for (int i = 0; i < 3; ++i) st4<double>(a.cZ, ip[i], Zb[i]);
+  in.kn = rk2 ? a.kN + 2 * t : nullptr;
+  in.kt = rk2 ? a.kT + t : nullptr;
+  adj_tri1_compute<SCHEME>(t, d, a, in);
 }
 
 // Wall-term transpose at one wall vertex b: sum over its wall edges of
@@ -764,6 +805,68 @@ __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const 
   double ln[4];
   for (int k = 0; k < 4; ++k) ln[k] = -wb[k];
   st4<double>(a.lamN, v, ln);
+  // the stage-1 reverse's record of this vertex: Z at W^n and mu1
+  AdjRec1 r;
+  r.zn = a.Zn[v];
+  double mu[4];
+  mu_of(d, LamAoS{a.lamS}, v, mu);
+  for (int k = 0; k < 4; ++k) r.mu.v[k] = mu[k];
+  a.r1[v] = r;
+}
+
+// The adjoint's recomputation of the first stage at one vertex: the sums of
+// the stage-1 parts and the update (the arithmetic of the stage-1 gather,
+// so W* is bitwise the forward step's), writing W* and the vertex's
+// stage-2 reverse record: Z at W* (at W^n on ghosts), W* - W^n, mu2.
+__host__ __device__ inline void adj_star_body(int64_t v, const Dev& d, const AdjDev& a) {
+  const int32_t code = d.bc ? d.bc[v] : -1;
+  AdjRec2 r;
+  double mu[4];
+  mu_of(d, a.lam, v, mu);
+  for (int k = 0; k < 4; ++k) r.mu.v[k] = mu[k];
+  if (is_ghost(code)) {
+    d.Ws[v] = d.W[v];
+    r.zc = a.Zn[v];
+    for (int k = 0; k < 4; ++k) r.dw.v[k] = 0.0;
+    a.r2[v] = r;
+    return;
+  }
+  const int32_t b = wall_index(code);
+  double acc[4];
+  const int32_t deg = d.row[v + 1] - d.row[v];
+  const int64_t s0 = vslot(d, v);
+  sum_parts<double>(deg, [&](int32_t j) { return ld4<double>(d.C, s0 + 64 * (int64_t)j); }, acc);
+  if (b >= 0) {
+    const D4 wn = d.WCn[b];
+    for (int k = 0; k < 4; ++k) acc[k] = acc[k] + wn.v[k];
+  }
+  const double f = d.dt[0] / d.V[v];
+  const D4 win = d.W[v];
+  double wo[4];
+  vertex_update(win.v, f, acc, wo);
+  st4<double>(d.Ws, v, wo);
+  const VertexDerived o = derive(d.gamma, wo);
+  for (int k = 0; k < 4; ++k) {
+    r.zc.v[k] = o.z[k];
+    r.dw.v[k] = wo[k] - win.v[k];
+  }
+  a.r2[v] = r;
+  if (!o.ok) d.flag[0] = 1;
+}
+
+// Forward Euler: dL/dW* is dL/dW^{n+1} itself; the stage-1 reverse's record
+// and the running sums are set from it.
+__host__ __device__ inline void adj_euler_prep_body(int64_t v, const Dev& d, const AdjDev& a) {
+  const D4 l = a.lam.at(v);
+  a.lamS[v] = l;
+  const D4 z = {{0.0, 0.0, 0.0, 0.0}};
+  a.lamN[v] = z;
+  AdjRec1 r;
+  r.zn = a.Zn[v];
+  double mu[4];
+  mu_of(d, a.lam, v, mu);
+  for (int k = 0; k < 4; ++k) r.mu.v[k] = mu[k];
+  a.r1[v] = r;
 }
 
 // Reverse of the stage-1 vertex sums and of W -> Z at W^n: dL/dW^n, written

@@ -977,20 +977,21 @@ rd_status adjoint_enqueue(rd_mesh* m, const rd::AdjDev& a, rd::D4* Wa, double* s
   d.sig = sig;
   d.flag = a.flag;
   // parameter vectors at W^n go straight to Zn (read by the stage-1 passes and
-  // the adjoint); the stage-1 gather writes those at W* to the mesh's Z
+  // the adjoint); the first-stage vertex pass writes W* and the stage-2
+  // reverse records
   rd::Dev dn = d;
   dn.Z = a.Zn;
+  rd::AdjDev ad = a;
+  ad.lam = rd::LamSoA{lam_np1, m->d.nv};  // read in the caller's layout
+  ad.idt = 1.0 / dt;
   HIPCHK(rd::launch_set_state(dn, W_n, 0, s));
   HIPCHK(rd::launch_set_scalar(d.dt, dt, s));
   const bool rk2 = time == RD_RK2;
   if (rk2) {
     HIPCHK(rd::launch_wall(dn, false, s));
     HIPCHK(rd::launch_tri(dn, 0, scheme, 1, true, false, s));
-    HIPCHK(rd::launch_gather(d, 0, rd::G_STAGE1, nullptr, s));
+    HIPCHK(rd::launch_adj_star(d, ad, s));
   }
-  rd::AdjDev ad = a;
-  ad.lam = rd::LamSoA{lam_np1, m->d.nv};  // read in the caller's layout
-  ad.idt = 1.0 / dt;
   HIPCHK(rd::launch_adjoint(d, ad, scheme, rk2 ? 1 : 0, lam_n, s));
   m->zprec = -1;  // the parameter-vector buffer now holds the recomputation's values
   return RD_OK;
@@ -1009,9 +1010,12 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     rd::AdjDev& a = m->adj;
     rd::D4 *lamS, *lamN, *Zn, *cZ, *kN, *kT, *Wa;
     rd::ZW* cZW;
+    rd::AdjRec2* r2;
+    rd::AdjRec1* r1;
     double *in, *out, *sig;
     int* flag;
-    if ((st = dalloc(m, &lamS, nv)) || (st = dalloc(m, &lamN, nv)) ||
+    if ((st = dalloc(m, &lamS, nv)) || (st = dalloc(m, &lamN, nv)) || (st = dalloc(m, &r2, nv)) ||
+        (st = dalloc(m, &r1, nv)) ||
         (st = dalloc(m, &Zn, nv)) || (st = dalloc(m, &cZ, m->d.ns)) || (st = dalloc(m, &cZW, m->d.ns)) ||
         (st = dalloc(m, &kN, 2 * nt)) || (st = dalloc(m, &kT, nt)) || (st = dalloc(m, &Wa, nv)) ||
         (st = dalloc(m, &in, 4 * nv)) || (st = dalloc(m, &out, 4 * nv)) || (st = dalloc(m, &sig, nv)) ||
@@ -1023,6 +1027,8 @@ RD_API rd_status rd_adjoint_step(rd_mesh* m, const double* W_n, double dt, int s
     m->adjSig = sig;
     a.lamS = lamS;
     a.lamN = lamN;
+    a.r2 = r2;
+    a.r1 = r1;
     a.Zn = Zn;
     a.cZ = cZ;
     a.cZW = cZW;
@@ -1067,7 +1073,8 @@ RD_API rd_status rd_adjoint_step_noalloc(rd_mesh* m, const double* W_n, double d
     off += (bytes + 255) & ~size_t(255);
     return at;
   };
-  const size_t oLamS = take(sizeof(rd::D4) * nv),
+  const size_t oR2 = take(sizeof(rd::AdjRec2) * nv), oR1 = take(sizeof(rd::AdjRec1) * nv),
+               oLamS = take(sizeof(rd::D4) * nv),
                oLamN = take(sizeof(rd::D4) * nv), oZn = take(sizeof(rd::D4) * nv), oWa = take(sizeof(rd::D4) * nv),
                oSig = take(sizeof(double) * nv), oCZ = take(sizeof(rd::D4) * ns), oCZW = take(sizeof(rd::ZW) * ns),
                oKN = take(sizeof(rd::D4) * 2 * nt), oKT = take(sizeof(rd::D4) * nt);
@@ -1080,6 +1087,8 @@ RD_API rd_status rd_adjoint_step_noalloc(rd_mesh* m, const double* W_n, double d
   HIPCHK(rd::noalloc_scratch(&base));
   char* p = static_cast<char*>(base);
   rd::AdjDev a;
+  a.r2 = reinterpret_cast<rd::AdjRec2*>(p + oR2);
+  a.r1 = reinterpret_cast<rd::AdjRec1*>(p + oR1);
   a.lamS = reinterpret_cast<rd::D4*>(p + oLamS);
   a.lamN = reinterpret_cast<rd::D4*>(p + oLamN);
   a.Zn = reinterpret_cast<rd::D4*>(p + oZn);

@@ -158,6 +158,16 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_tri1(Dev d, AdjDev a, int rk2
   if (t < d.nt) adj_tri1_body<SCHEME>(t, d, a, rk2 != 0);
 }
 
+__global__ __launch_bounds__(kBlock) void k_adj_star(Dev d, AdjDev a) {
+  const int64_t v = xcd_block() * kBlock + threadIdx.x;
+  if (v < d.nv) adj_star_body(v, d, a);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_euler_prep(Dev d, AdjDev a) {
+  const int64_t v = xcd_block() * kBlock + threadIdx.x;
+  if (v < d.nv) adj_euler_prep_body(v, d, a);
+}
+
 __global__ __launch_bounds__(kBlock) void k_adj_gather2(Dev d, AdjDev a) {
   const int64_t v = xcd_block() * kBlock + threadIdx.x;
   if (v < d.nv) adj_gather2_body(v, d, a);
@@ -203,11 +213,16 @@ hipError_t launch_adjoint(const Dev& d, const AdjDev& a, int scheme, int rk2, do
     tris(2);
     hipLaunchKernelGGL(k_adj_gather2, dim3(nblk(d.nv)), dim3(kBlock), 0, s, d, a);
   } else {
-    hipLaunchKernelGGL(k_soa_to_aos, dim3(nblk(d.nv)), dim3(kBlock), 0, s, a.lam.p, a.lamS, d.nv);
-    hipLaunchKernelGGL(k_zero4, dim3(nblk(d.nv)), dim3(kBlock), 0, s, a.lamN, d.nv);
+    hipLaunchKernelGGL(k_adj_euler_prep, dim3(nblk(d.nv)), dim3(kBlock), 0, s, d, a);
   }
   tris(1);
   hipLaunchKernelGGL(k_adj_gather1, dim3(nblk(d.nv)), dim3(kBlock), 0, s, d, a, rk2, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_star(const Dev& d, const AdjDev& a, hipStream_t s) {
+  if (d.nv == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_star, dim3(nblk(d.nv)), dim3(kBlock), 0, s, d, a);
   return hipGetLastError();
 }
 

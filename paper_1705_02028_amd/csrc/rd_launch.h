@@ -65,6 +65,9 @@ hipError_t launch_euler_apply(const Dev& d, int fp32, hipStream_t s);
 // Dynamic LDS bytes of a tile workgroup.
 size_t tile_lds_bytes(const Tiles& tl, int fp32, int stage, bool cfl);
 
+// The adjoint's first-stage vertex pass: W* from the stage-1 parts and the
+// stage-2 reverse records (Z at W*, W* - W^n, mu2) of every vertex.
+hipError_t launch_adj_star(const Dev& d, const AdjDev& a, hipStream_t s);
 // Reverse of one step (FP64): stage-2 triangles and gather (rk2), then
 // stage-1 triangles and gather; dL/dW^n goes to out [4][nv].
 hipError_t launch_adjoint(const Dev& d, const AdjDev& a, int scheme, int rk2, double* out, hipStream_t s);

@@ -8,8 +8,8 @@
 namespace rd {
 
 // Bytes of the per-GPU workspace: 128 MiB, enough for meshes of about
-// 130,000 vertices and 260,000 triangles (the adjoint needs about
-// 136 B per vertex, 96 B per corner slot and 96 B per triangle).
+// 110,000 vertices and 220,000 triangles (the adjoint needs about
+// 296 B per vertex, 96 B per corner slot and 96 B per triangle).
 constexpr size_t kNoallocScratchBytes = size_t(128) << 20;
 
 // Device address of the current GPU's workspace (looked up on the first call
