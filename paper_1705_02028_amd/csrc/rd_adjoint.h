@@ -65,7 +65,11 @@ struct AdjDev {
   D4* wcbar = nullptr;       // [nwv] cotangent of the wall term at W^n (stage 1 + half of stage 2)
   int* flag = nullptr;       // [2]: [0] the recomputed step went non-physical, [1] a solve skipped a column
   double idt = 0.0;          // 1 / dt of the step being reversed
+  int32_t waves = 0;         // workgroups of the staged reverse triangle passes (0: one per 64 triangles)
 };
+
+// The staged reverse triangle passes keep one wavefront per SIMD resident.
+constexpr int kAdjWavesPerCu = 4;
 
 // Cotangents of the quantities shared by all corners of a triangle.
 struct RoeBar {
@@ -219,11 +223,36 @@ __host__ __device__ inline void build_A_bar(const Roe<double>& q, const Corner<d
 // Inputs of the stage-2 function of one triangle besides its parameter
 // vectors: the records are read where they are used (not held in registers
 // across the triangle's forward recomputation).
+// A D4 the reverse reads where it uses it: from memory (D4Ptr) or from the
+// staging buffer of the staged passes (D4Lds: 16-byte units laid out
+// [unit][lane], so a record's two halves sit 64 units apart). Null = absent.
+struct D4Ptr {
+  const D4* p = nullptr;
+  __host__ __device__ D4 operator*() const { return *p; }
+  __host__ __device__ explicit operator bool() const { return p != nullptr; }
+};
+struct D4Lds {
+  const double2* p = nullptr;
+  __host__ __device__ D4 operator*() const {
+    const double2 lo = p[0], hi = p[64];
+    return D4{{lo.x, lo.y, hi.x, hi.y}};
+  }
+  __host__ __device__ explicit operator bool() const { return p != nullptr; }
+};
+
+// The corners' mu (cotangents of their parts) as values in registers; the
+// staged passes read it from LDS where the reverse uses it.
+struct MuVal {
+  D4 m[3];
+  __host__ __device__ D4 get(int i) const { return m[i]; }
+};
+
+template <class P>
 struct Stage2In {
   double mass = 0.0, idt = 0.0;
-  const D4* dw[3] = {nullptr, nullptr, nullptr};  // W*_i - W^n_i
-  const D4* kn[2] = {nullptr, nullptr};           // stage-1 N parts of corners 0 and 1
-  const D4* kt = nullptr;                         // stage-1 residual
+  P dw[3];  // W*_i - W^n_i
+  P kn[2];  // stage-1 N parts of corners 0 and 1
+  D4 kt;    // stage-1 residual
 };
 struct Stage2Bar {
   double dw[3][4];
@@ -232,18 +261,17 @@ struct Stage2Bar {
 };
 
 // Reverse of one triangle. Zc: corner parameter vectors; geometry from the
-// unwrapped normals (nxd, nyd). ob[i]: cotangent of the scheme's part of
+// unwrapped normals (nxd, nyd). mu.get(i): cotangent of the scheme's part of
 // corner i. Stage 1 also takes the cotangents of the kept N parts of corners
-// 0 and 1 (kNs, two records) and of the kept residual (kTs), or null for a
+// 0 and 1 (kN0, kN1) and of the kept residual (kT), or null for a
 // forward Euler step; stage 2 takes its extra inputs in s2 and returns theirs in
 // s2b. Returns the corner cotangents of Z in Zb.
 // Returns true when the pivoted solve skipped a column (A singular), where
 // the cotangents are not the derivative.
-template <int SCHEME, int STAGE>
+template <int SCHEME, int STAGE, class P, class MU>
 __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3], const double nyd[3], double gamma,
-                                            double igamma,
-                                            const double ob[3][4], const D4* kNs, const D4* kTs,
-                                            const Stage2In* s2, Stage2Bar* s2b, double Zb[3][4]) {
+                                            double igamma, const MU& mu, P kN0, P kN1, P kT,
+                                            const Stage2In<P>* s2, Stage2Bar* s2b, double Zb[3][4]) {
   // ---------------- forward (recomputed, as in tri_compute) ----------------
   Roe<double> q;
   q.g1 = gamma - 1.0;
@@ -307,7 +335,7 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
       const D4 w = *s2->dw[i];
       for (int k = 0; k < 4; ++k) srate[k] += w.v[k] * s2->idt;
     }
-    const D4 kt = SCHEME == SCH_N ? D4{{0.0, 0.0, 0.0, 0.0}} : *s2->kt;
+    const D4 kt = SCHEME == SCH_N ? D4{{0.0, 0.0, 0.0, 0.0}} : s2->kt;
     for (int k = 0; k < 4; ++k) rhs1[k] = s2->mass * srate[k] + 0.5 * (kt.v[k] + phiT[k]);
   }
   // A^{-1} (columns from unit right-hand sides) and the two solutions
@@ -361,7 +389,7 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
     if (STAGE == 2) {
       const D4 z = {{0.0, 0.0, 0.0, 0.0}};
       const bool keep = SCHEME != SCH_LDA;
-      const D4 k0 = keep ? *s2->kn[0] : z, k1 = keep ? *s2->kn[1] : z, kt = keep ? *s2->kt : z;
+      const D4 k0 = keep ? *s2->kn[0] : z, k1 = keep ? *s2->kn[1] : z, kt = keep ? s2->kt : z;
       for (int k = 0; k < 4; ++k) {
         kn[0][k] = k0.v[k];
         kn[1][k] = k1.v[k];
@@ -372,14 +400,16 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
         for (int k = 0; k < 4; ++k) dw[i][k] = w.v[k];
       }
     }
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i) {
+      const D4 ob = mu.get(i);
       for (int k = 0; k < 4; ++k) {
         const double PN = STAGE == 1 ? pN[i][k] : s2->mass * (dw[i][k] * s2->idt) + 0.5 * (kn[i][k] + pN[i][k]);
         den[k] = den[k] + fabs(PN);
-        thb[k] = thb[k] + ob[i][k] * (PN - pl[i][k]);
+        thb[k] = thb[k] + ob.v[k] * (PN - pl[i][k]);
         spos |= (PN > 0.0 ? 1u : 0u) << (4 * i + k);
         sneg |= (PN < 0.0 ? 1u : 0u) << (4 * i + k);
       }
+    }
   }
   bool active[4] = {false, false, false, false};  // Theta_k = |r_k| / den_k, not 0/0, not clamped
   double idn[4] = {0, 0, 0, 0};                    // 1 / den_k (0 where den_k = 0)
@@ -426,19 +456,20 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
     for (int k = 0; k < 4; ++k) dWhb[i][k] = 0.0;
   double plb[3][4], pNb[3][4];
   for (int i = 0; i < 3; ++i) {
+    const D4 ob = mu.get(i);
     for (int k = 0; k < 4; ++k) {
       double PNb;
       if (SCHEME == SCH_N) {
-        PNb = ob[i][k];
+        PNb = ob.v[k];
         plb[i][k] = 0.0;
       } else if (SCHEME == SCH_LDA) {
         PNb = 0.0;
-        plb[i][k] = ob[i][k];
+        plb[i][k] = ob.v[k];
       } else {
         const unsigned bit = 1u << (4 * i + k);
         const double sg = (spos & bit) ? 1.0 : ((sneg & bit) ? -1.0 : 0.0);
-        PNb = ob[i][k] * th[k] + denb[k] * sg;
-        plb[i][k] = ob[i][k] * (1.0 - th[k]);
+        PNb = ob.v[k] * th[k] + denb[k] * sg;
+        plb[i][k] = ob.v[k] * (1.0 - th[k]);
       }
       if (STAGE == 1) {
         pNb[i][k] = PNb;
@@ -449,9 +480,9 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
       }
     }
   }
-  if (STAGE == 1 && kNs) {
+  if (STAGE == 1 && kN0) {
     // cotangents of the kept stage-1 N parts of corners 0 and 1
-    const D4 c0 = kNs[0], c1 = kNs[1];
+    const D4 c0 = *kN0, c1 = *kN1;
     for (int k = 0; k < 4; ++k) {
       pNb[0][k] += c0.v[k];
       pNb[1][k] += c1.v[k];
@@ -487,7 +518,7 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
   }
   for (int k = 0; k < 4; ++k) rhs1b[k] += rb[k];
   if (STAGE == 1) {
-    const D4 ct = kTs ? *kTs : D4{{0.0, 0.0, 0.0, 0.0}};
+    const D4 ct = kT ? *kT : D4{{0.0, 0.0, 0.0, 0.0}};
     for (int k = 0; k < 4; ++k) phiTb[k] += rhs1b[k] + ct.v[k];
   } else {
     for (int k = 0; k < 4; ++k) {
@@ -643,8 +674,8 @@ __host__ __device__ inline void mu_of(const Dev& d, const L& lam, int64_t v, dou
 // from its corner coordinates.
 __host__ __device__ inline void tri_normals_p(const Dev& d, const double2 p[3], double nxd[3], double nyd[3],
                                               double* area) {
-  const double d1x = unwrap(p[1].x - p[0].x, d.px), d1y = unwrap(p[1].y - p[0].y, d.py);
-  const double d2x = unwrap(p[2].x - p[0].x, d.px), d2y = unwrap(p[2].y - p[0].y, d.py);
+  const double d1x = unwrap(p[1].x - p[0].x, d.px, d.hpx), d1y = unwrap(p[1].y - p[0].y, d.py, d.hpy);
+  const double d2x = unwrap(p[2].x - p[0].x, d.px, d.hpx), d2y = unwrap(p[2].y - p[0].y, d.py, d.hpy);
   nxd[0] = -(d2y - d1y);
   nxd[1] = d2y;
   nxd[2] = -d1y;
@@ -654,48 +685,47 @@ __host__ __device__ inline void tri_normals_p(const Dev& d, const double2 p[3], 
   if (area) *area = 0.5 * (d1x * d2y - d1y * d2x);
 }
 
-// Inputs of one triangle's reverse: corner ids and slot ranks, corner
+// Inputs of one triangle's reverse: the corners' part slots, corner
 // coordinates, parameter vectors and mu; for stage 2 the records W* - W^n
 // and the kept stage-1 N parts of corners 0, 1 and residual; for stage 1
 // (after a stage 2) the cotangents of those kept values. The records are
 // addressed through pointers, read where the reverse uses them.
+template <class P, class MU>
 struct AdjTriIn {
-  int32_t iv[3];
-  uint32_t rk;
+  int32_t slot[3];  // part slots of the corners
   double2 p[3];
-  D4 z[3], mu[3];
-  const D4* dw[3];
-  const D4* kn;  // two records
-  const D4* kt;
+  D4 z[3];
+  MU mu;
+  P dw[3];
+  P kn[2];
+  P kt;      // stage 1
+  D4 keepT;  // stage 2
 };
 
 // Stage-2 reverse of one triangle: cotangents of Z*, W* - W^n (CSR order) and
 // of the kept stage-1 parts (triangle order), from mu2 = -(dt/V) dL/dW^{n+1}.
-template <int SCHEME>
-__host__ __device__ inline void adj_tri2_compute(int64_t t, const Dev& d, const AdjDev& a, const AdjTriIn& in) {
+template <int SCHEME, class P, class MU>
+__host__ __device__ inline void adj_tri2_compute(int64_t t, const Dev& d, const AdjDev& a, const AdjTriIn<P, MU>& in) {
   double nxd[3], nyd[3], area;
   tri_normals_p(d, in.p, nxd, nyd, &area);
-  Stage2In s2;
+  Stage2In<P> s2;
   s2.mass = area * (1.0 / 3.0);
   s2.idt = a.idt;
-  s2.kn[0] = in.kn;
-  s2.kn[1] = in.kn + 1;
-  s2.kt = in.kt;
-  double ob[3][4];
-  for (int i = 0; i < 3; ++i) {
-    s2.dw[i] = in.dw[i];
-    for (int k = 0; k < 4; ++k) ob[i][k] = in.mu[i].v[k];
-  }
+  s2.kn[0] = in.kn[0];
+  s2.kn[1] = in.kn[1];
+  s2.kt = in.keepT;
+  for (int i = 0; i < 3; ++i) s2.dw[i] = in.dw[i];
   Stage2Bar s2b;
   double Zb[3][4];
-  if (tri_adjoint<SCHEME, 2>(in.z, nxd, nyd, d.gamma, d.igamma, ob, nullptr, nullptr, &s2, &s2b, Zb)) a.flag[1] = 1;
+  if (tri_adjoint<SCHEME, 2, P, MU>(in.z, nxd, nyd, d.gamma, d.igamma, in.mu, P{}, P{}, P{}, &s2, &s2b, Zb))
+    a.flag[1] = 1;
   for (int i = 0; i < 3; ++i) {
     ZW c;
     for (int k = 0; k < 4; ++k) {
       c.z.v[k] = Zb[i][k];
       c.w.v[k] = s2b.dw[i][k];
     }
-    a.cZW[corner_slot(d, in.iv[i], in.rk, i)] = c;
+    a.cZW[in.slot[i]] = c;
   }
   // the kept stage-1 values are corners 0 and 1 and phi^T (corner 2 = phi^T
   // minus the other two), so corner 2's cotangent moves onto those three
@@ -713,50 +743,54 @@ __host__ __device__ inline void adj_tri2_compute(int64_t t, const Dev& d, const 
 // Stage-1 reverse of one triangle: cotangents of Z^n (CSR order), from
 // mu1 = -(dt/V) dL/dW* and the cotangents of the kept parts (in.kn, in.kt;
 // null after a forward Euler step).
-template <int SCHEME>
-__host__ __device__ inline void adj_tri1_compute(int64_t, const Dev& d, const AdjDev& a, const AdjTriIn& in) {
+template <int SCHEME, class P, class MU>
+__host__ __device__ inline void adj_tri1_compute(int64_t, const Dev& d, const AdjDev& a, const AdjTriIn<P, MU>& in) {
   double nxd[3], nyd[3];
   tri_normals_p(d, in.p, nxd, nyd, nullptr);
-  double ob[3][4];
-  for (int i = 0; i < 3; ++i)
-    for (int k = 0; k < 4; ++k) ob[i][k] = in.mu[i].v[k];
   double Zb[3][4];
-  if (tri_adjoint<SCHEME, 1>(in.z, nxd, nyd, d.gamma, d.igamma, ob, in.kn, in.kt, nullptr, nullptr, Zb)) a.flag[1] = 1;
-  for (int i = 0; i < 3; ++i) st4<double>(a.cZ, corner_slot(d, in.iv[i], in.rk, i), Zb[i]);
+  if (tri_adjoint<SCHEME, 1, P, MU>(in.z, nxd, nyd, d.gamma, d.igamma, in.mu, in.kn[0], in.kn[1], in.kt, nullptr,
+                                    nullptr, Zb))
+    a.flag[1] = 1;
+  for (int i = 0; i < 3; ++i) st4<double>(a.cZ, in.slot[i], Zb[i]);
 }
 
 // The same two bodies reading their inputs straight from memory.
 template <int SCHEME>
 __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const AdjDev& a) {
-  AdjTriIn in;
-  in.rk = d.rk[t];
+  AdjTriIn<D4Ptr, MuVal> in;
+  const uint32_t rk = d.rk[t];
   for (int i = 0; i < 3; ++i) {
-    in.iv[i] = d.tv[i * d.nt + t];
-    in.p[i] = d.xy[in.iv[i]];
-    const AdjRec2& r = a.r2[in.iv[i]];
+    const int32_t v = d.tv[i * d.nt + t];
+    in.slot[i] = corner_slot(d, v, rk, i);
+    in.p[i] = d.xy[v];
+    const AdjRec2& r = a.r2[v];
     in.z[i] = r.zc;
-    in.mu[i] = r.mu;
-    in.dw[i] = &r.dw;
+    in.mu.m[i] = r.mu;
+    in.dw[i].p = &r.dw;
   }
-  in.kn = reinterpret_cast<const D4*>(d.keepN) + 2 * t;
-  in.kt = reinterpret_cast<const D4*>(d.keepT) + t;
+  in.kn[0].p = reinterpret_cast<const D4*>(d.keepN) + 2 * t;
+  in.kn[1].p = in.kn[0].p + 1;
+  in.keepT = reinterpret_cast<const D4*>(d.keepT)[t];
   adj_tri2_compute<SCHEME>(t, d, a, in);
 }
 
 template <int SCHEME>
 __host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const AdjDev& a, bool rk2) {
-  AdjTriIn in;
-  in.rk = d.rk[t];
+  AdjTriIn<D4Ptr, MuVal> in;
+  const uint32_t rk = d.rk[t];
   for (int i = 0; i < 3; ++i) {
-    in.iv[i] = d.tv[i * d.nt + t];
-    in.p[i] = d.xy[in.iv[i]];
-    const AdjRec1 r = a.r1[in.iv[i]];
+    const int32_t v = d.tv[i * d.nt + t];
+    in.slot[i] = corner_slot(d, v, rk, i);
+    in.p[i] = d.xy[v];
+    const AdjRec1 r = a.r1[v];
     in.z[i] = r.zn;
-    in.mu[i] = r.mu;
-    in.dw[i] = nullptr;
+    in.mu.m[i] = r.mu;
   }
-  in.kn = rk2 ? a.kN + 2 * t : nullptr;
-  in.kt = rk2 ? a.kT + t : nullptr;
+  if (rk2) {
+    in.kn[0].p = a.kN + 2 * t;
+    in.kn[1].p = a.kN + 2 * t + 1;
+    in.kt.p = a.kT + t;
+  }
   adj_tri1_compute<SCHEME>(t, d, a, in);
 }
 

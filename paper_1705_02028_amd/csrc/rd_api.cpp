@@ -110,6 +110,7 @@ struct rd_mesh {
   rd::Dev d;
   hipStream_t stream = nullptr;
   int device = 0;
+  int ncu = 0;  // compute units of the device
   // host copies, kept for batches
   std::vector<double> x, y, V;
   std::vector<int32_t> tri, wall, row, slot, bc, wv, wptr;
@@ -428,7 +429,9 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
   if (st != RD_OK) return st;
   rd_mesh* m = new rd_mesh();
   m->stream = static_cast<hipStream_t>(stream);
-  if (hipGetDevice(&m->device) != hipSuccess) {
+  if (hipGetDevice(&m->device) != hipSuccess ||
+      hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
+      m->ncu <= 0) {
     delete m;
     return fail(RD_EDEVICE, "no HIP device");
   }
@@ -495,6 +498,8 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
   d.igamma = 1.0 / m->gamma;
   d.px = m->px;
   d.py = m->py;
+  d.hpx = m->px > 0.0 ? 0.5 * m->px : HUGE_VAL;
+  d.hpy = m->py > 0.0 ? 0.5 * m->py : HUGE_VAL;
   {
     DeviceGuard g(m->device);
     std::vector<double2> xy(nv);
@@ -984,6 +989,7 @@ rd_status adjoint_enqueue(rd_mesh* m, const rd::AdjDev& a, rd::D4* Wa, double* s
   rd::AdjDev ad = a;
   ad.lam = rd::LamSoA{lam_np1, m->d.nv};  // read in the caller's layout
   ad.idt = 1.0 / dt;
+  ad.waves = rd::kAdjWavesPerCu * m->ncu;
   HIPCHK(rd::launch_set_state(dn, W_n, 0, s));
   HIPCHK(rd::launch_set_scalar(d.dt, dt, s));
   const bool rk2 = time == RD_RK2;

@@ -63,6 +63,7 @@ struct Dev {
   int64_t nv = 0, nt = 0;
   int32_t nwv = 0;
   double gamma = 1.4, px = 0.0, py = 0.0;
+  double hpx = 0.0, hpy = 0.0;  // half periods, +inf on an axis that is not periodic
   double igamma = 1.0 / 1.4;  // 1 / gamma (set with gamma on the host)
   // geometry and connectivity
   const double2* xy = nullptr;   // [nv]
@@ -122,6 +123,15 @@ __host__ __device__ inline double unwrap(double d, double period) {
     if (d > 0.5 * period) d -= period;
     else if (d < -0.5 * period) d += period;
   }
+  return d;
+}
+
+// The same with the half period given: 0.5 period (exact) on a periodic
+// axis, +inf on another (no difference exceeds it). The comparisons then
+// read it where it is, with nothing to keep per thread.
+__host__ __device__ inline double unwrap(double d, double period, double half) {
+  if (d > half) d -= period;
+  else if (d < -half) d += period;
   return d;
 }
 

@@ -192,8 +192,209 @@ __global__ __launch_bounds__(kBlock) void k_zero4(D4* dst, int64_t n) {
   st4<double>(dst, i, z);
 }
 
+// Staged reverse triangle passes. Each one-wavefront workgroup walks a
+// contiguous run of 64-triangle batches, its inputs streaming from HBM into
+// LDS through direct loads to LDS (16 bytes per lane per instruction,
+// landing 16 bytes per lane apart: the staging is laid out [unit][lane]) so
+// the wavefront never stalls on the gather of vertex records. Three kinds of
+// input:
+//  - eager (corner ids, slot ranks and slot bases, coordinates, parameter
+//    vectors; for stage 2 the kept residual): loaded one batch ahead into
+//    one buffer, moved to registers at the start of the batch, the buffer
+//    then refilled with the next batch;
+//  - lazy (W* - W^n and the kept N parts, or the stage-1 cotangents of the
+//    kept values): loaded one batch ahead into one of two buffers, by batch
+//    parity, read where the reverse uses them;
+//  - mu: loaded at the start of its own batch into one buffer and read where
+//    the reverse uses it (past the forward recomputation, which covers the
+//    load's latency), after a wait for that load alone.
+// Corner ids two batches ahead also go through LDS. At most 40 KB of LDS
+// per workgroup, so four fit a compute unit.
+template <int STAGE>
+struct AdjStaged {
+  static constexpr int eager = STAGE == 2 ? 11 : 9;  // xy (3), Z (6); stage 2: kept residual (2)
+  static constexpr int lazy = STAGE == 2 ? 10 : 6;   // stage 2: W* - W^n (6), kept N parts (4); stage 1: their cotangents (6)
+  // 16-byte stores every triangle's reverse issues unconditionally: stage 2
+  // three 64-byte corner records and three 32-byte kept-value cotangents,
+  // stage 1 three 32-byte corner records
+  static constexpr int stores = STAGE == 2 ? 18 : 6;
+  // direct loads issued after a batch's mu and before its reverse: the next
+  // batch's ids (4), slot bases (3), eager and lazy units (stage 1: lazy ones
+  // only after an RK2 second stage, so not counted), and the ids two ahead (4)
+  static constexpr int after_mu = STAGE == 2 ? 4 + 3 + 11 + 10 + 4 : 4 + 3 + 9 + 4;
+};
+
+// Waits the compiler keeps where they are written (it moves no memory access
+// across them). Vector memory operations, direct loads to LDS included,
+// complete in issue order, so vmcnt(N) means all but the last N issued have.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt takes 6 bits");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void wait_lgkmcnt0() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Direct load to LDS: lane l's 16 (4) bytes from src land at dst + 16 l (4 l);
+// dst is the same for the whole wavefront (it goes in M0). Written as asm so
+// that the compiler does not track these loads: the kernel orders every read
+// of the staged data after them with its own waits (its tracking of such
+// loads, when it cannot tell the LDS buffers apart, waits on every load in
+// flight before any LDS read, which would undo the staging).
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void*)p;
+}
+__device__ __forceinline__ void lds_dma16(const void* src, double2* dst) {
+  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(lds_addr(dst)) : "memory");
+}
+__device__ __forceinline__ void lds_dma4(const void* src, int32_t* dst) {
+  asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "{m0}"(lds_addr(dst)) : "memory");
+}
+
+// mu of the current batch in LDS (corner i in rows 2i, 2i+1): each read first
+// waits for its batch's load, issued K direct loads before the last one.
+template <int K>
+struct MuLds {
+  const double2* p;  // this lane's unit in row 0
+  __device__ D4 get(int i) const {
+    wait_vmcnt<K>();
+    return *D4Lds{p + 128 * i};
+  }
+};
+
+// The eager inputs of one batch held in registers.
+struct AdjEager {
+  int32_t slot[3];
+  double2 p[3];
+  D4 z[3];
+  D4 kt;  // stage 2
+};
+
+template <int SCHEME, int STAGE>
+__global__ __launch_bounds__(kAdjBlock) void k_adj_tri_staged(Dev d, AdjDev a, int rk2, int64_t per) {
+  using S = AdjStaged<STAGE>;
+  constexpr int NE = S::eager, NL = S::lazy;
+  __shared__ __attribute__((aligned(16))) double2 eb[NE * 64];       // eager units of the next batch
+  __shared__ __attribute__((aligned(16))) double2 lzb[2 * NL * 64];  // lazy units, batches of even / odd parity
+  __shared__ __attribute__((aligned(16))) double2 mub[6 * 64];       // mu of the current batch
+  __shared__ int32_t ie[7 * 64];  // next batch: corner ids, rank word, slot bases of the corners' vertex slices
+  __shared__ int32_t ib[4 * 64];  // corner ids and rank word two batches ahead
+  const int l = threadIdx.x;
+  const int64_t nb = (d.nt + 63) >> 6;
+  const int64_t b0 = xcd_block() * per;
+  const int64_t b1 = b0 + per < nb ? b0 + per : nb;
+  if (b0 >= b1) return;
+  const bool kept = STAGE == 2 || rk2 != 0;
+  // this lane's triangle in batch b; batches past the run repeat its last one
+  // and lanes past the mesh its last triangle (same inputs, same results)
+  auto tri = [&](int64_t b) {
+    const int64_t t = (b < b1 ? b : b1 - 1) * 64 + l;
+    return t < d.nt ? t : d.nt - 1;
+  };
+  auto issue_ids = [&](int64_t t, int32_t* dst) {
+    for (int i = 0; i < 3; ++i) lds_dma4(&d.tv[i * d.nt + t], &dst[i * 64]);
+    lds_dma4(&d.rk[t], &dst[3 * 64]);
+  };
+  auto rec = [&](int32_t v) {
+    return STAGE == 2 ? reinterpret_cast<const char*>(&a.r2[v]) : reinterpret_cast<const char*>(&a.r1[v]);
+  };
+  // eager and lazy loads of batch b (corner ids iv) into eb, ie and the lazy buffer lz
+  auto issue = [&](int64_t b, const int32_t iv[3], double2* lz) {
+    const int64_t t = tri(b);
+    issue_ids(t, ie);
+    for (int i = 0; i < 3; ++i) lds_dma4(&d.sbase[iv[i] >> 6], &ie[(4 + i) * 64]);
+    for (int i = 0; i < 3; ++i) lds_dma16(&d.xy[iv[i]], &eb[i * 64]);
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + 16 * c, &eb[(3 + 2 * i + c) * 64]);  // Z
+    if (STAGE == 2) {
+      const char* kt = reinterpret_cast<const char*>(d.keepT) + 32 * t;
+      for (int c = 0; c < 2; ++c) lds_dma16(kt + 16 * c, &eb[(9 + c) * 64]);
+      for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + 32 + 16 * c, &lz[(2 * i + c) * 64]);  // W* - W^n
+      const char* kn = reinterpret_cast<const char*>(d.keepN) + 64 * t;
+      for (int c = 0; c < 4; ++c) lds_dma16(kn + 16 * c, &lz[(6 + c) * 64]);
+    } else if (kept) {
+      const char* kn = reinterpret_cast<const char*>(a.kN + 2 * t);
+      for (int c = 0; c < 4; ++c) lds_dma16(kn + 16 * c, &lz[c * 64]);
+      const char* kt = reinterpret_cast<const char*>(a.kT + t);
+      for (int c = 0; c < 2; ++c) lds_dma16(kt + 16 * c, &lz[(4 + c) * 64]);
+    }
+  };
+  // batch b's eager inputs into registers; then the loads of its mu, of batch
+  // b+1 (lazy units into lz) and of the ids of batch b+2. The eager and lazy
+  // loads of batch b and the ids of b+1 were issued before the previous
+  // batch's reverse, whose stores have been issued since: waiting until no
+  // more than those stores are outstanding waits for exactly those loads
+  // (the first batch waits for everything).
+  AdjEager e;
+  auto advance = [&](int64_t b, double2* lz, bool first) {
+    if (first) wait_vmcnt<0>();
+    else wait_vmcnt<S::stores>();
+    const uint32_t rk = (uint32_t)ie[3 * 64 + l];
+    int32_t iv[3];
+    for (int i = 0; i < 3; ++i) {
+      iv[i] = ie[i * 64 + l];
+      e.slot[i] = ie[(4 + i) * 64 + l] + (iv[i] & 63) + 64 * (int32_t)((rk >> (10 * i)) & 1023u);
+      e.p[i] = eb[i * 64 + l];
+      e.z[i] = *D4Lds{&eb[(3 + 2 * i) * 64 + l]};
+    }
+    if (STAGE == 2) e.kt = *D4Lds{&eb[9 * 64 + l]};
+    const int32_t nx[3] = {ib[l], ib[64 + l], ib[128 + l]};
+    // every read of the buffers has returned before new loads overwrite them
+    wait_lgkmcnt0();
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + (STAGE == 2 ? 64 : 32) + 16 * c, &mub[(2 * i + c) * 64]);
+    issue(b + 1, nx, lz);
+    issue_ids(tri(b + 2), ib);
+  };
+  auto compute = [&](int64_t b, const double2* lz) {
+    AdjTriIn<D4Lds, MuLds<S::after_mu>> in;
+    for (int i = 0; i < 3; ++i) {
+      in.slot[i] = e.slot[i];
+      in.p[i] = e.p[i];
+      in.z[i] = e.z[i];
+    }
+    in.mu.p = &mub[l];
+    if (STAGE == 2) {
+      for (int i = 0; i < 3; ++i) in.dw[i].p = &lz[2 * i * 64 + l];
+      in.kn[0].p = &lz[6 * 64 + l];
+      in.kn[1].p = &lz[8 * 64 + l];
+      in.keepT = e.kt;
+    } else if (kept) {
+      in.kn[0].p = &lz[l];
+      in.kn[1].p = &lz[2 * 64 + l];
+      in.kt.p = &lz[4 * 64 + l];
+    }
+    const int64_t t = tri(b);
+    if (STAGE == 2) adj_tri2_compute<SCHEME>(t, d, a, in);
+    else adj_tri1_compute<SCHEME>(t, d, a, in);
+  };
+  {
+    const int64_t t = tri(b0);
+    const int32_t iv[3] = {d.tv[t], d.tv[d.nt + t], d.tv[2 * d.nt + t]};
+    issue(b0, iv, lzb);
+    issue_ids(tri(b0 + 1), ib);
+  }
+  advance(b0, lzb + NL * 64, true);
+  for (int64_t b = b0; b < b1; ++b) {
+    double2* lz = lzb + ((b - b0) & 1) * (NL * 64);
+    compute(b, lz);
+    advance(b + 1, lz, false);
+  }
+  // the last (repeated) loads land before the workgroup's LDS is released
+  wait_vmcnt<0>();
+}
+
 template <int SCHEME>
 static void adj_tris(const Dev& d, const AdjDev& a, int stage, int rk2, hipStream_t s) {
+  if (d.nt == 0) return;
+  if (a.waves > 0) {
+    const int64_t nb = (d.nt + 63) / 64;
+    const int64_t per = (nb + a.waves - 1) / a.waves;
+    const unsigned g = (unsigned)((nb + per - 1) / per);
+    if (stage == 2) hipLaunchKernelGGL((k_adj_tri_staged<SCHEME, 2>), dim3(g), dim3(kAdjBlock), 0, s, d, a, rk2, per);
+    else hipLaunchKernelGGL((k_adj_tri_staged<SCHEME, 1>), dim3(g), dim3(kAdjBlock), 0, s, d, a, rk2, per);
+    return;
+  }
   const unsigned g = (unsigned)((d.nt + kAdjBlock - 1) / kAdjBlock);
   if (stage == 2) hipLaunchKernelGGL((k_adj_tri2<SCHEME>), dim3(g), dim3(kAdjBlock), 0, s, d, a);
   else hipLaunchKernelGGL((k_adj_tri1<SCHEME>), dim3(g), dim3(kAdjBlock), 0, s, d, a, rk2);
