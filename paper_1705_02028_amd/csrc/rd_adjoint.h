@@ -252,7 +252,7 @@ struct Stage2In {
   double mass = 0.0, idt = 0.0;
   P dw[3];  // W*_i - W^n_i
   P kn[2];  // stage-1 N parts of corners 0 and 1
-  D4 kt;    // stage-1 residual
+  P kt;     // stage-1 residual
 };
 struct Stage2Bar {
   double dw[3][4];
@@ -327,17 +327,6 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
   apply_split(q, kc[1], kc[1].l3m, kc[1].h1m, kc[1].h2m, dWh[1], t1);
   apply_split(q, kc[2], kc[2].l3m, kc[2].h1m, kc[2].h2m, dWh[2], t2);
   for (int k = 0; k < 4; ++k) bN[k] = t1[k] + t2[k];
-  double rhs1[4], srate[4] = {0, 0, 0, 0};
-  if (STAGE == 1) {
-    for (int k = 0; k < 4; ++k) rhs1[k] = phiT[k];
-  } else {
-    for (int i = 0; i < 3; ++i) {
-      const D4 w = *s2->dw[i];
-      for (int k = 0; k < 4; ++k) srate[k] += w.v[k] * s2->idt;
-    }
-    const D4 kt = SCHEME == SCH_N ? D4{{0.0, 0.0, 0.0, 0.0}} : s2->kt;
-    for (int k = 0; k < 4; ++k) rhs1[k] = s2->mass * srate[k] + 0.5 * (kt.v[k] + phiT[k]);
-  }
   // A^{-1} (columns from unit right-hand sides) and the two solutions
   double Ai[4][4];
   bool singular = false;
@@ -357,6 +346,19 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
         Ai[r][c2 + 1] = x1[r];
       }
     }
+  }
+  // the LDA right-hand side (stage 2: with the rate of W* - W^n and the kept
+  // stage-1 residual), formed after the inverse: its inputs are read late
+  double rhs1[4], srate[4] = {0, 0, 0, 0};
+  if (STAGE == 1) {
+    for (int k = 0; k < 4; ++k) rhs1[k] = phiT[k];
+  } else {
+    for (int i = 0; i < 3; ++i) {
+      const D4 w = *s2->dw[i];
+      for (int k = 0; k < 4; ++k) srate[k] += w.v[k] * s2->idt;
+    }
+    const D4 kt = SCHEME == SCH_N ? D4{{0.0, 0.0, 0.0, 0.0}} : *s2->kt;
+    for (int k = 0; k < 4; ++k) rhs1[k] = s2->mass * srate[k] + 0.5 * (kt.v[k] + phiT[k]);
   }
   double xN[4], xL[4];
   for (int r = 0; r < 4; ++r) {
@@ -389,7 +391,7 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
     if (STAGE == 2) {
       const D4 z = {{0.0, 0.0, 0.0, 0.0}};
       const bool keep = SCHEME != SCH_LDA;
-      const D4 k0 = keep ? *s2->kn[0] : z, k1 = keep ? *s2->kn[1] : z, kt = keep ? s2->kt : z;
+      const D4 k0 = keep ? *s2->kn[0] : z, k1 = keep ? *s2->kn[1] : z, kt = keep ? *s2->kt : z;
       for (int k = 0; k < 4; ++k) {
         kn[0][k] = k0.v[k];
         kn[1][k] = k1.v[k];
@@ -698,8 +700,7 @@ struct AdjTriIn {
   MU mu;
   P dw[3];
   P kn[2];
-  P kt;      // stage 1
-  D4 keepT;  // stage 2
+  P kt;
 };
 
 // Stage-2 reverse of one triangle: cotangents of Z*, W* - W^n (CSR order) and
@@ -713,7 +714,7 @@ __host__ __device__ inline void adj_tri2_compute(int64_t t, const Dev& d, const 
   s2.idt = a.idt;
   s2.kn[0] = in.kn[0];
   s2.kn[1] = in.kn[1];
-  s2.kt = in.keepT;
+  s2.kt = in.kt;
   for (int i = 0; i < 3; ++i) s2.dw[i] = in.dw[i];
   Stage2Bar s2b;
   double Zb[3][4];
@@ -770,7 +771,7 @@ __host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const Adj
   }
   in.kn[0].p = reinterpret_cast<const D4*>(d.keepN) + 2 * t;
   in.kn[1].p = in.kn[0].p + 1;
-  in.keepT = reinterpret_cast<const D4*>(d.keepT)[t];
+  in.kt.p = reinterpret_cast<const D4*>(d.keepT) + t;
   adj_tri2_compute<SCHEME>(t, d, a, in);
 }
 

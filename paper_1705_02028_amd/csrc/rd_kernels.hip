@@ -196,32 +196,28 @@ __global__ __launch_bounds__(kBlock) void k_zero4(D4* dst, int64_t n) {
 // contiguous run of 64-triangle batches, its inputs streaming from HBM into
 // LDS through direct loads to LDS (16 bytes per lane per instruction,
 // landing 16 bytes per lane apart: the staging is laid out [unit][lane]) so
-// the wavefront never stalls on the gather of vertex records. Three kinds of
-// input:
-//  - eager (corner ids, slot ranks and slot bases, coordinates, parameter
-//    vectors; for stage 2 the kept residual): loaded one batch ahead into
-//    one buffer, moved to registers at the start of the batch, the buffer
-//    then refilled with the next batch;
-//  - lazy (W* - W^n and the kept N parts, or the stage-1 cotangents of the
-//    kept values): loaded one batch ahead into one of two buffers, by batch
-//    parity, read where the reverse uses them;
-//  - mu: loaded at the start of its own batch into one buffer and read where
-//    the reverse uses it (past the forward recomputation, which covers the
-//    load's latency), after a wait for that load alone.
-// Corner ids two batches ahead also go through LDS. At most 40 KB of LDS
-// per workgroup, so four fit a compute unit.
+// the wavefront never stalls on the gather of vertex records:
+//  - eager inputs (corner ids, slot ranks and slot bases, coordinates,
+//    parameter vectors) are loaded one batch ahead, moved to registers at the
+//    start of the batch, and their buffer refilled with the next batch's;
+//  - the rest (mu; for stage 2 W* - W^n and the kept stage-1 values, for
+//    stage 1 their cotangents) is loaded at the start of its own batch and
+//    read where the reverse uses it, past the start of the forward
+//    recomputation, which covers the load's latency; each read first waits
+//    for that batch's loads alone.
+// Corner ids two batches ahead also go through LDS.
 template <int STAGE>
 struct AdjStaged {
-  static constexpr int eager = STAGE == 2 ? 11 : 9;  // xy (3), Z (6); stage 2: kept residual (2)
-  static constexpr int lazy = STAGE == 2 ? 10 : 6;   // stage 2: W* - W^n (6), kept N parts (4); stage 1: their cotangents (6)
+  static constexpr int eager = 9;                   // xy (3), Z (6)
+  static constexpr int late = STAGE == 2 ? 18 : 12;  // mu (6); stage 2: W* - W^n (6), kept N parts (4), kept residual (2);
+                                                     // stage 1: cotangents of the kept values (6)
   // 16-byte stores every triangle's reverse issues unconditionally: stage 2
   // three 64-byte corner records and three 32-byte kept-value cotangents,
   // stage 1 three 32-byte corner records
   static constexpr int stores = STAGE == 2 ? 18 : 6;
-  // direct loads issued after a batch's mu and before its reverse: the next
-  // batch's ids (4), slot bases (3), eager and lazy units (stage 1: lazy ones
-  // only after an RK2 second stage, so not counted), and the ids two ahead (4)
-  static constexpr int after_mu = STAGE == 2 ? 4 + 3 + 11 + 10 + 4 : 4 + 3 + 9 + 4;
+  // direct loads issued after a batch's late ones and before its reverse:
+  // the next batch's ids (4), slot bases (3) and eager units, the ids two ahead (4)
+  static constexpr int after_late = 4 + 3 + eager + 4;
 };
 
 // Waits the compiler keeps where they are written (it moves no memory access
@@ -250,15 +246,25 @@ __device__ __forceinline__ void lds_dma4(const void* src, int32_t* dst) {
   asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "{m0}"(lds_addr(dst)) : "memory");
 }
 
-// mu of the current batch in LDS (corner i in rows 2i, 2i+1): each read first
-// waits for its batch's load, issued K direct loads before the last one.
+// A late input in LDS (its two 16-byte halves 64 units apart): each read
+// first waits for its batch's loads, issued K direct loads before the last.
+// The scheduling barrier keeps the wait where the reverse reads the value
+// (the compiler would otherwise hoist it, and its stall, to the top).
 template <int K>
-struct MuLds {
-  const double2* p;  // this lane's unit in row 0
-  __device__ D4 get(int i) const {
+struct D4Late {
+  const double2* p = nullptr;
+  __device__ D4 operator*() const {
+    __builtin_amdgcn_sched_barrier(0);
     wait_vmcnt<K>();
-    return *D4Lds{p + 128 * i};
+    return *D4Lds{p};
   }
+  __device__ explicit operator bool() const { return p != nullptr; }
+};
+// mu of the current batch (corner i in rows 2i, 2i+1)
+template <int K>
+struct MuLate {
+  const double2* p;  // this lane's unit in row 0
+  __device__ D4 get(int i) const { return *D4Late<K>{p + 128 * i}; }
 };
 
 // The eager inputs of one batch held in registers.
@@ -266,16 +272,14 @@ struct AdjEager {
   int32_t slot[3];
   double2 p[3];
   D4 z[3];
-  D4 kt;  // stage 2
 };
 
 template <int SCHEME, int STAGE>
 __global__ __launch_bounds__(kAdjBlock) void k_adj_tri_staged(Dev d, AdjDev a, int rk2, int64_t per) {
   using S = AdjStaged<STAGE>;
-  constexpr int NE = S::eager, NL = S::lazy;
-  __shared__ __attribute__((aligned(16))) double2 eb[NE * 64];       // eager units of the next batch
-  __shared__ __attribute__((aligned(16))) double2 lzb[2 * NL * 64];  // lazy units, batches of even / odd parity
-  __shared__ __attribute__((aligned(16))) double2 mub[6 * 64];       // mu of the current batch
+  constexpr int K = S::after_late;
+  __shared__ __attribute__((aligned(16))) double2 eb[S::eager * 64];  // eager units of the next batch
+  __shared__ __attribute__((aligned(16))) double2 lt[S::late * 64];   // late units of the current batch
   __shared__ int32_t ie[7 * 64];  // next batch: corner ids, rank word, slot bases of the corners' vertex slices
   __shared__ int32_t ib[4 * 64];  // corner ids and rank word two batches ahead
   const int l = threadIdx.x;
@@ -288,45 +292,48 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_tri_staged(Dev d, AdjDev a, i
   // and lanes past the mesh its last triangle (same inputs, same results)
   auto tri = [&](int64_t b) {
     const int64_t t = (b < b1 ? b : b1 - 1) * 64 + l;
-    return t < d.nt ? t : d.nt - 1;
+    return (int32_t)(t < d.nt ? t : d.nt - 1);
   };
-  auto issue_ids = [&](int64_t t, int32_t* dst) {
+  auto issue_ids = [&](int32_t t, int32_t* dst) {
     for (int i = 0; i < 3; ++i) lds_dma4(&d.tv[i * d.nt + t], &dst[i * 64]);
     lds_dma4(&d.rk[t], &dst[3 * 64]);
   };
   auto rec = [&](int32_t v) {
     return STAGE == 2 ? reinterpret_cast<const char*>(&a.r2[v]) : reinterpret_cast<const char*>(&a.r1[v]);
   };
-  // eager and lazy loads of batch b (corner ids iv) into eb, ie and the lazy buffer lz
-  auto issue = [&](int64_t b, const int32_t iv[3], double2* lz) {
-    const int64_t t = tri(b);
-    issue_ids(t, ie);
+  // eager loads of batch b (corner ids iv) into eb and ie
+  auto issue_eager = [&](int64_t b, const int32_t iv[3]) {
+    issue_ids(tri(b), ie);
     for (int i = 0; i < 3; ++i) lds_dma4(&d.sbase[iv[i] >> 6], &ie[(4 + i) * 64]);
     for (int i = 0; i < 3; ++i) lds_dma16(&d.xy[iv[i]], &eb[i * 64]);
     for (int i = 0; i < 3; ++i)
       for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + 16 * c, &eb[(3 + 2 * i + c) * 64]);  // Z
+  };
+  // late loads of batch b (triangle t, corner ids iv) into lt
+  auto issue_late = [&](int32_t t, const int32_t iv[3]) {
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + (STAGE == 2 ? 64 : 32) + 16 * c, &lt[(2 * i + c) * 64]);
     if (STAGE == 2) {
-      const char* kt = reinterpret_cast<const char*>(d.keepT) + 32 * t;
-      for (int c = 0; c < 2; ++c) lds_dma16(kt + 16 * c, &eb[(9 + c) * 64]);
       for (int i = 0; i < 3; ++i)
-        for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + 32 + 16 * c, &lz[(2 * i + c) * 64]);  // W* - W^n
-      const char* kn = reinterpret_cast<const char*>(d.keepN) + 64 * t;
-      for (int c = 0; c < 4; ++c) lds_dma16(kn + 16 * c, &lz[(6 + c) * 64]);
+        for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + 32 + 16 * c, &lt[(6 + 2 * i + c) * 64]);  // W* - W^n
+      const char* kn = reinterpret_cast<const char*>(d.keepN) + 64 * (int64_t)t;
+      for (int c = 0; c < 4; ++c) lds_dma16(kn + 16 * c, &lt[(12 + c) * 64]);
+      const char* kt = reinterpret_cast<const char*>(d.keepT) + 32 * (int64_t)t;
+      for (int c = 0; c < 2; ++c) lds_dma16(kt + 16 * c, &lt[(16 + c) * 64]);
     } else if (kept) {
-      const char* kn = reinterpret_cast<const char*>(a.kN + 2 * t);
-      for (int c = 0; c < 4; ++c) lds_dma16(kn + 16 * c, &lz[c * 64]);
+      const char* kn = reinterpret_cast<const char*>(a.kN + 2 * (int64_t)t);
+      for (int c = 0; c < 4; ++c) lds_dma16(kn + 16 * c, &lt[(6 + c) * 64]);
       const char* kt = reinterpret_cast<const char*>(a.kT + t);
-      for (int c = 0; c < 2; ++c) lds_dma16(kt + 16 * c, &lz[(4 + c) * 64]);
+      for (int c = 0; c < 2; ++c) lds_dma16(kt + 16 * c, &lt[(10 + c) * 64]);
     }
   };
-  // batch b's eager inputs into registers; then the loads of its mu, of batch
-  // b+1 (lazy units into lz) and of the ids of batch b+2. The eager and lazy
-  // loads of batch b and the ids of b+1 were issued before the previous
-  // batch's reverse, whose stores have been issued since: waiting until no
-  // more than those stores are outstanding waits for exactly those loads
-  // (the first batch waits for everything).
+  // Batch b's eager inputs into registers; then its late loads, the eager
+  // loads of batch b+1 and the ids of batch b+2. The eager loads of batch b
+  // and the ids of b+1 were issued before the previous batch's reverse, whose
+  // stores have been issued since: waiting until no more than those stores
+  // are outstanding waits for them (the first batch waits for everything).
   AdjEager e;
-  auto advance = [&](int64_t b, double2* lz, bool first) {
+  auto advance = [&](int64_t b, bool first) {
     if (first) wait_vmcnt<0>();
     else wait_vmcnt<S::stores>();
     const uint32_t rk = (uint32_t)ie[3 * 64 + l];
@@ -337,48 +344,45 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_tri_staged(Dev d, AdjDev a, i
       e.p[i] = eb[i * 64 + l];
       e.z[i] = *D4Lds{&eb[(3 + 2 * i) * 64 + l]};
     }
-    if (STAGE == 2) e.kt = *D4Lds{&eb[9 * 64 + l]};
     const int32_t nx[3] = {ib[l], ib[64 + l], ib[128 + l]};
     // every read of the buffers has returned before new loads overwrite them
     wait_lgkmcnt0();
-    for (int i = 0; i < 3; ++i)
-      for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + (STAGE == 2 ? 64 : 32) + 16 * c, &mub[(2 * i + c) * 64]);
-    issue(b + 1, nx, lz);
+    issue_late(tri(b), iv);
+    issue_eager(b + 1, nx);
     issue_ids(tri(b + 2), ib);
   };
-  auto compute = [&](int64_t b, const double2* lz) {
-    AdjTriIn<D4Lds, MuLds<S::after_mu>> in;
+  auto compute = [&](int64_t b) {
+    AdjTriIn<D4Late<K>, MuLate<K>> in;
     for (int i = 0; i < 3; ++i) {
       in.slot[i] = e.slot[i];
       in.p[i] = e.p[i];
       in.z[i] = e.z[i];
     }
-    in.mu.p = &mub[l];
+    in.mu.p = &lt[l];
     if (STAGE == 2) {
-      for (int i = 0; i < 3; ++i) in.dw[i].p = &lz[2 * i * 64 + l];
-      in.kn[0].p = &lz[6 * 64 + l];
-      in.kn[1].p = &lz[8 * 64 + l];
-      in.keepT = e.kt;
+      for (int i = 0; i < 3; ++i) in.dw[i].p = &lt[(6 + 2 * i) * 64 + l];
+      in.kn[0].p = &lt[12 * 64 + l];
+      in.kn[1].p = &lt[14 * 64 + l];
+      in.kt.p = &lt[16 * 64 + l];
     } else if (kept) {
-      in.kn[0].p = &lz[l];
-      in.kn[1].p = &lz[2 * 64 + l];
-      in.kt.p = &lz[4 * 64 + l];
+      in.kn[0].p = &lt[6 * 64 + l];
+      in.kn[1].p = &lt[8 * 64 + l];
+      in.kt.p = &lt[10 * 64 + l];
     }
-    const int64_t t = tri(b);
+    const int32_t t = tri(b);
     if (STAGE == 2) adj_tri2_compute<SCHEME>(t, d, a, in);
     else adj_tri1_compute<SCHEME>(t, d, a, in);
   };
   {
-    const int64_t t = tri(b0);
+    const int32_t t = tri(b0);
     const int32_t iv[3] = {d.tv[t], d.tv[d.nt + t], d.tv[2 * d.nt + t]};
-    issue(b0, iv, lzb);
+    issue_eager(b0, iv);
     issue_ids(tri(b0 + 1), ib);
   }
-  advance(b0, lzb + NL * 64, true);
+  advance(b0, true);
   for (int64_t b = b0; b < b1; ++b) {
-    double2* lz = lzb + ((b - b0) & 1) * (NL * 64);
-    compute(b, lz);
-    advance(b + 1, lz, false);
+    compute(b);
+    advance(b + 1, false);
   }
   // the last (repeated) loads land before the workgroup's LDS is released
   wait_vmcnt<0>();
