@@ -65,7 +65,7 @@ struct AdjDev {
   D4* wcbar = nullptr;       // [nwv] cotangent of the wall term at W^n (stage 1 + half of stage 2)
   int* flag = nullptr;       // [2]: [0] the recomputed step went non-physical, [1] a solve skipped a column
   double idt = 0.0;          // 1 / dt of the step being reversed
-  int32_t waves = 0;         // workgroups of the staged reverse triangle passes (0: one per 64 triangles)
+  int32_t waves = 0;         // workgroups of the reverse triangle passes (one per SIMD)
 };
 
 // The staged reverse triangle passes keep one wavefront per SIMD resident.
@@ -220,17 +220,8 @@ __host__ __device__ inline void build_A_bar(const Roe<double>& q, const Corner<d
   qb.ic += q.g1 * Gb[3];
 }
 
-// Inputs of the stage-2 function of one triangle besides its parameter
-// vectors: the records are read where they are used (not held in registers
-// across the triangle's forward recomputation).
-// A D4 the reverse reads where it uses it: from memory (D4Ptr) or from the
-// staging buffer of the staged passes (D4Lds: 16-byte units laid out
-// [unit][lane], so a record's two halves sit 64 units apart). Null = absent.
-struct D4Ptr {
-  const D4* p = nullptr;
-  __host__ __device__ D4 operator*() const { return *p; }
-  __host__ __device__ explicit operator bool() const { return p != nullptr; }
-};
+// A D4 in the staging buffer of the reverse triangle passes: 16-byte units
+// laid out [unit][lane], so a record's two halves sit 64 units apart.
 struct D4Lds {
   const double2* p = nullptr;
   __host__ __device__ D4 operator*() const {
@@ -240,13 +231,10 @@ struct D4Lds {
   __host__ __device__ explicit operator bool() const { return p != nullptr; }
 };
 
-// The corners' mu (cotangents of their parts) as values in registers; the
-// staged passes read it from LDS where the reverse uses it.
-struct MuVal {
-  D4 m[3];
-  __host__ __device__ D4 get(int i) const { return m[i]; }
-};
-
+// Inputs of the stage-2 function of one triangle besides its parameter
+// vectors, read where they are used (not held in registers across the
+// triangle's forward recomputation) through P: a pointer-like type whose
+// operator* gives the D4 and whose bool conversion says whether it is there.
 template <class P>
 struct Stage2In {
   double mass = 0.0, idt = 0.0;
@@ -690,8 +678,8 @@ __host__ __device__ inline void tri_normals_p(const Dev& d, const double2 p[3], 
 // Inputs of one triangle's reverse: the corners' part slots, corner
 // coordinates, parameter vectors and mu; for stage 2 the records W* - W^n
 // and the kept stage-1 N parts of corners 0, 1 and residual; for stage 1
-// (after a stage 2) the cotangents of those kept values. The records are
-// addressed through pointers, read where the reverse uses them.
+// (after a stage 2) the cotangents of those kept values. mu (through MU's
+// get(i)) and the records (through P) are read where the reverse uses them.
 template <class P, class MU>
 struct AdjTriIn {
   int32_t slot[3];  // part slots of the corners
@@ -753,46 +741,6 @@ __host__ __device__ inline void adj_tri1_compute(int64_t, const Dev& d, const Ad
                                     nullptr, Zb))
     a.flag[1] = 1;
   for (int i = 0; i < 3; ++i) st4<double>(a.cZ, in.slot[i], Zb[i]);
-}
-
-// The same two bodies reading their inputs straight from memory.
-template <int SCHEME>
-__host__ __device__ inline void adj_tri2_body(int64_t t, const Dev& d, const AdjDev& a) {
-  AdjTriIn<D4Ptr, MuVal> in;
-  const uint32_t rk = d.rk[t];
-  for (int i = 0; i < 3; ++i) {
-    const int32_t v = d.tv[i * d.nt + t];
-    in.slot[i] = corner_slot(d, v, rk, i);
-    in.p[i] = d.xy[v];
-    const AdjRec2& r = a.r2[v];
-    in.z[i] = r.zc;
-    in.mu.m[i] = r.mu;
-    in.dw[i].p = &r.dw;
-  }
-  in.kn[0].p = reinterpret_cast<const D4*>(d.keepN) + 2 * t;
-  in.kn[1].p = in.kn[0].p + 1;
-  in.kt.p = reinterpret_cast<const D4*>(d.keepT) + t;
-  adj_tri2_compute<SCHEME>(t, d, a, in);
-}
-
-template <int SCHEME>
-__host__ __device__ inline void adj_tri1_body(int64_t t, const Dev& d, const AdjDev& a, bool rk2) {
-  AdjTriIn<D4Ptr, MuVal> in;
-  const uint32_t rk = d.rk[t];
-  for (int i = 0; i < 3; ++i) {
-    const int32_t v = d.tv[i * d.nt + t];
-    in.slot[i] = corner_slot(d, v, rk, i);
-    in.p[i] = d.xy[v];
-    const AdjRec1 r = a.r1[v];
-    in.z[i] = r.zn;
-    in.mu.m[i] = r.mu;
-  }
-  if (rk2) {
-    in.kn[0].p = a.kN + 2 * t;
-    in.kn[1].p = a.kN + 2 * t + 1;
-    in.kt.p = a.kT + t;
-  }
-  adj_tri1_compute<SCHEME>(t, d, a, in);
 }
 
 // Wall-term transpose at one wall vertex b: sum over its wall edges of

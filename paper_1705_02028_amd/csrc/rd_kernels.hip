@@ -142,21 +142,8 @@ __global__ __launch_bounds__(kBlock) void k_copy4(D4* dst, const D4* src, int64_
 // ------------------------------------------------------------- adjoint --
 
 // The reverse triangle kernels run one wavefront per SIMD (their registers
-// fill the SIMD); one-wavefront workgroups let each SIMD start its next
-// wavefront as soon as its own finishes.
+// fill the SIMD), in one-wavefront workgroups.
 constexpr int kAdjBlock = 64;
-
-template <int SCHEME>
-__global__ __launch_bounds__(kAdjBlock) void k_adj_tri2(Dev d, AdjDev a) {
-  const int64_t t = xcd_block() * kAdjBlock + threadIdx.x;
-  if (t < d.nt) adj_tri2_body<SCHEME>(t, d, a);
-}
-
-template <int SCHEME>
-__global__ __launch_bounds__(kAdjBlock) void k_adj_tri1(Dev d, AdjDev a, int rk2) {
-  const int64_t t = xcd_block() * kAdjBlock + threadIdx.x;
-  if (t < d.nt) adj_tri1_body<SCHEME>(t, d, a, rk2 != 0);
-}
 
 __global__ __launch_bounds__(kBlock) void k_adj_star(Dev d, AdjDev a) {
   const int64_t v = xcd_block() * kBlock + threadIdx.x;
@@ -388,23 +375,20 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_tri_staged(Dev d, AdjDev a, i
   wait_vmcnt<0>();
 }
 
+// a.waves workgroups (one per SIMD the device has), each taking a run of
+// ceil(batches / a.waves) batches of 64 triangles
 template <int SCHEME>
 static void adj_tris(const Dev& d, const AdjDev& a, int stage, int rk2, hipStream_t s) {
   if (d.nt == 0) return;
-  if (a.waves > 0) {
-    const int64_t nb = (d.nt + 63) / 64;
-    const int64_t per = (nb + a.waves - 1) / a.waves;
-    const unsigned g = (unsigned)((nb + per - 1) / per);
-    if (stage == 2) hipLaunchKernelGGL((k_adj_tri_staged<SCHEME, 2>), dim3(g), dim3(kAdjBlock), 0, s, d, a, rk2, per);
-    else hipLaunchKernelGGL((k_adj_tri_staged<SCHEME, 1>), dim3(g), dim3(kAdjBlock), 0, s, d, a, rk2, per);
-    return;
-  }
-  const unsigned g = (unsigned)((d.nt + kAdjBlock - 1) / kAdjBlock);
-  if (stage == 2) hipLaunchKernelGGL((k_adj_tri2<SCHEME>), dim3(g), dim3(kAdjBlock), 0, s, d, a);
-  else hipLaunchKernelGGL((k_adj_tri1<SCHEME>), dim3(g), dim3(kAdjBlock), 0, s, d, a, rk2);
+  const int64_t nb = (d.nt + 63) / 64;
+  const int64_t per = (nb + a.waves - 1) / a.waves;
+  const unsigned g = (unsigned)((nb + per - 1) / per);
+  if (stage == 2) hipLaunchKernelGGL((k_adj_tri_staged<SCHEME, 2>), dim3(g), dim3(kAdjBlock), 0, s, d, a, rk2, per);
+  else hipLaunchKernelGGL((k_adj_tri_staged<SCHEME, 1>), dim3(g), dim3(kAdjBlock), 0, s, d, a, rk2, per);
 }
 
 hipError_t launch_adjoint(const Dev& d, const AdjDev& a, int scheme, int rk2, double* out, hipStream_t s) {
+  if (a.waves <= 0) return hipErrorInvalidValue;
   auto tris = [&](int stage) {
     switch (scheme) {
       case SCH_N: adj_tris<SCH_N>(d, a, stage, rk2, s); break;
