@@ -11,7 +11,12 @@ namespace rd {
 
 // One thread per triangle. (A persistent grid with the next triangle's loads
 // software-pipelined was measured slower: fewer waves in flight and, with
-// per-workgroup chunks, scattered working sets.)
+// per-workgroup chunks, scattered working sets. So was the adjoint's staged
+// form below applied to the FP64 passes, persistent one-wavefront workgroups
+// with the next batch's gathered inputs loaded straight to LDS: 0.72-0.87 ms
+// against 0.545 ms for the stage-1 pass at 2048^2, 0.51 against 0.50 for
+// stage 2; two to three waves per SIMD already overlap these passes' gathers
+// with each other's arithmetic.)
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP>
 __global__ __launch_bounds__(kBlock, (TriKernelWaves<R, SCHEME, STAGE, SAVE, CFL>::value)) void k_tri(Dev d) {
   const int64_t t = xcd_block() * kBlock + threadIdx.x;
