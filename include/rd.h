@@ -233,7 +233,7 @@ rd_status rd_adjoint_step(rd_mesh* mesh, const double* W_n, double dt, int schem
  * stream-ordered on the mesh's stream), computed by the same kernels; it
  * calls no allocator. Its workspace is one fixed array of 128 MiB per GPU
  * (held by the process from its first use on that GPU until exit), which
- * fits meshes of about 130,000 vertices / 260,000 triangles; a larger mesh
+ * fits meshes of about 125,000 vertices / 250,000 triangles; a larger mesh
  * gives RD_EINVAL with the sizes in rd_last_error. flags: device int[2],
  * cleared by the call, then set by the kernels: flags[0] = 1 when W_n or its
  * recomputed first stage is non-physical, flags[1] = 1 when a triangle's

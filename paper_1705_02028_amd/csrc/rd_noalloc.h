@@ -8,7 +8,7 @@
 namespace rd {
 
 // Bytes of the per-GPU workspace: 128 MiB, enough for meshes of about
-// 110,000 vertices and 220,000 triangles (the adjoint needs about
+// 125,000 vertices and 250,000 triangles (the adjoint needs about
 // 296 B per vertex, 96 B per corner slot and 96 B per triangle).
 constexpr size_t kNoallocScratchBytes = size_t(128) << 20;
 
