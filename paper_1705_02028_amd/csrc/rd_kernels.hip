@@ -215,10 +215,14 @@ struct AdjStaged {
 // Waits the compiler keeps where they are written (it moves no memory access
 // across them). Vector memory operations, direct loads to LDS included,
 // complete in issue order, so vmcnt(N) means all but the last N issued have.
-template <int N>
+// The assembly comments name the waits and loads for the check of their
+// counts on the compiled code (tests/test_staged_waits.py): a "late" wait
+// waits for the last "late" loads, any other for the last direct loads.
+template <int N, bool LATE = false>
 __device__ __forceinline__ void wait_vmcnt() {
   static_assert(N >= 0 && N < 64, "vmcnt takes 6 bits");
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+  if constexpr (LATE) asm volatile("s_waitcnt vmcnt(%0) ; staged wait: late" ::"n"(N) : "memory");
+  else asm volatile("s_waitcnt vmcnt(%0) ; staged wait" ::"n"(N) : "memory");
 }
 __device__ __forceinline__ void wait_lgkmcnt0() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
@@ -231,11 +235,17 @@ __device__ __forceinline__ void wait_lgkmcnt0() { asm volatile("s_waitcnt lgkmcn
 __device__ __forceinline__ uint32_t lds_addr(const void* p) {
   return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void*)p;
 }
+template <bool LATE = false>
 __device__ __forceinline__ void lds_dma16(const void* src, double2* dst) {
-  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(lds_addr(dst)) : "memory");
+  if constexpr (LATE)
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off ; staged load: late" ::"v"(src), "{m0}"(lds_addr(dst))
+                 : "memory");
+  else
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off ; staged load" ::"v"(src), "{m0}"(lds_addr(dst))
+                 : "memory");
 }
 __device__ __forceinline__ void lds_dma4(const void* src, int32_t* dst) {
-  asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "{m0}"(lds_addr(dst)) : "memory");
+  asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off ; staged load" ::"v"(src), "{m0}"(lds_addr(dst)) : "memory");
 }
 
 // A late input in LDS (its two 16-byte halves 64 units apart): each read
@@ -247,7 +257,7 @@ struct D4Late {
   const double2* p = nullptr;
   __device__ D4 operator*() const {
     __builtin_amdgcn_sched_barrier(0);
-    wait_vmcnt<K>();
+    wait_vmcnt<K, true>();
     return *D4Lds{p};
   }
   __device__ explicit operator bool() const { return p != nullptr; }
@@ -304,19 +314,19 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_tri_staged(Dev d, AdjDev a, i
   // late loads of batch b (triangle t, corner ids iv) into lt
   auto issue_late = [&](int32_t t, const int32_t iv[3]) {
     for (int i = 0; i < 3; ++i)
-      for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + (STAGE == 2 ? 64 : 32) + 16 * c, &lt[(2 * i + c) * 64]);
+      for (int c = 0; c < 2; ++c) lds_dma16<true>(rec(iv[i]) + (STAGE == 2 ? 64 : 32) + 16 * c, &lt[(2 * i + c) * 64]);
     if (STAGE == 2) {
       for (int i = 0; i < 3; ++i)
-        for (int c = 0; c < 2; ++c) lds_dma16(rec(iv[i]) + 32 + 16 * c, &lt[(6 + 2 * i + c) * 64]);  // W* - W^n
+        for (int c = 0; c < 2; ++c) lds_dma16<true>(rec(iv[i]) + 32 + 16 * c, &lt[(6 + 2 * i + c) * 64]);  // W* - W^n
       const char* kn = reinterpret_cast<const char*>(d.keepN) + 64 * (int64_t)t;
-      for (int c = 0; c < 4; ++c) lds_dma16(kn + 16 * c, &lt[(12 + c) * 64]);
+      for (int c = 0; c < 4; ++c) lds_dma16<true>(kn + 16 * c, &lt[(12 + c) * 64]);
       const char* kt = reinterpret_cast<const char*>(d.keepT) + 32 * (int64_t)t;
-      for (int c = 0; c < 2; ++c) lds_dma16(kt + 16 * c, &lt[(16 + c) * 64]);
+      for (int c = 0; c < 2; ++c) lds_dma16<true>(kt + 16 * c, &lt[(16 + c) * 64]);
     } else if (kept) {
       const char* kn = reinterpret_cast<const char*>(a.kN + 2 * (int64_t)t);
-      for (int c = 0; c < 4; ++c) lds_dma16(kn + 16 * c, &lt[(6 + c) * 64]);
+      for (int c = 0; c < 4; ++c) lds_dma16<true>(kn + 16 * c, &lt[(6 + c) * 64]);
       const char* kt = reinterpret_cast<const char*>(a.kT + t);
-      for (int c = 0; c < 2; ++c) lds_dma16(kt + 16 * c, &lt[(10 + c) * 64]);
+      for (int c = 0; c < 2; ++c) lds_dma16<true>(kt + 16 * c, &lt[(10 + c) * 64]);
     }
   };
   // Batch b's eager inputs into registers; then its late loads, the eager
