@@ -187,7 +187,9 @@ def time_variant(rd, torch, mesh, W0, prec, steps, warmup, cfl, timed_reps, tile
     g.lumping = lump
     tuned = None
     if tile < 0:
-        best, table = g.tune(cfl, scheme, rd.RK2, prec, n_steps=3)
+        # twelve timed steps per candidate: the forms can differ by a few per
+        # cent, about the spread of a three-step replay
+        best, table = g.tune(cfl, scheme, rd.RK2, prec, n_steps=12)
         tuned = {"chosen": best, "ms_per_step": {str(k): round(v, 5) for k, v in table.items()}}
     else:
         g.tile = tile
