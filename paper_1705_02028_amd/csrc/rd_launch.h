@@ -51,9 +51,15 @@ hipError_t launch_fill_int(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_or_int(int* dst, const int* src, hipStream_t s);
 hipError_t launch_copy4(D4* dst, const D4* src, int64_t n, hipStream_t s);
 hipError_t launch_soa_to_aos(const double* soa, D4* dst, int64_t n, hipStream_t s);
-// Tiled form (rd_tiles.hip): one workgroup of min(tl.tt, kBlock) threads per
-// tile (a thread takes several triangles of a larger tile).
-inline int tile_threads(const Tiles& tl) { return tl.tt < kBlock ? tl.tt : kBlock; }
+// Tiled form (rd_tiles.hip): one workgroup per tile of min(tl.tt, kBlock)
+// threads in stage 1, half as many (at least 64) in stage 2, whose tile pass
+// idles its waves less at the barriers with two triangles per thread (a
+// thread takes several triangles of a larger tile).
+inline int tile_threads(const Tiles& tl, int stage) {
+  int t = stage == 2 ? tl.tt / 2 : tl.tt;
+  t = t < 64 ? 64 : t;
+  return t < kBlock ? t : kBlock;
+}
 // stage 1 (also Euler): R1 and, with cfl, the CFL bounds of interior
 // vertices; stage 2: the new state of interior vertices.
 hipError_t launch_tile(const Dev& d, const Tiles& tl, int fp32, int scheme, int stage, bool save, bool cfl,

@@ -64,7 +64,7 @@ size_t tile_lds_bytes(const Tiles& tl, int fp32, int stage, bool cfl) {
 
 template <typename R, int SCHEME>
 static hipError_t tile_go(const Dev& d, const Tiles& tl, int stage, bool save, bool cfl, hipStream_t s) {
-  const dim3 g(tl.ntiles), b(tile_threads(tl));
+  const dim3 g(tl.ntiles), b(tile_threads(tl, stage));
   const size_t lds = tile_lds<R>(tl, stage, cfl, nullptr, nullptr);
   if (stage == 2 && d.slump) hipLaunchKernelGGL((k_tile2<R, SCHEME, true>), g, b, lds, s, d, tl);
   else if (stage == 2) hipLaunchKernelGGL((k_tile2<R, SCHEME, false>), g, b, lds, s, d, tl);
