@@ -925,13 +925,13 @@ RD_API rd_status rd_residual(rd_mesh* m, int scheme, double* R, double* phiT, in
   HIPCHK(rd::launch_tri(d, 0, scheme, 1, true, false, s));
   if (on_device) {
     HIPCHK(rd::launch_gather(d, 0, rd::G_RESIDUAL, R, s));
-    if (phiT) HIPCHK(rd::launch_aos_to_soa(static_cast<const rd::D4*>(d.keepT), phiT, nt, s));
+    if (phiT) HIPCHK(rd::launch_keep_to_soa(d.keepT, phiT, nt, s));
     return RD_OK;
   }
   HIPCHK(rd::launch_gather(d, 0, rd::G_RESIDUAL, m->scratch, s));
   HIPCHK(hipMemcpyAsync(R, m->scratch, sizeof(double) * 4 * nv, hipMemcpyDeviceToHost, s));
   if (phiT) {
-    HIPCHK(rd::launch_aos_to_soa(static_cast<const rd::D4*>(d.keepT), m->scratch, nt, s));
+    HIPCHK(rd::launch_keep_to_soa(d.keepT, m->scratch, nt, s));
     HIPCHK(hipMemcpyAsync(phiT, m->scratch, sizeof(double) * 4 * nt, hipMemcpyDeviceToHost, s));
   }
   HIPCHK(hipStreamSynchronize(s));

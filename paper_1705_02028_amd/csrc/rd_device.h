@@ -89,8 +89,8 @@ struct Dev {
   double* sig = nullptr;   // [nv] |v| + c
   // triangle buffers
   void* C = nullptr;      // [ns] distributed parts, sliced layout (D4 or F4)
-  void* keepN = nullptr;  // [2nt] stage-1 N parts of corners 0 and 1 (D4 or F4)
-  void* keepT = nullptr;  // [nt] stage-1 triangle residual (D4 or F4)
+  void* keepN = nullptr;  // stage-1 N parts of corners 0 and 1 (2 nt records, D4 or F4; 16-byte planes)
+  void* keepT = nullptr;  // stage-1 triangle residual (nt records, D4 or F4; 16-byte planes)
   D4* WCn = nullptr;      // [nwv] wall term at W^n
   D4* WCs = nullptr;      // [nwv] wall term at W*
   void* lam = nullptr;    // [nt] l_max^T lambda_max^T per triangle: float from the FP32 triangle
@@ -365,19 +365,46 @@ __host__ __device__ inline void st4(void* base, int64_t i, const R a[4]) {
   reinterpret_cast<Q4<R>*>(base)[i] = q;
 }
 
-// The same as a non-temporal store: for records read back only much later
-// (the kept stage-1 parts, read by the stage-2 pass after the gather), so
-// that they do not evict from the caches the parts and parameter vectors the
-// next kernel reads.
+// The kept stage-1 records of a triangle (N parts of corners 0 and 1 in
+// keepN, phi^T in keepT) are read back only by the stage-2 pass, after the
+// gather. They are laid out in planes of 16-byte chunks: chunk c of record j
+// of triangle t sits at chunk index (KC j + c) nt + t, where KC is the
+// number of chunks per record (2 for FP64, 1 for FP32). One store or load
+// instruction of a wavefront then covers one contiguous kilobyte instead of
+// a strided span of partly written lines. The stores are non-temporal, so
+// that the records do not evict from the caches the parts and parameter
+// vectors the next kernel reads.
+template <typename R> struct KeepChunk;
+template <> struct KeepChunk<double> { typedef double V __attribute__((ext_vector_type(2))); };
+template <> struct KeepChunk<float> { typedef float V __attribute__((ext_vector_type(4))); };
+
 template <typename R>
-__host__ __device__ inline void st4_stream(void* base, int64_t i, const R a[4]) {
+__host__ __device__ inline void keep_store(void* base, int64_t nt, int64_t t, int j, const R a[4]) {
+  typedef typename KeepChunk<R>::V V;
+  constexpr int per = 16 / sizeof(R), kc = 4 / per;
+  V* p = reinterpret_cast<V*>(base);
+  for (int c = 0; c < kc; ++c) {
+    V q;
+    for (int e = 0; e < per; ++e) q[e] = a[c * per + e];
 #ifdef __HIP_DEVICE_COMPILE__
-  typedef R V4 __attribute__((ext_vector_type(4)));
-  const V4 q = {a[0], a[1], a[2], a[3]};
-  __builtin_nontemporal_store(q, reinterpret_cast<V4*>(base) + i);
+    __builtin_nontemporal_store(q, p + (kc * j + c) * nt + t);
 #else
-  st4<R>(base, i, a);
+    p[(kc * j + c) * nt + t] = q;
 #endif
+  }
+}
+
+template <typename R>
+__host__ __device__ inline Q4<R> keep_load(const void* base, int64_t nt, int64_t t, int j) {
+  typedef typename KeepChunk<R>::V V;
+  constexpr int per = 16 / sizeof(R), kc = 4 / per;
+  const V* p = reinterpret_cast<const V*>(base);
+  Q4<R> q;
+  for (int c = 0; c < kc; ++c) {
+    const V x = p[(kc * j + c) * nt + t];
+    for (int e = 0; e < per; ++e) q.v[c * per + e] = x[e];
+  }
+  return q;
 }
 
 template <typename R> __host__ __device__ inline const Q4<R>* zbuf(const Dev& d);
@@ -564,7 +591,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
         const Q4<R> dwv = io.dw(i);
         for (int k = 0; k < 4; ++k) srate[k] = srate[k] + dwv.v[k] * idt;
       }
-      const Q4<R> kt = ld4<R>(d.keepT, t);
+      const Q4<R> kt = keep_load<R>(d.keepT, d.nt, t, 0);
       for (int k = 0; k < 4; ++k) rhs1[k] = mass * srate[k] + R(0.5) * (kt.v[k] + phiT[k]);
     } else {
       for (int k = 0; k < 4; ++k) rhs1[k] = R(0);
@@ -619,14 +646,15 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     // those two, and stage 2 forms it again from the kept phi^T with the same
     // two subtractions, which gives back the identical value.
     if (STAGE == 1 && SAVE) {
-      st4_stream<R>(d.keepN, 2 * t, pN[0]);
-      st4_stream<R>(d.keepN, 2 * t + 1, pN[1]);
+      keep_store<R>(d.keepN, d.nt, t, 0, pN[0]);
+      keep_store<R>(d.keepN, d.nt, t, 1, pN[1]);
     }
     if (STAGE == 2) {
       // Phi^N_i = |T|/3 (W*_i - W^n_i)/dt + (phi^N_i(n) + phi^N_i(*))/2; the
       // kept parts and per-vertex differences are loaded here (cached) to
       // keep them out of registers across the solve
-      const Q4<R> k0 = ld4<R>(d.keepN, 2 * t), k1 = ld4<R>(d.keepN, 2 * t + 1), kt = ld4<R>(d.keepT, t);
+      const Q4<R> k0 = keep_load<R>(d.keepN, d.nt, t, 0), k1 = keep_load<R>(d.keepN, d.nt, t, 1),
+                  kt = keep_load<R>(d.keepT, d.nt, t, 0);
       R kn[3][4];
       for (int k = 0; k < 4; ++k) {
         kn[0][k] = k0.v[k];
@@ -644,7 +672,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     for (int i = 0; i < 3; ++i)
       for (int k = 0; k < 4; ++k) den[k] = den[k] + (R)fabs(pN[i][k]);
   }
-  if (STAGE == 1 && SAVE) st4_stream<R>(d.keepT, t, phiT);
+  if (STAGE == 1 && SAVE) keep_store<R>(d.keepT, d.nt, t, 0, phiT);
   // rhs1 is the residual being split (phi^T or Phi^T)
   R th[4] = {R(0), R(0), R(0), R(0)};
   if (SCHEME >= SCH_B && SCHEME <= SCH_BMIN) blend_theta<R, SCHEME>(rhs1, den, th);

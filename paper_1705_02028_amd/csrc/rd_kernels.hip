@@ -130,6 +130,18 @@ __global__ __launch_bounds__(kBlock) void k_aos_to_soa(const D4* src, double* so
   for (int k = 0; k < 4; ++k) soa[k * n + i] = w.v[k];
 }
 
+// FP64 kept triangle residuals (two 16-byte planes: components 0-1, then
+// 2-3) to component-major arrays.
+__global__ __launch_bounds__(kBlock) void k_keep_to_soa(const double2* src, double* soa, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double2 a = src[i], b = src[n + i];
+  soa[i] = a.x;
+  soa[n + i] = a.y;
+  soa[2 * n + i] = b.x;
+  soa[3 * n + i] = b.y;
+}
+
 __global__ void k_set_scalar(double* p, double v) { p[0] = v; }
 __global__ void k_set_int(int* p, int v) { p[0] = v; }
 __global__ void k_or_int(int* dst, const int* src) { dst[0] = dst[0] | src[0]; }
@@ -318,10 +330,11 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_tri_staged(Dev d, AdjDev a, i
     if (STAGE == 2) {
       for (int i = 0; i < 3; ++i)
         for (int c = 0; c < 2; ++c) lds_dma16<true>(rec(iv[i]) + 32 + 16 * c, &lt[(6 + 2 * i + c) * 64]);  // W* - W^n
-      const char* kn = reinterpret_cast<const char*>(d.keepN) + 64 * (int64_t)t;
-      for (int c = 0; c < 4; ++c) lds_dma16<true>(kn + 16 * c, &lt[(12 + c) * 64]);
-      const char* kt = reinterpret_cast<const char*>(d.keepT) + 32 * (int64_t)t;
-      for (int c = 0; c < 2; ++c) lds_dma16<true>(kt + 16 * c, &lt[(16 + c) * 64]);
+      // kept stage-1 records: 16-byte planes, chunk c of triangle t at c nt + t
+      const char* kn = reinterpret_cast<const char*>(d.keepN) + 16 * (int64_t)t;
+      for (int c = 0; c < 4; ++c) lds_dma16<true>(kn + 16 * c * d.nt, &lt[(12 + c) * 64]);
+      const char* kt = reinterpret_cast<const char*>(d.keepT) + 16 * (int64_t)t;
+      for (int c = 0; c < 2; ++c) lds_dma16<true>(kt + 16 * c * d.nt, &lt[(16 + c) * 64]);
     } else if (kept) {
       const char* kn = reinterpret_cast<const char*>(a.kN + 2 * (int64_t)t);
       for (int c = 0; c < 4; ++c) lds_dma16<true>(kn + 16 * c, &lt[(6 + c) * 64]);
@@ -542,6 +555,12 @@ hipError_t launch_get_state(const Dev& d, const D4* src, double* soa, hipStream_
 hipError_t launch_aos_to_soa(const D4* src, double* soa, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_aos_to_soa, dim3(nblk(n)), dim3(kBlock), 0, s, src, soa, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_keep_to_soa(const void* keep, double* soa, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_keep_to_soa, dim3(nblk(n)), dim3(kBlock), 0, s, static_cast<const double2*>(keep), soa, n);
   return hipGetLastError();
 }
 

@@ -43,6 +43,8 @@ hipError_t launch_set_state(const Dev& d, const double* soa, int fp32, hipStream
 hipError_t launch_refresh(const Dev& d, int fp32, hipStream_t s);
 hipError_t launch_get_state(const Dev& d, const D4* src, double* soa, hipStream_t s);
 hipError_t launch_aos_to_soa(const D4* src, double* soa, int64_t n, hipStream_t s);
+// FP64 kept triangle residuals (keepT) to component-major arrays
+hipError_t launch_keep_to_soa(const void* keep, double* soa, int64_t n, hipStream_t s);
 hipError_t launch_set_scalar(double* p, double v, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 // p[0..n) = v
