@@ -818,7 +818,7 @@ __host__ __device__ inline void adj_star_body(int64_t v, const Dev& d, const Adj
   double acc[4];
   const int32_t deg = d.row[v + 1] - d.row[v];
   const int64_t s0 = vslot(d, v);
-  sum_parts<double>(deg, [&](int32_t j) { return ld4<double>(d.C, s0 + 64 * (int64_t)j); }, acc);
+  sum_parts<double>(deg, [&](int32_t j) { return part_load<double>(d, s0 + 64 * (int64_t)j); }, acc);
   if (b >= 0) {
     const D4 wn = d.WCn[b];
     for (int k = 0; k < 4; ++k) acc[k] = acc[k] + wn.v[k];

@@ -88,7 +88,7 @@ struct Dev {
   void* dW = nullptr; // [nv] W* - W^n (D4 or F4)
   double* sig = nullptr;   // [nv] |v| + c
   // triangle buffers
-  void* C = nullptr;      // [ns] distributed parts, sliced layout (D4 or F4)
+  void* C = nullptr;      // [ns] distributed parts, sliced layout (D4 or F4 records in 16-byte planes)
   void* keepN = nullptr;  // stage-1 N parts of corners 0 and 1 (2 nt records, D4 or F4; 16-byte planes)
   void* keepT = nullptr;  // stage-1 triangle residual (nt records, D4 or F4; 16-byte planes)
   D4* WCn = nullptr;      // [nwv] wall term at W^n
@@ -365,46 +365,66 @@ __host__ __device__ inline void st4(void* base, int64_t i, const R a[4]) {
   reinterpret_cast<Q4<R>*>(base)[i] = q;
 }
 
-// The kept stage-1 records of a triangle (N parts of corners 0 and 1 in
-// keepN, phi^T in keepT) are read back only by the stage-2 pass, after the
-// gather. They are laid out in planes of 16-byte chunks: chunk c of record j
-// of triangle t sits at chunk index (KC j + c) nt + t, where KC is the
-// number of chunks per record (2 for FP64, 1 for FP32). One store or load
-// instruction of a wavefront then covers one contiguous kilobyte instead of
-// a strided span of partly written lines. The stores are non-temporal, so
-// that the records do not evict from the caches the parts and parameter
-// vectors the next kernel reads.
-template <typename R> struct KeepChunk;
-template <> struct KeepChunk<double> { typedef double V __attribute__((ext_vector_type(2))); };
-template <> struct KeepChunk<float> { typedef float V __attribute__((ext_vector_type(4))); };
+// Records of four reals in planes of 16-byte chunks: chunk c of record j of
+// item i sits at chunk index (KC j + c) n + i, where n is the number of items
+// and KC the number of chunks per record (2 for FP64, 1 for FP32). One store
+// or load instruction of a wavefront over consecutive items then covers one
+// contiguous kilobyte instead of a strided span of partly written lines.
+// Used for the distributed parts (item = part slot, one record) and for the
+// kept stage-1 records of a triangle (N parts of corners 0 and 1 in keepN,
+// phi^T in keepT), which are read back only by the stage-2 pass, after the
+// gather: those are stored non-temporally (NT), so that they do not evict
+// from the caches the parts and parameter vectors the next kernel reads.
+template <typename R> struct Chunk16;
+template <> struct Chunk16<double> { typedef double V __attribute__((ext_vector_type(2))); };
+template <> struct Chunk16<float> { typedef float V __attribute__((ext_vector_type(4))); };
 
-template <typename R>
-__host__ __device__ inline void keep_store(void* base, int64_t nt, int64_t t, int j, const R a[4]) {
-  typedef typename KeepChunk<R>::V V;
+template <typename R, bool NT>
+__host__ __device__ inline void plane_store(void* base, int64_t n, int64_t i, int j, const R a[4]) {
+  typedef typename Chunk16<R>::V V;
   constexpr int per = 16 / sizeof(R), kc = 4 / per;
   V* p = reinterpret_cast<V*>(base);
   for (int c = 0; c < kc; ++c) {
     V q;
     for (int e = 0; e < per; ++e) q[e] = a[c * per + e];
 #ifdef __HIP_DEVICE_COMPILE__
-    __builtin_nontemporal_store(q, p + (kc * j + c) * nt + t);
+    if (NT) __builtin_nontemporal_store(q, p + (kc * j + c) * n + i);
+    else p[(kc * j + c) * n + i] = q;
 #else
-    p[(kc * j + c) * nt + t] = q;
+    p[(kc * j + c) * n + i] = q;
 #endif
   }
 }
 
 template <typename R>
-__host__ __device__ inline Q4<R> keep_load(const void* base, int64_t nt, int64_t t, int j) {
-  typedef typename KeepChunk<R>::V V;
+__host__ __device__ inline Q4<R> plane_load(const void* base, int64_t n, int64_t i, int j) {
+  typedef typename Chunk16<R>::V V;
   constexpr int per = 16 / sizeof(R), kc = 4 / per;
   const V* p = reinterpret_cast<const V*>(base);
   Q4<R> q;
   for (int c = 0; c < kc; ++c) {
-    const V x = p[(kc * j + c) * nt + t];
+    const V x = p[(kc * j + c) * n + i];
     for (int e = 0; e < per; ++e) q.v[c * per + e] = x[e];
   }
   return q;
+}
+
+template <typename R>
+__host__ __device__ inline void keep_store(void* base, int64_t nt, int64_t t, int j, const R a[4]) {
+  plane_store<R, true>(base, nt, t, j, a);
+}
+template <typename R>
+__host__ __device__ inline Q4<R> keep_load(const void* base, int64_t nt, int64_t t, int j) {
+  return plane_load<R>(base, nt, t, j);
+}
+// Part of slot s in C.
+template <typename R>
+__host__ __device__ inline void part_store(const Dev& d, int64_t s, const R a[4]) {
+  plane_store<R, false>(d.C, d.ns, s, 0, a);
+}
+template <typename R>
+__host__ __device__ inline Q4<R> part_load(const Dev& d, int64_t s) {
+  return plane_load<R>(d.C, d.ns, s, 0);
 }
 
 template <typename R> __host__ __device__ inline const Q4<R>* zbuf(const Dev& d);
@@ -461,9 +481,7 @@ struct GlobalIO {
   __host__ __device__ const double* vr(int64_t t) const { return d.vr + 3 * (d.tmesh ? d.tmesh[t] : 0); }
   __host__ __device__ Q4<R> dw(int i) const { return reinterpret_cast<const Q4<R>*>(d.dW)[iv[i]]; }
   __host__ __device__ void part(int i, const R out[4]) const {
-    Q4<R> q;
-    for (int k = 0; k < 4; ++k) q.v[k] = out[k];
-    reinterpret_cast<Q4<R>*>(d.C)[ip[i]] = q;
+    part_store<R>(d, ip[i], out);
   }
   __host__ __device__ void cfl(int64_t t, double x) const { reinterpret_cast<R*>(d.lam)[t] = (R)x; }
   // Where the corner coefficients wait while the 4x4 solve runs (kept in
@@ -809,7 +827,7 @@ __host__ __device__ inline void gather_body(int64_t v, const Dev& d, double* out
   double acc[4];
   const int32_t deg = d.row[v + 1] - d.row[v];
   const int64_t s0 = vslot(d, v);
-  sum_parts<R>(deg, [&](int32_t j) { return ld4<R>(d.C, s0 + 64 * (int64_t)j); }, acc);
+  sum_parts<R>(deg, [&](int32_t j) { return part_load<R>(d, s0 + 64 * (int64_t)j); }, acc);
   if (b >= 0) {
     const D4 wn = d.WCn[b];
     if (MODE == G_STAGE2) {
