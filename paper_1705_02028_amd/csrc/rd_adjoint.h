@@ -327,7 +327,7 @@ __host__ __device__ inline bool tri_adjoint(const D4 Zc[3], const double nxd[3],
         for (int c = 0; c < 4; ++c) Aw[r][c] = A[r][c];
       }
       bool skipped;
-      solve2(Aw, e0, e1, x0, x1, skipped);
+      solve2<double, false>(Aw, e0, e1, x0, x1, skipped);  // IEEE division: the fast one spills here
       singular = singular || skipped;
       for (int r = 0; r < 4; ++r) {
         Ai[r][c2] = x0[r];

@@ -140,9 +140,26 @@ __host__ __device__ inline double unwrap(double d, double period, double half) {
 template <typename R> __host__ __device__ inline R rmax(R a, R b) { return fmax(a, b); }
 template <typename R> __host__ __device__ inline R rmin(R a, R b) { return fmin(a, b); }
 
-// Reciprocal: IEEE for FP64; the hardware reciprocal (about 1 ulp) for the
-// FP32 algebra, whose error budget is set by FP32 rounding anyway.
-__host__ __device__ inline double rcp(double x) { return 1.0 / x; }
+// Reciprocal. FP64 with FD (fast division): the hardware approximation
+// refined by two Newton-Raphson steps r <- r + r (1 - x r), each of which
+// about squares the relative error, so the result is within about an ulp of
+// 1/x; where a step is not finite (x zero or infinite, or so small that 1/x
+// overflows) the hardware value is kept. FP64 without FD: IEEE division.
+// FP32: the hardware reciprocal (about 1 ulp), whose error budget is set by
+// FP32 rounding anyway.
+template <bool FD = true>
+__host__ __device__ inline double rcp(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  if (FD) {
+    const double r0 = __builtin_amdgcn_rcp(x);
+    double r = fma(r0, fma(-x, r0, 1.0), r0);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r == r ? r : r0;
+  }
+#endif
+  return 1.0 / x;
+}
+template <bool FD = true>
 __host__ __device__ inline float rcp(float x) {
 #ifdef __HIP_DEVICE_COMPILE__
   return __builtin_amdgcn_rcpf(x);
@@ -151,12 +168,28 @@ __host__ __device__ inline float rcp(float x) {
 #endif
 }
 
-// Length L = sqrt(e2) and its reciprocal: IEEE square root and division
-// for FP64; one hardware reciprocal square root (about 1 ulp) for FP32.
+// Length L = sqrt(e2) > 0 and its reciprocal (e2 is a squared edge length or
+// the squared sound speed of a Roe state, positive and finite). FP64 with FD:
+// iL from the hardware reciprocal square root refined by two Newton-Raphson
+// steps y <- y + (y / 2)(1 - e2 y^2), and L = e2 iL (each within about an ulp
+// or two); without FD: IEEE square root and division. FP32: one hardware
+// reciprocal square root (about 1 ulp).
+template <bool FD = true>
 __host__ __device__ inline void len_rcp(double e2, double& L, double& iL) {
+#ifdef __HIP_DEVICE_COMPILE__
+  if (FD) {
+    double y = __builtin_amdgcn_rsq(e2);
+    y = fma(0.5 * y, fma(-(e2 * y), y, 1.0), y);
+    y = fma(0.5 * y, fma(-(e2 * y), y, 1.0), y);
+    iL = y;
+    L = e2 * y;
+    return;
+  }
+#endif
   L = sqrt(e2);
   iL = 1.0 / L;
 }
+template <bool FD = true>
 __host__ __device__ inline void len_rcp(float e2, float& L, float& iL) {
 #ifdef __HIP_DEVICE_COMPILE__
   iL = __builtin_amdgcn_rsqf(e2);
@@ -263,7 +296,7 @@ __host__ __device__ inline void build_A(const Roe<R>& q, const Corner<R> k[3], R
 // column whose best pivot is at most 2^-45 max|A| is skipped and its unknown
 // set to 0 (A is singular at stagnation; the K^+ x products stay unique).
 // `skipped` reports whether any column was skipped.
-template <typename R>
+template <typename R, bool FD = true>
 __host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x1[4], bool& skipped) {
   R amax = R(0);
   for (int r = 0; r < 4; ++r)
@@ -289,7 +322,7 @@ __host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x
     for (int j = k; j < 4; ++j) P[k][j] = sel4(r, A[0][j], A[1][j], A[2][j], A[3][j]);
     PB0[k] = sel4(r, b0[0], b0[1], b0[2], b0[3]);
     PB1[k] = sel4(r, b1[0], b1[1], b1[2], b1[3]);
-    PI[k] = ok ? rcp(P[k][k]) : R(0);
+    PI[k] = ok ? rcp<FD>(P[k][k]) : R(0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) used[i] = used[i] || (ok && r == i);
     // rows not eliminated get factor 0, which leaves them exactly unchanged
@@ -316,10 +349,10 @@ __host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x
   skipped = !(OK[0] && OK[1] && OK[2] && OK[3]);
 }
 
-template <typename R>
+template <typename R, bool FD = true>
 __host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x1[4]) {
   bool skipped;
-  solve2(A, b0, b1, x0, x1, skipped);
+  solve2<R, FD>(A, b0, b1, x0, x1, skipped);
 }
 
 // Blend of Section 3.3.3: Theta_k = |res_k| / sum_i |N_{i,k}| (0 if the sum is
@@ -330,13 +363,13 @@ __host__ __device__ inline void solve2(R A[4][4], R b0[4], R b1[4], R x0[4], R x
 // is below ~1/DBL_MAX, as happens at the edge of a uniform state at rest
 // where the parts have decayed to subnormal values) the exact quotient
 // decides.
-template <typename R, int SCHEME>
+template <typename R, int SCHEME, bool FD = true>
 __host__ __device__ inline void blend_theta(const R res[4], const R den[4], R th[4]) {
   for (int k = 0; k < 4; ++k) {
     const R a = (R)fabs(res[k]);
     R q = R(0);
     if (den[k] > R(0) && a > R(0)) {
-      q = a * rcp(den[k]);
+      q = a * rcp<FD>(den[k]);
       if (!(q < R(1))) q = a < den[k] ? a / den[k] : R(1);
     }
     th[k] = q;
@@ -472,8 +505,11 @@ __host__ __device__ inline void tri_load_verts(const Dev& d, TriIn<R>& in) {
 // and sends its parts: GlobalIO is the two-pass form (vertex arrays and the
 // sliced part buffer in HBM); the tiled form has its own (LDS-staged) IO.
 // `t` indexes the triangle's saved stage-1 values (keepN, keepT).
-template <typename R>
+// FD: fast FP64 reciprocals and square roots in the triangle body (see rcp,
+// len_rcp), else IEEE ones.
+template <typename R, bool FD = true>
 struct GlobalIO {
+  static constexpr bool kFastDiv = FD;
   const Dev& d;
   const int32_t* iv;
   const int32_t* ip;
@@ -491,6 +527,7 @@ struct GlobalIO {
 // LUMP (stage 2 only): selective lumping of Section 3.4 instead of global lumping.
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP = false, class IO>
 __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const Dev& d, const IO& io) {
+  constexpr bool FD = IO::kFastDiv;
   const double2 p0 = in.p[0], p1 = in.p[1], p2 = in.p[2];
   const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
   const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
@@ -522,12 +559,12 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   const R third = R(1) / R(3);
   R zb[4];
   for (int k = 0; k < 4; ++k) zb[k] = (Zc[0].v[k] + Zc[1].v[k] + Zc[2].v[k]) * third;
-  const R iz = rcp(zb[0]);
+  const R iz = rcp<FD>(zb[0]);
   q.u = zb[1] * iz;
   q.v = zb[2] * iz;
   q.h = zb[3] * iz;
   const R q2 = q.u * q.u + q.v * q.v;
-  len_rcp(q.g1 * (q.h - R(0.5) * q2), q.c, q.ic);
+  len_rcp<FD>(q.g1 * (q.h - R(0.5) * q2), q.c, q.ic);
   q.ac = R(0.5) * q.g1 * q2 * q.ic;
   q.uc = q.u * q.ic;
   q.vc = q.v * q.ic;
@@ -552,7 +589,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     // edge geometry in the algebra's precision, from FP64 coordinate differences
     const R ex = (R)nxd[i], ey = (R)nyd[i];
     R L, iL;
-    len_rcp(ex * ex + ey * ey, L, iL);
+    len_rcp<FD>(ex * ex + ey * ey, L, iL);
     lmax = rmax(lmax, L);
     Corner<R>& k = kc[i];
     k.nx = ex * iL;
@@ -620,7 +657,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     b0[k] = bN[k];
     b1[k] = rhs1[k];
   }
-  solve2(A, b0, b1, xN, xL);
+  solve2<R, FD>(A, b0, b1, xN, xL);
   // Corner parts. The parts of a distribution sum to the residual they
   // split (sum_i K_i^+ = A): sum_i K_i^+ (dW_i + xN) = phi^T and
   // sum_i K_i^+ xL = rhs1, so corner 2's parts are the residual minus those
@@ -693,7 +730,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   if (STAGE == 1 && SAVE) keep_store<R>(d.keepT, d.nt, t, 0, phiT);
   // rhs1 is the residual being split (phi^T or Phi^T)
   R th[4] = {R(0), R(0), R(0), R(0)};
-  if (SCHEME >= SCH_B && SCHEME <= SCH_BMIN) blend_theta<R, SCHEME>(rhs1, den, th);
+  if (SCHEME >= SCH_B && SCHEME <= SCH_BMIN) blend_theta<R, SCHEME, FD>(rhs1, den, th);
   if (SCHEME == SCH_BX)
     for (int k = 0; k < 4; ++k) th[k] = bx;
   for (int i = 0; i < 3; ++i) {
@@ -707,12 +744,12 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   }
 }
 
-template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP = false>
+template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP = false, bool FD = true>
 __host__ __device__ inline void tri_body(int64_t t, const Dev& d) {
   TriIn<R> in;
   tri_load_ids<R>(t, d, in);
   tri_load_verts<R, CFL>(d, in);
-  const GlobalIO<R> io{d, in.iv, in.ip};
+  const GlobalIO<R, FD> io{d, in.iv, in.ip};
   tri_compute<R, SCHEME, STAGE, SAVE, CFL, LUMP>(t, in, d, io);
 }
 

@@ -20,7 +20,8 @@ namespace rd {
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP>
 __global__ __launch_bounds__(kBlock, (TriKernelWaves<R, SCHEME, STAGE, SAVE, CFL>::value)) void k_tri(Dev d) {
   const int64_t t = xcd_block() * kBlock + threadIdx.x;
-  if (t < d.nt) tri_body<R, SCHEME, STAGE, SAVE, CFL, LUMP>(t, d);
+  if (t < d.nt)
+    tri_body<R, SCHEME, STAGE, SAVE, CFL, LUMP, TriKernelWaves<R, SCHEME, STAGE, SAVE, CFL>::fast_div>(t, d);
 }
 
 template <typename R, int MODE>
