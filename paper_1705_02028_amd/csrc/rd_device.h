@@ -169,27 +169,22 @@ __host__ __device__ inline float rcp(float x) {
 }
 
 // Length L = sqrt(e2) > 0 and its reciprocal (e2 is a squared edge length or
-// the squared sound speed of a Roe state, positive and finite). FP64 with FD:
-// iL from the hardware reciprocal square root refined by two Newton-Raphson
-// steps y <- y + (y / 2)(1 - e2 y^2), and L = e2 iL (each within about an ulp
-// or two); without FD: IEEE square root and division. FP32: one hardware
-// reciprocal square root (about 1 ulp).
-template <bool FD = true>
+// the squared sound speed of a Roe state, positive and finite). FP64: iL from
+// the hardware reciprocal square root refined by two Newton-Raphson steps
+// y <- y + (y / 2)(1 - e2 y^2), and L = e2 iL (each within about an ulp or
+// two). FP32: one hardware reciprocal square root (about 1 ulp).
 __host__ __device__ inline void len_rcp(double e2, double& L, double& iL) {
 #ifdef __HIP_DEVICE_COMPILE__
-  if (FD) {
-    double y = __builtin_amdgcn_rsq(e2);
-    y = fma(0.5 * y, fma(-(e2 * y), y, 1.0), y);
-    y = fma(0.5 * y, fma(-(e2 * y), y, 1.0), y);
-    iL = y;
-    L = e2 * y;
-    return;
-  }
-#endif
+  double y = __builtin_amdgcn_rsq(e2);
+  y = fma(0.5 * y, fma(-(e2 * y), y, 1.0), y);
+  y = fma(0.5 * y, fma(-(e2 * y), y, 1.0), y);
+  iL = y;
+  L = e2 * y;
+#else
   L = sqrt(e2);
   iL = 1.0 / L;
+#endif
 }
-template <bool FD = true>
 __host__ __device__ inline void len_rcp(float e2, float& L, float& iL) {
 #ifdef __HIP_DEVICE_COMPILE__
   iL = __builtin_amdgcn_rsqf(e2);
@@ -505,8 +500,8 @@ __host__ __device__ inline void tri_load_verts(const Dev& d, TriIn<R>& in) {
 // and sends its parts: GlobalIO is the two-pass form (vertex arrays and the
 // sliced part buffer in HBM); the tiled form has its own (LDS-staged) IO.
 // `t` indexes the triangle's saved stage-1 values (keepN, keepT).
-// FD: fast FP64 reciprocals and square roots in the triangle body (see rcp,
-// len_rcp), else IEEE ones.
+// FD: fast FP64 reciprocals in the triangle body (see rcp), else IEEE
+// division.
 template <typename R, bool FD = true>
 struct GlobalIO {
   static constexpr bool kFastDiv = FD;
@@ -564,7 +559,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
   q.v = zb[2] * iz;
   q.h = zb[3] * iz;
   const R q2 = q.u * q.u + q.v * q.v;
-  len_rcp<FD>(q.g1 * (q.h - R(0.5) * q2), q.c, q.ic);
+  len_rcp(q.g1 * (q.h - R(0.5) * q2), q.c, q.ic);
   q.ac = R(0.5) * q.g1 * q2 * q.ic;
   q.uc = q.u * q.ic;
   q.vc = q.v * q.ic;
@@ -589,7 +584,7 @@ __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const
     // edge geometry in the algebra's precision, from FP64 coordinate differences
     const R ex = (R)nxd[i], ey = (R)nyd[i];
     R L, iL;
-    len_rcp<FD>(ex * ex + ey * ey, L, iL);
+    len_rcp(ex * ex + ey * ey, L, iL);
     lmax = rmax(lmax, L);
     Corner<R>& k = kc[i];
     k.nx = ex * iL;

@@ -29,9 +29,8 @@ struct TriKernelWaves {
   static constexpr bool three = sizeof(R) == sizeof(double) &&
                                 (STAGE == 1 ? !(SCHEME == SCH_N && SAVE && CFL) : SCHEME <= SCH_LDA);
   static constexpr int value = three ? 3 : TriWaves<R>::value;
-  // fast FP64 reciprocals and square roots (rcp, len_rcp), except in the
-  // three-wave instances whose schedule would then spill (stage 2, and the
-  // Bx stage 1 with its sensor)
+  // fast FP64 reciprocals (rcp), except in the three-wave instances whose
+  // schedule would then spill (stage 2, and the Bx stage 1 with its sensor)
   static constexpr bool fast_div = !(three && (STAGE == 2 || SCHEME == SCH_BX));
 };
 

@@ -81,11 +81,11 @@ __host__ __device__ inline size_t tile_lds(const Tiles& tl, int stage, bool cfl,
 __host__ __device__ inline int tile_mesh(const Tiles& tl, int64_t tile) { return tl.tmesh ? tl.tmesh[tile] : 0; }
 
 // Triangle IO of the tiled form.
-// FD: fast FP64 reciprocals and square roots in the triangle body, else IEEE
-// ones. The stage-1 tile pass keeps the IEEE ones: with the shorter fast
-// sequences the compiler's schedule of that kernel needs more than the 168
-// registers of three waves per SIMD (measured slower); the stage-2 tile pass,
-// at two waves either way, takes the fast ones.
+// FD: fast FP64 reciprocals in the triangle body, else IEEE division. The
+// stage-1 tile pass keeps IEEE division: with the fast reciprocals the
+// compiler's schedule of that kernel needs more than the 168 registers of
+// three waves per SIMD (measured slower); the stage-2 tile pass, at two waves
+// either way, takes them.
 template <typename R, bool FD>
 struct TileIO {
   static constexpr bool kFastDiv = FD;
