@@ -110,7 +110,8 @@ struct rd_mesh {
   rd::Dev d;
   hipStream_t stream = nullptr;
   int device = 0;
-  int ncu = 0;  // compute units of the device
+  int ncu = 0;      // compute units of the device
+  int lds_max = 0;  // bytes of LDS one workgroup may use on the device
   // host copies, kept for batches
   std::vector<double> x, y, V;
   std::vector<int32_t> tri, wall, row, slot, bc, wv, wptr;
@@ -317,9 +318,6 @@ rd_status run_step_tiled(rd_mesh* m, int scheme, int time, int fp32, double cfl,
   return RD_OK;
 }
 
-// Largest dynamic LDS a tile workgroup may use.
-constexpr size_t kTileLdsLimit = 64 * 1024;
-
 // Builds (or drops, tt = 0) the tiles of a mesh.
 rd_status set_tile(rd_mesh* m, int tt) {
   if (tt == m->tile) return RD_OK;
@@ -347,7 +345,7 @@ rd_status set_tile(rd_mesh* m, int tt) {
   tl.nsv = (int64_t)P.sv.size();
   tl.nss = P.nss;
   const size_t need = std::max(rd::tile_lds_bytes(tl, 0, 1, true), rd::tile_lds_bytes(tl, 0, 2, false));
-  if (need > kTileLdsLimit)
+  if (need > (size_t)m->lds_max)
     return fail(RD_EUNSUPPORTED, "tiles of " + std::to_string(tt) + " triangles need " + std::to_string(need) +
                                      " bytes of LDS");
   std::vector<void*> list;
@@ -431,7 +429,8 @@ RD_API rd_status rd_mesh_create(const rd_mesh_desc* desc, void* stream, rd_mesh*
   m->stream = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&m->device) != hipSuccess ||
       hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
-      m->ncu <= 0) {
+      hipDeviceGetAttribute(&m->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device) != hipSuccess ||
+      m->ncu <= 0 || m->lds_max <= 0) {
     delete m;
     return fail(RD_EDEVICE, "no HIP device");
   }
