@@ -118,21 +118,21 @@ __host__ __device__ inline int32_t corner_slot(const Dev& d, int32_t v, uint32_t
   return d.sbase[v >> 6] + (v & 63) + 64 * (int32_t)((rk >> (10 * i)) & 1023u);
 }
 
-__host__ __device__ inline double unwrap(double d, double period) {
-  if (period > 0.0) {
-    if (d > 0.5 * period) d -= period;
-    else if (d < -0.5 * period) d += period;
-  }
-  return d;
-}
-
-// The same with the half period given: 0.5 period (exact) on a periodic
-// axis, +inf on another (no difference exceeds it). The comparisons then
-// read it where it is, with nothing to keep per thread.
+// Periodic difference: d shifted by one period into [-period/2, period/2]
+// on a periodic axis. The half period is given: 0.5 period (exact) on a
+// periodic axis, +inf on another (no difference exceeds it), so the
+// comparisons read it where it is, with nothing to keep per thread.
 __host__ __device__ inline double unwrap(double d, double period, double half) {
   if (d > half) d -= period;
   else if (d < -half) d += period;
   return d;
+}
+
+// The same value, selected rather than branched to (the forward triangle
+// bodies: no basic-block boundaries between their loads and arithmetic).
+__host__ __device__ inline double unwrap_select(double d, double period, double half) {
+  const double hi = d - period, lo = d + period;
+  return d > half ? hi : (d < -half ? lo : d);
 }
 
 // max / min of non-NaN values (one v_max / v_min instruction; the sign of a
@@ -524,8 +524,8 @@ template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL, bool LUMP = fa
 __host__ __device__ inline void tri_compute(int64_t t, const TriIn<R>& in, const Dev& d, const IO& io) {
   constexpr bool FD = IO::kFastDiv;
   const double2 p0 = in.p[0], p1 = in.p[1], p2 = in.p[2];
-  const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
-  const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
+  const double d1x = unwrap_select(p1.x - p0.x, d.px, d.hpx), d1y = unwrap_select(p1.y - p0.y, d.py, d.hpy);
+  const double d2x = unwrap_select(p2.x - p0.x, d.px, d.hpx), d2y = unwrap_select(p2.y - p0.y, d.py, d.hpy);
   // inward normals scaled by edge length: rotate the opposite edge by +90 degrees
   const double nxd[3] = {-(d2y - d1y), d2y, -d1y};
   const double nyd[3] = {d2x - d1x, -d2x, d1x};
@@ -958,8 +958,8 @@ __host__ __device__ inline void cfl_tri_body(int64_t t, const Dev& d) {
   const int64_t nt = d.nt;
   const int32_t iv[3] = {d.tv[t], d.tv[nt + t], d.tv[2 * nt + t]};
   const double2 p0 = d.xy[iv[0]], p1 = d.xy[iv[1]], p2 = d.xy[iv[2]];
-  const double d1x = unwrap(p1.x - p0.x, d.px), d1y = unwrap(p1.y - p0.y, d.py);
-  const double d2x = unwrap(p2.x - p0.x, d.px), d2y = unwrap(p2.y - p0.y, d.py);
+  const double d1x = unwrap_select(p1.x - p0.x, d.px, d.hpx), d1y = unwrap_select(p1.y - p0.y, d.py, d.hpy);
+  const double d2x = unwrap_select(p2.x - p0.x, d.px, d.hpx), d2y = unwrap_select(p2.y - p0.y, d.py, d.hpy);
   const double nxd[3] = {-(d2y - d1y), d2y, -d1y};
   const double nyd[3] = {d2x - d1x, -d2x, d1x};
   double lmax = 0.0, lam = 0.0;

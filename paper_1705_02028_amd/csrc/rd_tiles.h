@@ -81,14 +81,10 @@ __host__ __device__ inline size_t tile_lds(const Tiles& tl, int stage, bool cfl,
 __host__ __device__ inline int tile_mesh(const Tiles& tl, int64_t tile) { return tl.tmesh ? tl.tmesh[tile] : 0; }
 
 // Triangle IO of the tiled form.
-// FD: fast FP64 reciprocals in the triangle body, else IEEE division. The
-// stage-1 tile pass keeps IEEE division: with the fast reciprocals the
-// compiler's schedule of that kernel needs more than the 168 registers of
-// three waves per SIMD (measured slower); the stage-2 tile pass, at two waves
-// either way, takes them.
-template <typename R, bool FD>
+template <typename R>
 struct TileIO {
-  static constexpr bool kFastDiv = FD;
+  // fast FP64 reciprocals in the triangle body (see rcp)
+  static constexpr bool kFastDiv = true;
   const TileLds<R>& L;
   int lvi[3];
   int32_t dst[3];
@@ -154,7 +150,7 @@ __host__ __device__ inline void tile_tri(int64_t tile, int32_t j, const Dev& d, 
                                          const TileLds<R>& L) {
   const int64_t s = (int64_t)tl.tbeg[tile] + j;
   const int64_t nt = d.nt;
-  TileIO<R, STAGE == 2> io{L, {0, 0, 0}, {0, 0, 0}, tl.Cs, tl.lams, R(0), d.vr + 3 * tile_mesh(tl, tile)};
+  TileIO<R> io{L, {0, 0, 0}, {0, 0, 0}, tl.Cs, tl.lams, R(0), d.vr + 3 * tile_mesh(tl, tile)};
   TriIn<R> in;
   for (int i = 0; i < 3; ++i) {
     const int q = tl.lv[i * nt + s];
