@@ -58,9 +58,11 @@ struct AdjDev {
   D4* lamS = nullptr;        // [nv] dL/dW*
   D4* lamN = nullptr;        // [nv] running dL/dW^n (output)
   D4* Zn = nullptr;          // [nv] parameter vectors at W^n
+  // per-slot and per-triangle records below are stored in 16-byte planes
+  // (plane_store / plane_load: chunk c of record j of item i at (2 j + c) n + i)
   D4* cZ = nullptr;          // [ns] stage-1 corner cotangent of Z (sliced part layout)
-  ZW* cZW = nullptr;         // [ns] stage-2 corner cotangents of Z* and W* - W^n (sliced part layout)
-  D4* kN = nullptr;          // [2nt] cotangent of the kept stage-1 N parts of corners 0 and 1 (triangle order)
+  ZW* cZW = nullptr;         // [ns] stage-2 corner cotangents of Z* (record 0) and W* - W^n (record 1)
+  D4* kN = nullptr;          // [2nt] cotangent of the kept stage-1 N parts of corners 0 and 1 (records 0, 1)
   D4* kT = nullptr;          // [nt] cotangent of kept stage-1 residual
   D4* wcbar = nullptr;       // [nwv] cotangent of the wall term at W^n (stage 1 + half of stage 2)
   int* flag = nullptr;       // [2]: [0] the recomputed step went non-physical, [1] a solve skipped a column
@@ -709,12 +711,8 @@ __host__ __device__ inline void adj_tri2_compute(int64_t t, const Dev& d, const 
   if (tri_adjoint<SCHEME, 2, P, MU>(in.z, nxd, nyd, d.gamma, d.igamma, in.mu, P{}, P{}, P{}, &s2, &s2b, Zb))
     a.flag[1] = 1;
   for (int i = 0; i < 3; ++i) {
-    ZW c;
-    for (int k = 0; k < 4; ++k) {
-      c.z.v[k] = Zb[i][k];
-      c.w.v[k] = s2b.dw[i][k];
-    }
-    a.cZW[in.slot[i]] = c;
+    plane_store<double, false>(a.cZW, d.ns, in.slot[i], 0, Zb[i]);
+    plane_store<double, false>(a.cZW, d.ns, in.slot[i], 1, s2b.dw[i]);
   }
   // the kept stage-1 values are corners 0 and 1 and phi^T (corner 2 = phi^T
   // minus the other two), so corner 2's cotangent moves onto those three
@@ -724,9 +722,9 @@ __host__ __device__ inline void adj_tri2_compute(int64_t t, const Dev& d, const 
     b[1][k] = s2b.keepN[1][k] - s2b.keepN[2][k];
     b[2][k] = s2b.keepT[k] + s2b.keepN[2][k];
   }
-  st4<double>(a.kN, 2 * t, b[0]);
-  st4<double>(a.kN, 2 * t + 1, b[1]);
-  st4<double>(a.kT, t, b[2]);
+  plane_store<double, false>(a.kN, d.nt, t, 0, b[0]);
+  plane_store<double, false>(a.kN, d.nt, t, 1, b[1]);
+  plane_store<double, false>(a.kT, d.nt, t, 0, b[2]);
 }
 
 // Stage-1 reverse of one triangle: cotangents of Z^n (CSR order), from
@@ -740,7 +738,7 @@ __host__ __device__ inline void adj_tri1_compute(int64_t, const Dev& d, const Ad
   if (tri_adjoint<SCHEME, 1, P, MU>(in.z, nxd, nyd, d.gamma, d.igamma, in.mu, in.kn[0], in.kn[1], in.kt, nullptr,
                                     nullptr, Zb))
     a.flag[1] = 1;
-  for (int i = 0; i < 3; ++i) st4<double>(a.cZ, in.slot[i], Zb[i]);
+  for (int i = 0; i < 3; ++i) plane_store<double, false>(a.cZ, d.ns, in.slot[i], 0, Zb[i]);
 }
 
 // Wall-term transpose at one wall vertex b: sum over its wall edges of
@@ -773,7 +771,14 @@ __host__ __device__ inline void adj_gather2_body(int64_t v, const Dev& d, const 
   double zb[4] = {0, 0, 0, 0}, wb[4] = {0, 0, 0, 0};
   const int32_t deg = d.row[v + 1] - d.row[v];
   const int64_t s0 = vslot(d, v);
-  for_loaded(deg, [&](int32_t j) { return a.cZW[s0 + 64 * (int64_t)j]; }, [&](int32_t, const ZW& c) {
+  auto ld = [&](int32_t j) {
+    const int64_t s = s0 + 64 * (int64_t)j;
+    ZW c;
+    c.z = plane_load<double>(a.cZW, d.ns, s, 0);
+    c.w = plane_load<double>(a.cZW, d.ns, s, 1);
+    return c;
+  };
+  for_loaded(deg, ld, [&](int32_t, const ZW& c) {
     for (int k = 0; k < 4; ++k) {
       zb[k] += c.z.v[k];
       wb[k] += c.w.v[k];
@@ -858,7 +863,8 @@ __host__ __device__ inline void adj_gather1_body(int64_t v, const Dev& d, const 
   double zb[4] = {0, 0, 0, 0};
   const int32_t deg = d.row[v + 1] - d.row[v];
   const int64_t s0 = vslot(d, v);
-  for_loaded(deg, [&](int32_t j) { return a.cZ[s0 + 64 * (int64_t)j]; }, [&](int32_t, const D4& cz) {
+  for_loaded(deg, [&](int32_t j) { return plane_load<double>(a.cZ, d.ns, s0 + 64 * (int64_t)j, 0); },
+             [&](int32_t, const D4& cz) {
     for (int k = 0; k < 4; ++k) zb[k] += cz.v[k];
   });
   const D4 w = d.W[v], ls = a.lamS[v], ln = a.lamN[v];

@@ -337,10 +337,11 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_tri_staged(Dev d, AdjDev a, i
       const char* kt = reinterpret_cast<const char*>(d.keepT) + 16 * (int64_t)t;
       for (int c = 0; c < 2; ++c) lds_dma16<true>(kt + 16 * c * d.nt, &lt[(16 + c) * 64]);
     } else if (kept) {
-      const char* kn = reinterpret_cast<const char*>(a.kN + 2 * (int64_t)t);
-      for (int c = 0; c < 4; ++c) lds_dma16<true>(kn + 16 * c, &lt[(6 + c) * 64]);
-      const char* kt = reinterpret_cast<const char*>(a.kT + t);
-      for (int c = 0; c < 2; ++c) lds_dma16<true>(kt + 16 * c, &lt[(10 + c) * 64]);
+      // the stage-2 reverse's kept-part cotangents: 16-byte planes as above
+      const char* kn = reinterpret_cast<const char*>(a.kN) + 16 * (int64_t)t;
+      for (int c = 0; c < 4; ++c) lds_dma16<true>(kn + 16 * c * d.nt, &lt[(6 + c) * 64]);
+      const char* kt = reinterpret_cast<const char*>(a.kT) + 16 * (int64_t)t;
+      for (int c = 0; c < 2; ++c) lds_dma16<true>(kt + 16 * c * d.nt, &lt[(10 + c) * 64]);
     }
   };
   // Batch b's eager inputs into registers; then its late loads, the eager
