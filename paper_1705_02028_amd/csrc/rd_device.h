@@ -970,17 +970,46 @@ __host__ __device__ inline void cfl_tri_body(int64_t t, const Dev& d) {
   reinterpret_cast<double*>(d.lam)[t] = lmax * lam;
 }
 
-// 2 V_i / sum_{T ni i} l_max lambda_max of one vertex (terms of type R), its
-// triangles taken in ascending order.
-template <typename R = double>
-__host__ __device__ inline double cfl_vertex_bound(int64_t v, const Dev& d) {
-  double acc = 0.0;
-  const int32_t deg = d.row[v + 1] - d.row[v];
-  const int64_t s0 = vslot(d, v);
+// 2 V_i / sum_{T ni i} l_max lambda_max of U vertices v[u] (terms of type R),
+// each vertex's triangles taken in ascending order; out[u] is meaningful
+// where in[u]. The triangles of the first J ranks of all U vertices are
+// loaded before any term, and all those terms before any sum, so that the U
+// chains of dependent loads (row bounds and slice base, triangle, term)
+// overlap. Every load is in bounds whatever the degree, so none needs a
+// branch: a vertex out of range reads vertex vsafe, a rank past the degree
+// rereads the last rank (or slot 0 at degree 0) and its term is replaced by
+// an exact zero. Ranks from J on follow one at a time.
+template <typename R, int U, int J = 8>
+__host__ __device__ inline void cfl_vertex_bounds(const int64_t v[U], const bool in[U], int64_t vsafe,
+                                                  const Dev& d, double out[U]) {
   const R* lam = reinterpret_cast<const R*>(d.lam);
-  for_loaded(deg, [&](int32_t j) { return d.vtri[s0 + 64 * (int64_t)j]; },
-             [&](int32_t, int32_t t) { acc += (double)lam[t]; });
-  return 2.0 * d.V[v] / acc;
+  int32_t deg[U];
+  int64_t s0[U];
+  double vol[U];
+  for (int u = 0; u < U; ++u) {
+    const int64_t w = in[u] ? v[u] : vsafe;
+    deg[u] = d.row[w + 1] - d.row[w];
+    s0[u] = vslot(d, w);
+    vol[u] = d.V[w];
+  }
+  int32_t t[U][J];
+  for (int u = 0; u < U; ++u)
+    for (int j = 0; j < J; ++j) {
+      const int64_t k = deg[u] > 0 ? s0[u] + 64 * (int64_t)(j < deg[u] ? j : deg[u] - 1) : 0;
+      t[u][j] = d.vtri[k];
+    }
+  R term[U][J];
+  for (int u = 0; u < U; ++u)
+    for (int j = 0; j < J; ++j) {
+      const R x = lam[t[u][j] > 0 ? t[u][j] : 0];
+      term[u][j] = j < deg[u] ? x : R(0);
+    }
+  for (int u = 0; u < U; ++u) {
+    double acc = 0.0;
+    for (int j = 0; j < J; ++j) acc += (double)term[u][j];
+    for (int32_t j = J; j < deg[u]; ++j) acc += (double)lam[d.vtri[s0[u] + 64 * (int64_t)j]];
+    out[u] = 2.0 * vol[u] / acc;
+  }
 }
 
 }  // namespace rd

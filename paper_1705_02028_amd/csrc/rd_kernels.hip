@@ -46,12 +46,23 @@ __global__ __launch_bounds__(kBlock) void k_cfl_tri(Dev d) {
 // their block minima.
 template <bool FROM_CFLV, typename R>
 __global__ __launch_bounds__(kBlock) void k_cfl_vertex(Dev d, CflPlan p) {
+  constexpr int U = kCflSpan / kBlock;
   const int b = blockIdx.x;
   double x = INFINITY;
-#pragma unroll
-  for (int u = 0; u < kCflSpan / kBlock; ++u) {
-    const int64_t v = (int64_t)p.blk_v0[b] + u * kBlock + threadIdx.x;
-    if (v < p.blk_v1[b]) x = rmin(x, FROM_CFLV ? d.cflv[v] : cfl_vertex_bound<R>(v, d));
+  int64_t v[U];
+  bool in[U];
+  for (int u = 0; u < U; ++u) {
+    v[u] = (int64_t)p.blk_v0[b] + u * kBlock + threadIdx.x;
+    in[u] = v[u] < p.blk_v1[b];
+  }
+  if (FROM_CFLV) {
+    for (int u = 0; u < U; ++u)
+      if (in[u]) x = rmin(x, d.cflv[v[u]]);
+  } else {
+    double bound[U];
+    cfl_vertex_bounds<R, U>(v, in, p.blk_v0[b], d, bound);
+    for (int u = 0; u < U; ++u)
+      if (in[u]) x = rmin(x, bound[u]);
   }
   const double m = block_min(x);
   if (threadIdx.x == 0) p.part[b] = m;
