@@ -37,8 +37,18 @@ __global__ __launch_bounds__(kBlock) void k3_gather(Dev3 d) {
   double r[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int64_t first = d.sbase[v >> 6] + (v & 63);
   const int32_t n = d.deg[v];
-  for (int32_t j = 0; j < n; ++j)
-    for (int k = 0; k < 5; ++k) r[k] += d.part[k * d.ns + first + 64 * j];
+  // J ranks of parts loaded before any is summed (slot order kept; ranks
+  // past the degree reload its last rank and are left out of the sums)
+  constexpr int J = 4;
+  for (int32_t j0 = 0; j0 < n; j0 += J) {
+    double x[J][5];
+    for (int u = 0; u < J; ++u) {
+      const int64_t q = first + 64 * (int64_t)(j0 + u < n ? j0 + u : n - 1);
+      for (int k = 0; k < 5; ++k) x[u][k] = d.part[k * d.ns + q];
+    }
+    for (int u = 0; u < J; ++u)
+      for (int k = 0; k < 5; ++k) r[k] = j0 + u < n ? r[k] + x[u][k] : r[k];
+  }
   const double f = *d.dt / d.V[v];
   const double* src = MODE == 2 ? d.Ws : d.W;
   double* dst = MODE == 1 ? d.Ws : d.W;
@@ -72,10 +82,21 @@ __global__ __launch_bounds__(kBlock) void k3_cfl_vertex(Dev3 d) {
   const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double best = INFINITY;
   if (v < d.nv) {
+    // The parts are loaded J at a time before any of them is summed (in
+    // slot order, as one sequential sum), so that a thread keeps J loads in
+    // flight; ranks past the degree reload its last rank (every vertex has
+    // a tetrahedron) and are left out of the sum.
+    constexpr int J = 8;
     double acc = 0.0;
     const int64_t base = d.sbase[v >> 6] + (v & 63);
-    for (int32_t j = 0; j < d.deg[v]; ++j) acc += d.cpart[base + 64 * j];
-    best = 3.0 * d.V[v] / acc;
+    const int32_t n = d.deg[v];
+    const double vol = d.V[v];
+    for (int32_t j0 = 0; j0 < n; j0 += J) {
+      double x[J];
+      for (int u = 0; u < J; ++u) x[u] = d.cpart[base + 64 * (int64_t)(j0 + u < n ? j0 + u : n - 1)];
+      for (int u = 0; u < J; ++u) acc = j0 + u < n ? acc + x[u] : acc;
+    }
+    best = 3.0 * vol / acc;
   }
   red[threadIdx.x] = best;
   __syncthreads();
