@@ -620,6 +620,22 @@ def main():
                           "kernels_GBps": {k: round(b64[k] / (v * 1e-3) / 1e9, 1)
                                            for k, v in per64.items() if v > 0 and b64.get(k)},
                           "form": form64}
+        if form64["tile"]:
+            # the two-pass form beside the tuner's tiled pick: its triangle passes are the FP64
+            # kernels with a per-triangle roofline of their own
+            ms2, per2, _ = time_variant(rd, torch, mesh, W0, rd.FP64, args.steps, args.warmup, args.cfl,
+                                        args.timed_reps, 0)
+            b2 = algorithmic_bytes(nt, nv, False)
+            dom2 = max(per2, key=per2.get)
+            result["fp64"]["two_pass"] = {
+                "ms_per_step": round(ms2 / args.steps, 5),
+                "value": round(nt * args.steps / (ms2 * 1e-3), 1),
+                "roofline": roofline_entry(dom2, method_bytes(nt, False)[dom2], b2[dom2], per2[dom2],
+                                           f"fp64/two-pass/{dom2}"
+                                           if args.renumber == "none" and args.N == 2048 else None),
+                "kernels_ms": {k: round(v, 5) for k, v in per2.items()},
+                "kernels_GBps": {k: round(b2[k] / (v * 1e-3) / 1e9, 1) for k, v in per2.items()
+                                 if v > 0 and b2.get(k)}}
     if not args.no_variants:
         # the other blends and lumpings of Sections 3.3.3 and 3.4 on the same workload (two-pass form)
         print("bench: scheme variants", file=sys.stderr, flush=True)
