@@ -173,8 +173,9 @@ rd_status rd_step_timed(rd_mesh* mesh, double cfl, int scheme, int time, int pre
  * tile's vertex data in LDS and finishes the vertices all of whose
  * triangles are in the tile. Every vertex sums its parts in ascending
  * triangle order in both forms, so results are bitwise identical for every
- * choice. RD_EUNSUPPORTED if a tile would need more LDS than a workgroup
- * may use (64 KiB). Waits for the mesh's stream. The default is 0. */
+ * tile size and equal to the two-pass form's up to rounding. RD_EUNSUPPORTED
+ * if a tile would need more LDS than one workgroup may use on the device
+ * (160 KiB on MI355X). Waits for the mesh's stream. The default is 0. */
 rd_status rd_mesh_set_tile(rd_mesh* mesh, int tile_triangles);
 rd_status rd_mesh_get_tile(const rd_mesh* mesh, int* tile_triangles);
 /* Lumping of the mesh's RK2 steps (rd_lumping; RD_EINVAL for other values).
