@@ -109,7 +109,7 @@ def test_tiled_tiny_meshes_and_ragged_tiles(orc, rd):
     om = orc.OracleMesh(m)
     dt = om.max_dt(W, 0.4)
     ref = om.step(W, dt, orc.B, orc.RK2)
-    outs = [run(rd, m, W, dt, rd.B, rd.RK2, rd.FP64, t) for t in (32, 100, 200, 512)]
+    outs = [run(rd, m, W, dt, rd.B, rd.RK2, rd.FP64, t) for t in (32, 100, 200, 512, 1024)]
     assert err(outs[0], ref) <= TOL64
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
