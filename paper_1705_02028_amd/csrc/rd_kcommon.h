@@ -18,10 +18,11 @@ __device__ __forceinline__ int64_t xcd_block() {
 }
 
 // Minimum waves per SIMD the triangle kernels are compiled for: 4 for FP32;
-// for FP64, 3 where the kernel fits 168 VGPRs without spilling (every
-// stage-1 kernel but the N one with both outputs, and the N and LDA stage-2
-// kernels), else 2. (Parking the corner coefficients in LDS across the solve
-// to fit 3 waves was measured slower than 2 waves without it.)
+// for FP64, 3 where the kernel fits 168 VGPRs (every stage-1 kernel but the
+// N one with both outputs, and the N and LDA stage-2 kernels; the N stage-2
+// one and the LDA one with selective lumping spill one or two registers),
+// else 2. (Parking the corner coefficients in LDS across the solve to fit 3
+// waves was measured slower than 2 waves without it.)
 template <typename R> struct TriWaves { static constexpr int value = 2; };
 template <> struct TriWaves<float> { static constexpr int value = 4; };
 template <typename R, int SCHEME, int STAGE, bool SAVE, bool CFL>
